@@ -1,0 +1,185 @@
+/*
+ * fdtd.h -- C ABI of the MI355X reversible 3D FDTD library (libfdtd.so).
+ *
+ * The library advances Maxwell's curl equations on a Yee grid (arXiv
+ * 2412.12360, section 2.1, eqs. 1-2) in normalised units: cell size 1,
+ * c = eps0 = mu0 = 1, time step dt = S (the Courant number).  One step is
+ *     H^{n+1/2} = H^{n-1/2} - S * curl E^n           (forward differences)
+ *     E^{n+1}   = E^n + S/eps_r * curl H^{n+1/2}      (backward differences)
+ * with a convolutional PML on all six faces (section 2.1), a perfectly
+ * conducting box behind it, additive E sources and non-interpolated
+ * Poynting-flux detectors (section 2.1).  The gradient of the detector
+ * objective with respect to eps_r is computed by the paper's time-reversal
+ * method (section 2.2): the interior is rebuilt step by step by the exact
+ * inverse update, the PML-interface layers are replayed from a per-step
+ * record, and a hand-written adjoint runs alongside.
+ *
+ * Conventions
+ *  - Every array is float32, [nz][ny][nx] with x fastest, in device memory
+ *    unless stated otherwise.  Component ids: 0..2 = Ex,Ey,Ez, 3..5 = Hx,Hy,Hz.
+ *    Component positions (cell (i,j,k)): Ex(i+1/2,j,k), Ey(i,j+1/2,k),
+ *    Ez(i,j,k+1/2), Hx(i,j+1/2,k+1/2), Hy(i+1/2,j,k+1/2), Hz(i+1/2,j+1/2,k).
+ *  - The box is perfectly conducting: tangential E on the index-0 planes is
+ *    held at zero; reads at index n_a are zero.
+ *  - Ownership: the caller owns every device buffer (workspace, inputs,
+ *    outputs).  The library copies inv_eps and source amplitudes into the
+ *    workspace at create time; the workspace must outlive the handle.  The
+ *    library allocates no device memory.
+ *  - Streams: every call enqueues work on the stream given at create time (a
+ *    hipStream_t passed as void*; NULL = the default stream) and returns
+ *    without synchronising.  Outputs are valid once that stream has drained.
+ *    One handle must not be used by two host threads at once.
+ *  - Errors: arguments are validated before any work is enqueued; on error
+ *    nothing is enqueued and fdtd_last_error() describes the cause.  No
+ *    exception or abort crosses the ABI.
+ *  - Determinism: no atomics; every reduction has a fixed order, so results
+ *    are bitwise reproducible and independent of the time-block size.
+ */
+#ifndef FDTD_H
+#define FDTD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fdtd_ctx *fdtd_handle;
+
+typedef enum {
+    FDTD_OK = 0,
+    FDTD_E_INVALID = 1,      /* an argument is out of range or inconsistent   */
+    FDTD_E_NOMEM = 2,        /* workspace smaller than fdtd_footprint()        */
+    FDTD_E_DEVICE = 3,       /* a HIP call or kernel launch failed             */
+    FDTD_E_STATE = 4,        /* call not allowed in the handle's current state */
+    FDTD_E_UNSUPPORTED = 5   /* valid request this build does not implement    */
+} fdtd_status;
+
+enum { FDTD_EX = 0, FDTD_EY, FDTD_EZ, FDTD_HX, FDTD_HY, FDTD_HZ };
+
+/* Grid, materials and run length (section 2.1: Yee grid, eps per cell, CPML). */
+typedef struct {
+    int32_t nx, ny, nz;          /* cells per axis, each >= 4                          */
+    float courant;               /* S = c dt / dx, 0 < S < 1/sqrt(3)                   */
+    int32_t pml_cells;           /* p >= 0 CPML cells on every face (0 = bare PEC box) */
+    /* CFS-CPML grading in per-step units.  A negative value selects the default:
+     * order 3, sigma_max = 0.8 (order+1) S / sqrt(pml_eps_bg), kappa_max 1,
+     * alpha_max 0.01.  pml_eps_bg <= 0 means 1.                                    */
+    float pml_order, pml_sigma_max, pml_kappa_max, pml_alpha_max, pml_eps_bg;
+    const float *inv_eps;        /* device, N values of 1/eps_r (> 0); copied      */
+    int32_t design_lo[3];        /* half-open design box (x,y,z); gradient target  */
+    int32_t design_hi[3];
+    int32_t n_steps;             /* T: length of the source amplitudes and trace,  */
+                                 /* and the number of steps fdtd_grad reverses     */
+    int32_t record;              /* 1: keep the per-step interface record (needed  */
+                                 /* by fdtd_grad and by fdtd_inverse with a PML)   */
+    int32_t time_block;          /* K steps fused per pass over the grid (0 = auto,*/
+                                 /* 1..4); results are bitwise independent of K    */
+} fdtd_desc;
+
+/* Additive E source (section 2.1 uses total-field/scattered-field injection;
+ * this is the soft variant): after each E update, E_comp += amp[n] at one cell
+ * (kind 0) or on every cell of the z-normal plane k (kind 1).  Held PEC cells
+ * are skipped.  amp: device, n_steps floats (copied at create). */
+typedef struct {
+    int32_t kind, comp, i, j, k;
+    const float *amp;
+} fdtd_source;
+
+/* Non-interpolated Poynting flux through the z-normal plane k over the window
+ * [i0,i1) x [j0,j1) (section 2.1, detectors without interpolation):
+ *     P[n] = sum Ex*Hy - Ey*Hx   with E^{n+1} and H^{n+1/2}
+ * and the objective J = S * sum_n weight * P[n]. */
+typedef struct {
+    int32_t k, i0, i1, j0, j1;
+    float weight;
+} fdtd_flux_detector;
+
+#define FDTD_MAX_SOURCES 4
+#define FDTD_MAX_DETECTORS 4
+
+/* Bytes of workspace the problem needs (fields, material, PML state, record,
+ * adjoint state, scratch).  No device work.  bytes: host. */
+fdtd_status fdtd_footprint(const fdtd_desc *desc, const fdtd_source *src, int32_t nsrc,
+                           const fdtd_flux_detector *det, int32_t ndet, size_t *bytes);
+
+/* Validate the problem, carve the caller's workspace and enqueue its
+ * initialisation (fields zero, t = 0) on `stream`.  Checks: sizes, S, indices,
+ * nsrc/ndet limits, design box and detector windows inside the interior
+ * [p, n-p) when record = 1, inv_eps > 0 is the caller's duty.  Returns
+ * FDTD_E_NOMEM if workspace_bytes < fdtd_footprint().  out: host. */
+fdtd_status fdtd_create(const fdtd_desc *desc, const fdtd_source *src, int32_t nsrc,
+                        const fdtd_flux_detector *det, int32_t ndet,
+                        void *workspace, size_t workspace_bytes, void *stream,
+                        fdtd_handle *out);
+
+/* Advance n_steps time steps (section 2.1).  Requires t + n_steps <= n_steps of
+ * the descriptor.  trace (device, may be NULL): receives [n_steps][ndet] fluxes
+ * of these steps.  J (device, may be NULL): receives the objective accumulated
+ * from t = 0 to the new t.  With record = 1 each step also writes its interface
+ * record (section 2.2). */
+fdtd_status fdtd_forward(fdtd_handle h, int32_t n_steps, float *trace, float *J);
+
+/* Undo n_steps steps by the inverse update (section 2.2): E then H un-updated.
+ * On a bare PEC box (p = 0) the whole grid is rebuilt; with a PML only the
+ * interior [p, n-p)^3 is, using the record (record = 1 required). */
+fdtd_status fdtd_inverse(fdtd_handle h, int32_t n_steps);
+
+/* Gradient of J with respect to eps_r over the design box (section 2.2): runs
+ * all T steps backwards, each an adjoint step fused with the inverse step.
+ * Requires record = 1 and t = T reached from a reset.  Leaves t = 0.
+ * dJ_deps: device, design-box cells, x fastest.  recon_err (device, may be
+ * NULL): RMS of the rebuilt interior fields at t = 0 (exactly zero in exact
+ * arithmetic) over the RMS of the interior fields at t = T. */
+fdtd_status fdtd_grad(fdtd_handle h, float *dJ_deps, float *recon_err);
+
+/* Replace 1/eps_r (device, N values) and the per-cell update coefficients;
+ * allowed when t = 0. */
+fdtd_status fdtd_set_inv_eps(fdtd_handle h, const float *inv_eps);
+
+/* Zero the fields, PML state and adjoint state; t = 0. */
+fdtd_status fdtd_reset(fdtd_handle h);
+
+/* Release host-side state.  The workspace is the caller's to free. */
+fdtd_status fdtd_destroy(fdtd_handle h);
+
+/* Current time step t (host). */
+fdtd_status fdtd_time(fdtd_handle h, int32_t *t);
+
+/* Message of the last failed call on this handle (or of the last failed
+ * handle-less call on this thread when h is NULL). */
+const char *fdtd_last_error(fdtd_handle h);
+
+/* ---- test and diagnostic hooks ------------------------------------------ */
+
+/* Device pointer of the current buffer of field component comp (0..5) of the
+ * forward state (which = 0) or the adjoint state (which = 1). */
+fdtd_status fdtd_field_ptr(fdtd_handle h, int32_t which, int32_t comp, float **dev);
+
+/* All device arrays that make up the forward (which = 0) or adjoint (which = 1)
+ * state: the six fields and every CPML auxiliary array.  ptrs/counts are host
+ * arrays of capacity `cap`; *n receives the number of arrays.  Inner products
+ * over these arrays are layout independent. */
+fdtd_status fdtd_state_arrays(fdtd_handle h, int32_t which, float **ptrs, size_t *counts,
+                              int32_t cap, int32_t *n);
+
+/* Apply the source-free step map M n times to the forward state (adjoint = 0),
+ * or its exact transpose M^T n times to the adjoint state (adjoint = 1), with
+ * the same kernels and launch configuration as fdtd_forward / fdtd_grad.
+ * Does not change t. */
+fdtd_status fdtd_linear_steps(fdtd_handle h, int32_t n, int32_t adjoint);
+
+/* Device pointer to the interface record of step n: layout per step is, for
+ * faces f = 2a + side (a = axis, side 0 = low face: H on layer p-1, side 1 =
+ * high face: E on layer n_a - p), components (a+1)%3 then (a+2)%3, each over
+ * the interior window of the two other axes u < v as [v][u]. */
+fdtd_status fdtd_record_ptr(fdtd_handle h, int32_t n, float **dev, size_t *floats_per_step);
+
+/* Time-block size K actually used (host). */
+fdtd_status fdtd_time_block(fdtd_handle h, int32_t *K);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FDTD_H */

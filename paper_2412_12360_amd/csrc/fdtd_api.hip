@@ -1,0 +1,791 @@
+// Host side of libfdtd: validation, workspace planning, CPML grading tables,
+// launch sequencing and the extern "C" entry points declared in fdtd.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fdtd.h"
+#include "fdtd_internal.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+// ------------------------------------------------------------ bump planner
+// The same sequence of take() calls sizes the workspace (base == nullptr) and
+// carves it at create time, so footprint and layout can never disagree.
+struct Bump {
+    char *base;
+    size_t off = 0;
+    explicit Bump(void *b) : base((char *)b) {}
+    float *take(size_t floats)
+    {
+        off = (off + 255) & ~(size_t)255;
+        float *p = base ? (float *)(base + off) : nullptr;
+        off += floats * sizeof(float);
+        return p;
+    }
+    template <class T> T *take_as(size_t count)
+    {
+        off = (off + 255) & ~(size_t)255;
+        T *p = base ? (T *)(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+struct Geometry {
+    int nx, ny, nz, p;
+    long long N, slab_n[3];
+    RecGeom R;
+    Detectors D;
+    long long design_cells;
+};
+
+}  // namespace
+
+struct fdtd_ctx {
+    fdtd_desc desc;
+    fdtd_source src[FDTD_MAX_SOURCES];
+    fdtd_flux_detector det[FDTD_MAX_DETECTORS];
+    int nsrc = 0, ndet = 0;
+    hipStream_t stream = nullptr;
+    char err[512] = "";
+    int t = 0;
+    int T = 0;
+    int K = 1;
+    Geometry geo;
+    Grid g;
+    // forward state, ping-pong
+    float *fld[2][6];
+    float *psi[2][3][4];
+    int cur = 0;
+    // adjoint state: fields, psi-bar E-type (in place), psi-bar H-type (ping-pong)
+    float *adj[6];
+    float *pbE[3][2];
+    float *pbH[2][3][2];
+    int hpar = 0;
+    float *ce = nullptr, *inv_eps = nullptr, *d_design = nullptr;
+    float *prof[2][3][3];
+    float *amps[FDTD_MAX_SOURCES];
+    float *trace = nullptr, *planes = nullptr, *wdev = nullptr, *rec = nullptr, *gacc = nullptr;
+    float *parts[2] = {nullptr, nullptr};
+    int nparts_cap = 0;
+    int4 *tiles = nullptr;                 // tile tables of every K' <= K, two classes each
+    int tb_off[5][2], tb_cnt[5][2];
+    bool naive = false;                    // per-cell kernels instead of the z-march
+    float wS[FDTD_MAX_DETECTORS];
+    std::vector<float> host_tables;        // kept alive for async uploads
+    std::vector<int4> host_tiles;
+};
+
+namespace {
+
+fdtd_status fail(fdtd_ctx *h, fdtd_status st, const char *fmt, ...)
+{
+    char *dst = h ? h->err : g_err;
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(dst, 512, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+#define HIPCHK(h, expr)                                                                        \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail((h), FDTD_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));   \
+    } while (0)
+
+int dim_of(const fdtd_desc *d, int a) { return a == 0 ? d->nx : a == 1 ? d->ny : d->nz; }
+
+fdtd_status validate(fdtd_ctx *h, const fdtd_desc *d, const fdtd_source *src, int nsrc,
+                     const fdtd_flux_detector *det, int ndet)
+{
+    if (!d) return fail(h, FDTD_E_INVALID, "desc is NULL");
+    for (int a = 0; a < 3; a++)
+        if (dim_of(d, a) < 4 || dim_of(d, a) > (1 << 20))
+            return fail(h, FDTD_E_INVALID, "grid size %d on axis %d out of range [4, 2^20]", dim_of(d, a), a);
+    if ((double)d->nx * d->ny * d->nz > 4.0e10) return fail(h, FDTD_E_INVALID, "grid too large");
+    if (!(d->courant > 0.f) || !((double)d->courant < 1.0 / std::sqrt(3.0)))
+        return fail(h, FDTD_E_INVALID, "courant %g outside (0, 1/sqrt(3))", (double)d->courant);
+    const int p = d->pml_cells;
+    if (p < 0) return fail(h, FDTD_E_INVALID, "pml_cells < 0");
+    for (int a = 0; a < 3; a++)
+        if (p > 0 && dim_of(d, a) < 2 * p + 2)
+            return fail(h, FDTD_E_INVALID, "axis %d too small for %d PML cells", a, p);
+    if (!d->inv_eps) return fail(h, FDTD_E_INVALID, "inv_eps is NULL");
+    if (d->n_steps < 1) return fail(h, FDTD_E_INVALID, "n_steps < 1");
+    if (d->time_block < 0 || d->time_block > 4) return fail(h, FDTD_E_INVALID, "time_block outside [0,4]");
+    if (d->record != 0 && d->record != 1) return fail(h, FDTD_E_INVALID, "record must be 0 or 1");
+    if (nsrc < 0 || nsrc > FDTD_MAX_SOURCES) return fail(h, FDTD_E_INVALID, "nsrc outside [0,%d]", FDTD_MAX_SOURCES);
+    if (ndet < 0 || ndet > FDTD_MAX_DETECTORS) return fail(h, FDTD_E_INVALID, "ndet outside [0,%d]", FDTD_MAX_DETECTORS);
+    if (nsrc > 0 && !src) return fail(h, FDTD_E_INVALID, "sources NULL");
+    if (ndet > 0 && !det) return fail(h, FDTD_E_INVALID, "detectors NULL");
+    for (int s = 0; s < nsrc; s++) {
+        const fdtd_source &q = src[s];
+        if (q.kind != 0 && q.kind != 1) return fail(h, FDTD_E_INVALID, "source %d: kind must be 0 or 1", s);
+        if (q.comp < 0 || q.comp > 2) return fail(h, FDTD_E_INVALID, "source %d: comp must be 0..2", s);
+        if (q.k < 0 || q.k >= d->nz) return fail(h, FDTD_E_INVALID, "source %d: k out of range", s);
+        if (q.kind == 0 && (q.i < 0 || q.i >= d->nx || q.j < 0 || q.j >= d->ny))
+            return fail(h, FDTD_E_INVALID, "source %d: (i,j) out of range", s);
+        if (!q.amp) return fail(h, FDTD_E_INVALID, "source %d: amp is NULL", s);
+    }
+    const bool rec = d->record == 1;
+    auto inside = [&](int lo, int hi, int a) {
+        const int n = dim_of(d, a);
+        const int L = rec ? p : 0, H = rec ? n - p : n;
+        return lo >= L && hi <= H && lo < hi;
+    };
+    for (int m = 0; m < ndet; m++) {
+        const fdtd_flux_detector &q = det[m];
+        if (q.k < 0 || q.k >= d->nz || !inside(q.i0, q.i1, 0) || !inside(q.j0, q.j1, 1) ||
+            (rec && (q.k < p || q.k >= d->nz - p)))
+            return fail(h, FDTD_E_INVALID, "detector %d outside the %s", m, rec ? "interior" : "grid");
+        if (!std::isfinite(q.weight)) return fail(h, FDTD_E_INVALID, "detector %d: weight not finite", m);
+    }
+    for (int a = 0; a < 3; a++)
+        if (!inside(d->design_lo[a], d->design_hi[a], a))
+            return fail(h, FDTD_E_INVALID, "design box axis %d outside the %s or empty", a, rec ? "interior" : "grid");
+    return FDTD_OK;
+}
+
+void geometry(const fdtd_desc *d, const fdtd_flux_detector *det, int ndet, Geometry &G)
+{
+    G.nx = d->nx; G.ny = d->ny; G.nz = d->nz; G.p = d->pml_cells;
+    G.N = (long long)d->nx * d->ny * d->nz;
+    const int n[3] = {d->nx, d->ny, d->nz};
+    for (int a = 0; a < 3; a++) G.slab_n[a] = G.p > 0 ? 2LL * G.p * (G.N / n[a]) : 0;
+    long long off = 0;
+    for (int a = 0; a < 3; a++) {
+        const int ua = a == 0 ? 1 : 0, va = a == 2 ? 1 : 2;
+        G.R.Lu[a] = G.p > 0 ? n[ua] - 2 * G.p : 0;
+        G.R.Lv[a] = G.p > 0 ? n[va] - 2 * G.p : 0;
+        for (int side = 0; side < 2; side++) {
+            G.R.off[2 * a + side] = off;
+            off += 2LL * G.R.Lu[a] * G.R.Lv[a];
+        }
+    }
+    G.R.per_step = off;
+    G.D.ndet = ndet;
+    long long doff = 0;
+    for (int m = 0; m < FDTD_MAX_DETECTORS; m++) {
+        if (m < ndet) {
+            G.D.k[m] = det[m].k; G.D.i0[m] = det[m].i0; G.D.i1[m] = det[m].i1;
+            G.D.j0[m] = det[m].j0; G.D.j1[m] = det[m].j1;
+            G.D.off[m] = doff;
+            doff += (long long)(det[m].i1 - det[m].i0) * (det[m].j1 - det[m].j0);
+        } else {
+            G.D.k[m] = G.D.i0[m] = G.D.i1[m] = G.D.j0[m] = G.D.j1[m] = 0;
+            G.D.off[m] = doff;
+        }
+    }
+    G.D.per_step = doff;
+    G.design_cells = 1;
+    for (int a = 0; a < 3; a++) G.design_cells *= (d->design_hi[a] - d->design_lo[a]);
+}
+
+int choose_K(const fdtd_desc *d)
+{
+    if (d->time_block > 0) return d->time_block;
+    return 2;
+}
+
+// z extent of one workgroup's march: enough workgroups to fill the chip
+// (about 1024) without letting the 2K-plane z halo dominate.
+int zchunk(const Geometry &G, int K)
+{
+    if (const char *e = getenv("FDTD_TB_ZC")) {
+        const int v = atoi(e);
+        if (v > 0) return std::min(v, G.nz);
+    }
+    const long long tx = (G.nx + tb_tile_x(K) - 1) / tb_tile_x(K);
+    const long long ty = (G.ny + tb_tile_y(K) - 1) / tb_tile_y(K);
+    long long chunks = (1024 + tx * ty - 1) / (tx * ty);
+    chunks = std::max(1LL, std::min(chunks, (long long)(G.nz + 31) / 32));
+    return (int)((G.nz + chunks - 1) / chunks);
+}
+
+// Tile tables of the z-march kernel for K' = 1..K.  Class 1 tiles have an
+// x or y CPML slab inside their halo-extended footprint; class 0 tiles do not.
+void build_tiles(const Geometry &G, int K, std::vector<int4> &out, int off[5][2], int cnt[5][2])
+{
+    out.clear();
+    for (int kk = 0; kk < 5; kk++) off[kk][0] = off[kk][1] = cnt[kk][0] = cnt[kk][1] = 0;
+    for (int kk = 1; kk <= K; kk++) {
+        const int TX = tb_tile_x(kk), TY = tb_tile_y(kk), ZC = zchunk(G, kk);
+        std::vector<int4> cls[2];
+        for (int z0 = 0; z0 < G.nz; z0 += ZC)
+            for (int y0 = 0; y0 < G.ny; y0 += TY)
+                for (int x0 = 0; x0 < G.nx; x0 += TX) {
+                    const int z1 = std::min(z0 + ZC, G.nz);
+                    bool xy = false;
+                    if (G.p > 0) {
+                        const int xa = x0 - kk, xb = x0 + TX + kk, ya = y0 - kk, yb = y0 + TY + kk;
+                        xy = xa < G.p || xb > G.nx - G.p || ya < G.p || yb > G.ny - G.p;
+                    }
+                    cls[xy ? 1 : 0].push_back(make_int4(x0, y0, z0, z1));
+                }
+        for (int c = 0; c < 2; c++) {
+            off[kk][c] = (int)out.size();
+            cnt[kk][c] = (int)cls[c].size();
+            out.insert(out.end(), cls[c].begin(), cls[c].end());
+        }
+    }
+}
+
+long long interior_cells(const Geometry &G)
+{
+    return (long long)(G.nx - 2 * G.p) * (G.ny - 2 * G.p) * (G.nz - 2 * G.p);
+}
+
+// Carve (or size) the workspace.  Every pointer of h is set when base != nullptr.
+size_t plan(fdtd_ctx *h, const fdtd_desc *d, const Geometry &G, int K, void *base)
+{
+    Bump B(base);
+    const long long N = G.N;
+    for (int b = 0; b < 2; b++)
+        for (int q = 0; q < 6; q++) h->fld[b][q] = B.take(N);
+    for (int b = 0; b < 2; b++)
+        for (int a = 0; a < 3; a++)
+            for (int q = 0; q < 4; q++) h->psi[b][a][q] = G.p > 0 ? B.take(G.slab_n[a]) : nullptr;
+    h->ce = B.take(N);
+    h->d_design = B.take(G.design_cells);
+    const int n[3] = {d->nx, d->ny, d->nz};
+    for (int t = 0; t < 2; t++)
+        for (int a = 0; a < 3; a++)
+            for (int f = 0; f < 3; f++) h->prof[t][a][f] = B.take(n[a]);
+    for (int s = 0; s < FDTD_MAX_SOURCES; s++) h->amps[s] = B.take(d->n_steps);
+    h->trace = B.take((size_t)d->n_steps * std::max(1, G.D.ndet));
+    h->planes = B.take((size_t)std::max(1, K) * std::max<long long>(1, G.D.per_step));
+    h->wdev = B.take(FDTD_MAX_DETECTORS);
+    build_tiles(G, K, h->host_tiles, h->tb_off, h->tb_cnt);
+    h->tiles = B.take_as<int4>(std::max<size_t>(1, h->host_tiles.size()));
+    const long long nparts = (interior_cells(G) + 255) / 256;
+    h->nparts_cap = (int)nparts;
+    h->parts[0] = B.take(nparts);
+    h->parts[1] = B.take(nparts);
+    if (d->record) {
+        h->rec = B.take((size_t)d->n_steps * G.R.per_step);
+        for (int q = 0; q < 6; q++) h->adj[q] = B.take(N);
+        for (int a = 0; a < 3; a++)
+            for (int q = 0; q < 2; q++) h->pbE[a][q] = G.p > 0 ? B.take(G.slab_n[a]) : nullptr;
+        for (int b = 0; b < 2; b++)
+            for (int a = 0; a < 3; a++)
+                for (int q = 0; q < 2; q++) h->pbH[b][a][q] = G.p > 0 ? B.take(G.slab_n[a]) : nullptr;
+        h->gacc = B.take(G.design_cells);
+    } else {
+        h->rec = nullptr;
+        h->gacc = nullptr;
+        for (int q = 0; q < 6; q++) h->adj[q] = nullptr;
+        for (int a = 0; a < 3; a++)
+            for (int q = 0; q < 2; q++) h->pbE[a][q] = nullptr;
+        for (int b = 0; b < 2; b++)
+            for (int a = 0; a < 3; a++)
+                for (int q = 0; q < 2; q++) h->pbH[b][a][q] = nullptr;
+    }
+    return B.off + 256;
+}
+
+// CFS-CPML grading (Roden-Gedney form) at the staggered coordinate u of an
+// axis with n cells and p PML cells.
+void grade(int n, int p, double u, double m, double smax, double kmax, double amax, float out[3])
+{
+    double delta = 0.0;
+    if (p > 0) delta = std::max(std::max(p - u, u - (n - p)), 0.0) / p;
+    if (delta <= 0.0) { out[0] = 1.f; out[1] = 0.f; out[2] = 1.f; return; }
+    const double dm = std::pow(delta, m);
+    const double sig = smax * dm;
+    const double kap = 1.0 + (kmax - 1.0) * dm;
+    const double alp = amax * (1.0 - delta);
+    const double b = std::exp(-(sig / kap + alp));
+    const double a = sig > 0.0 ? sig / (sig * kap + kap * kap * alp) * (b - 1.0) : 0.0;
+    out[0] = (float)b; out[1] = (float)a; out[2] = (float)(1.0 / kap);
+}
+
+Fields fields_of(fdtd_ctx *h, int b)
+{
+    Fields F;
+    for (int q = 0; q < 6; q++) F.c[q] = h->fld[b][q];
+    return F;
+}
+
+Psi psi_of(fdtd_ctx *h, int b)
+{
+    Psi P;
+    for (int a = 0; a < 3; a++)
+        for (int q = 0; q < 4; q++) P.a[a][q] = h->psi[b][a][q];
+    return P;
+}
+
+Psi psibar_of(fdtd_ctx *h, int hb)
+{
+    Psi P;
+    for (int a = 0; a < 3; a++) {
+        P.a[a][0] = h->pbE[a][0];
+        P.a[a][1] = h->pbE[a][1];
+        P.a[a][2] = h->pbH[hb][a][0];
+        P.a[a][3] = h->pbH[hb][a][1];
+    }
+    return P;
+}
+
+Fields adj_of(fdtd_ctx *h)
+{
+    Fields A;
+    for (int q = 0; q < 6; q++) A.c[q] = h->adj[q];
+    return A;
+}
+
+fdtd_status zero_forward(fdtd_ctx *h)
+{
+    const Geometry &G = h->geo;
+    for (int b = 0; b < 2; b++) {
+        for (int q = 0; q < 6; q++) HIPCHK(h, launch_fill(h->fld[b][q], G.N, 0.f, h->stream));
+        for (int a = 0; a < 3; a++)
+            for (int q = 0; q < 4; q++)
+                if (h->psi[b][a][q]) HIPCHK(h, launch_fill(h->psi[b][a][q], G.slab_n[a], 0.f, h->stream));
+    }
+    h->cur = 0;
+    return FDTD_OK;
+}
+
+fdtd_status zero_adjoint(fdtd_ctx *h)
+{
+    if (!h->desc.record) return FDTD_OK;
+    const Geometry &G = h->geo;
+    for (int q = 0; q < 6; q++) HIPCHK(h, launch_fill(h->adj[q], G.N, 0.f, h->stream));
+    for (int a = 0; a < 3; a++)
+        for (int q = 0; q < 2; q++) {
+            if (h->pbE[a][q]) HIPCHK(h, launch_fill(h->pbE[a][q], G.slab_n[a], 0.f, h->stream));
+            for (int b = 0; b < 2; b++)
+                if (h->pbH[b][a][q]) HIPCHK(h, launch_fill(h->pbH[b][a][q], G.slab_n[a], 0.f, h->stream));
+        }
+    h->hpar = 0;
+    return FDTD_OK;
+}
+
+// one forward step n with the per-cell kernels (in place on buffer cur)
+fdtd_status step_naive(fdtd_ctx *h, int n, int with_src, int with_rec, int with_det)
+{
+    Fields F = fields_of(h, h->cur);
+    Psi P = psi_of(h, h->cur);
+    const Geometry &G = h->geo;
+    HIPCHK(h, launch_h_naive(h->g, F, P, h->stream));
+    if (with_rec && h->rec && G.R.per_step > 0)
+        HIPCHK(h, launch_record(h->g, F, G.R, h->rec + (size_t)n * G.R.per_step, 0, 0, h->stream));
+    HIPCHK(h, launch_e_naive(h->g, F, P, n, with_src, h->stream));
+    if (with_rec && h->rec && G.R.per_step > 0)
+        HIPCHK(h, launch_record(h->g, F, G.R, h->rec + (size_t)n * G.R.per_step, 1, 0, h->stream));
+    if (with_det && G.D.ndet > 0) {
+        HIPCHK(h, launch_det_planes(h->g, F, G.D, h->planes, h->stream));
+        for (int m = 0; m < G.D.ndet; m++) {
+            const long long L = (long long)(G.D.i1[m] - G.D.i0[m]) * (G.D.j1[m] - G.D.j0[m]);
+            HIPCHK(h, launch_reduce_rows(h->planes + G.D.off[m], L, 1, G.D.per_step,
+                                         h->trace + (size_t)n * G.D.ndet + m, G.D.ndet, h->stream));
+        }
+    }
+    return FDTD_OK;
+}
+
+// K' steps from n0 with the z-march kernel (buffer cur -> cur^1)
+fdtd_status steps_tb(fdtd_ctx *h, int n0, int kk, int with_src, int with_rec, int with_det)
+{
+    const Geometry &G = h->geo;
+    TbArgs a;
+    a.g = h->g;
+    a.in = fields_of(h, h->cur);
+    a.out = fields_of(h, h->cur ^ 1);
+    a.pin = psi_of(h, h->cur);
+    a.pout = psi_of(h, h->cur ^ 1);
+    a.n0 = n0;
+    a.with_src = with_src;
+    a.rec = (with_rec && h->rec && G.R.per_step > 0) ? h->rec + (size_t)n0 * G.R.per_step : nullptr;
+    a.R = G.R;
+    a.planes = (with_det && G.D.ndet > 0) ? h->planes : nullptr;
+    a.D = G.D;
+    a.xcd_remap = 1;
+    for (int c = 0; c < 2; c++) {
+        a.tiles = h->tiles + h->tb_off[kk][c];
+        a.ntiles = h->tb_cnt[kk][c];
+        HIPCHK(h, launch_tb_forward_class(a, kk, c == 1, h->stream));
+    }
+    h->cur ^= 1;
+    if (a.planes)
+        for (int m = 0; m < G.D.ndet; m++) {
+            const long long L = (long long)(G.D.i1[m] - G.D.i0[m]) * (G.D.j1[m] - G.D.j0[m]);
+            HIPCHK(h, launch_reduce_rows(h->planes + G.D.off[m], L, kk, G.D.per_step,
+                                         h->trace + (size_t)n0 * G.D.ndet + m, G.D.ndet, h->stream));
+        }
+    return FDTD_OK;
+}
+
+fdtd_status advance(fdtd_ctx *h, int t0, int n, int with_src, int with_rec, int with_det)
+{
+    if (h->naive) {
+        for (int s = t0; s < t0 + n; s++) {
+            fdtd_status st = step_naive(h, s, with_src, with_rec, with_det);
+            if (st != FDTD_OK) return st;
+        }
+        return FDTD_OK;
+    }
+    for (int s = t0; s < t0 + n;) {
+        const int kk = std::min(h->K, t0 + n - s);
+        fdtd_status st = steps_tb(h, s, kk, with_src, with_rec, with_det);
+        if (st != FDTD_OK) return st;
+        s += kk;
+    }
+    return FDTD_OK;
+}
+
+// one reverse step n: restore the interface layers, then the two phases
+fdtd_status reverse_step(fdtd_ctx *h, int n, int do_adj)
+{
+    const Geometry &G = h->geo;
+    Fields F = fields_of(h, h->cur);
+    if (G.p > 0) {
+        HIPCHK(h, launch_record(h->g, F, G.R, h->rec + (size_t)n * G.R.per_step, 0, 1, h->stream));
+        if (n > 0)
+            HIPCHK(h, launch_record(h->g, F, G.R, h->rec + (size_t)(n - 1) * G.R.per_step, 1, 1, h->stream));
+        else
+            HIPCHK(h, launch_record_zero_e(h->g, F, G.R, h->stream));
+    }
+    Fields A = adj_of(h);
+    if (do_adj && G.D.ndet > 0) HIPCHK(h, launch_det_adjoint(h->g, F, A, G.D, h->wS, h->stream));
+    Psi Pc = psibar_of(h, h->hpar), Pn = psibar_of(h, h->hpar ^ 1);
+    HIPCHK(h, launch_bwd_a(h->g, F, A, Pc, n, 1, do_adj, do_adj ? h->gacc : nullptr, h->desc.design_lo,
+                           h->desc.design_hi, h->stream));
+    HIPCHK(h, launch_bwd_b(h->g, F, A, Pc, Pn, 1, do_adj, h->stream));
+    if (do_adj) h->hpar ^= 1;
+    return FDTD_OK;
+}
+
+fdtd_status upload_materials(fdtd_ctx *h, const float *inv_eps)
+{
+    const Geometry &G = h->geo;
+    HIPCHK(h, launch_scale_ce(inv_eps, h->desc.courant, h->ce, G.N, h->stream));
+    HIPCHK(h, launch_gather_box(inv_eps, h->g, h->desc.design_lo, h->desc.design_hi, h->d_design, h->stream));
+    return FDTD_OK;
+}
+
+}  // namespace
+
+// ==================================================================== C ABI
+
+extern "C" {
+
+fdtd_status fdtd_footprint(const fdtd_desc *desc, const fdtd_source *src, int32_t nsrc,
+                           const fdtd_flux_detector *det, int32_t ndet, size_t *bytes)
+{
+    if (!bytes) return fail(nullptr, FDTD_E_INVALID, "bytes is NULL");
+    fdtd_status st = validate(nullptr, desc, src, nsrc, det, ndet);
+    if (st != FDTD_OK) return st;
+    fdtd_ctx *tmp = new (std::nothrow) fdtd_ctx();
+    if (!tmp) return fail(nullptr, FDTD_E_NOMEM, "host allocation failed");
+    Geometry G;
+    geometry(desc, det, ndet, G);
+    *bytes = plan(tmp, desc, G, choose_K(desc), nullptr);
+    delete tmp;
+    return FDTD_OK;
+}
+
+fdtd_status fdtd_create(const fdtd_desc *desc, const fdtd_source *src, int32_t nsrc,
+                        const fdtd_flux_detector *det, int32_t ndet, void *workspace, size_t workspace_bytes,
+                        void *stream, fdtd_handle *out)
+{
+    if (!out) return fail(nullptr, FDTD_E_INVALID, "out is NULL");
+    *out = nullptr;
+    fdtd_status st = validate(nullptr, desc, src, nsrc, det, ndet);
+    if (st != FDTD_OK) return st;
+    if (!workspace) return fail(nullptr, FDTD_E_INVALID, "workspace is NULL");
+    if (((uintptr_t)workspace & 255) != 0) return fail(nullptr, FDTD_E_INVALID, "workspace not 256-byte aligned");
+    fdtd_ctx *h = new (std::nothrow) fdtd_ctx();
+    if (!h) return fail(nullptr, FDTD_E_NOMEM, "host allocation failed");
+    h->desc = *desc;
+    h->nsrc = nsrc;
+    h->ndet = ndet;
+    for (int s = 0; s < nsrc; s++) h->src[s] = src[s];
+    for (int m = 0; m < ndet; m++) h->det[m] = det[m];
+    h->stream = (hipStream_t)stream;
+    h->T = desc->n_steps;
+    h->K = choose_K(desc);
+    h->naive = true;
+    if (const char *e = getenv("FDTD_NAIVE")) h->naive = atoi(e) != 0;
+    geometry(desc, det, ndet, h->geo);
+    const size_t need = plan(h, desc, h->geo, h->K, nullptr);
+    if (workspace_bytes < need) {
+        delete h;
+        return fail(nullptr, FDTD_E_NOMEM, "workspace %zu bytes < footprint %zu", workspace_bytes, need);
+    }
+    plan(h, desc, h->geo, h->K, workspace);
+
+    // device problem description
+    const Geometry &G = h->geo;
+    Grid &g = h->g;
+    g.nx = G.nx; g.ny = G.ny; g.nz = G.nz; g.p = G.p;
+    g.N = G.N; g.nxy = (long long)G.nx * G.ny;
+    g.S = desc->courant;
+    g.ce = h->ce;
+    for (int t = 0; t < 2; t++)
+        for (int a = 0; a < 3; a++)
+            for (int f = 0; f < 3; f++) g.prof[t][a][f] = h->prof[t][a][f];
+    for (int a = 0; a < 3; a++) g.slab_n[a] = G.slab_n[a];
+    g.nsrc = nsrc;
+    for (int s = 0; s < FD_MAXSRC; s++) {
+        const bool on = s < nsrc;
+        g.skind[s] = on ? src[s].kind : 0; g.scomp[s] = on ? src[s].comp : 0;
+        g.si[s] = on ? src[s].i : 0; g.sj[s] = on ? src[s].j : 0; g.sk[s] = on ? src[s].k : -1;
+        g.samp[s] = h->amps[s];
+    }
+
+    // CPML grading tables (double precision on the host, stored as float)
+    const double m = desc->pml_order >= 0.f ? desc->pml_order : 3.0;
+    const double ebg = desc->pml_eps_bg > 0.f ? desc->pml_eps_bg : 1.0;
+    const double smax = desc->pml_sigma_max >= 0.f ? desc->pml_sigma_max
+                                                   : 0.8 * (m + 1.0) * desc->courant / std::sqrt(ebg);
+    const double kmax = desc->pml_kappa_max >= 0.f ? desc->pml_kappa_max : 1.0;
+    const double amax = desc->pml_alpha_max >= 0.f ? desc->pml_alpha_max : 0.01;
+    const int n[3] = {G.nx, G.ny, G.nz};
+    h->host_tables.clear();
+    std::vector<size_t> starts;
+    for (int t = 0; t < 2; t++)
+        for (int a = 0; a < 3; a++) {
+            std::vector<float> b(n[a]), aa(n[a]), kv(n[a]);
+            for (int i = 0; i < n[a]; i++) {
+                float o[3];
+                grade(n[a], G.p, t == 0 ? (double)i : i + 0.5, m, smax, kmax, amax, o);
+                b[i] = o[0]; aa[i] = o[1]; kv[i] = o[2];
+            }
+            starts.push_back(h->host_tables.size());
+            h->host_tables.insert(h->host_tables.end(), b.begin(), b.end());
+            h->host_tables.insert(h->host_tables.end(), aa.begin(), aa.end());
+            h->host_tables.insert(h->host_tables.end(), kv.begin(), kv.end());
+        }
+    for (int m2 = 0; m2 < FDTD_MAX_DETECTORS; m2++) {
+        const float w = m2 < ndet ? det[m2].weight : 0.f;
+        h->wS[m2] = desc->courant * w;
+        h->host_tables.push_back(w);
+    }
+    {
+        size_t si = 0;
+        for (int t = 0; t < 2; t++)
+            for (int a = 0; a < 3; a++, si++)
+                for (int f = 0; f < 3; f++) {
+                    hipError_t e = hipMemcpyAsync(h->prof[t][a][f], h->host_tables.data() + starts[si] + (size_t)f * n[a],
+                                                  sizeof(float) * n[a], hipMemcpyHostToDevice, h->stream);
+                    if (e != hipSuccess) { fdtd_status r = fail(nullptr, FDTD_E_DEVICE, "upload: %s", hipGetErrorString(e)); delete h; return r; }
+                }
+        hipError_t e = hipMemcpyAsync(h->wdev, h->host_tables.data() + h->host_tables.size() - FDTD_MAX_DETECTORS,
+                                      sizeof(float) * FDTD_MAX_DETECTORS, hipMemcpyHostToDevice, h->stream);
+        if (e != hipSuccess) { fdtd_status r = fail(nullptr, FDTD_E_DEVICE, "upload: %s", hipGetErrorString(e)); delete h; return r; }
+    }
+    if (!h->host_tiles.empty()) {
+        hipError_t e = hipMemcpyAsync(h->tiles, h->host_tiles.data(), sizeof(int4) * h->host_tiles.size(),
+                                      hipMemcpyHostToDevice, h->stream);
+        if (e != hipSuccess) { fdtd_status r = fail(nullptr, FDTD_E_DEVICE, "tiles: %s", hipGetErrorString(e)); delete h; return r; }
+    }
+    for (int s = 0; s < nsrc; s++) {
+        hipError_t e = hipMemcpyAsync(h->amps[s], src[s].amp, sizeof(float) * desc->n_steps,
+                                      hipMemcpyDeviceToDevice, h->stream);
+        if (e != hipSuccess) { fdtd_status r = fail(nullptr, FDTD_E_DEVICE, "amp copy: %s", hipGetErrorString(e)); delete h; return r; }
+    }
+    st = upload_materials(h, desc->inv_eps);
+    if (st == FDTD_OK) st = zero_forward(h);
+    if (st == FDTD_OK) st = zero_adjoint(h);
+    if (st == FDTD_OK) {
+        hipError_t e = launch_fill(h->trace, (long long)desc->n_steps * std::max(1, ndet), 0.f, h->stream);
+        if (e != hipSuccess) st = fail(h, FDTD_E_DEVICE, "fill: %s", hipGetErrorString(e));
+    }
+    if (st != FDTD_OK) {
+        snprintf(g_err, sizeof g_err, "%s", h->err);
+        delete h;
+        return st;
+    }
+    // the host tables must outlive the asynchronous uploads
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        fail(nullptr, FDTD_E_DEVICE, "create sync: %s", hipGetErrorString(e));
+        delete h;
+        return FDTD_E_DEVICE;
+    }
+    h->t = 0;
+    *out = h;
+    return FDTD_OK;
+}
+
+fdtd_status fdtd_forward(fdtd_handle h, int32_t n_steps, float *trace, float *J)
+{
+    if (!h) return fail(nullptr, FDTD_E_INVALID, "handle is NULL");
+    if (n_steps < 0) return fail(h, FDTD_E_INVALID, "n_steps < 0");
+    if (h->t + n_steps > h->T)
+        return fail(h, FDTD_E_STATE, "t + n_steps = %d exceeds n_steps of the descriptor (%d)", h->t + n_steps, h->T);
+    const int t0 = h->t;
+    fdtd_status st = advance(h, t0, n_steps, 1, 1, 1);
+    if (st != FDTD_OK) return st;
+    h->t = t0 + n_steps;
+    const Geometry &G = h->geo;
+    if (trace && G.D.ndet > 0 && n_steps > 0)
+        HIPCHK(h, launch_copy(trace, h->trace + (size_t)t0 * G.D.ndet, (long long)n_steps * G.D.ndet, h->stream));
+    if (J) {
+        if (G.D.ndet > 0)
+            HIPCHK(h, launch_objective(h->trace, h->t, G.D.ndet, h->wdev, h->desc.courant, J, h->stream));
+        else
+            HIPCHK(h, launch_fill(J, 1, 0.f, h->stream));
+    }
+    return FDTD_OK;
+}
+
+fdtd_status fdtd_inverse(fdtd_handle h, int32_t n_steps)
+{
+    if (!h) return fail(nullptr, FDTD_E_INVALID, "handle is NULL");
+    if (n_steps < 0 || n_steps > h->t) return fail(h, FDTD_E_STATE, "cannot undo %d steps at t = %d", n_steps, h->t);
+    if (h->geo.p > 0 && !h->desc.record) return fail(h, FDTD_E_STATE, "inverse with a PML needs record = 1");
+    for (int s = 0; s < n_steps; s++) {
+        fdtd_status st = reverse_step(h, h->t - 1, 0);
+        if (st != FDTD_OK) return st;
+        h->t -= 1;
+    }
+    return FDTD_OK;
+}
+
+fdtd_status fdtd_grad(fdtd_handle h, float *dJ_deps, float *recon_err)
+{
+    if (!h) return fail(nullptr, FDTD_E_INVALID, "handle is NULL");
+    if (!h->desc.record) return fail(h, FDTD_E_STATE, "fdtd_grad needs record = 1");
+    if (h->t != h->T) return fail(h, FDTD_E_STATE, "fdtd_grad needs t = T (t = %d, T = %d)", h->t, h->T);
+    if (!dJ_deps) return fail(h, FDTD_E_INVALID, "dJ_deps is NULL");
+    const Geometry &G = h->geo;
+    int np = 0;
+    HIPCHK(h, launch_interior_sumsq(h->g, fields_of(h, h->cur), h->parts[0], &np, h->stream));
+    fdtd_status st = zero_adjoint(h);
+    if (st != FDTD_OK) return st;
+    HIPCHK(h, launch_fill(h->gacc, G.design_cells, 0.f, h->stream));
+    for (int n = h->T - 1; n >= 0; n--) {
+        st = reverse_step(h, n, 1);
+        if (st != FDTD_OK) return st;
+    }
+    HIPCHK(h, launch_interior_sumsq(h->g, fields_of(h, h->cur), h->parts[1], &np, h->stream));
+    if (recon_err) HIPCHK(h, launch_recon(h->parts[0], h->parts[1], np, recon_err, h->stream));
+    HIPCHK(h, launch_deps(h->gacc, h->d_design, G.design_cells, h->desc.courant, dJ_deps, h->stream));
+    st = zero_forward(h);
+    if (st != FDTD_OK) return st;
+    HIPCHK(h, launch_fill(h->trace, (long long)h->T * std::max(1, G.D.ndet), 0.f, h->stream));
+    h->t = 0;
+    return FDTD_OK;
+}
+
+fdtd_status fdtd_set_inv_eps(fdtd_handle h, const float *inv_eps)
+{
+    if (!h) return fail(nullptr, FDTD_E_INVALID, "handle is NULL");
+    if (!inv_eps) return fail(h, FDTD_E_INVALID, "inv_eps is NULL");
+    if (h->t != 0) return fail(h, FDTD_E_STATE, "materials can change only at t = 0");
+    return upload_materials(h, inv_eps);
+}
+
+fdtd_status fdtd_reset(fdtd_handle h)
+{
+    if (!h) return fail(nullptr, FDTD_E_INVALID, "handle is NULL");
+    fdtd_status st = zero_forward(h);
+    if (st == FDTD_OK) st = zero_adjoint(h);
+    if (st != FDTD_OK) return st;
+    HIPCHK(h, launch_fill(h->trace, (long long)h->T * std::max(1, h->geo.D.ndet), 0.f, h->stream));
+    h->t = 0;
+    return FDTD_OK;
+}
+
+fdtd_status fdtd_destroy(fdtd_handle h)
+{
+    delete h;
+    return FDTD_OK;
+}
+
+fdtd_status fdtd_time(fdtd_handle h, int32_t *t)
+{
+    if (!h || !t) return fail(h, FDTD_E_INVALID, "NULL argument");
+    *t = h->t;
+    return FDTD_OK;
+}
+
+const char *fdtd_last_error(fdtd_handle h) { return h ? h->err : g_err; }
+
+fdtd_status fdtd_field_ptr(fdtd_handle h, int32_t which, int32_t comp, float **dev)
+{
+    if (!h || !dev) return fail(h, FDTD_E_INVALID, "NULL argument");
+    if (comp < 0 || comp > 5) return fail(h, FDTD_E_INVALID, "comp outside 0..5");
+    if (which == 0) { *dev = h->fld[h->cur][comp]; return FDTD_OK; }
+    if (which == 1) {
+        if (!h->desc.record) return fail(h, FDTD_E_STATE, "no adjoint state without record = 1");
+        *dev = h->adj[comp];
+        return FDTD_OK;
+    }
+    return fail(h, FDTD_E_INVALID, "which must be 0 or 1");
+}
+
+fdtd_status fdtd_state_arrays(fdtd_handle h, int32_t which, float **ptrs, size_t *counts, int32_t cap, int32_t *n)
+{
+    if (!h || !ptrs || !counts || !n) return fail(h, FDTD_E_INVALID, "NULL argument");
+    if (which == 1 && !h->desc.record) return fail(h, FDTD_E_STATE, "no adjoint state without record = 1");
+    if (which != 0 && which != 1) return fail(h, FDTD_E_INVALID, "which must be 0 or 1");
+    std::vector<std::pair<float *, size_t>> v;
+    const Geometry &G = h->geo;
+    for (int q = 0; q < 6; q++) v.push_back({which == 0 ? h->fld[h->cur][q] : h->adj[q], (size_t)G.N});
+    if (G.p > 0)
+        for (int a = 0; a < 3; a++)
+            for (int q = 0; q < 4; q++) {
+                float *p = which == 0 ? h->psi[h->cur][a][q] : (q < 2 ? h->pbE[a][q] : h->pbH[h->hpar][a][q - 2]);
+                v.push_back({p, (size_t)G.slab_n[a]});
+            }
+    if ((int)v.size() > cap) return fail(h, FDTD_E_INVALID, "capacity %d < %zu arrays", cap, v.size());
+    for (size_t i = 0; i < v.size(); i++) { ptrs[i] = v[i].first; counts[i] = v[i].second; }
+    *n = (int32_t)v.size();
+    return FDTD_OK;
+}
+
+fdtd_status fdtd_linear_steps(fdtd_handle h, int32_t n, int32_t adjoint)
+{
+    if (!h) return fail(nullptr, FDTD_E_INVALID, "handle is NULL");
+    if (n < 0) return fail(h, FDTD_E_INVALID, "n < 0");
+    if (adjoint && !h->desc.record) return fail(h, FDTD_E_STATE, "no adjoint state without record = 1");
+    if (!adjoint) return advance(h, 0, n, 0, 0, 0);
+    for (int s = 0; s < n; s++) {
+        fdtd_status st;
+        {
+            Fields F = fields_of(h, h->cur), A = adj_of(h);
+            Psi Pc = psibar_of(h, h->hpar), Pn = psibar_of(h, h->hpar ^ 1);
+            HIPCHK(h, launch_bwd_a(h->g, F, A, Pc, 0, 0, 1, nullptr, h->desc.design_lo, h->desc.design_hi, h->stream));
+            HIPCHK(h, launch_bwd_b(h->g, F, A, Pc, Pn, 0, 1, h->stream));
+            h->hpar ^= 1;
+            st = FDTD_OK;
+        }
+        if (st != FDTD_OK) return st;
+    }
+    return FDTD_OK;
+}
+
+fdtd_status fdtd_record_ptr(fdtd_handle h, int32_t n, float **dev, size_t *floats_per_step)
+{
+    if (!h || !dev || !floats_per_step) return fail(h, FDTD_E_INVALID, "NULL argument");
+    if (!h->desc.record) return fail(h, FDTD_E_STATE, "record = 0");
+    if (n < 0 || n >= h->T) return fail(h, FDTD_E_INVALID, "step outside [0, T)");
+    *dev = h->rec + (size_t)n * h->geo.R.per_step;
+    *floats_per_step = (size_t)h->geo.R.per_step;
+    return FDTD_OK;
+}
+
+fdtd_status fdtd_time_block(fdtd_handle h, int32_t *K)
+{
+    if (!h || !K) return fail(h, FDTD_E_INVALID, "NULL argument");
+    *K = h->K;
+    return FDTD_OK;
+}
+
+}  // extern "C"

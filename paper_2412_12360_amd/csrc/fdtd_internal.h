@@ -1,0 +1,164 @@
+// Internal declarations of libfdtd: device-side problem description, the
+// canonical float32 update expressions every kernel shares, and launchers.
+//
+// Update expressions (the Yee leapfrog of arXiv 2412.12360, section 2.1, with
+// the convolutional PML the paper cites).  For a difference d along axis a of a
+// component inside that axis' PML slab:
+//     psi' = fma(b, psi, a*d)          T = fma(d, 1/kappa, psi')
+// and outside any slab T = d.  With b = 1, a = 0, 1/kappa = 1 both forms give
+// the same bits.  Then
+//     H' = fma(-S, T1 - T2, H)         E' = fma(S/eps_r, T1 - T2, E)
+// and the inverse step (section 2.2) evaluates the identical increment:
+//     E  = fma(-S/eps_r, T1 - T2, E')  H  = fma(S, T1 - T2, H')
+// Every kernel, at any time-block size, uses exactly these expressions, so the
+// naive and the temporally blocked paths agree bit for bit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#define FD_MAXSRC 4
+#define FD_MAXDET 4
+
+// CPML auxiliary arrays per slab axis a (cells with coordinate a in [0,p) or
+// [n_a-p, n_a), the other two coordinates full range):
+//   0: E comp (a+1)%3   1: E comp (a+2)%3   2: H comp (a+1)%3   3: H comp (a+2)%3
+// Slab storage replaces coordinate a by s in [0,2p) (s = c for c < p,
+// s = c - (n_a - 2p) for c >= n_a - p) and keeps [z][y][x] order.
+struct Grid {
+    int nx, ny, nz, p;
+    long long N;
+    long long nxy;
+    float S;
+    const float *ce;               // S/eps_r per cell
+    const float *prof[2][3][3];    // [E=0/H=1][axis][b=0, a=1, 1/kappa=2] -> n_a values
+    long long slab_n[3];           // cells per slab axis
+    // sources
+    int nsrc;
+    int skind[FD_MAXSRC], scomp[FD_MAXSRC], si[FD_MAXSRC], sj[FD_MAXSRC], sk[FD_MAXSRC];
+    const float *samp[FD_MAXSRC];
+};
+
+struct Fields {
+    float *c[6];                   // Ex, Ey, Ez, Hx, Hy, Hz
+};
+
+struct Psi {
+    float *a[3][4];                // per slab axis, the four arrays above (nullptr if p == 0)
+};
+
+// interface record geometry (section 2.2): per face f = 2a + side, two
+// tangential components over the interior window of the two other axes.
+struct RecGeom {
+    int Lu[3], Lv[3];              // window sizes per face axis
+    long long off[6];              // float offset of face f within one step
+    long long per_step;            // floats per step
+};
+
+struct Detectors {
+    int ndet;
+    int k[FD_MAXDET], i0[FD_MAXDET], i1[FD_MAXDET], j0[FD_MAXDET], j1[FD_MAXDET];
+    long long off[FD_MAXDET];      // offset of the detector's window in a flux plane set
+    long long per_step;            // floats of all windows for one step
+};
+
+// ------------------------------------------------------------ device helpers
+
+__device__ __forceinline__ int slab_coord(int c, int n, int p)
+{
+    return c < p ? c : (c >= n - p ? c - (n - 2 * p) : -1);
+}
+
+__device__ __forceinline__ long long slab_index(const Grid &g, int axis, int s, int i, int j, int k)
+{
+    const int w = 2 * g.p;
+    if (axis == 0) return ((long long)k * g.ny + j) * w + s;
+    if (axis == 1) return ((long long)k * w + s) * g.nx + i;
+    return ((long long)s * g.ny + j) * g.nx + i;
+}
+
+__device__ __forceinline__ float cpml_term(float d, float &psi, float b, float a, float kinv)
+{
+    psi = fmaf(b, psi, a * d);
+    return fmaf(d, kinv, psi);
+}
+
+__device__ __forceinline__ float h_update(float h, float S, float t1, float t2) { return fmaf(-S, t1 - t2, h); }
+__device__ __forceinline__ float e_update(float e, float ce, float t1, float t2) { return fmaf(ce, t1 - t2, e); }
+__device__ __forceinline__ float e_unupdate(float e, float ce, float t1, float t2) { return fmaf(-ce, t1 - t2, e); }
+__device__ __forceinline__ float h_unupdate(float h, float S, float t1, float t2) { return fmaf(S, t1 - t2, h); }
+
+// adjoint of one CPML-wrapped difference: with weight w on T, the coefficient
+// of the difference is w/kappa + a*(psibar + w) and psibar becomes b*(psibar + w).
+__device__ __forceinline__ float cpml_adj_coef(float w, float psibar, float a, float kinv)
+{
+    return fmaf(w, kinv, a * (psibar + w));
+}
+
+// non-interpolated flux density Ex*Hy - Ey*Hx
+__device__ __forceinline__ float flux_density(float ex, float ey, float hx, float hy)
+{
+    return fmaf(ex, hy, -(ey * hx));
+}
+
+// tangential E on the index-0 planes is held at zero
+__device__ __forceinline__ bool held_ex(int i, int j, int k) { (void)i; return j == 0 || k == 0; }
+__device__ __forceinline__ bool held_ey(int i, int j, int k) { (void)j; return i == 0 || k == 0; }
+__device__ __forceinline__ bool held_ez(int i, int j, int k) { (void)k; return i == 0 || j == 0; }
+
+// ------------------------------------------------------------------ launchers
+// All return hipSuccess or the launch error.
+
+hipError_t launch_h_naive(const Grid &g, const Fields &F, const Psi &P, hipStream_t s);
+hipError_t launch_e_naive(const Grid &g, const Fields &F, const Psi &P, int n, int with_src, hipStream_t s);
+
+// phase A of a reverse step: inverse E (interior), dJ/dd accumulation, adjoint H
+hipError_t launch_bwd_a(const Grid &g, const Fields &F, const Fields &A, const Psi &Pb, int n,
+                        int do_inv, int do_adj, float *gacc, const int *dlo, const int *dhi,
+                        hipStream_t s);
+// phase B: inverse H (interior), adjoint E, psi-bar updates (H-type ping-pong)
+hipError_t launch_bwd_b(const Grid &g, const Fields &F, const Fields &A, const Psi &Pb_cur,
+                        const Psi &Pb_next, int do_inv, int do_adj, hipStream_t s);
+
+hipError_t launch_record(const Grid &g, const Fields &F, const RecGeom &R, float *rec_step,
+                         int side, int restore, hipStream_t s);
+hipError_t launch_record_zero_e(const Grid &g, const Fields &F, const RecGeom &R, hipStream_t s);
+hipError_t launch_det_planes(const Grid &g, const Fields &F, const Detectors &D, float *planes,
+                             hipStream_t s);
+hipError_t launch_det_adjoint(const Grid &g, const Fields &F, const Fields &A, const Detectors &D,
+                              const float *weights_S, hipStream_t s);
+hipError_t launch_reduce_rows(const float *in, long long len, int rows, long long row_stride,
+                              float *out, int out_stride, hipStream_t s);
+hipError_t launch_objective(const float *trace, int steps, int ndet, const float *w, float S,
+                            float *J, hipStream_t s);
+hipError_t launch_interior_sumsq(const Grid &g, const Fields &F, float *partials, int *nparts,
+                                 hipStream_t s);
+hipError_t launch_recon(const float *part_T, const float *part_0, int nparts, float *out,
+                        hipStream_t s);
+hipError_t launch_deps(const float *gacc, const float *d_design, long long D, float S, float *out,
+                       hipStream_t s);
+hipError_t launch_fill(float *p, long long n, float v, hipStream_t s);
+hipError_t launch_copy(float *dst, const float *src, long long n, hipStream_t s);
+hipError_t launch_scale_ce(const float *inv_eps, float S, float *ce, long long n, hipStream_t s);
+hipError_t launch_gather_box(const float *src, const Grid &g, const int *lo, const int *hi,
+                             float *dst, hipStream_t s);
+
+// temporally blocked forward pass over K steps (fields and psi ping-pong)
+struct TbArgs {
+    Grid g;
+    Fields in, out;
+    Psi pin, pout;
+    int n0;                 // first step index of this block of K steps
+    int with_src;
+    float *rec;             // record of step n0 (or nullptr); step n0+s at rec + s*per_step
+    RecGeom R;
+    float *planes;          // detector flux planes of step n0 (or nullptr); + s*D.per_step
+    Detectors D;
+    const int4 *tiles;      // tile table: (x0, y0, z0, z1) owned region start; sizes fixed per K
+    int ntiles;
+    int xcd_remap;          // 1: map consecutive tiles to one XCD
+};
+hipError_t launch_tb_forward_class(const TbArgs &a, int K, bool xy, hipStream_t s);
+int tb_tile_x(int K);
+int tb_tile_y(int K);

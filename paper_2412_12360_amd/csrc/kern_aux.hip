@@ -1,0 +1,288 @@
+// Auxiliary kernels: the interface record (arXiv 2412.12360, section 2.2),
+// detector flux planes and their fixed-order reductions (section 2.1),
+// the detector adjoint source, the objective, reconstruction norms and small
+// element-wise helpers.  No atomics: every sum has one fixed order.
+#include "fdtd_internal.h"
+
+namespace {
+
+constexpr int NT = 256;
+
+__device__ __forceinline__ long long cidx(const Grid &g, int i, int j, int k)
+{
+    return (long long)k * g.nxy + (long long)j * g.nx + i;
+}
+
+// Record layout per step: faces f = 2a + side, each [comp 0..1][v][u] over the
+// interior window of axes u < v.  side 0: H comps (a+1)%3, (a+2)%3 at layer
+// p-1; side 1: E comps at layer n_a - p.  restore = 1 writes the record back
+// into the fields (rec == nullptr writes zeros).
+__global__ __launch_bounds__(NT) void k_record(Grid g, Fields F, RecGeom R, float *rec, int side, int restore,
+                                               long long total)
+{
+    long long t = (long long)blockIdx.x * NT + threadIdx.x;
+    if (t >= total) return;
+    int a = 0;
+    for (; a < 3; a++) {
+        const long long sz = 2LL * R.Lu[a] * R.Lv[a];
+        if (t < sz) break;
+        t -= sz;
+    }
+    const long long face = (long long)R.Lu[a] * R.Lv[a];
+    const int comp = (int)(t / face);
+    const long long rem = t - comp * face;
+    const int v = (int)(rem / R.Lu[a]);
+    const int u = (int)(rem - (long long)v * R.Lu[a]);
+    const int na[3] = {g.nx, g.ny, g.nz};
+    int x[3];
+    const int ua = a == 0 ? 1 : 0, va = a == 2 ? 1 : 2;
+    x[a] = side == 0 ? g.p - 1 : na[a] - g.p;
+    x[ua] = g.p + u;
+    x[va] = g.p + v;
+    const int fc = (side == 0 ? 3 : 0) + (a + 1 + comp) % 3;
+    const long long c = cidx(g, x[0], x[1], x[2]);
+    const long long r = R.off[2 * a + side] + t;
+    if (restore)
+        F.c[fc][c] = rec ? rec[r] : 0.f;
+    else
+        rec[r] = F.c[fc][c];
+}
+
+__global__ __launch_bounds__(NT) void k_det_planes(Grid g, Fields F, Detectors D, float *planes)
+{
+    const long long t = (long long)blockIdx.x * NT + threadIdx.x;
+    if (t >= D.per_step) return;
+    int m = 0;
+    while (m + 1 < D.ndet && t >= D.off[m + 1]) m++;
+    const long long e = t - D.off[m];
+    const int w = D.i1[m] - D.i0[m];
+    const int j = D.j0[m] + (int)(e / w);
+    const int i = D.i0[m] + (int)(e - (long long)(j - D.j0[m]) * w);
+    const long long c = cidx(g, i, j, D.k[m]);
+    planes[t] = flux_density(F.c[0][c], F.c[1][c], F.c[3][c], F.c[4][c]);
+}
+
+// dJ/dE^{n+1} and dJ/dH^{n+1/2} of J += S w sum (Ex Hy - Ey Hx)
+__global__ __launch_bounds__(NT) void k_det_adjoint(Grid g, Fields F, Fields A, Detectors D, int m, float sw)
+{
+    const long long e = (long long)blockIdx.x * NT + threadIdx.x;
+    const int w = D.i1[m] - D.i0[m];
+    const long long L = (long long)w * (D.j1[m] - D.j0[m]);
+    if (e >= L) return;
+    const int j = D.j0[m] + (int)(e / w);
+    const int i = D.i0[m] + (int)(e - (long long)(j - D.j0[m]) * w);
+    const long long c = cidx(g, i, j, D.k[m]);
+    const float ex = F.c[0][c], ey = F.c[1][c], hx = F.c[3][c], hy = F.c[4][c];
+    A.c[0][c] = fmaf(sw, hy, A.c[0][c]);
+    A.c[1][c] = fmaf(-sw, hx, A.c[1][c]);
+    A.c[4][c] = fmaf(sw, ex, A.c[4][c]);
+    A.c[3][c] = fmaf(-sw, ey, A.c[3][c]);
+}
+
+__device__ __forceinline__ float block_sum(float v, float *sh)
+{
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+// out[r * out_stride] = sum of in[r * row_stride + 0 .. len), fixed order
+__global__ __launch_bounds__(NT) void k_reduce_rows(const float *in, long long len, long long row_stride,
+                                                    float *out, int out_stride)
+{
+    __shared__ float sh[NT];
+    const float *row = in + (long long)blockIdx.x * row_stride;
+    float acc = 0.f;
+    for (long long e = threadIdx.x; e < len; e += NT) acc = acc + row[e];
+    const float s = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[(long long)blockIdx.x * out_stride] = s;
+}
+
+__global__ __launch_bounds__(NT) void k_objective(const float *trace, int steps, int ndet, const float *w,
+                                                  float S, float *J)
+{
+    __shared__ float sh[NT];
+    float acc = 0.f;
+    const long long tot = (long long)steps * ndet;
+    for (long long e = threadIdx.x; e < tot; e += NT) acc = fmaf(w[e % ndet], trace[e], acc);
+    const float s = block_sum(acc, sh);
+    if (threadIdx.x == 0) J[0] = S * s;
+}
+
+// per-block sums of squares of the six fields over the interior
+__global__ __launch_bounds__(NT) void k_sumsq(Grid g, Fields F, float *partials)
+{
+    __shared__ float sh[NT];
+    const int p = g.p;
+    const int Lx = g.nx - 2 * p, Ly = g.ny - 2 * p, Lz = g.nz - 2 * p;
+    const long long tot = (long long)Lx * Ly * Lz;
+    const long long t = (long long)blockIdx.x * NT + threadIdx.x;
+    float acc = 0.f;
+    if (t < tot) {
+        const int i = p + (int)(t % Lx);
+        const int j = p + (int)((t / Lx) % Ly);
+        const int k = p + (int)(t / ((long long)Lx * Ly));
+        const long long c = cidx(g, i, j, k);
+        for (int q = 0; q < 6; q++) acc = fmaf(F.c[q][c], F.c[q][c], acc);
+    }
+    const float s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(NT) void k_recon(const float *pT, const float *p0, int n, float *out)
+{
+    __shared__ float sh[NT];
+    float a = 0.f, b = 0.f;
+    for (int e = threadIdx.x; e < n; e += NT) { a = a + pT[e]; b = b + p0[e]; }
+    const float sT = block_sum(a, sh);
+    __syncthreads();
+    const float s0 = block_sum(b, sh);
+    if (threadIdx.x == 0) out[0] = sT > 0.f ? sqrtf(s0 / sT) : 0.f;
+}
+
+__global__ __launch_bounds__(NT) void k_deps(const float *gacc, const float *dd, long long D, float S, float *out)
+{
+    const long long t = (long long)blockIdx.x * NT + threadIdx.x;
+    if (t >= D) return;
+    const float d = dd[t];
+    out[t] = -(d * d) * (S * gacc[t]);
+}
+
+__global__ __launch_bounds__(NT) void k_fill(float *p, long long n, float v)
+{
+    const long long t = (long long)blockIdx.x * NT + threadIdx.x;
+    if (t < n) p[t] = v;
+}
+
+__global__ __launch_bounds__(NT) void k_copy(float *dst, const float *src, long long n)
+{
+    const long long t = (long long)blockIdx.x * NT + threadIdx.x;
+    if (t < n) dst[t] = src[t];
+}
+
+__global__ __launch_bounds__(NT) void k_scale(const float *x, float S, float *y, long long n)
+{
+    const long long t = (long long)blockIdx.x * NT + threadIdx.x;
+    if (t < n) y[t] = S * x[t];
+}
+
+__global__ __launch_bounds__(NT) void k_gather_box(const float *src, Grid g, int3 lo, int3 hi, float *dst)
+{
+    const int dx = hi.x - lo.x, dy = hi.y - lo.y, dz = hi.z - lo.z;
+    const long long tot = (long long)dx * dy * dz;
+    const long long t = (long long)blockIdx.x * NT + threadIdx.x;
+    if (t >= tot) return;
+    const int i = lo.x + (int)(t % dx);
+    const int j = lo.y + (int)((t / dx) % dy);
+    const int k = lo.z + (int)(t / ((long long)dx * dy));
+    dst[t] = src[cidx(g, i, j, k)];
+}
+
+unsigned nblk(long long n) { return (unsigned)((n + NT - 1) / NT); }
+
+}  // namespace
+
+hipError_t launch_record(const Grid &g, const Fields &F, const RecGeom &R, float *rec, int side, int restore,
+                         hipStream_t s)
+{
+    long long total = 0;
+    for (int a = 0; a < 3; a++) total += 2LL * R.Lu[a] * R.Lv[a];
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_record, dim3(nblk(total)), dim3(NT), 0, s, g, F, R, rec, side, restore, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_record_zero_e(const Grid &g, const Fields &F, const RecGeom &R, hipStream_t s)
+{
+    return launch_record(g, F, R, nullptr, 1, 1, s);
+}
+
+hipError_t launch_det_planes(const Grid &g, const Fields &F, const Detectors &D, float *planes, hipStream_t s)
+{
+    if (D.ndet == 0 || D.per_step == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_det_planes, dim3(nblk(D.per_step)), dim3(NT), 0, s, g, F, D, planes);
+    return hipGetLastError();
+}
+
+hipError_t launch_det_adjoint(const Grid &g, const Fields &F, const Fields &A, const Detectors &D,
+                              const float *weights_S, hipStream_t s)
+{
+    for (int m = 0; m < D.ndet; m++) {
+        const long long L = (long long)(D.i1[m] - D.i0[m]) * (D.j1[m] - D.j0[m]);
+        if (L <= 0) continue;
+        hipLaunchKernelGGL(k_det_adjoint, dim3(nblk(L)), dim3(NT), 0, s, g, F, A, D, m, weights_S[m]);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_reduce_rows(const float *in, long long len, int rows, long long row_stride, float *out,
+                              int out_stride, hipStream_t s)
+{
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_rows, dim3(rows), dim3(NT), 0, s, in, len, row_stride, out, out_stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_objective(const float *trace, int steps, int ndet, const float *w, float S, float *J,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL(k_objective, dim3(1), dim3(NT), 0, s, trace, steps, ndet, w, S, J);
+    return hipGetLastError();
+}
+
+hipError_t launch_interior_sumsq(const Grid &g, const Fields &F, float *partials, int *nparts, hipStream_t s)
+{
+    const long long tot = (long long)(g.nx - 2 * g.p) * (g.ny - 2 * g.p) * (g.nz - 2 * g.p);
+    *nparts = (int)nblk(tot);
+    hipLaunchKernelGGL(k_sumsq, dim3(*nparts), dim3(NT), 0, s, g, F, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_recon(const float *pT, const float *p0, int n, float *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_recon, dim3(1), dim3(NT), 0, s, pT, p0, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_deps(const float *gacc, const float *dd, long long D, float S, float *out, hipStream_t s)
+{
+    if (D == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_deps, dim3(nblk(D)), dim3(NT), 0, s, gacc, dd, D, S, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(float *p, long long n, float v, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3(nblk(n)), dim3(NT), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(float *dst, const float *src, long long n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy, dim3(nblk(n)), dim3(NT), 0, s, dst, src, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_ce(const float *inv_eps, float S, float *ce, long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scale, dim3(nblk(n)), dim3(NT), 0, s, inv_eps, S, ce, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_box(const float *src, const Grid &g, const int *lo, const int *hi, float *dst,
+                             hipStream_t s)
+{
+    const long long tot = (long long)(hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]);
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_box, dim3(nblk(tot)), dim3(NT), 0, s, src, g, make_int3(lo[0], lo[1], lo[2]),
+                       make_int3(hi[0], hi[1], hi[2]), dst);
+    return hipGetLastError();
+}

@@ -1,0 +1,296 @@
+"""Python binding of libfdtd (include/fdtd.h): ctypes marshalling only.
+
+Every step of the FDTD path runs in the HIP kernels of libfdtd.so; this module
+converts problem descriptions into the C structs, owns the device workspace as
+a torch tensor (PyTorch is used for device memory and streams only) and exposes
+the C entry points under their own names.  If the library is missing the
+import of `lib()` raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfdtd.so")
+MAX_SOURCES = 4
+MAX_DETECTORS = 4
+
+FDTD_OK, FDTD_E_INVALID, FDTD_E_NOMEM, FDTD_E_DEVICE, FDTD_E_STATE, FDTD_E_UNSUPPORTED = range(6)
+STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_STATE", 5: "E_UNSUPPORTED"}
+
+
+class fdtd_desc(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+        ("courant", C.c_float),
+        ("pml_cells", C.c_int32),
+        ("pml_order", C.c_float), ("pml_sigma_max", C.c_float), ("pml_kappa_max", C.c_float),
+        ("pml_alpha_max", C.c_float), ("pml_eps_bg", C.c_float),
+        ("inv_eps", C.c_void_p),
+        ("design_lo", C.c_int32 * 3), ("design_hi", C.c_int32 * 3),
+        ("n_steps", C.c_int32),
+        ("record", C.c_int32),
+        ("time_block", C.c_int32),
+    ]
+
+
+class fdtd_source(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("comp", C.c_int32), ("i", C.c_int32), ("j", C.c_int32),
+                ("k", C.c_int32), ("amp", C.c_void_p)]
+
+
+class fdtd_flux_detector(C.Structure):
+    _fields_ = [("k", C.c_int32), ("i0", C.c_int32), ("i1", C.c_int32), ("j0", C.c_int32),
+                ("j1", C.c_int32), ("weight", C.c_float)]
+
+
+ENTRY_POINTS = [
+    "fdtd_footprint", "fdtd_create", "fdtd_forward", "fdtd_inverse", "fdtd_grad", "fdtd_set_inv_eps",
+    "fdtd_reset", "fdtd_destroy", "fdtd_time", "fdtd_last_error", "fdtd_field_ptr", "fdtd_state_arrays",
+    "fdtd_linear_steps", "fdtd_record_ptr", "fdtd_time_block",
+]
+
+_lib = None
+
+
+def lib():
+    """The loaded libfdtd.so with argument types set.  Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2412_12360_amd/build.py "
+                           "(the FDTD path has no CPU fallback)")
+    L = C.CDLL(LIB_PATH)
+    H = C.c_void_p
+    D = C.POINTER(fdtd_desc)
+    Sp = C.POINTER(fdtd_source)
+    Dp = C.POINTER(fdtd_flux_detector)
+    fp = C.c_void_p
+    L.fdtd_footprint.argtypes = [D, Sp, C.c_int32, Dp, C.c_int32, C.POINTER(C.c_size_t)]
+    L.fdtd_create.argtypes = [D, Sp, C.c_int32, Dp, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
+                              C.POINTER(H)]
+    L.fdtd_forward.argtypes = [H, C.c_int32, fp, fp]
+    L.fdtd_inverse.argtypes = [H, C.c_int32]
+    L.fdtd_grad.argtypes = [H, fp, fp]
+    L.fdtd_set_inv_eps.argtypes = [H, fp]
+    L.fdtd_reset.argtypes = [H]
+    L.fdtd_destroy.argtypes = [H]
+    L.fdtd_time.argtypes = [H, C.POINTER(C.c_int32)]
+    L.fdtd_last_error.argtypes = [H]
+    L.fdtd_last_error.restype = C.c_char_p
+    L.fdtd_field_ptr.argtypes = [H, C.c_int32, C.c_int32, C.POINTER(C.c_void_p)]
+    L.fdtd_state_arrays.argtypes = [H, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_size_t), C.c_int32,
+                                    C.POINTER(C.c_int32)]
+    L.fdtd_linear_steps.argtypes = [H, C.c_int32, C.c_int32]
+    L.fdtd_record_ptr.argtypes = [H, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_size_t)]
+    L.fdtd_time_block.argtypes = [H, C.POINTER(C.c_int32)]
+    for name in ENTRY_POINTS:
+        if name != "fdtd_last_error":
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+class FdtdError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def check(status: int, handle=None):
+    if status != FDTD_OK:
+        m = lib().fdtd_last_error(handle)
+        raise FdtdError(status, m.decode() if m else "")
+
+
+def make_desc(prob, inv_eps_ptr: int = 0, record: bool = False, time_block: int = 0, T: Optional[int] = None):
+    d = fdtd_desc()
+    d.nx, d.ny, d.nz = prob.nx, prob.ny, prob.nz
+    d.courant = prob.S
+    d.pml_cells = prob.p
+    d.pml_order = prob.pml_m
+    d.pml_sigma_max = prob.pml_sigma_max
+    d.pml_kappa_max = prob.pml_kappa_max
+    d.pml_alpha_max = prob.pml_alpha_max
+    d.pml_eps_bg = 1.0
+    d.inv_eps = inv_eps_ptr
+    for a in range(3):
+        d.design_lo[a] = prob.design_lo[a]
+        d.design_hi[a] = prob.design_hi[a]
+    d.n_steps = prob.T if T is None else T
+    d.record = 1 if record else 0
+    d.time_block = time_block
+    return d
+
+
+def make_sources(prob, amp_ptrs: Sequence[int]):
+    arr = (fdtd_source * MAX_SOURCES)()
+    for i, (s, ptr) in enumerate(zip(prob.sources, amp_ptrs)):
+        arr[i].kind, arr[i].comp, arr[i].i, arr[i].j, arr[i].k = s.kind, s.comp, s.i, s.j, s.k
+        arr[i].amp = ptr
+    return arr
+
+
+def make_detectors(prob):
+    arr = (fdtd_flux_detector * MAX_DETECTORS)()
+    for i, d in enumerate(prob.detectors):
+        arr[i].k, arr[i].i0, arr[i].i1, arr[i].j0, arr[i].j1 = d.k, d.i0, d.i1, d.j0, d.j1
+        arr[i].weight = d.weight
+    return arr
+
+
+def footprint(prob, record: bool = False, time_block: int = 0, T: Optional[int] = None) -> int:
+    """Workspace bytes of a problem (no device work)."""
+    d = make_desc(prob, 1, record, time_block, T)
+    srcs = make_sources(prob, [1] * len(prob.sources))
+    dets = make_detectors(prob)
+    out = C.c_size_t(0)
+    check(lib().fdtd_footprint(C.byref(d), srcs, len(prob.sources), dets, len(prob.detectors), C.byref(out)))
+    return int(out.value)
+
+
+class Solver:
+    """One FDTD problem resident on the GPU.  Holds the workspace (a torch
+    uint8 tensor), the material and amplitude inputs, and the C handle."""
+
+    def __init__(self, prob, record: bool = False, time_block: int = 0, device: str = "cuda",
+                 T: Optional[int] = None, stream=None, workspace=None):
+        import torch
+        self.torch = torch
+        self.prob = prob
+        self.T = prob.T if T is None else T
+        self.record = record
+        dev = torch.device(device)
+        self.device = dev
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self.inv_eps = torch.from_numpy(np.ascontiguousarray(prob.inv_eps, np.float32)).to(dev)
+        self.amps = []
+        for s in prob.sources:
+            a = np.zeros(self.T, np.float32)
+            m = min(self.T, len(s.amp))
+            a[:m] = s.amp[:m]
+            self.amps.append(torch.from_numpy(a).to(dev))
+        self.desc = make_desc(prob, self.inv_eps.data_ptr(), record, time_block, self.T)
+        self.srcs = make_sources(prob, [a.data_ptr() for a in self.amps])
+        self.dets = make_detectors(prob)
+        self.ndet = len(prob.detectors)
+        nbytes = C.c_size_t(0)
+        check(lib().fdtd_footprint(C.byref(self.desc), self.srcs, len(prob.sources), self.dets, self.ndet,
+                                   C.byref(nbytes)))
+        self.footprint = int(nbytes.value)
+        if workspace is None:
+            workspace = torch.empty(self.footprint + 256, dtype=torch.uint8, device=dev)
+        self.ws_tensor = workspace
+        base = workspace.data_ptr()
+        self.ws_off = (-base) % 256
+        self.ws_ptr = base + self.ws_off
+        self.handle = C.c_void_p(0)
+        with torch.cuda.stream(self.stream):
+            torch.cuda.synchronize(dev)
+            check(lib().fdtd_create(C.byref(self.desc), self.srcs, len(prob.sources), self.dets, self.ndet,
+                                    C.c_void_p(self.ws_ptr), C.c_size_t(workspace.numel() - self.ws_off),
+                                    C.c_void_p(self.stream.cuda_stream), C.byref(self.handle)))
+        self._fws = workspace[self.ws_off:].view(torch.float32) if (workspace.numel() - self.ws_off) % 4 == 0 \
+            else workspace[self.ws_off: self.ws_off + ((workspace.numel() - self.ws_off) // 4) * 4].view(torch.float32)
+        self.J = torch.zeros(1, dtype=torch.float32, device=dev)
+
+    # ------------------------------------------------------------ helpers
+    def _view(self, ptr: int, count: int):
+        off = ptr - self.ws_ptr
+        assert off % 4 == 0 and 0 <= off and off // 4 + count <= self._fws.numel()
+        return self._fws[off // 4: off // 4 + count]
+
+    def close(self):
+        if self.handle:
+            lib().fdtd_destroy(self.handle)
+            self.handle = C.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------- entry points
+    def fdtd_forward(self, n: Optional[int] = None, trace=None, J=None):
+        n = self.T - self.t if n is None else n
+        check(lib().fdtd_forward(self.handle, n, C.c_void_p(trace.data_ptr() if trace is not None else 0),
+                                 C.c_void_p(J.data_ptr() if J is not None else 0)), self.handle)
+
+    def forward(self, n: Optional[int] = None):
+        """Advance n steps; returns (trace [n, ndet], J) as device tensors."""
+        n = self.T - self.t if n is None else n
+        trace = self.torch.zeros((max(n, 1), max(self.ndet, 1)), dtype=self.torch.float32, device=self.device)
+        self.fdtd_forward(n, trace, self.J)
+        return trace[:n, :self.ndet], self.J
+
+    def fdtd_inverse(self, n: int):
+        check(lib().fdtd_inverse(self.handle, n), self.handle)
+
+    inverse = fdtd_inverse
+
+    def fdtd_grad(self, dJ_deps, recon=None):
+        check(lib().fdtd_grad(self.handle, C.c_void_p(dJ_deps.data_ptr()),
+                              C.c_void_p(recon.data_ptr() if recon is not None else 0)), self.handle)
+
+    def grad(self):
+        """dJ/deps_r over the design box [dz, dy, dx] and the reconstruction error."""
+        g = self.torch.empty(self.prob.design_shape(), dtype=self.torch.float32, device=self.device)
+        r = self.torch.zeros(1, dtype=self.torch.float32, device=self.device)
+        self.fdtd_grad(g, r)
+        return g, r
+
+    def fdtd_set_inv_eps(self, inv_eps):
+        self._keep = inv_eps
+        check(lib().fdtd_set_inv_eps(self.handle, C.c_void_p(inv_eps.data_ptr())), self.handle)
+
+    set_inv_eps = fdtd_set_inv_eps
+
+    def fdtd_reset(self):
+        check(lib().fdtd_reset(self.handle), self.handle)
+
+    reset = fdtd_reset
+
+    @property
+    def t(self) -> int:
+        v = C.c_int32(0)
+        check(lib().fdtd_time(self.handle, C.byref(v)), self.handle)
+        return int(v.value)
+
+    @property
+    def time_block(self) -> int:
+        v = C.c_int32(0)
+        check(lib().fdtd_time_block(self.handle, C.byref(v)), self.handle)
+        return int(v.value)
+
+    def field(self, comp: int, which: int = 0):
+        """Device view [nz, ny, nx] of field component comp (0..5) of the
+        forward (which = 0) or adjoint (which = 1) state."""
+        p = C.c_void_p(0)
+        check(lib().fdtd_field_ptr(self.handle, which, comp, C.byref(p)), self.handle)
+        pr = self.prob
+        return self._view(p.value, pr.N).view(pr.nz, pr.ny, pr.nx)
+
+    def fields(self, which: int = 0):
+        return [self.field(c, which) for c in range(6)]
+
+    def state_arrays(self, which: int = 0):
+        ptrs = (C.c_void_p * 32)()
+        counts = (C.c_size_t * 32)()
+        n = C.c_int32(0)
+        check(lib().fdtd_state_arrays(self.handle, which, ptrs, counts, 32, C.byref(n)), self.handle)
+        return [self._view(ptrs[i], counts[i]) for i in range(n.value)]
+
+    def linear_steps(self, n: int, adjoint: bool = False):
+        check(lib().fdtd_linear_steps(self.handle, n, 1 if adjoint else 0), self.handle)
+
+    def record_step(self, n: int):
+        p = C.c_void_p(0)
+        cnt = C.c_size_t(0)
+        check(lib().fdtd_record_ptr(self.handle, n, C.byref(p), C.byref(cnt)), self.handle)
+        return self._view(p.value, cnt.value)

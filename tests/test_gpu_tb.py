@@ -1,0 +1,82 @@
+"""The temporally blocked z-march kernel: bitwise equal to the per-cell
+kernels for every time-block size K (same expressions, same order), and
+within tolerance of the FP64 oracle on ragged multi-tile grids."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle.oracle import Oracle
+from paper_2412_12360_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(*a, **k):
+    from paper_2412_12360_amd.fdtd import Solver
+    return Solver(*a, **k)
+
+
+def announce(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+def run(pr, K, naive, monkeypatch, record=True, steps=None):
+    monkeypatch.setenv("FDTD_NAIVE", "1" if naive else "0")
+    s = _solver(pr, record=record, time_block=K)
+    tr, J = s.forward(steps)
+    torch.cuda.synchronize()
+    out = {
+        "fields": torch.stack([f.clone() for f in s.fields()]),
+        "psi": [a.clone() for a in s.state_arrays(0)[6:]],
+        "trace": tr.clone(),
+        "J": J.clone(),
+    }
+    if record:
+        n = pr.T if steps is None else steps
+        out["rec"] = torch.stack([s.record_step(i).clone() for i in range(n)])
+    return out
+
+
+def assert_same(a, b):
+    assert torch.equal(a["fields"], b["fields"])
+    assert len(a["psi"]) == len(b["psi"])
+    for x, y in zip(a["psi"], b["psi"]):
+        assert torch.equal(x, y)
+    assert torch.equal(a["trace"], b["trace"])
+    assert torch.equal(a["J"], b["J"])
+    if "rec" in a:
+        assert torch.equal(a["rec"], b["rec"])
+
+
+@pytest.mark.parametrize("shape,p,T", [((70, 45, 38), 5, 37), ((130, 30, 21), 3, 23), ((33, 61, 70), 6, 30)])
+def test_tb_bitwise_equal_to_naive_all_K(shape, p, T, monkeypatch):
+    pr = W.small_cpml(nx=shape[0], ny=shape[1], nz=shape[2], p=p, T=T)
+    announce(f"tb bitwise {shape} p={p} T={T} naive")
+    ref = run(pr, 1, True, monkeypatch)
+    for K in (1, 2, 3, 4):
+        announce(f"tb bitwise {shape} p={p} T={T} K={K}")
+        assert_same(run(pr, K, False, monkeypatch), ref)
+
+
+def test_tb_bitwise_pec_point_source(monkeypatch):
+    pr = W.config1(T=45)
+    announce("tb bitwise c1 PEC")
+    ref = run(pr, 1, True, monkeypatch, record=False)
+    for K in (1, 2, 3, 4):
+        assert_same(run(pr, K, False, monkeypatch, record=False), ref)
+
+
+@pytest.mark.parametrize("K", [1, 2, 4])
+def test_tb_parity_with_oracle(K, monkeypatch):
+    pr = W.small_cpml(nx=75, ny=41, nz=36, p=6, T=120)
+    announce(f"tb parity 75x41x36 K={K}")
+    st, J, trace, _ = Oracle(pr).run()
+    monkeypatch.setenv("FDTD_NAIVE", "0")
+    s = _solver(pr, time_block=K)
+    tr, Jg = s.forward()
+    torch.cuda.synchronize()
+    f = np.stack([x.cpu().numpy().astype(np.float64) for x in s.fields()])
+    assert np.linalg.norm(f - st[:6]) / np.linalg.norm(st[:6]) <= 1e-4
+    assert np.linalg.norm(tr.cpu().numpy() - trace) / np.linalg.norm(trace) <= 1e-4
+    assert abs(float(Jg.item()) - J) <= 1e-4 * abs(J)
