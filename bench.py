@@ -1,0 +1,180 @@
+#!/usr/bin/env python3
+"""Benchmark of the reversible 3D FDTD hot path on one MI355X.
+
+A step is one complete solve of the benchmark workload: zero the fields, then
+T leapfrog steps of the Yee/CPML update with the plane-wave source and the
+flux detector.  The default workload is a 256^3 grid with a 10-cell CPML on
+every face and T = 2000 (forward only).  The line also carries:
+  - fwd_grad: the 200^3 gradient problem (CPML 10, 64^3 design cube,
+    T = 1500): forward with the interface record, then the time-reversed
+    adjoint pass, rated as N*T / (t_fwd + t_bwd);
+  - roofline: the forward pass (all tile classes of one K-step sweep)
+    against the 8 TB/s HBM peak, with algorithmic bytes 52 B per cell plus
+    32 B per CPML slab cell and slab axis, per time step;
+  - cpu_baseline: the FP64 oracle on the host cores, timed on a bounded
+    sample (the same 256^3 grid, a few time steps).
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Mcell-updates/s fwd and fwd+grad (FP32, % HBM roofline); p99 latency in serving mix"
+PEAK_GBS = 8000.0
+
+
+def slab_cell_axes(pr) -> int:
+    if pr.p == 0:
+        return 0
+    n = (pr.nx, pr.ny, pr.nz)
+    return sum(2 * pr.p * (pr.N // n[a]) for a in range(3))
+
+
+def alg_bytes_fwd_step(pr, record: bool = False) -> int:
+    b = 52 * pr.N + 32 * slab_cell_axes(pr)
+    if record and pr.p > 0:
+        Lx, Ly, Lz = pr.nx - 2 * pr.p, pr.ny - 2 * pr.p, pr.nz - 2 * pr.p
+        b += 4 * 2 * 2 * (Ly * Lz + Lx * Lz + Lx * Ly)
+    return b
+
+
+def time_solves(solver, count: int, torch):
+    """Events on the solver's stream around `count` full forward solves."""
+    st = solver.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(count):
+        solver.reset()
+        solver.forward()
+    e1.record(st)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def cpu_baseline(pr, target_s: float = 12.0):
+    """The FP64 oracle on the host: the benchmark grid for a few steps."""
+    from oracle.oracle import Oracle, build as build_oracle
+    build_oracle(force=False)
+    o = Oracle(pr)
+    st = o.new_state()
+    t0 = time.perf_counter()
+    o.forward(st, 1, 0)
+    one = time.perf_counter() - t0
+    n = max(1, min(pr.T - 1, int(target_s / max(one, 1e-3))))
+    t0 = time.perf_counter()
+    o.forward(st, n, 1)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(pr.N * n / dt / 1e6, 3), "unit": "Mcell-updates/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{pr.nx}x{pr.ny}x{pr.nz} grid, {n} FP64 time steps (steps 1..{n}) of the same problem"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="timed full solves")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--time-block", type=int, default=0)
+    ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU z-slab decomposition is a design, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2412_12360_amd import workloads as W
+    from paper_2412_12360_amd.fdtd import Solver
+
+    rank = int(os.environ.get("RANK", "0"))
+    pr = W.config2()
+    s = Solver(pr, record=False, time_block=args.time_block)
+    K = s.time_block
+    for _ in range(args.warmup):
+        s.reset()
+        s.forward()
+    torch.cuda.synchronize()
+    ms = time_solves(s, args.steps, torch)
+    cells = pr.N * pr.T * args.steps
+    value = cells / (ms / 1e3) / 1e6
+    passes = math.ceil(pr.T / K)
+    pass_ms = ms / args.steps / passes
+    alg = alg_bytes_fwd_step(pr) * K
+    achieved = alg / (pass_ms / 1e3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "Mcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "256^3 Yee grid, 10-cell CPML, 2000 steps forward, ramped Ex plane-wave sheet, "
+                        "flux detector, eps_r 2.25 with a 128^3 cube U[2.25,12.25] (seed 2)",
+            "grid": [pr.nx, pr.ny, pr.nz], "steps_per_solve": pr.T, "time_block": K,
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_GBS, 4), "traffic": None,
+            "kernel": f"forward z-march sweep (K={K} steps, all tile classes)",
+            "alg_bytes_per_launch": alg, "avg_launch_ms": round(pass_ms, 5),
+        },
+    }
+    del s
+    torch.cuda.empty_cache()
+
+    if not args.no_grad:
+        pg = W.config3()
+        g = Solver(pg, record=True, time_block=args.time_block)
+        g.reset()
+        g.forward()
+        g.grad()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e2 = torch.cuda.Event(enable_timing=True)
+        e0.record(g.stream)
+        g.reset()
+        g.forward()
+        e1.record(g.stream)
+        dg, recon = g.grad()
+        e2.record(g.stream)
+        torch.cuda.synchronize()
+        tf, tb = e0.elapsed_time(e1), e1.elapsed_time(e2)
+        out["fwd_grad"] = {
+            "workload": "200^3 grid, CPML 10, 64^3 design cube rho~U[0,1] (seed 3), eps_r = 2.25 + 10 rho, "
+                        "1500 steps, objective = time-integrated flux; forward with interface record, "
+                        "then inverse-step + adjoint backward",
+            "value": round(pg.N * pg.T / ((tf + tb) / 1e3) / 1e6, 1), "unit": "Mcell-steps/s",
+            "fwd_ms": round(tf, 2), "bwd_ms": round(tb, 2),
+            "recon_err": float(recon.item()),
+        }
+        del g
+        torch.cuda.empty_cache()
+
+    if rank == 0 and not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(pr)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

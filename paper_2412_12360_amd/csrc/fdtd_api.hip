@@ -76,11 +76,13 @@ struct fdtd_ctx {
     float *ce = nullptr, *inv_eps = nullptr, *d_design = nullptr;
     float *prof[2][3][3];
     float *amps[FDTD_MAX_SOURCES];
+    float *red = nullptr;
     float *trace = nullptr, *planes = nullptr, *wdev = nullptr, *rec = nullptr, *gacc = nullptr;
     float *parts[2] = {nullptr, nullptr};
     int nparts_cap = 0;
     int4 *tiles = nullptr;                 // tile tables of every K' <= K, two classes each
-    int tb_off[5][2], tb_cnt[5][2];
+    int tb_off[5][4], tb_cnt[5][4];
+    float4 *profv[3];
     bool naive = false;                    // per-cell kernels instead of the z-march
     float wS[FDTD_MAX_DETECTORS];
     std::vector<float> host_tables;        // kept alive for async uploads
@@ -200,6 +202,22 @@ int choose_K(const fdtd_desc *d)
     return 2;
 }
 
+// Split [0, n) into tiles of at most `w` cells: one full tile at each end,
+// the middle evenly.  With w - K >= p the middle tiles' halos stay clear of
+// the CPML slabs.
+std::vector<std::pair<int, int>> split_axis(int n, int w)
+{
+    std::vector<std::pair<int, int>> v;
+    if (n <= w) { v.push_back({0, n}); return v; }
+    if (n <= 2 * w) { v.push_back({0, n / 2}); v.push_back({n / 2, n}); return v; }
+    v.push_back({0, w});
+    const int mid = n - 2 * w;
+    const int m = (mid + w - 1) / w;
+    for (int i = 0; i < m; i++) v.push_back({w + (int)((long long)mid * i / m), w + (int)((long long)mid * (i + 1) / m)});
+    v.push_back({n - w, n});
+    return v;
+}
+
 // z extent of one workgroup's march: enough workgroups to fill the chip
 // (about 1024) without letting the 2K-plane z halo dominate.
 int zchunk(const Geometry &G, int K)
@@ -208,36 +226,39 @@ int zchunk(const Geometry &G, int K)
         const int v = atoi(e);
         if (v > 0) return std::min(v, G.nz);
     }
-    const long long tx = (G.nx + tb_tile_x(K) - 1) / tb_tile_x(K);
-    const long long ty = (G.ny + tb_tile_y(K) - 1) / tb_tile_y(K);
+    const long long tx = (long long)split_axis(G.nx, tb_tile_x(K)).size();
+    const long long ty = (long long)split_axis(G.ny, tb_tile_y(K)).size();
     long long chunks = (1024 + tx * ty - 1) / (tx * ty);
     chunks = std::max(1LL, std::min(chunks, (long long)(G.nz + 31) / 32));
     return (int)((G.nz + chunks - 1) / chunks);
 }
 
-// Tile tables of the z-march kernel for K' = 1..K.  Class 1 tiles have an
-// x or y CPML slab inside their halo-extended footprint; class 0 tiles do not.
-void build_tiles(const Geometry &G, int K, std::vector<int4> &out, int off[5][2], int cnt[5][2])
+// Tile tables of the z-march kernel for K' = 1..K, four classes each: bit 0
+// = an x CPML slab inside the halo-extended footprint, bit 1 = a y slab.
+void build_tiles(const Geometry &G, int K, std::vector<int4> &out, int off[5][4], int cnt[5][4])
 {
     out.clear();
-    for (int kk = 0; kk < 5; kk++) off[kk][0] = off[kk][1] = cnt[kk][0] = cnt[kk][1] = 0;
+    for (int kk = 0; kk < 5; kk++)
+        for (int c = 0; c < 4; c++) off[kk][c] = cnt[kk][c] = 0;
     for (int kk = 1; kk <= K; kk++) {
-        const int TX = tb_tile_x(kk), TY = tb_tile_y(kk), ZC = zchunk(G, kk);
-        std::vector<int4> cls[2];
+        const int ZC = zchunk(G, kk);
+        const auto xs = split_axis(G.nx, tb_tile_x(kk)), ys = split_axis(G.ny, tb_tile_y(kk));
+        std::vector<int4> cls[4];
         for (int z0 = 0; z0 < G.nz; z0 += ZC)
-            for (int y0 = 0; y0 < G.ny; y0 += TY)
-                for (int x0 = 0; x0 < G.nx; x0 += TX) {
+            for (const auto &yt : ys)
+                for (const auto &xt : xs) {
                     const int z1 = std::min(z0 + ZC, G.nz);
-                    bool xy = false;
+                    int c = 0;
                     if (G.p > 0) {
-                        const int xa = x0 - kk, xb = x0 + TX + kk, ya = y0 - kk, yb = y0 + TY + kk;
-                        xy = xa < G.p || xb > G.nx - G.p || ya < G.p || yb > G.ny - G.p;
+                        if (xt.first - kk < G.p || xt.second + kk > G.nx - G.p) c |= 1;
+                        if (yt.first - kk < G.p || yt.second + kk > G.ny - G.p) c |= 2;
                     }
-                    cls[xy ? 1 : 0].push_back(make_int4(x0, y0, z0, z1));
+                    cls[c].push_back(make_int4(xt.first, xt.second, yt.first, yt.second));
+                    cls[c].push_back(make_int4(z0, z1, 0, 0));
                 }
-        for (int c = 0; c < 2; c++) {
-            off[kk][c] = (int)out.size();
-            cnt[kk][c] = (int)cls[c].size();
+        for (int c = 0; c < 4; c++) {
+            off[kk][c] = (int)out.size() / 2;
+            cnt[kk][c] = (int)cls[c].size() / 2;
             out.insert(out.end(), cls[c].begin(), cls[c].end());
         }
     }
@@ -252,6 +273,7 @@ long long interior_cells(const Geometry &G)
 size_t plan(fdtd_ctx *h, const fdtd_desc *d, const Geometry &G, int K, void *base)
 {
     Bump B(base);
+    const int n[3] = {d->nx, d->ny, d->nz};
     const long long N = G.N;
     for (int b = 0; b < 2; b++)
         for (int q = 0; q < 6; q++) h->fld[b][q] = B.take(N);
@@ -260,7 +282,6 @@ size_t plan(fdtd_ctx *h, const fdtd_desc *d, const Geometry &G, int K, void *bas
             for (int q = 0; q < 4; q++) h->psi[b][a][q] = G.p > 0 ? B.take(G.slab_n[a]) : nullptr;
     h->ce = B.take(N);
     h->d_design = B.take(G.design_cells);
-    const int n[3] = {d->nx, d->ny, d->nz};
     for (int t = 0; t < 2; t++)
         for (int a = 0; a < 3; a++)
             for (int f = 0; f < 3; f++) h->prof[t][a][f] = B.take(n[a]);
@@ -268,8 +289,16 @@ size_t plan(fdtd_ctx *h, const fdtd_desc *d, const Geometry &G, int K, void *bas
     h->trace = B.take((size_t)d->n_steps * std::max(1, G.D.ndet));
     h->planes = B.take((size_t)std::max(1, K) * std::max<long long>(1, G.D.per_step));
     h->wdev = B.take(FDTD_MAX_DETECTORS);
+    {
+        long long rs = 1;
+        for (int m = 0; m < G.D.ndet; m++)
+            rs = std::max(rs, reduce_scratch_floats((long long)(G.D.i1[m] - G.D.i0[m]) * (G.D.j1[m] - G.D.j0[m]),
+                                                    std::max(1, K)));
+        h->red = B.take(rs);
+    }
     build_tiles(G, K, h->host_tiles, h->tb_off, h->tb_cnt);
     h->tiles = B.take_as<int4>(std::max<size_t>(1, h->host_tiles.size()));
+    for (int ax = 0; ax < 3; ax++) h->profv[ax] = B.take_as<float4>(2 * (size_t)n[ax]);
     const long long nparts = (interior_cells(G) + 255) / 256;
     h->nparts_cap = (int)nparts;
     h->parts[0] = B.take(nparts);
@@ -390,8 +419,8 @@ fdtd_status step_naive(fdtd_ctx *h, int n, int with_src, int with_rec, int with_
         HIPCHK(h, launch_det_planes(h->g, F, G.D, h->planes, h->stream));
         for (int m = 0; m < G.D.ndet; m++) {
             const long long L = (long long)(G.D.i1[m] - G.D.i0[m]) * (G.D.j1[m] - G.D.j0[m]);
-            HIPCHK(h, launch_reduce_rows(h->planes + G.D.off[m], L, 1, G.D.per_step,
-                                         h->trace + (size_t)n * G.D.ndet + m, G.D.ndet, h->stream));
+            HIPCHK(h, launch_reduce_rows2(h->planes + G.D.off[m], L, 1, G.D.per_step,
+                                          h->trace + (size_t)n * G.D.ndet + m, G.D.ndet, h->red, h->stream));
         }
     }
     return FDTD_OK;
@@ -414,17 +443,18 @@ fdtd_status steps_tb(fdtd_ctx *h, int n0, int kk, int with_src, int with_rec, in
     a.planes = (with_det && G.D.ndet > 0) ? h->planes : nullptr;
     a.D = G.D;
     a.xcd_remap = 1;
-    for (int c = 0; c < 2; c++) {
-        a.tiles = h->tiles + h->tb_off[kk][c];
+    for (int ax = 0; ax < 3; ax++) a.profv[ax] = h->profv[ax];
+    for (int c = 0; c < 4; c++) {
+        a.tiles = h->tiles + 2 * (size_t)h->tb_off[kk][c];
         a.ntiles = h->tb_cnt[kk][c];
-        HIPCHK(h, launch_tb_forward_class(a, kk, c == 1, h->stream));
+        HIPCHK(h, launch_tb_forward_class(a, kk, c, h->stream));
     }
     h->cur ^= 1;
     if (a.planes)
         for (int m = 0; m < G.D.ndet; m++) {
             const long long L = (long long)(G.D.i1[m] - G.D.i0[m]) * (G.D.j1[m] - G.D.j0[m]);
-            HIPCHK(h, launch_reduce_rows(h->planes + G.D.off[m], L, kk, G.D.per_step,
-                                         h->trace + (size_t)n0 * G.D.ndet + m, G.D.ndet, h->stream));
+            HIPCHK(h, launch_reduce_rows2(h->planes + G.D.off[m], L, kk, G.D.per_step,
+                                          h->trace + (size_t)n0 * G.D.ndet + m, G.D.ndet, h->red, h->stream));
         }
     return FDTD_OK;
 }
@@ -520,6 +550,7 @@ fdtd_status fdtd_create(const fdtd_desc *desc, const fdtd_source *src, int32_t n
     h->K = choose_K(desc);
     h->naive = true;
     if (const char *e = getenv("FDTD_NAIVE")) h->naive = atoi(e) != 0;
+    if (desc->pml_cells > tb_max_pml()) h->naive = true;   // the z-march stages at most that many CPML planes
     geometry(desc, det, ndet, h->geo);
     const size_t need = plan(h, desc, h->geo, h->K, nullptr);
     if (workspace_bytes < need) {
@@ -570,6 +601,17 @@ fdtd_status fdtd_create(const fdtd_desc *desc, const fdtd_source *src, int32_t n
             h->host_tables.insert(h->host_tables.end(), aa.begin(), aa.end());
             h->host_tables.insert(h->host_tables.end(), kv.begin(), kv.end());
         }
+    std::vector<size_t> vstarts;
+    for (int a2 = 0; a2 < 3; a2++) {
+        vstarts.push_back(h->host_tables.size());
+        for (int i = 0; i < n[a2]; i++)
+            for (int t = 0; t < 2; t++) {
+                float o[3];
+                grade(n[a2], G.p, t == 0 ? (double)i : i + 0.5, m, smax, kmax, amax, o);
+                h->host_tables.push_back(o[0]); h->host_tables.push_back(o[1]);
+                h->host_tables.push_back(o[2]); h->host_tables.push_back(0.f);
+            }
+    }
     for (int m2 = 0; m2 < FDTD_MAX_DETECTORS; m2++) {
         const float w = m2 < ndet ? det[m2].weight : 0.f;
         h->wS[m2] = desc->courant * w;
@@ -584,6 +626,11 @@ fdtd_status fdtd_create(const fdtd_desc *desc, const fdtd_source *src, int32_t n
                                                   sizeof(float) * n[a], hipMemcpyHostToDevice, h->stream);
                     if (e != hipSuccess) { fdtd_status r = fail(nullptr, FDTD_E_DEVICE, "upload: %s", hipGetErrorString(e)); delete h; return r; }
                 }
+        for (int a2 = 0; a2 < 3; a2++) {
+            hipError_t e2 = hipMemcpyAsync(h->profv[a2], h->host_tables.data() + vstarts[a2], sizeof(float) * 8 * n[a2],
+                                           hipMemcpyHostToDevice, h->stream);
+            if (e2 != hipSuccess) { fdtd_status r = fail(nullptr, FDTD_E_DEVICE, "upload: %s", hipGetErrorString(e2)); delete h; return r; }
+        }
         hipError_t e = hipMemcpyAsync(h->wdev, h->host_tables.data() + h->host_tables.size() - FDTD_MAX_DETECTORS,
                                       sizeof(float) * FDTD_MAX_DETECTORS, hipMemcpyHostToDevice, h->stream);
         if (e != hipSuccess) { fdtd_status r = fail(nullptr, FDTD_E_DEVICE, "upload: %s", hipGetErrorString(e)); delete h; return r; }

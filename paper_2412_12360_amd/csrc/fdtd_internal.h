@@ -130,6 +130,10 @@ hipError_t launch_det_adjoint(const Grid &g, const Fields &F, const Fields &A, c
                               const float *weights_S, hipStream_t s);
 hipError_t launch_reduce_rows(const float *in, long long len, int rows, long long row_stride,
                               float *out, int out_stride, hipStream_t s);
+// two-level fixed-order row sums for long rows (scratch: reduce_scratch_floats)
+hipError_t launch_reduce_rows2(const float *in, long long len, int rows, long long row_stride,
+                               float *out, int out_stride, float *scratch, hipStream_t s);
+long long reduce_scratch_floats(long long len, int rows);
 hipError_t launch_objective(const float *trace, int steps, int ndet, const float *w, float S,
                             float *J, hipStream_t s);
 hipError_t launch_interior_sumsq(const Grid &g, const Fields &F, float *partials, int *nparts,
@@ -155,10 +159,12 @@ struct TbArgs {
     RecGeom R;
     float *planes;          // detector flux planes of step n0 (or nullptr); + s*D.per_step
     Detectors D;
-    const int4 *tiles;      // tile table: (x0, y0, z0, z1) owned region start; sizes fixed per K
+    const int4 *tiles;      // per tile two int4: (x0, x1, y0, y1), (z0, z1, 0, 0) owned box
     int ntiles;
+    const float4 *profv[3]; // per axis, per index: (b, a, 1/kappa) at E then H positions
     int xcd_remap;          // 1: map consecutive tiles to one XCD
 };
-hipError_t launch_tb_forward_class(const TbArgs &a, int K, bool xy, hipStream_t s);
+hipError_t launch_tb_forward_class(const TbArgs &a, int K, int cls, hipStream_t s);
 int tb_tile_x(int K);
 int tb_tile_y(int K);
+int tb_max_pml();

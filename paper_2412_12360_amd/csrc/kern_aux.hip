@@ -102,6 +102,22 @@ __global__ __launch_bounds__(NT) void k_reduce_rows(const float *in, long long l
     if (threadIdx.x == 0) out[(long long)blockIdx.x * out_stride] = s;
 }
 
+// first level of a two-level row sum: block (c, r) sums elements
+// [c*CH, (c+1)*CH) of row r in a fixed order
+constexpr long long CH = 4096;
+__global__ __launch_bounds__(NT) void k_reduce_chunks(const float *in, long long len, long long row_stride,
+                                                      float *part, int nch)
+{
+    __shared__ float sh[NT];
+    const float *row = in + (long long)blockIdx.y * row_stride;
+    const long long a = (long long)blockIdx.x * CH;
+    const long long b = a + CH < len ? a + CH : len;
+    float acc = 0.f;
+    for (long long e = a + threadIdx.x; e < b; e += NT) acc = acc + row[e];
+    const float s = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[(long long)blockIdx.y * nch + blockIdx.x] = s;
+}
+
 __global__ __launch_bounds__(NT) void k_objective(const float *trace, int steps, int ndet, const float *w,
                                                   float S, float *J)
 {
@@ -227,6 +243,20 @@ hipError_t launch_reduce_rows(const float *in, long long len, int rows, long lon
     if (rows <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_reduce_rows, dim3(rows), dim3(NT), 0, s, in, len, row_stride, out, out_stride);
     return hipGetLastError();
+}
+
+long long reduce_scratch_floats(long long len, int rows) { return (long long)rows * ((len + CH - 1) / CH); }
+
+hipError_t launch_reduce_rows2(const float *in, long long len, int rows, long long row_stride, float *out,
+                               int out_stride, float *scratch, hipStream_t s)
+{
+    if (rows <= 0) return hipSuccess;
+    const int nch = (int)((len + CH - 1) / CH);
+    if (nch <= 1) return launch_reduce_rows(in, len, rows, row_stride, out, out_stride, s);
+    hipLaunchKernelGGL(k_reduce_chunks, dim3(nch, rows), dim3(NT), 0, s, in, len, row_stride, scratch, nch);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_reduce_rows(scratch, nch, rows, nch, out, out_stride, s);
 }
 
 hipError_t launch_objective(const float *trace, int steps, int ndet, const float *w, float S, float *J,

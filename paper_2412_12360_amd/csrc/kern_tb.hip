@@ -1,28 +1,48 @@
 // Temporally blocked forward pass: K leapfrog steps (arXiv 2412.12360,
 // section 2.1) per sweep over the grid.
 //
-// Each workgroup owns a tile of TX x TY columns and a z range [z0, z1).  It
-// loads the tile plus a K-cell halo in x and y and K planes below and above,
-// and marches up in z one plane per iteration.  Level s (1..K) of the
-// pipeline advances the fields from step n0+s-1 to n0+s and trails level s-1
-// by one plane: its H update at plane k needs E of level s-1 at k and k+1, its
-// E update needs its own H at k and k-1.  The x/y neighbours of a plane come
-// from LDS, the z neighbours are held in registers.  The halo shrinks by one
-// cell per level, so after K levels the owned tile is exact.  Fields and CPML
-// auxiliaries are read from one buffer and written to the other (ping-pong).
-// Sources, detector flux planes and the interface record are emitted at every
-// level for owned cells, so the result is bitwise the same for every K.
+// Each workgroup owns a tile of columns [x0,x1) x [y0,y1) and a z range
+// [z0, z1).  It reads the tile plus a K-cell halo in x and y and K planes
+// below and above, and marches up in z one plane per iteration, fetching the
+// next plane from HBM while it computes on the current one.  Level s (1..K)
+// of the pipeline advances the fields from step n0+s-1 to n0+s and trails
+// level s-1 by one plane: its H update at plane k needs E of level s-1 at k
+// and k+1, its E update needs its own H at k and k-1.  The x/y neighbours of
+// a plane come from LDS, the z neighbours are held in registers.  The halo
+// shrinks by one cell per level, so after K levels the owned tile is exact.
+// Fields and CPML auxiliaries are read from one buffer and written to the
+// other (ping-pong).  Sources, detector flux planes and the interface record
+// are emitted at every level for owned cells, so the result is bitwise the
+// same for every K and equal to the per-cell kernels.
+//
+// Tiles come in four classes by which CPML slabs (x, y) reach into their
+// halo-extended footprint; each class is its own instance so interior tiles
+// carry no x/y auxiliary registers.  z-slab planes are handled in every tile.
+//
+// Cost notes: cell addresses are 32-bit element offsets (one uniform plane
+// base plus one per-row offset), the conducting-wall rule is folded into the
+// update coefficient (a held component gets coefficient 0, which leaves it
+// bit-for-bit unchanged), and records, detectors and sources are gated by
+// uniform plane tests so the common plane pays nothing for them.
 #include "fdtd_internal.h"
 
 namespace {
 
 constexpr int EX = 64;
+constexpr int TB_MAXP = 64;   // largest CPML thickness the z-march kernel stages
 
-template <int K> struct TbShape;
-template <> struct TbShape<1> { static constexpr int W = 8, R = 2; };
-template <> struct TbShape<2> { static constexpr int W = 8, R = 2; };
-template <> struct TbShape<3> { static constexpr int W = 8, R = 2; };
-template <> struct TbShape<4> { static constexpr int W = 8, R = 2; };
+template <int K> struct TbShape { static constexpr int W = 16, R = 1; };
+
+// a float at a 32-bit byte offset from a uniform base (lets the compiler use
+// the scalar-base + vector-offset addressing form)
+__device__ __forceinline__ float ldo(const float *__restrict__ base, unsigned byteoff)
+{
+    return *(const float *)((const char *)base + byteoff);
+}
+__device__ __forceinline__ void sto(float *__restrict__ base, unsigned byteoff, float v)
+{
+    *(float *)((char *)base + byteoff) = v;
+}
 
 __device__ __forceinline__ int remap_xcd(int b, int nb)
 {
@@ -31,173 +51,251 @@ __device__ __forceinline__ int remap_xcd(int b, int nb)
     return xcd < rem ? xcd * (q + 1) + slot : rem * (q + 1) + (xcd - rem) * q + slot;
 }
 
-// CPML auxiliaries of one column at one plane: z-slab pairs (always present in
-// the registers) and, for tiles that touch the x/y slabs, x- and y-slab pairs.
-// Index order per axis as in the slab arrays: E (a+1)%3, E (a+2)%3, H (a+1)%3, H (a+2)%3.
-template <bool XY> struct PsiReg;
-template <> struct PsiReg<false> { float z[4]; };
-template <> struct PsiReg<true> { float z[4], x[4], y[4]; };
+// CPML auxiliaries of one column at one plane.  Per axis, as in the slab
+// arrays: E (a+1)%3, E (a+2)%3, H (a+1)%3, H (a+2)%3.
+template <bool XP, bool YP> struct PsiReg {
+    float z[4];
+    float x[XP ? 4 : 1];
+    float y[YP ? 4 : 1];
+};
 
-template <bool XY> __device__ __forceinline__ void psi_zero(PsiReg<XY> &p)
+template <int R, bool XP, bool YP> struct Plane {
+    float e[R][3], h[R][3], ce[R];
+    PsiReg<XP, YP> p[R];
+};
+
+template <bool XP, bool YP> __device__ __forceinline__ void psi_zero(PsiReg<XP, YP> &p)
 {
 #pragma unroll
     for (int q = 0; q < 4; q++) p.z[q] = 0.f;
-    if constexpr (XY) {
+    if constexpr (XP) {
 #pragma unroll
-        for (int q = 0; q < 4; q++) { p.x[q] = 0.f; p.y[q] = 0.f; }
+        for (int q = 0; q < 4; q++) p.x[q] = 0.f;
+    }
+    if constexpr (YP) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) p.y[q] = 0.f;
     }
 }
 
-template <int K, bool XY>
-__global__ __launch_bounds__(EX * TbShape<K>::W) void k_tb_forward(TbArgs A)
+// psi of a held component is not advanced
+__device__ __forceinline__ float cpml_term_h(float d, float &psi, float b, float a, float kinv, bool held)
+{
+    const float np = fmaf(b, psi, a * d);
+    psi = held ? psi : np;
+    return fmaf(d, kinv, psi);
+}
+
+template <int K, bool XP, bool YP, int PD>
+__global__ __launch_bounds__(EX *TbShape<K>::W) void k_tb_forward(TbArgs A)
 {
     constexpr int W = TbShape<K>::W, R = TbShape<K>::R;
-    constexpr int EY = W * R, TX = EX - 2 * K, TY = EY - 2 * K;
+    constexpr int EY = W * R;
     __shared__ float sE[3][EY][EX];
     __shared__ float sH[3][EY][EX];
+    // z grading of the 2p slab planes (E b, a, 1/k, H b, a, 1/k) and the
+    // source amplitudes of the K steps of this sweep, staged once so the
+    // march never waits on a vector load other than its own plane fetches
+    __shared__ float sGz[2 * TB_MAXP][6];
+    __shared__ float sAmp[FD_MAXSRC][K];
 
-    const Grid &g = A.g;
+    const int nx = A.g.nx, ny = A.g.ny, nz = A.g.nz, p = A.g.p;
+    for (int e = threadIdx.x; e < 2 * p; e += blockDim.x) {
+        const int kk = e < p ? e : nz - 2 * p + e;
+        const float4 gE = A.profv[2][2 * kk], gH = A.profv[2][2 * kk + 1];
+        sGz[e][0] = gE.x; sGz[e][1] = gE.y; sGz[e][2] = gE.z;
+        sGz[e][3] = gH.x; sGz[e][4] = gH.y; sGz[e][5] = gH.z;
+    }
+    if ((int)threadIdx.x < FD_MAXSRC * K) {
+        const int q = threadIdx.x / K, s = threadIdx.x % K;
+        sAmp[q][s] = (A.with_src && q < A.g.nsrc) ? A.g.samp[q][A.n0 + s] : 0.f;
+    }
+    __syncthreads();
+    const unsigned nxy = (unsigned)A.g.nxy;
+    const float S = A.g.S;
     int b = blockIdx.x;
     if (A.xcd_remap) b = remap_xcd(b, gridDim.x);
-    const int4 tl = A.tiles[b];
-    const int x0 = tl.x, y0 = tl.y, z0 = tl.z, z1 = tl.w;
+    const int4 tl = A.tiles[2 * b], tz = A.tiles[2 * b + 1];
+    const int x0 = tl.x, x1 = tl.y, y0 = tl.z, y1 = tl.w, z0 = tz.x, z1 = tz.y;
     const int lane = threadIdx.x & (EX - 1);
     const int wv = threadIdx.x / EX;
     const int x = x0 - K + lane;
-    const bool inx = x >= 0 && x < g.nx;
-    const bool ownx = x >= x0 && x < x0 + TX && x < g.nx;
-    const int p = g.p;
-    const int sx = (XY && inx && p > 0) ? slab_coord(x, g.nx, p) : -1;
+    const bool inx = x >= 0 && x < nx;
+    const int xc = x < 0 ? 0 : (x >= nx ? nx - 1 : x);
+    const int sx = (XP && inx) ? slab_coord(x, nx, p) : -1;
 
+    // per-column CPML grading along x and y (E then H: b, a, 1/kappa)
+    float4 gxE = make_float4(1.f, 0.f, 1.f, 0.f), gxH = gxE;
+    if constexpr (XP) {
+        if (sx >= 0) { gxE = A.profv[0][2 * x]; gxH = A.profv[0][2 * x + 1]; }
+    }
     int ys[R], row[R], sy[R];
+    unsigned off[R], soff_x[R], soff_y[R];
     bool incol[R], own[R];
+    float mex[R], mey[R], mez[R];   // 1 unless a conducting wall holds the component
+    float4 gyE[YP ? R : 1], gyH[YP ? R : 1];
 #pragma unroll
     for (int r = 0; r < R; r++) {
         row[r] = wv * R + r;
         ys[r] = y0 - K + row[r];
-        incol[r] = inx && ys[r] >= 0 && ys[r] < g.ny;
-        own[r] = ownx && ys[r] >= y0 && ys[r] < y0 + TY && ys[r] < g.ny;
-        sy[r] = (XY && incol[r] && p > 0) ? slab_coord(ys[r], g.ny, p) : -1;
+        incol[r] = inx && ys[r] >= 0 && ys[r] < ny;
+        own[r] = x >= x0 && x < x1 && ys[r] >= y0 && ys[r] < y1;
+        const int yc = ys[r] < 0 ? 0 : (ys[r] >= ny ? ny - 1 : ys[r]);
+        off[r] = (unsigned)yc * (unsigned)nx + (unsigned)xc;
+        sy[r] = (YP && incol[r]) ? slab_coord(ys[r], ny, p) : -1;
+        mex[r] = ys[r] == 0 ? 0.f : 1.f;
+        mey[r] = x == 0 ? 0.f : 1.f;
+        mez[r] = (x == 0 || ys[r] == 0) ? 0.f : 1.f;
+        // slab offsets without the plane term
+        soff_x[r] = sx >= 0 ? (unsigned)yc * (unsigned)(2 * p) + (unsigned)sx : 0u;
+        soff_y[r] = sy[r] >= 0 ? (unsigned)sy[r] * (unsigned)nx + (unsigned)xc : 0u;
+        if constexpr (YP) {
+            gyE[r] = make_float4(1.f, 0.f, 1.f, 0.f);
+            gyH[r] = gyE[r];
+            if (sy[r] >= 0) { gyE[r] = A.profv[1][2 * ys[r]]; gyH[r] = A.profv[1][2 * ys[r] + 1]; }
+        }
     }
 
-    // pipeline registers: Eo[s], Ho[s], Po[s] = output of level s at the plane
-    // level s+1 works on next; Ho[K] = last H of level K; cd[s] = S/eps of the
-    // plane level s works on.
-    float Eo[K][R][3], Ho[K + 1][R][3], cd[K + 1][R];
-    PsiReg<XY> Po[K][R];
+    const float *__restrict__ iEx = A.in.c[0];
+    const float *__restrict__ iEy = A.in.c[1];
+    const float *__restrict__ iEz = A.in.c[2];
+    const float *__restrict__ iHx = A.in.c[3];
+    const float *__restrict__ iHy = A.in.c[4];
+    const float *__restrict__ iHz = A.in.c[5];
+    const float *__restrict__ ice = A.g.ce;
+
+    auto load_plane = [&](int t, Plane<R, XP, YP> &P) {
+        const bool tin = t >= 0 && t < nz;
+        const unsigned base = (unsigned)(tin ? t : 0) * nxy;
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const unsigned c = (base + off[r]) * 4u;
+            const bool v = tin && incol[r];
+            const float e0 = ldo(iEx, c), e1 = ldo(iEy, c), e2 = ldo(iEz, c);
+            const float h0 = ldo(iHx, c), h1 = ldo(iHy, c), h2 = ldo(iHz, c);
+            const float cc = ldo(ice, c);
+            P.e[r][0] = v ? e0 : 0.f; P.e[r][1] = v ? e1 : 0.f; P.e[r][2] = v ? e2 : 0.f;
+            P.h[r][0] = v ? h0 : 0.f; P.h[r][1] = v ? h1 : 0.f; P.h[r][2] = v ? h2 : 0.f;
+            P.ce[r] = v ? cc : 0.f;
+            psi_zero<XP, YP>(P.p[r]);
+        }
+        if (p > 0 && tin) {
+            const int szt = slab_coord(t, nz, p);
+            if (szt >= 0) {
+                const unsigned zb = (unsigned)szt * nxy;
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+#pragma unroll
+                    for (int q = 0; q < 4; q++) P.p[r].z[q] = A.pin.a[2][q][zb + off[r]];
+                }
+            }
+            if constexpr (XP) {
+                const unsigned xb = (unsigned)t * (unsigned)ny * (unsigned)(2 * p);
+#pragma unroll
+                for (int r = 0; r < R; r++)
+#pragma unroll
+                    for (int q = 0; q < 4; q++) P.p[r].x[q] = A.pin.a[0][q][xb + soff_x[r]];
+            }
+            if constexpr (YP) {
+                const unsigned yb = (unsigned)t * (unsigned)(2 * p) * (unsigned)nx;
+#pragma unroll
+                for (int r = 0; r < R; r++)
+#pragma unroll
+                    for (int q = 0; q < 4; q++) P.p[r].y[q] = A.pin.a[1][q][yb + soff_y[r]];
+            }
+        }
+    };
+
+    // pipeline registers: Eo[s], Ho[s]/Hc[s], Po[s] = output of level s at the
+    // plane level s+1 works on next; Ho[K] = last Hx, Hy of level K; cd[s] =
+    // S/eps of the plane level s works on.
+    float Eo[K][R][3], Ho[K + 1][R][2], Hc[K][R], cd[K + 1][R];
+    PsiReg<XP, YP> Po[K][R];
 #pragma unroll
     for (int s = 0; s <= K; s++)
 #pragma unroll
         for (int r = 0; r < R; r++) {
             cd[s][r] = 0.f;
-#pragma unroll
-            for (int q = 0; q < 3; q++) {
-                Ho[s][r][q] = 0.f;
-                if (s < K) Eo[s][r][q] = 0.f;
+            Ho[s][r][0] = Ho[s][r][1] = 0.f;
+            if (s < K) {
+                Eo[s][r][0] = Eo[s][r][1] = Eo[s][r][2] = 0.f;
+                Hc[s][r] = 0.f;
+                psi_zero<XP, YP>(Po[s][r]);
             }
-            if (s < K) psi_zero<XY>(Po[s][r]);
         }
 
-    const long long nxy = g.nxy;
     const int zlo = z0 - K;
+    const int zend = z1 + K;
 
-    for (int t = zlo; t < z1 + K; t++) {
-        // ---------------------------------------------------- level 0: load plane t
+    auto body = [&](const int t, const Plane<R, XP, YP> &cur) {
         float nE[R][3], nH[R][3];
-        PsiReg<XY> nP[R];
-        const bool tin = t >= 0 && t < g.nz;
-        const int szt = (tin && p > 0) ? slab_coord(t, g.nz, p) : -1;
+        PsiReg<XP, YP> nP[R];
 #pragma unroll
         for (int r = 0; r < R; r++) {
-            psi_zero<XY>(nP[r]);
-            float ce = 0.f;
-            if (incol[r] && tin) {
-                const long long c = (long long)t * nxy + (long long)ys[r] * g.nx + x;
 #pragma unroll
-                for (int q = 0; q < 3; q++) {
-                    nE[r][q] = A.in.c[q][c];
-                    nH[r][q] = A.in.c[3 + q][c];
-                }
-                ce = g.ce[c];
-                if (szt >= 0) {
-                    const long long zi = slab_index(g, 2, szt, x, ys[r], t);
-#pragma unroll
-                    for (int q = 0; q < 4; q++) nP[r].z[q] = A.pin.a[2][q][zi];
-                }
-                if constexpr (XY) {
-                    if (sx >= 0) {
-                        const long long xi = slab_index(g, 0, sx, x, ys[r], t);
-#pragma unroll
-                        for (int q = 0; q < 4; q++) nP[r].x[q] = A.pin.a[0][q][xi];
-                    }
-                    if (sy[r] >= 0) {
-                        const long long yi = slab_index(g, 1, sy[r], x, ys[r], t);
-#pragma unroll
-                        for (int q = 0; q < 4; q++) nP[r].y[q] = A.pin.a[1][q][yi];
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int q = 0; q < 3; q++) { nE[r][q] = 0.f; nH[r][q] = 0.f; }
-            }
+            for (int q = 0; q < 3; q++) { nE[r][q] = cur.e[r][q]; nH[r][q] = cur.h[r][q]; }
+            nP[r] = cur.p[r];
 #pragma unroll
             for (int s = K; s > 0; s--) cd[s][r] = cd[s - 1][r];
-            cd[0][r] = ce;
+            cd[0][r] = cur.ce[r];
         }
-
-        // ------------------------------------------------------ levels 1..K
 #pragma unroll
         for (int s = 1; s <= K; s++) {
             const int k = t - s;
             float mE[R][3], mH[R][3];
-            PsiReg<XY> mP[R];
+            PsiReg<XP, YP> mP[R];
             if (k >= zlo) {
-                const bool kin = k >= 0 && k < g.nz;
-                const int szk = (kin && p > 0) ? slab_coord(k, g.nz, p) : -1;
-                // E of level s-1 at plane k into LDS
+                const bool kin = k >= 0 && k < nz;
+                const int szk = (kin && p > 0) ? slab_coord(k, nz, p) : -1;
+                float4 gzE = make_float4(1.f, 0.f, 1.f, 0.f), gzH = gzE;
+                if (szk >= 0) {
+                    gzE = make_float4(sGz[szk][0], sGz[szk][1], sGz[szk][2], 0.f);
+                    gzH = make_float4(sGz[szk][3], sGz[szk][4], sGz[szk][5], 0.f);
+                }
+                const float mk = k == 0 ? 0.f : 1.f;
 #pragma unroll
-                for (int r = 0; r < R; r++)
-#pragma unroll
-                    for (int q = 0; q < 3; q++) sE[q][row[r]][lane] = Eo[s - 1][r][q];
+                for (int r = 0; r < R; r++) {
+                    sE[0][row[r]][lane] = Eo[s - 1][r][0];
+                    sE[1][row[r]][lane] = Eo[s - 1][r][1];
+                    sE[2][row[r]][lane] = Eo[s - 1][r][2];
+                }
                 __syncthreads();
                 // ---- H half step at plane k
 #pragma unroll
                 for (int r = 0; r < R; r++) {
                     const float ex = Eo[s - 1][r][0], ey = Eo[s - 1][r][1], ez = Eo[s - 1][r][2];
                     const float ex_z = nE[r][0], ey_z = nE[r][1];
-                    const bool up = row[r] + 1 < EY, rt = lane + 1 < EX;
-                    const float ez_y = up ? sE[2][row[r] + 1][lane] : 0.f;
-                    const float ex_y = up ? sE[0][row[r] + 1][lane] : 0.f;
-                    const float ey_x = rt ? sE[1][row[r]][lane + 1] : 0.f;
-                    const float ez_x = rt ? sE[2][row[r]][lane + 1] : 0.f;
+                    const int ru = row[r] + 1 < EY ? row[r] + 1 : row[r];
+                    const int lr = lane + 1 < EX ? lane + 1 : lane;
+                    const float ez_y = sE[2][ru][lane], ex_y = sE[0][ru][lane];
+                    const float ey_x = sE[1][row[r]][lr], ez_x = sE[2][row[r]][lr];
                     float dy_ez = ez_y - ez, dz_ey = ey_z - ey;
                     float dz_ex = ex_z - ex, dx_ez = ez_x - ez;
                     float dx_ey = ey_x - ey, dy_ex = ex_y - ex;
                     mP[r] = Po[s - 1][r];
                     if (szk >= 0) {   // Hx (idx 2), Hy (idx 3) along z
-                        const float bb = g.prof[1][2][0][k], aa = g.prof[1][2][1][k], kv = g.prof[1][2][2][k];
-                        dz_ey = cpml_term(dz_ey, mP[r].z[2], bb, aa, kv);
-                        dz_ex = cpml_term(dz_ex, mP[r].z[3], bb, aa, kv);
+                        dz_ey = cpml_term(dz_ey, mP[r].z[2], gzH.x, gzH.y, gzH.z);
+                        dz_ex = cpml_term(dz_ex, mP[r].z[3], gzH.x, gzH.y, gzH.z);
                     }
-                    if constexpr (XY) {
+                    if constexpr (XP) {
                         if (sx >= 0) {   // Hy (idx 2), Hz (idx 3) along x
-                            const float bb = g.prof[1][0][0][x], aa = g.prof[1][0][1][x], kv = g.prof[1][0][2][x];
-                            dx_ez = cpml_term(dx_ez, mP[r].x[2], bb, aa, kv);
-                            dx_ey = cpml_term(dx_ey, mP[r].x[3], bb, aa, kv);
+                            dx_ez = cpml_term(dx_ez, mP[r].x[2], gxH.x, gxH.y, gxH.z);
+                            dx_ey = cpml_term(dx_ey, mP[r].x[3], gxH.x, gxH.y, gxH.z);
                         }
+                    }
+                    if constexpr (YP) {
                         if (sy[r] >= 0) {   // Hz (idx 2), Hx (idx 3) along y
-                            const int yy = ys[r];
-                            const float bb = g.prof[1][1][0][yy], aa = g.prof[1][1][1][yy], kv = g.prof[1][1][2][yy];
-                            dy_ex = cpml_term(dy_ex, mP[r].y[2], bb, aa, kv);
-                            dy_ez = cpml_term(dy_ez, mP[r].y[3], bb, aa, kv);
+                            dy_ex = cpml_term(dy_ex, mP[r].y[2], gyH[r].x, gyH[r].y, gyH[r].z);
+                            dy_ez = cpml_term(dy_ez, mP[r].y[3], gyH[r].x, gyH[r].y, gyH[r].z);
                         }
                     }
                     const bool live = incol[r] && kin;
-                    mH[r][0] = live ? h_update(Ho[s - 1][r][0], g.S, dy_ez, dz_ey) : 0.f;
-                    mH[r][1] = live ? h_update(Ho[s - 1][r][1], g.S, dz_ex, dx_ez) : 0.f;
-                    mH[r][2] = live ? h_update(Ho[s - 1][r][2], g.S, dx_ey, dy_ex) : 0.f;
-#pragma unroll
-                    for (int q = 0; q < 3; q++) sH[q][row[r]][lane] = mH[r][q];
+                    mH[r][0] = live ? h_update(Ho[s - 1][r][0], S, dy_ez, dz_ey) : 0.f;
+                    mH[r][1] = live ? h_update(Ho[s - 1][r][1], S, dz_ex, dx_ez) : 0.f;
+                    mH[r][2] = live ? h_update(Hc[s - 1][r], S, dx_ey, dy_ex) : 0.f;
+                    sH[0][row[r]][lane] = mH[r][0];
+                    sH[1][row[r]][lane] = mH[r][1];
+                    sH[2][row[r]][lane] = mH[r][2];
                 }
                 __syncthreads();
                 // ---- E half step at plane k
@@ -205,95 +303,106 @@ __global__ __launch_bounds__(EX * TbShape<K>::W) void k_tb_forward(TbArgs A)
                 for (int r = 0; r < R; r++) {
                     const float hx = mH[r][0], hy = mH[r][1], hz = mH[r][2];
                     const float hx_z = Ho[s][r][0], hy_z = Ho[s][r][1];
-                    const bool dn = row[r] > 0, lf = lane > 0;
-                    const float hz_y = dn ? sH[2][row[r] - 1][lane] : 0.f;
-                    const float hx_y = dn ? sH[0][row[r] - 1][lane] : 0.f;
-                    const float hz_x = lf ? sH[2][row[r]][lane - 1] : 0.f;
-                    const float hy_x = lf ? sH[1][row[r]][lane - 1] : 0.f;
+                    const int rd = row[r] > 0 ? row[r] - 1 : row[r];
+                    const int ll = lane > 0 ? lane - 1 : lane;
+                    const float hz_y = sH[2][rd][lane], hx_y = sH[0][rd][lane];
+                    const float hz_x = sH[2][row[r]][ll], hy_x = sH[1][row[r]][ll];
                     float dy_hz = hz - hz_y, dz_hy = hy - hy_z;
                     float dz_hx = hx - hx_z, dx_hz = hz - hz_x;
                     float dx_hy = hy - hy_x, dy_hx = hx - hx_y;
-                    const int yy = ys[r];
-                    const bool hex = yy == 0 || k == 0, hey = x == 0 || k == 0, hez = x == 0 || yy == 0;
+                    const float ax = mex[r] * mk, ay = mey[r] * mk, az = mez[r];
                     if (szk >= 0) {   // Ex (idx 0), Ey (idx 1) along z
-                        const float bb = g.prof[0][2][0][k], aa = g.prof[0][2][1][k], kv = g.prof[0][2][2][k];
-                        if (!hex) dz_hy = cpml_term(dz_hy, mP[r].z[0], bb, aa, kv);
-                        if (!hey) dz_hx = cpml_term(dz_hx, mP[r].z[1], bb, aa, kv);
+                        dz_hy = cpml_term_h(dz_hy, mP[r].z[0], gzE.x, gzE.y, gzE.z, ax == 0.f);
+                        dz_hx = cpml_term_h(dz_hx, mP[r].z[1], gzE.x, gzE.y, gzE.z, ay == 0.f);
                     }
-                    if constexpr (XY) {
+                    if constexpr (XP) {
                         if (sx >= 0) {   // Ey (idx 0), Ez (idx 1) along x
-                            const float bb = g.prof[0][0][0][x], aa = g.prof[0][0][1][x], kv = g.prof[0][0][2][x];
-                            if (!hey) dx_hz = cpml_term(dx_hz, mP[r].x[0], bb, aa, kv);
-                            if (!hez) dx_hy = cpml_term(dx_hy, mP[r].x[1], bb, aa, kv);
+                            dx_hz = cpml_term_h(dx_hz, mP[r].x[0], gxE.x, gxE.y, gxE.z, ay == 0.f);
+                            dx_hy = cpml_term_h(dx_hy, mP[r].x[1], gxE.x, gxE.y, gxE.z, az == 0.f);
                         }
+                    }
+                    if constexpr (YP) {
                         if (sy[r] >= 0) {   // Ez (idx 0), Ex (idx 1) along y
-                            const float bb = g.prof[0][1][0][yy], aa = g.prof[0][1][1][yy], kv = g.prof[0][1][2][yy];
-                            if (!hez) dy_hx = cpml_term(dy_hx, mP[r].y[0], bb, aa, kv);
-                            if (!hex) dy_hz = cpml_term(dy_hz, mP[r].y[1], bb, aa, kv);
+                            dy_hx = cpml_term_h(dy_hx, mP[r].y[0], gyE[r].x, gyE[r].y, gyE[r].z, az == 0.f);
+                            dy_hz = cpml_term_h(dy_hz, mP[r].y[1], gyE[r].x, gyE[r].y, gyE[r].z, ax == 0.f);
                         }
                     }
                     const float ce = cd[s][r];
-                    float ex = Eo[s - 1][r][0], ey = Eo[s - 1][r][1], ez = Eo[s - 1][r][2];
-                    if (!hex) ex = e_update(ex, ce, dy_hz, dz_hy);
-                    if (!hey) ey = e_update(ey, ce, dz_hx, dx_hz);
-                    if (!hez) ez = e_update(ez, ce, dx_hy, dy_hx);
-                    if (A.with_src) {
-                        for (int q = 0; q < g.nsrc; q++) {
-                            if (k != g.sk[q]) continue;
-                            if (g.skind[q] == 0 && (x != g.si[q] || yy != g.sj[q])) continue;
-                            const float am = g.samp[q][A.n0 + s - 1];
-                            if (g.scomp[q] == 0 && !hex) ex = ex + am;
-                            if (g.scomp[q] == 1 && !hey) ey = ey + am;
-                            if (g.scomp[q] == 2 && !hez) ez = ez + am;
-                        }
-                    }
                     const bool live = incol[r] && kin;
+                    const float ex = e_update(Eo[s - 1][r][0], ce * ax, dy_hz, dz_hy);
+                    const float ey = e_update(Eo[s - 1][r][1], ce * ay, dz_hx, dx_hz);
+                    const float ez = e_update(Eo[s - 1][r][2], ce * az, dx_hy, dy_hx);
                     mE[r][0] = live ? ex : 0.f;
                     mE[r][1] = live ? ey : 0.f;
                     mE[r][2] = live ? ez : 0.f;
-
-                    // ---- outputs of this step for owned cells
-                    if (own[r] && k >= z0 && k < z1) {
-                        const long long step = A.n0 + s - 1;
-                        if (A.planes) {
-                            for (int m = 0; m < A.D.ndet; m++) {
-                                if (k != A.D.k[m] || x < A.D.i0[m] || x >= A.D.i1[m] || yy < A.D.j0[m] ||
-                                    yy >= A.D.j1[m])
-                                    continue;
+                }
+                // ---- sources (uniform plane test)
+                if (A.with_src) {
+                    for (int q = 0; q < A.g.nsrc; q++) {
+                        if (k != A.g.sk[q]) continue;
+                        const float am = sAmp[q][s - 1];
+                        const int comp = A.g.scomp[q];
+#pragma unroll
+                        for (int r = 0; r < R; r++) {
+                            const bool hit = incol[r] && kin &&
+                                             (A.g.skind[q] == 1 || (x == A.g.si[q] && ys[r] == A.g.sj[q]));
+                            const float mask = comp == 0 ? mex[r] * mk : comp == 1 ? mey[r] * mk : mez[r];
+                            if (hit && mask != 0.f) {
+                                if (comp == 0) mE[r][0] = mE[r][0] + am;
+                                if (comp == 1) mE[r][1] = mE[r][1] + am;
+                                if (comp == 2) mE[r][2] = mE[r][2] + am;
+                            }
+                        }
+                    }
+                }
+                // ---- detector flux planes (uniform plane test)
+                if (A.planes && k >= z0 && k < z1) {
+                    for (int m = 0; m < A.D.ndet; m++) {
+                        if (k != A.D.k[m]) continue;
+#pragma unroll
+                        for (int r = 0; r < R; r++) {
+                            const int yy = ys[r];
+                            if (own[r] && x >= A.D.i0[m] && x < A.D.i1[m] && yy >= A.D.j0[m] && yy < A.D.j1[m]) {
                                 const long long e = A.D.off[m] + (long long)(yy - A.D.j0[m]) * (A.D.i1[m] - A.D.i0[m]) +
                                                     (x - A.D.i0[m]);
                                 A.planes[(long long)(s - 1) * A.D.per_step + e] =
                                     flux_density(mE[r][0], mE[r][1], mH[r][0], mH[r][1]);
                             }
                         }
-                        if (A.rec && p > 0) {
-                            float *rs = A.rec + (long long)(s - 1) * A.R.per_step;
-                            const bool wx = x >= p && x < g.nx - p, wy = yy >= p && yy < g.ny - p,
-                                       wz = k >= p && k < g.nz - p;
-                            // z faces: u = x, v = y
-                            if (wx && wy && (k == p - 1 || k == g.nz - p)) {
-                                const int side = k == p - 1 ? 0 : 1;
-                                const long long fs = (long long)A.R.Lu[2] * A.R.Lv[2];
-                                const long long e = A.R.off[4 + side] + (long long)(yy - p) * A.R.Lu[2] + (x - p);
-                                rs[e] = side ? mE[r][0] : mH[r][0];
-                                rs[e + fs] = side ? mE[r][1] : mH[r][1];
-                            }
-                            // x faces: u = y, v = z; comps (y, z)
-                            if (wy && wz && (x == p - 1 || x == g.nx - p)) {
-                                const int side = x == p - 1 ? 0 : 1;
-                                const long long fs = (long long)A.R.Lu[0] * A.R.Lv[0];
-                                const long long e = A.R.off[0 + side] + (long long)(k - p) * A.R.Lu[0] + (yy - p);
-                                rs[e] = side ? mE[r][1] : mH[r][1];
-                                rs[e + fs] = side ? mE[r][2] : mH[r][2];
-                            }
-                            // y faces: u = x, v = z; comps (z, x)
-                            if (wx && wz && (yy == p - 1 || yy == g.ny - p)) {
-                                const int side = yy == p - 1 ? 0 : 1;
-                                const long long fs = (long long)A.R.Lu[1] * A.R.Lv[1];
-                                const long long e = A.R.off[2 + side] + (long long)(k - p) * A.R.Lu[1] + (x - p);
-                                rs[e] = side ? mE[r][2] : mH[r][2];
-                                rs[e + fs] = side ? mE[r][0] : mH[r][0];
-                            }
+                    }
+                }
+                // ---- interface record (section 2.2)
+                if (A.rec && k >= z0 && k < z1 && k >= p - 1 && k <= nz - p) {
+                    float *rs = A.rec + (long long)(s - 1) * A.R.per_step;
+                    const bool wz = k >= p && k < nz - p;
+#pragma unroll
+                    for (int r = 0; r < R; r++) {
+                        if (!own[r]) continue;
+                        const int yy = ys[r];
+                        const bool wx = x >= p && x < nx - p, wy = yy >= p && yy < ny - p;
+                        // z faces: u = x, v = y
+                        if (wx && wy && (k == p - 1 || k == nz - p)) {
+                            const int side = k == p - 1 ? 0 : 1;
+                            const long long fs = (long long)A.R.Lu[2] * A.R.Lv[2];
+                            const long long e = A.R.off[4 + side] + (long long)(yy - p) * A.R.Lu[2] + (x - p);
+                            rs[e] = side ? mE[r][0] : mH[r][0];
+                            rs[e + fs] = side ? mE[r][1] : mH[r][1];
+                        }
+                        // x faces: u = y, v = z; comps (y, z)
+                        if (wy && wz && (x == p - 1 || x == nx - p)) {
+                            const int side = x == p - 1 ? 0 : 1;
+                            const long long fs = (long long)A.R.Lu[0] * A.R.Lv[0];
+                            const long long e = A.R.off[0 + side] + (long long)(k - p) * A.R.Lu[0] + (yy - p);
+                            rs[e] = side ? mE[r][1] : mH[r][1];
+                            rs[e + fs] = side ? mE[r][2] : mH[r][2];
+                        }
+                        // y faces: u = x, v = z; comps (z, x)
+                        if (wx && wz && (yy == p - 1 || yy == ny - p)) {
+                            const int side = yy == p - 1 ? 0 : 1;
+                            const long long fs = (long long)A.R.Lu[1] * A.R.Lv[1];
+                            const long long e = A.R.off[2 + side] + (long long)(k - p) * A.R.Lu[1] + (x - p);
+                            rs[e] = side ? mE[r][2] : mH[r][2];
+                            rs[e + fs] = side ? mE[r][0] : mH[r][0];
                         }
                     }
                 }
@@ -302,19 +411,19 @@ __global__ __launch_bounds__(EX * TbShape<K>::W) void k_tb_forward(TbArgs A)
                 for (int r = 0; r < R; r++) {
 #pragma unroll
                     for (int q = 0; q < 3; q++) { mE[r][q] = 0.f; mH[r][q] = 0.f; }
-                    psi_zero<XY>(mP[r]);
+                    psi_zero<XP, YP>(mP[r]);
                 }
             }
             // rotate level s-1: its new plane becomes the one level s reads next
 #pragma unroll
             for (int r = 0; r < R; r++) {
 #pragma unroll
-                for (int q = 0; q < 3; q++) {
-                    Eo[s - 1][r][q] = nE[r][q];
-                    Ho[s - 1][r][q] = nH[r][q];
-                    nE[r][q] = mE[r][q];
-                    nH[r][q] = mH[r][q];
-                }
+                for (int q = 0; q < 3; q++) Eo[s - 1][r][q] = nE[r][q];
+                Ho[s - 1][r][0] = nH[r][0];
+                Ho[s - 1][r][1] = nH[r][1];
+                Hc[s - 1][r] = nH[r][2];
+#pragma unroll
+                for (int q = 0; q < 3; q++) { nE[r][q] = mE[r][q]; nH[r][q] = mH[r][q]; }
                 Po[s - 1][r] = nP[r];
                 nP[r] = mP[r];
             }
@@ -324,54 +433,91 @@ __global__ __launch_bounds__(EX * TbShape<K>::W) void k_tb_forward(TbArgs A)
         const int kK = t - K;
 #pragma unroll
         for (int r = 0; r < R; r++) {
+            Ho[K][r][0] = nH[r][0];
+            Ho[K][r][1] = nH[r][1];
+        }
+        if (kK >= z0 && kK < z1) {
+            const unsigned base = (unsigned)kK * nxy;
 #pragma unroll
-            for (int q = 0; q < 3; q++) Ho[K][r][q] = nH[r][q];
-            if (own[r] && kK >= z0 && kK < z1) {
-                const long long c = (long long)kK * nxy + (long long)ys[r] * g.nx + x;
+            for (int r = 0; r < R; r++) {
+                if (!own[r]) continue;
+                const unsigned c = (base + off[r]) * 4u;
 #pragma unroll
                 for (int q = 0; q < 3; q++) {
-                    A.out.c[q][c] = nE[r][q];
-                    A.out.c[3 + q][c] = nH[r][q];
+                    sto(A.out.c[q], c, nE[r][q]);
+                    sto(A.out.c[3 + q], c, nH[r][q]);
                 }
-                const int szo = p > 0 ? slab_coord(kK, g.nz, p) : -1;
+            }
+            if (p > 0) {
+                const int szo = slab_coord(kK, nz, p);
                 if (szo >= 0) {
-                    const long long zi = slab_index(g, 2, szo, x, ys[r], kK);
+                    const unsigned zb = (unsigned)szo * nxy;
 #pragma unroll
-                    for (int q = 0; q < 4; q++) A.pout.a[2][q][zi] = nP[r].z[q];
+                    for (int r = 0; r < R; r++)
+                        if (own[r]) {
+#pragma unroll
+                            for (int q = 0; q < 4; q++) A.pout.a[2][q][zb + off[r]] = nP[r].z[q];
+                        }
                 }
-                if constexpr (XY) {
+                if constexpr (XP) {
                     if (sx >= 0) {
-                        const long long xi = slab_index(g, 0, sx, x, ys[r], kK);
+                        const unsigned xb = (unsigned)kK * (unsigned)ny * (unsigned)(2 * p);
 #pragma unroll
-                        for (int q = 0; q < 4; q++) A.pout.a[0][q][xi] = nP[r].x[q];
-                    }
-                    if (sy[r] >= 0) {
-                        const long long yi = slab_index(g, 1, sy[r], x, ys[r], kK);
+                        for (int r = 0; r < R; r++)
+                            if (own[r]) {
 #pragma unroll
-                        for (int q = 0; q < 4; q++) A.pout.a[1][q][yi] = nP[r].y[q];
+                                for (int q = 0; q < 4; q++) A.pout.a[0][q][xb + soff_x[r]] = nP[r].x[q];
+                            }
                     }
                 }
+                if constexpr (YP) {
+                    const unsigned yb = (unsigned)kK * (unsigned)(2 * p) * (unsigned)nx;
+#pragma unroll
+                    for (int r = 0; r < R; r++)
+                        if (own[r] && sy[r] >= 0) {
+#pragma unroll
+                            for (int q = 0; q < 4; q++) A.pout.a[1][q][yb + soff_y[r]] = nP[r].y[q];
+                        }
+                }
+            }
+        }
+    };
+
+    // ring of PD planes in flight
+    Plane<R, XP, YP> ring[PD];
+#pragma unroll
+    for (int u = 0; u < PD; u++) load_plane(zlo + u, ring[u]);
+    for (int t0 = zlo; t0 < zend; t0 += PD) {
+#pragma unroll
+        for (int u = 0; u < PD; u++) {
+            const int t = t0 + u;
+            if (t < zend) {
+                const Plane<R, XP, YP> cur = ring[u];
+                load_plane(t + PD, ring[u]);
+                body(t, cur);
             }
         }
     }
 }
 
 template <int K>
-hipError_t launch_k(const TbArgs &a, bool xy, hipStream_t s)
+hipError_t launch_k(const TbArgs &a, int cls, hipStream_t s)
 {
     constexpr int threads = EX * TbShape<K>::W;
     if (a.ntiles <= 0) return hipSuccess;
-    if (xy)
-        hipLaunchKernelGGL((k_tb_forward<K, true>), dim3(a.ntiles), dim3(threads), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_tb_forward<K, false>), dim3(a.ntiles), dim3(threads), 0, s, a);
+    switch (cls) {
+    case 0: hipLaunchKernelGGL((k_tb_forward<K, false, false, 1>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_tb_forward<K, true, false, 1>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_tb_forward<K, false, true, 1>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_tb_forward<K, true, true, 1>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
+    }
     return hipGetLastError();
 }
 
 }  // namespace
 
 int tb_tile_x(int K) { return EX - 2 * K; }
-
+int tb_max_pml() { return TB_MAXP; }
 int tb_tile_y(int K)
 {
     switch (K) {
@@ -382,14 +528,14 @@ int tb_tile_y(int K)
     }
 }
 
-// a.ntiles > 0 tiles of one class; xy selects the instance with x/y CPML
-hipError_t launch_tb_forward_class(const TbArgs &a, int K, bool xy, hipStream_t s)
+// Tiles of class cls: bit 0 = x CPML slab in the extended footprint, bit 1 = y.
+hipError_t launch_tb_forward_class(const TbArgs &a, int K, int cls, hipStream_t s)
 {
     switch (K) {
-    case 1: return launch_k<1>(a, xy, s);
-    case 2: return launch_k<2>(a, xy, s);
-    case 3: return launch_k<3>(a, xy, s);
-    case 4: return launch_k<4>(a, xy, s);
+    case 1: return launch_k<1>(a, cls, s);
+    case 2: return launch_k<2>(a, cls, s);
+    case 3: return launch_k<3>(a, cls, s);
+    case 4: return launch_k<4>(a, cls, s);
     default: return hipErrorInvalidValue;
     }
 }
