@@ -84,6 +84,9 @@ struct fdtd_ctx {
     int tb_off[5][4], tb_cnt[5][4];
     float4 *profv[3];
     bool naive = false;                    // per-cell kernels instead of the z-march
+    hipStream_t side[3] = {nullptr, nullptr, nullptr};   // concurrent tile classes (default priority)
+    hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
+    int shape = 0;                         // z-march workgroup shape
     float wS[FDTD_MAX_DETECTORS];
     std::vector<float> host_tables;        // kept alive for async uploads
     std::vector<int4> host_tiles;
@@ -196,6 +199,14 @@ void geometry(const fdtd_desc *d, const fdtd_flux_detector *det, int ndet, Geome
     for (int a = 0; a < 3; a++) G.design_cells *= (d->design_hi[a] - d->design_lo[a]);
 }
 
+// z-march variant: ones digit = workgroup shape (0: 16 waves x 1 row, 1: 8 x 2),
+// tens digit = planes fetched ahead (1..3)
+int tb_shape()
+{
+    if (const char *e = getenv("FDTD_TB_SHAPE")) return atoi(e);
+    return 0;
+}
+
 int choose_K(const fdtd_desc *d)
 {
     if (d->time_block > 0) return d->time_block;
@@ -227,10 +238,11 @@ int zchunk(const Geometry &G, int K)
         if (v > 0) return std::min(v, G.nz);
     }
     const long long tx = (long long)split_axis(G.nx, tb_tile_x(K)).size();
-    const long long ty = (long long)split_axis(G.ny, tb_tile_y(K)).size();
-    long long chunks = (1024 + tx * ty - 1) / (tx * ty);
-    chunks = std::max(1LL, std::min(chunks, (long long)(G.nz + 31) / 32));
-    return (int)((G.nz + chunks - 1) / chunks);
+    const long long ty = (long long)split_axis(G.ny, tb_tile_y(K, tb_shape())).size();
+    // short marches: the work per workgroup is serial, so many short
+    // marches balance better than few long ones (16 planes measured best)
+    (void)tx; (void)ty;
+    return std::min(16, G.nz);
 }
 
 // Tile tables of the z-march kernel for K' = 1..K, four classes each: bit 0
@@ -242,7 +254,7 @@ void build_tiles(const Geometry &G, int K, std::vector<int4> &out, int off[5][4]
         for (int c = 0; c < 4; c++) off[kk][c] = cnt[kk][c] = 0;
     for (int kk = 1; kk <= K; kk++) {
         const int ZC = zchunk(G, kk);
-        const auto xs = split_axis(G.nx, tb_tile_x(kk)), ys = split_axis(G.ny, tb_tile_y(kk));
+        const auto xs = split_axis(G.nx, tb_tile_x(kk)), ys = split_axis(G.ny, tb_tile_y(kk, tb_shape()));
         std::vector<int4> cls[4];
         for (int z0 = 0; z0 < G.nz; z0 += ZC)
             for (const auto &yt : ys)
@@ -444,10 +456,23 @@ fdtd_status steps_tb(fdtd_ctx *h, int n0, int kk, int with_src, int with_rec, in
     a.D = G.D;
     a.xcd_remap = 1;
     for (int ax = 0; ax < 3; ax++) a.profv[ax] = h->profv[ax];
+    // The four tile classes are independent (all read buffer cur, write
+    // disjoint cells of buffer cur^1): classes 1..3 run on side streams that
+    // fork from and join back into the handle's stream, so a small class
+    // does not serialise a whole march behind the large ones.
+    const bool par = h->side[0] != nullptr;
+    if (par) HIPCHK(h, hipEventRecord(h->fork, h->stream));
     for (int c = 0; c < 4; c++) {
         a.tiles = h->tiles + 2 * (size_t)h->tb_off[kk][c];
         a.ntiles = h->tb_cnt[kk][c];
-        HIPCHK(h, launch_tb_forward_class(a, kk, c, h->stream));
+        if (a.ntiles == 0) continue;
+        hipStream_t st = (par && c > 0) ? h->side[c - 1] : h->stream;
+        if (st != h->stream) HIPCHK(h, hipStreamWaitEvent(st, h->fork, 0));
+        HIPCHK(h, launch_tb_forward_class(a, kk, c, h->shape, st));
+        if (st != h->stream) {
+            HIPCHK(h, hipEventRecord(h->join[c - 1], st));
+            HIPCHK(h, hipStreamWaitEvent(h->stream, h->join[c - 1], 0));
+        }
     }
     h->cur ^= 1;
     if (a.planes)
@@ -548,9 +573,11 @@ fdtd_status fdtd_create(const fdtd_desc *desc, const fdtd_source *src, int32_t n
     h->stream = (hipStream_t)stream;
     h->T = desc->n_steps;
     h->K = choose_K(desc);
-    h->naive = true;
+    h->naive = false;
     if (const char *e = getenv("FDTD_NAIVE")) h->naive = atoi(e) != 0;
-    if (desc->pml_cells > tb_max_pml()) h->naive = true;   // the z-march stages at most that many CPML planes
+    // the z-march stages at most tb_max_pml() CPML planes per side
+    if (desc->pml_cells > tb_max_pml()) h->naive = true;
+    h->shape = tb_shape();
     geometry(desc, det, ndet, h->geo);
     const size_t need = plan(h, desc, h->geo, h->K, nullptr);
     if (workspace_bytes < need) {
@@ -664,6 +691,20 @@ fdtd_status fdtd_create(const fdtd_desc *desc, const fdtd_source *src, int32_t n
         delete h;
         return FDTD_E_DEVICE;
     }
+    // side streams for concurrent tile classes (large grids only: on small
+    // grids the fork/join costs more than it saves)
+    if (!h->naive && G.N >= (1LL << 22) && getenv("FDTD_TB_SERIAL") == nullptr) {
+        bool ok = hipEventCreateWithFlags(&h->fork, hipEventDisableTiming) == hipSuccess;
+        for (int i = 0; i < 3 && ok; i++) {
+            ok = hipStreamCreateWithFlags(&h->side[i], hipStreamNonBlocking) == hipSuccess &&
+                 hipEventCreateWithFlags(&h->join[i], hipEventDisableTiming) == hipSuccess;
+        }
+        if (!ok) {
+            fail(nullptr, FDTD_E_DEVICE, "side stream creation failed");
+            fdtd_destroy(h);
+            return FDTD_E_DEVICE;
+        }
+    }
     h->t = 0;
     *out = h;
     return FDTD_OK;
@@ -751,6 +792,12 @@ fdtd_status fdtd_reset(fdtd_handle h)
 
 fdtd_status fdtd_destroy(fdtd_handle h)
 {
+    if (!h) return FDTD_OK;
+    for (int i = 0; i < 3; i++) {
+        if (h->side[i]) hipStreamDestroy(h->side[i]);
+        if (h->join[i]) hipEventDestroy(h->join[i]);
+    }
+    if (h->fork) hipEventDestroy(h->fork);
     delete h;
     return FDTD_OK;
 }

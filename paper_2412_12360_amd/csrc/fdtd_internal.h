@@ -164,7 +164,7 @@ struct TbArgs {
     const float4 *profv[3]; // per axis, per index: (b, a, 1/kappa) at E then H positions
     int xcd_remap;          // 1: map consecutive tiles to one XCD
 };
-hipError_t launch_tb_forward_class(const TbArgs &a, int K, int cls, hipStream_t s);
+hipError_t launch_tb_forward_class(const TbArgs &a, int K, int cls, int shape, hipStream_t s);
 int tb_tile_x(int K);
-int tb_tile_y(int K);
+int tb_tile_y(int K, int shape);
 int tb_max_pml();

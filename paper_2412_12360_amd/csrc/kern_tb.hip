@@ -31,7 +31,6 @@ namespace {
 constexpr int EX = 64;
 constexpr int TB_MAXP = 64;   // largest CPML thickness the z-march kernel stages
 
-template <int K> struct TbShape { static constexpr int W = 16, R = 1; };
 
 // a float at a 32-bit byte offset from a uniform base (lets the compiler use
 // the scalar-base + vector-offset addressing form)
@@ -86,10 +85,9 @@ __device__ __forceinline__ float cpml_term_h(float d, float &psi, float b, float
     return fmaf(d, kinv, psi);
 }
 
-template <int K, bool XP, bool YP, int PD>
-__global__ __launch_bounds__(EX *TbShape<K>::W) void k_tb_forward(TbArgs A)
+template <int K, bool XP, bool YP, int PD, int W, int R>
+__global__ __launch_bounds__(EX *W) void k_tb_forward(TbArgs A)
 {
-    constexpr int W = TbShape<K>::W, R = TbShape<K>::R;
     constexpr int EY = W * R;
     __shared__ float sE[3][EY][EX];
     __shared__ float sH[3][EY][EX];
@@ -500,42 +498,56 @@ __global__ __launch_bounds__(EX *TbShape<K>::W) void k_tb_forward(TbArgs A)
     }
 }
 
-template <int K>
-hipError_t launch_k(const TbArgs &a, int cls, hipStream_t s)
+template <int K, int W, int R, int PD>
+hipError_t launch_kwrp(const TbArgs &a, int cls, hipStream_t s)
 {
-    constexpr int threads = EX * TbShape<K>::W;
+    constexpr int threads = EX * W;
     if (a.ntiles <= 0) return hipSuccess;
     switch (cls) {
-    case 0: hipLaunchKernelGGL((k_tb_forward<K, false, false, 1>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
-    case 1: hipLaunchKernelGGL((k_tb_forward<K, true, false, 1>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_tb_forward<K, false, true, 1>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_tb_forward<K, true, true, 1>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
+    case 0: hipLaunchKernelGGL((k_tb_forward<K, false, false, PD, W, R>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_tb_forward<K, true, false, PD, W, R>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_tb_forward<K, false, true, PD, W, R>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_tb_forward<K, true, true, PD, W, R>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
     }
     return hipGetLastError();
+}
+
+// workgroup shapes (waves x rows per thread) and plane-prefetch depths
+constexpr int NSHAPE = 2;
+constexpr int SHAPE_W[NSHAPE] = {16, 8};
+constexpr int SHAPE_R[NSHAPE] = {1, 2};
+
+template <int K>
+hipError_t launch_k(const TbArgs &a, int cls, int shape, hipStream_t s)
+{
+    const int sh = shape % 10, pd = shape / 10;
+    if (sh == 1) {
+        if (pd == 2) return launch_kwrp<K, 8, 2, 2>(a, cls, s);
+        return launch_kwrp<K, 8, 2, 1>(a, cls, s);
+    }
+    if (pd == 2) return launch_kwrp<K, 16, 1, 2>(a, cls, s);
+    if (pd == 3) return launch_kwrp<K, 16, 1, 3>(a, cls, s);
+    return launch_kwrp<K, 16, 1, 1>(a, cls, s);
 }
 
 }  // namespace
 
 int tb_tile_x(int K) { return EX - 2 * K; }
 int tb_max_pml() { return TB_MAXP; }
-int tb_tile_y(int K)
+int tb_tile_y(int K, int shape)
 {
-    switch (K) {
-    case 1: return TbShape<1>::W * TbShape<1>::R - 2;
-    case 2: return TbShape<2>::W * TbShape<2>::R - 4;
-    case 3: return TbShape<3>::W * TbShape<3>::R - 6;
-    default: return TbShape<4>::W * TbShape<4>::R - 8;
-    }
+    const int sh = (shape % 10) < NSHAPE ? shape % 10 : 0;
+    return SHAPE_W[sh] * SHAPE_R[sh] - 2 * K;
 }
 
 // Tiles of class cls: bit 0 = x CPML slab in the extended footprint, bit 1 = y.
-hipError_t launch_tb_forward_class(const TbArgs &a, int K, int cls, hipStream_t s)
+hipError_t launch_tb_forward_class(const TbArgs &a, int K, int cls, int shape, hipStream_t s)
 {
     switch (K) {
-    case 1: return launch_k<1>(a, cls, s);
-    case 2: return launch_k<2>(a, cls, s);
-    case 3: return launch_k<3>(a, cls, s);
-    case 4: return launch_k<4>(a, cls, s);
+    case 1: return launch_k<1>(a, cls, shape, s);
+    case 2: return launch_k<2>(a, cls, shape, s);
+    case 3: return launch_k<3>(a, cls, shape, s);
+    case 4: return launch_k<4>(a, cls, shape, s);
     default: return hipErrorInvalidValue;
     }
 }

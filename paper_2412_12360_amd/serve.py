@@ -1,0 +1,399 @@
+"""Continuous-batching serving loop for FDTD forward and gradient solves.
+
+Requests of uneven grid sizes arrive at arbitrary times.  Each scheduler
+iteration
+  1. admits queued requests (FIFO) while the sum of the admitted requests'
+     exact workspace footprints (fdtd_footprint) stays within the HBM budget
+     and a slot is free; an admitted request gets its own handle, workspace
+     and one of several device streams, so its fields and interface record
+     stay resident until it finishes;
+  2. gives every active request whose previous chunk has finished its next
+     chunk of work: `chunk` more forward time steps, or, once a gradient
+     request's forward is complete, its time-reversed backward pass;
+  3. retires finished requests: copies their results out, releases the slot
+     and its memory, records the latency.
+Work of different requests runs on different streams and overlaps on the
+device; a request that arrives while others run is admitted as soon as memory
+and a slot are free.  A request that cannot be served (invalid problem,
+footprint above the whole budget, a device error) fails alone with an error
+result and frees its slot.
+
+The scheduler only talks to an executor object, so its policy is testable on
+the CPU with a mock executor that simulates durations.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import math
+import threading
+import time
+from typing import Callable, Deque, Dict, List, Optional
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    kind: str                      # "forward" or "gradient"
+    problem: object                # workloads.Problem
+    arrival: float = 0.0           # seconds after the start of the run (open loop)
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    kind: str
+    ok: bool
+    J: Optional[float] = None
+    trace: Optional[object] = None
+    grad: Optional[object] = None
+    recon: Optional[float] = None
+    error: Optional[str] = None
+    t_arrival: float = 0.0
+    t_admit: float = math.nan
+    t_done: float = math.nan
+    footprint: int = 0
+    cell_steps: int = 0
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.t_arrival
+
+
+class Executor:
+    """Interface the scheduler drives (one slot per admitted request)."""
+
+    def footprint(self, req: Request) -> int:
+        raise NotImplementedError
+
+    def start(self, req: Request):
+        """Create the request's solver; returns an opaque slot.  May raise."""
+        raise NotImplementedError
+
+    def forward(self, slot, nsteps: int) -> None:
+        """Enqueue nsteps forward steps (non-blocking)."""
+        raise NotImplementedError
+
+    def backward(self, slot) -> None:
+        """Enqueue the gradient pass (non-blocking)."""
+        raise NotImplementedError
+
+    def ready(self, slot) -> bool:
+        """True when everything enqueued for the slot has finished."""
+        raise NotImplementedError
+
+    def result(self, slot) -> dict:
+        """Host copies of the outputs (only after ready())."""
+        raise NotImplementedError
+
+    def release(self, slot) -> None:
+        raise NotImplementedError
+
+
+@dataclasses.dataclass
+class _Active:
+    req: Request
+    slot: object
+    footprint: int
+    t: int = 0
+    phase: str = "forward"        # forward -> backward -> done
+    t_admit: float = 0.0
+    cancel: bool = False
+
+
+class Scheduler:
+    def __init__(self, executor: Executor, budget_bytes: int, max_active: int = 32, chunk: int = 64,
+                 clock: Callable[[], float] = time.perf_counter):
+        if budget_bytes <= 0 or max_active <= 0 or chunk <= 0:
+            raise ValueError("budget, max_active and chunk must be positive")
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.max_active = int(max_active)
+        self.chunk = int(chunk)
+        self.clock = clock
+        self.queue: Deque[Request] = collections.deque()
+        self.active: Dict[int, _Active] = {}
+        self.results: Dict[int, Result] = {}
+        self.in_use = 0
+        self.peak_in_use = 0
+        self._t0 = None
+        self._lock = threading.Lock()
+        self._cancelled = set()
+
+    # ------------------------------------------------------------ clients
+    def now(self) -> float:
+        if self._t0 is None:
+            self._t0 = self.clock()
+        return self.clock() - self._t0
+
+    def submit(self, req: Request) -> None:
+        with self._lock:
+            self.queue.append(req)
+
+    def cancel(self, rid: int) -> None:
+        with self._lock:
+            self._cancelled.add(rid)
+
+    def idle(self) -> bool:
+        return not self.queue and not self.active
+
+    # --------------------------------------------------------- one iteration
+    def _fail(self, req: Request, msg: str, t_admit=math.nan, fp=0):
+        self.results[req.rid] = Result(rid=req.rid, kind=req.kind, ok=False, error=msg, t_arrival=req.arrival,
+                                       t_admit=t_admit, t_done=self.now(), footprint=fp)
+
+    def _admit(self) -> int:
+        n = 0
+        while True:
+            with self._lock:
+                if not self.queue or len(self.active) >= self.max_active:
+                    return n
+                req = self.queue[0]
+                if req.rid in self._cancelled:
+                    self.queue.popleft()
+                    self._fail(req, "cancelled")
+                    continue
+            try:
+                fp = int(self.ex.footprint(req))
+            except Exception as e:       # invalid problem: fails alone
+                with self._lock:
+                    self.queue.popleft()
+                self._fail(req, f"rejected: {e}")
+                continue
+            if fp > self.budget:
+                with self._lock:
+                    self.queue.popleft()
+                self._fail(req, f"footprint {fp} exceeds the HBM budget {self.budget}", fp=fp)
+                continue
+            if self.in_use + fp > self.budget:
+                return n                  # FIFO: wait for memory to free up
+            with self._lock:
+                self.queue.popleft()
+            t_admit = self.now()
+            try:
+                slot = self.ex.start(req)
+            except Exception as e:
+                self._fail(req, f"start failed: {e}", t_admit, fp)
+                continue
+            self.active[req.rid] = _Active(req=req, slot=slot, footprint=fp, t_admit=t_admit)
+            self.in_use += fp
+            self.peak_in_use = max(self.peak_in_use, self.in_use)
+            n += 1
+
+    def _retire(self, a: _Active, ok: bool, error: Optional[str] = None):
+        res = Result(rid=a.req.rid, kind=a.req.kind, ok=ok, error=error, t_arrival=a.req.arrival,
+                     t_admit=a.t_admit, footprint=a.footprint)
+        if ok:
+            try:
+                out = self.ex.result(a.slot)
+                res.J = out.get("J")
+                res.trace = out.get("trace")
+                res.grad = out.get("grad")
+                res.recon = out.get("recon")
+                pr = a.req.problem
+                res.cell_steps = pr.N * pr.T * (2 if a.req.kind == "gradient" else 1)
+            except Exception as e:
+                res.ok = False
+                res.error = f"result failed: {e}"
+        res.t_done = self.now()
+        try:
+            self.ex.release(a.slot)
+        finally:
+            self.in_use -= a.footprint
+            del self.active[a.req.rid]
+            self.results[a.req.rid] = res
+
+    def step(self) -> int:
+        """One scheduler iteration; returns how many actions it took."""
+        acted = self._admit()
+        for rid in list(self.active.keys()):
+            a = self.active[rid]
+            if rid in self._cancelled:
+                a.cancel = True
+            try:
+                if not self.ex.ready(a.slot):
+                    continue
+                if a.cancel:
+                    self._retire(a, False, "cancelled")
+                    acted += 1
+                    continue
+                T = a.req.problem.T
+                if a.phase == "forward" and a.t < T:
+                    n = min(self.chunk, T - a.t)
+                    self.ex.forward(a.slot, n)
+                    a.t += n
+                elif a.phase == "forward":
+                    if a.req.kind == "gradient":
+                        self.ex.backward(a.slot)
+                        a.phase = "backward"
+                    else:
+                        a.phase = "done"
+                        self._retire(a, True)
+                elif a.phase == "backward":
+                    a.phase = "done"
+                    self._retire(a, True)
+                acted += 1
+            except Exception as e:          # a device or API error fails only this request
+                if rid in self.active:
+                    self._retire(a, False, f"{type(e).__name__}: {e}")
+                acted += 1
+        return acted
+
+    # -------------------------------------------------------------- driver
+    def run(self, requests: List[Request], open_loop: bool = True, poll_s: float = 2e-4,
+            sleep: Callable[[float], None] = time.sleep) -> Dict[int, Result]:
+        """Feed `requests` by their arrival times (or all at once) and serve
+        until every one has a result."""
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        self.now()
+        while pending or not self.idle():
+            t = self.now()
+            while pending and (not open_loop or pending[0].arrival <= t):
+                r = pending.popleft()
+                if not open_loop:
+                    r = dataclasses.replace(r, arrival=t)
+                self.submit(r)
+            if self.step() == 0:
+                if pending and self.idle():
+                    sleep(max(0.0, min(pending[0].arrival - self.now(), 0.01)))
+                else:
+                    sleep(poll_s)
+        return self.results
+
+
+def summarize(results: Dict[int, Result], wall_s: float) -> dict:
+    ok = [r for r in results.values() if r.ok]
+    lat = sorted(r.latency for r in ok)
+
+    def pct(q):
+        if not lat:
+            return None
+        i = min(len(lat) - 1, max(0, int(math.ceil(q / 100.0 * len(lat))) - 1))
+        return lat[i]
+    cells = sum(r.cell_steps for r in ok)
+    return {
+        "requests": len(results), "ok": len(ok), "failed": len(results) - len(ok),
+        "wall_s": wall_s, "throughput_mcell_steps_s": cells / wall_s / 1e6 if wall_s > 0 else None,
+        "req_per_s": len(ok) / wall_s if wall_s > 0 else None,
+        "p50_latency_s": pct(50), "p99_latency_s": pct(99),
+        "mean_latency_s": sum(lat) / len(lat) if lat else None,
+    }
+
+
+# ------------------------------------------------------------ GPU executor
+
+class GpuExecutor(Executor):
+    """Slots are libfdtd handles (fdtd.Solver) on a pool of device streams.
+    Completion is tested with a device event recorded after each chunk."""
+
+    def __init__(self, n_streams: int = 8, time_block: int = 0, device: str = "cuda"):
+        import torch
+        from . import fdtd
+        self.torch = torch
+        self.fdtd = fdtd
+        self.device = torch.device(device)
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
+        self._next = 0
+        self.time_block = time_block
+
+    def footprint(self, req: Request) -> int:
+        return self.fdtd.footprint(req.problem, record=req.kind == "gradient", time_block=self.time_block) + 256
+
+    def start(self, req: Request):
+        st = self.streams[self._next % len(self.streams)]
+        self._next += 1
+        with self.torch.cuda.stream(st):
+            s = self.fdtd.Solver(req.problem, record=req.kind == "gradient", time_block=self.time_block,
+                                 device=str(self.device), stream=st)
+            slot = {"s": s, "ev": self.torch.cuda.Event(), "stream": st, "kind": req.kind,
+                    "trace": [], "grad": None, "recon": None}
+            slot["ev"].record(st)
+        return slot
+
+    def forward(self, slot, nsteps: int) -> None:
+        st = slot["stream"]
+        with self.torch.cuda.stream(st):
+            tr, J = slot["s"].forward(nsteps)
+            slot["trace"].append(tr)
+            slot["J"] = J
+            slot["ev"].record(st)
+
+    def backward(self, slot) -> None:
+        st = slot["stream"]
+        with self.torch.cuda.stream(st):
+            J = slot["J"].clone()
+            g, r = slot["s"].grad()
+            slot["J"] = J
+            slot["grad"], slot["recon"] = g, r
+            slot["ev"].record(st)
+
+    def ready(self, slot) -> bool:
+        return slot["ev"].query()
+
+    def result(self, slot) -> dict:
+        slot["stream"].synchronize()
+        out = {"J": float(slot["J"].item())}
+        if slot["trace"]:
+            out["trace"] = self.torch.cat(slot["trace"]).cpu().numpy()
+        if slot["grad"] is not None:
+            out["grad"] = slot["grad"].cpu().numpy()
+            out["recon"] = float(slot["recon"].item())
+        return out
+
+    def release(self, slot) -> None:
+        slot["stream"].synchronize()
+        slot["s"].close()
+        slot.clear()
+
+
+# ------------------------------------------------------------ mock executor
+
+class MockExecutor(Executor):
+    """CPU stand-in: work takes simulated time proportional to cell-steps on a
+    device that runs up to `lanes` slots at once; `clock` must be the same
+    virtual clock the scheduler reads.  Used to test the scheduler policy."""
+
+    def __init__(self, clock, rate_cells_per_s: float = 1e9, lanes: int = 4, fail_rids=(), bad_rids=(),
+                 bytes_per_cell: int = 100):
+        self.clock = clock
+        self.rate = rate_cells_per_s
+        self.lanes = lanes
+        self.fail_rids = set(fail_rids)      # device error during the forward
+        self.bad_rids = set(bad_rids)        # invalid problem (footprint raises)
+        self.bpc = bytes_per_cell
+        self.live = 0
+        self.log = []
+
+    def footprint(self, req: Request) -> int:
+        if req.rid in self.bad_rids:
+            raise ValueError("invalid problem")
+        return req.problem.N * self.bpc
+
+    def start(self, req: Request):
+        self.live += 1
+        self.log.append(("start", req.rid, self.clock.t))
+        return {"rid": req.rid, "busy_until": self.clock.t, "steps": 0, "req": req, "grad": False}
+
+    def _work(self, slot, cells):
+        slot["busy_until"] = max(slot["busy_until"], self.clock.t) + cells / self.rate * max(1, self.live) / self.lanes
+
+    def forward(self, slot, nsteps: int) -> None:
+        if slot["rid"] in self.fail_rids and slot["steps"] > 0:
+            raise RuntimeError("simulated device error")
+        slot["steps"] += nsteps
+        self._work(slot, slot["req"].problem.N * nsteps)
+
+    def backward(self, slot) -> None:
+        slot["grad"] = True
+        self._work(slot, 2 * slot["req"].problem.N * slot["req"].problem.T)
+
+    def ready(self, slot) -> bool:
+        return self.clock.t >= slot["busy_until"]
+
+    def result(self, slot) -> dict:
+        pr = slot["req"].problem
+        return {"J": float(pr.N * slot["steps"]), "grad": [1.0] if slot["grad"] else None}
+
+    def release(self, slot) -> None:
+        self.live -= 1
+        self.log.append(("release", slot["rid"], self.clock.t))
