@@ -81,6 +81,58 @@ def cpu_baseline(pr, target_s: float = 12.0):
             "sample": f"{pr.nx}x{pr.ny}x{pr.nz} grid, {n} FP64 time steps (steps 1..{n}) of the same problem"}
 
 
+def serving_bench(count: int, torch, seed_rate: float = 0.8):
+    """Serving mix: `count` requests of the Poisson mix recipe (edges U{64..256},
+    50% forward / 50% gradient, T = 8 x max edge, CPML 8).  Measures saturation
+    throughput one-at-a-time and with continuous batching (all queued at t=0),
+    then open-loop Poisson arrivals at 0.8 x the one-at-a-time request rate for
+    both systems, reporting p50/p99 latency."""
+    from paper_2412_12360_amd import serve
+    from paper_2412_12360_amd import workloads as W
+    descs = W.serving_mix(count=count, rate_hz=None)
+    probs = {rid: W.serving_request(e, k == "gradient", seed=1000 + rid, p=8, rid=rid) for (rid, e, k, _) in descs}
+    kinds = {rid: k for (rid, _, k, _) in descs}
+    budget = int(torch.cuda.mem_get_info()[0] * 0.8)
+
+    def run(max_active, streams, arrivals=None):
+        reqs = [serve.Request(rid=rid, kind=kinds[rid], problem=probs[rid],
+                              arrival=0.0 if arrivals is None else arrivals[i])
+                for i, rid in enumerate(sorted(probs))]
+        sch = serve.Scheduler(serve.GpuExecutor(n_streams=streams), budget_bytes=budget,
+                              max_active=max_active, chunk=64)
+        t0 = time.perf_counter()
+        res = sch.run(reqs, open_loop=arrivals is not None)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out = serve.summarize(res, wall)
+        out["peak_hbm_gb"] = round(sch.peak_in_use / 1e9, 2)
+        return out
+
+    run(1, 1)                                   # warm-up (code objects, allocator)
+    seq = run(1, 1)
+    bat = run(16, 8)
+    rate = seed_rate * seq["req_per_s"]
+    import numpy as np
+    rng = np.random.Generator(np.random.PCG64(8))
+    arr = list(np.cumsum(rng.exponential(1.0 / rate, size=count)))
+    seq_open = run(1, 1, arr)
+    bat_open = run(16, 8, arr)
+    r = lambda v: None if v is None else round(v, 4)
+    return {
+        "workload": f"{count} requests of the serving mix (edges U{{64..256}} per axis, 50% gradient, "
+                    f"T = 8 x max edge, CPML 8, eps_r U[1,12.25]; seeds 6/7/1000+rid)",
+        "one_at_a_time": {"throughput_mcell_steps_s": r(seq["throughput_mcell_steps_s"]),
+                          "req_per_s": r(seq["req_per_s"]), "wall_s": r(seq["wall_s"])},
+        "batched": {"throughput_mcell_steps_s": r(bat["throughput_mcell_steps_s"]),
+                    "req_per_s": r(bat["req_per_s"]), "wall_s": r(bat["wall_s"]),
+                    "peak_hbm_gb": bat["peak_hbm_gb"]},
+        "open_loop_rate_req_s": r(rate),
+        "one_at_a_time_open": {"p50_s": r(seq_open["p50_latency_s"]), "p99_s": r(seq_open["p99_latency_s"])},
+        "batched_open": {"p50_s": r(bat_open["p50_latency_s"]), "p99_s": r(bat_open["p99_latency_s"])},
+        "speedup_throughput": r(bat["throughput_mcell_steps_s"] / seq["throughput_mcell_steps_s"]),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +141,7 @@ def main():
     ap.add_argument("--time-block", type=int, default=0)
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving", type=int, default=0, help="requests of the serving mix to run (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -170,6 +223,9 @@ def main():
         }
         del g
         torch.cuda.empty_cache()
+
+    if args.serving > 0:
+        out["serving"] = serving_bench(args.serving, torch)
 
     if rank == 0 and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pr)

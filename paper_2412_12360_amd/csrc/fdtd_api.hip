@@ -69,10 +69,9 @@ struct fdtd_ctx {
     float *psi[2][3][4];
     int cur = 0;
     // adjoint state: fields, psi-bar E-type (in place), psi-bar H-type (ping-pong)
-    float *adj[6];
-    float *pbE[3][2];
-    float *pbH[2][3][2];
-    int hpar = 0;
+    float *adj[2][6];
+    float *pb[2][3][4];
+    int acur = 0, apar = 0;
     float *ce = nullptr, *inv_eps = nullptr, *d_design = nullptr;
     float *prof[2][3][3];
     float *amps[FDTD_MAX_SOURCES];
@@ -252,7 +251,7 @@ void build_tiles(const Geometry &G, int K, std::vector<int4> &out, int off[5][4]
     out.clear();
     for (int kk = 0; kk < 5; kk++)
         for (int c = 0; c < 4; c++) off[kk][c] = cnt[kk][c] = 0;
-    for (int kk = 1; kk <= K; kk++) {
+    for (int kk = 1; kk <= std::max(K, rev_halo()); kk++) {
         const int ZC = zchunk(G, kk);
         const auto xs = split_axis(G.nx, tb_tile_x(kk)), ys = split_axis(G.ny, tb_tile_y(kk, tb_shape()));
         std::vector<int4> cls[4];
@@ -317,22 +316,20 @@ size_t plan(fdtd_ctx *h, const fdtd_desc *d, const Geometry &G, int K, void *bas
     h->parts[1] = B.take(nparts);
     if (d->record) {
         h->rec = B.take((size_t)d->n_steps * G.R.per_step);
-        for (int q = 0; q < 6; q++) h->adj[q] = B.take(N);
-        for (int a = 0; a < 3; a++)
-            for (int q = 0; q < 2; q++) h->pbE[a][q] = G.p > 0 ? B.take(G.slab_n[a]) : nullptr;
+        for (int b = 0; b < 2; b++)
+            for (int q = 0; q < 6; q++) h->adj[b][q] = B.take(N);
         for (int b = 0; b < 2; b++)
             for (int a = 0; a < 3; a++)
-                for (int q = 0; q < 2; q++) h->pbH[b][a][q] = G.p > 0 ? B.take(G.slab_n[a]) : nullptr;
+                for (int q = 0; q < 4; q++) h->pb[b][a][q] = G.p > 0 ? B.take(G.slab_n[a]) : nullptr;
         h->gacc = B.take(G.design_cells);
     } else {
         h->rec = nullptr;
         h->gacc = nullptr;
-        for (int q = 0; q < 6; q++) h->adj[q] = nullptr;
-        for (int a = 0; a < 3; a++)
-            for (int q = 0; q < 2; q++) h->pbE[a][q] = nullptr;
-        for (int b = 0; b < 2; b++)
+        for (int b = 0; b < 2; b++) {
+            for (int q = 0; q < 6; q++) h->adj[b][q] = nullptr;
             for (int a = 0; a < 3; a++)
-                for (int q = 0; q < 2; q++) h->pbH[b][a][q] = nullptr;
+                for (int q = 0; q < 4; q++) h->pb[b][a][q] = nullptr;
+        }
     }
     return B.off + 256;
 }
@@ -368,22 +365,18 @@ Psi psi_of(fdtd_ctx *h, int b)
     return P;
 }
 
-Psi psibar_of(fdtd_ctx *h, int hb)
+Psi psibar_of(fdtd_ctx *h, int par)
 {
     Psi P;
-    for (int a = 0; a < 3; a++) {
-        P.a[a][0] = h->pbE[a][0];
-        P.a[a][1] = h->pbE[a][1];
-        P.a[a][2] = h->pbH[hb][a][0];
-        P.a[a][3] = h->pbH[hb][a][1];
-    }
+    for (int a = 0; a < 3; a++)
+        for (int q = 0; q < 4; q++) P.a[a][q] = h->pb[par][a][q];
     return P;
 }
 
-Fields adj_of(fdtd_ctx *h)
+Fields adj_of(fdtd_ctx *h, int buf)
 {
     Fields A;
-    for (int q = 0; q < 6; q++) A.c[q] = h->adj[q];
+    for (int q = 0; q < 6; q++) A.c[q] = h->adj[buf][q];
     return A;
 }
 
@@ -404,14 +397,14 @@ fdtd_status zero_adjoint(fdtd_ctx *h)
 {
     if (!h->desc.record) return FDTD_OK;
     const Geometry &G = h->geo;
-    for (int q = 0; q < 6; q++) HIPCHK(h, launch_fill(h->adj[q], G.N, 0.f, h->stream));
-    for (int a = 0; a < 3; a++)
-        for (int q = 0; q < 2; q++) {
-            if (h->pbE[a][q]) HIPCHK(h, launch_fill(h->pbE[a][q], G.slab_n[a], 0.f, h->stream));
-            for (int b = 0; b < 2; b++)
-                if (h->pbH[b][a][q]) HIPCHK(h, launch_fill(h->pbH[b][a][q], G.slab_n[a], 0.f, h->stream));
-        }
-    h->hpar = 0;
+    for (int b = 0; b < 2; b++) {
+        for (int q = 0; q < 6; q++) HIPCHK(h, launch_fill(h->adj[b][q], G.N, 0.f, h->stream));
+        for (int a = 0; a < 3; a++)
+            for (int q = 0; q < 4; q++)
+                if (h->pb[b][a][q]) HIPCHK(h, launch_fill(h->pb[b][a][q], G.slab_n[a], 0.f, h->stream));
+    }
+    h->acur = 0;
+    h->apar = 0;
     return FDTD_OK;
 }
 
@@ -514,13 +507,63 @@ fdtd_status reverse_step(fdtd_ctx *h, int n, int do_adj)
         else
             HIPCHK(h, launch_record_zero_e(h->g, F, G.R, h->stream));
     }
-    Fields A = adj_of(h);
+    Fields A = do_adj ? adj_of(h, h->acur) : Fields{};
     if (do_adj && G.D.ndet > 0) HIPCHK(h, launch_det_adjoint(h->g, F, A, G.D, h->wS, h->stream));
-    Psi Pc = psibar_of(h, h->hpar), Pn = psibar_of(h, h->hpar ^ 1);
+    Psi Pc = psibar_of(h, h->apar), Pn = psibar_of(h, h->apar ^ 1);
     HIPCHK(h, launch_bwd_a(h->g, F, A, Pc, n, 1, do_adj, do_adj ? h->gacc : nullptr, h->desc.design_lo,
                            h->desc.design_hi, h->stream));
     HIPCHK(h, launch_bwd_b(h->g, F, A, Pc, Pn, 1, do_adj, h->stream));
-    if (do_adj) h->hpar ^= 1;
+    if (do_adj) h->apar ^= 1;
+    return FDTD_OK;
+}
+
+// one reverse step n with the fused z-march kernel (all state ping-pong);
+// do_inv = 0 applies only the adjoint of the source-free step map
+fdtd_status reverse_fused(fdtd_ctx *h, int n, int do_inv, int do_adj, int with_det, float *gacc)
+{
+    const Geometry &G = h->geo;
+    RevArgs a;
+    a.g = h->g;
+    a.fin = fields_of(h, h->cur);
+    a.fout = fields_of(h, h->cur ^ 1);
+    a.ain = do_adj ? adj_of(h, h->acur) : Fields{};
+    a.aout = do_adj ? adj_of(h, h->acur ^ 1) : Fields{};
+    a.pin = psibar_of(h, h->apar);
+    a.pout = psibar_of(h, h->apar ^ 1);
+    a.n = n;
+    a.do_inv = do_inv;
+    a.do_adj = do_adj;
+    a.with_det = with_det && G.D.ndet > 0;
+    a.rec_h = (do_inv && G.p > 0) ? h->rec + (size_t)n * G.R.per_step : nullptr;
+    a.rec_e = (do_inv && G.p > 0 && n > 0) ? h->rec + (size_t)(n - 1) * G.R.per_step : nullptr;
+    a.R = G.R;
+    a.D = G.D;
+    for (int m = 0; m < FD_MAXDET; m++) a.wS[m] = h->wS[m];
+    a.gacc = gacc;
+    a.dlo = make_int3(h->desc.design_lo[0], h->desc.design_lo[1], h->desc.design_lo[2]);
+    a.dhi = make_int3(h->desc.design_hi[0], h->desc.design_hi[1], h->desc.design_hi[2]);
+    for (int ax = 0; ax < 3; ax++) a.profv[ax] = h->profv[ax];
+    a.xcd_remap = 1;
+    const int kt = rev_halo();   // the tile tables of halo K = 2 fit the reverse march
+    const bool par = h->side[0] != nullptr;
+    if (par) HIPCHK(h, hipEventRecord(h->fork, h->stream));
+    for (int c = 0; c < 4; c++) {
+        a.tiles = h->tiles + 2 * (size_t)h->tb_off[kt][c];
+        a.ntiles = h->tb_cnt[kt][c];
+        if (a.ntiles == 0) continue;
+        hipStream_t st = (par && c > 0) ? h->side[c - 1] : h->stream;
+        if (st != h->stream) HIPCHK(h, hipStreamWaitEvent(st, h->fork, 0));
+        HIPCHK(h, launch_tb_reverse_class(a, c, st));
+        if (st != h->stream) {
+            HIPCHK(h, hipEventRecord(h->join[c - 1], st));
+            HIPCHK(h, hipStreamWaitEvent(h->stream, h->join[c - 1], 0));
+        }
+    }
+    if (do_inv) h->cur ^= 1;
+    if (do_adj) {
+        h->acur ^= 1;
+        h->apar ^= 1;
+    }
     return FDTD_OK;
 }
 
@@ -738,7 +781,7 @@ fdtd_status fdtd_inverse(fdtd_handle h, int32_t n_steps)
     if (n_steps < 0 || n_steps > h->t) return fail(h, FDTD_E_STATE, "cannot undo %d steps at t = %d", n_steps, h->t);
     if (h->geo.p > 0 && !h->desc.record) return fail(h, FDTD_E_STATE, "inverse with a PML needs record = 1");
     for (int s = 0; s < n_steps; s++) {
-        fdtd_status st = reverse_step(h, h->t - 1, 0);
+        fdtd_status st = h->naive ? reverse_step(h, h->t - 1, 0) : reverse_fused(h, h->t - 1, 1, 0, 0, nullptr);
         if (st != FDTD_OK) return st;
         h->t -= 1;
     }
@@ -758,7 +801,7 @@ fdtd_status fdtd_grad(fdtd_handle h, float *dJ_deps, float *recon_err)
     if (st != FDTD_OK) return st;
     HIPCHK(h, launch_fill(h->gacc, G.design_cells, 0.f, h->stream));
     for (int n = h->T - 1; n >= 0; n--) {
-        st = reverse_step(h, n, 1);
+        st = h->naive ? reverse_step(h, n, 1) : reverse_fused(h, n, 1, 1, 1, h->gacc);
         if (st != FDTD_OK) return st;
     }
     HIPCHK(h, launch_interior_sumsq(h->g, fields_of(h, h->cur), h->parts[1], &np, h->stream));
@@ -818,7 +861,7 @@ fdtd_status fdtd_field_ptr(fdtd_handle h, int32_t which, int32_t comp, float **d
     if (which == 0) { *dev = h->fld[h->cur][comp]; return FDTD_OK; }
     if (which == 1) {
         if (!h->desc.record) return fail(h, FDTD_E_STATE, "no adjoint state without record = 1");
-        *dev = h->adj[comp];
+        *dev = h->adj[h->acur][comp];
         return FDTD_OK;
     }
     return fail(h, FDTD_E_INVALID, "which must be 0 or 1");
@@ -831,11 +874,11 @@ fdtd_status fdtd_state_arrays(fdtd_handle h, int32_t which, float **ptrs, size_t
     if (which != 0 && which != 1) return fail(h, FDTD_E_INVALID, "which must be 0 or 1");
     std::vector<std::pair<float *, size_t>> v;
     const Geometry &G = h->geo;
-    for (int q = 0; q < 6; q++) v.push_back({which == 0 ? h->fld[h->cur][q] : h->adj[q], (size_t)G.N});
+    for (int q = 0; q < 6; q++) v.push_back({which == 0 ? h->fld[h->cur][q] : h->adj[h->acur][q], (size_t)G.N});
     if (G.p > 0)
         for (int a = 0; a < 3; a++)
             for (int q = 0; q < 4; q++) {
-                float *p = which == 0 ? h->psi[h->cur][a][q] : (q < 2 ? h->pbE[a][q] : h->pbH[h->hpar][a][q - 2]);
+                float *p = which == 0 ? h->psi[h->cur][a][q] : h->pb[h->apar][a][q];
                 v.push_back({p, (size_t)G.slab_n[a]});
             }
     if ((int)v.size() > cap) return fail(h, FDTD_E_INVALID, "capacity %d < %zu arrays", cap, v.size());
@@ -852,12 +895,14 @@ fdtd_status fdtd_linear_steps(fdtd_handle h, int32_t n, int32_t adjoint)
     if (!adjoint) return advance(h, 0, n, 0, 0, 0);
     for (int s = 0; s < n; s++) {
         fdtd_status st;
-        {
-            Fields F = fields_of(h, h->cur), A = adj_of(h);
-            Psi Pc = psibar_of(h, h->hpar), Pn = psibar_of(h, h->hpar ^ 1);
+        if (!h->naive) {
+            st = reverse_fused(h, 0, 0, 1, 0, nullptr);
+        } else {
+            Fields F = fields_of(h, h->cur), A = adj_of(h, h->acur);
+            Psi Pc = psibar_of(h, h->apar), Pn = psibar_of(h, h->apar ^ 1);
             HIPCHK(h, launch_bwd_a(h->g, F, A, Pc, 0, 0, 1, nullptr, h->desc.design_lo, h->desc.design_hi, h->stream));
             HIPCHK(h, launch_bwd_b(h->g, F, A, Pc, Pn, 0, 1, h->stream));
-            h->hpar ^= 1;
+            h->apar ^= 1;
             st = FDTD_OK;
         }
         if (st != FDTD_OK) return st;

@@ -168,3 +168,26 @@ hipError_t launch_tb_forward_class(const TbArgs &a, int K, int cls, int shape, h
 int tb_tile_x(int K);
 int tb_tile_y(int K, int shape);
 int tb_max_pml();
+
+// fused reverse step (inverse + adjoint) as a z-march, tile halo rev_halo()
+struct RevArgs {
+    Grid g;
+    Fields fin, fout;        // forward state s_{n+1} -> s_n (interior cells written)
+    Fields ain, aout;        // adjoint fields
+    Psi pin, pout;           // CPML auxiliaries of the adjoint (all four per slab axis)
+    int n;                   // forward step being reversed
+    int do_inv, do_adj, with_det;
+    const float *rec_h;      // record of step n (H on the low faces) or nullptr
+    const float *rec_e;      // record of step n-1 (E on the high faces) or nullptr (E^0 = 0)
+    RecGeom R;
+    Detectors D;
+    float wS[FD_MAXDET];     // S * detector weight
+    float *gacc;             // dJ/dd accumulator over the design box (or nullptr)
+    int3 dlo, dhi;
+    const int4 *tiles;
+    int ntiles;
+    const float4 *profv[3];
+    int xcd_remap;
+};
+hipError_t launch_tb_reverse_class(const RevArgs &a, int cls, hipStream_t s);
+int rev_halo();

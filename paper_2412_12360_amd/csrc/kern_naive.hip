@@ -236,9 +236,9 @@ __global__ __launch_bounds__(256) void k_bwd_a(Grid g, Fields F, Fields A, Psi P
 }
 
 // ---------------------------------------------------------- reverse, phase B
-// psibar_E <- b (psibar_E + w) in place; inverse H on the interior:
-// H^{n-1/2} = H^{n+1/2} + S curl E^n; adjoint E: Ebar -= S C^T Hbar, CPML
-// wrapped, psibar_H read from `Pc` and written updated to `Pn`.
+// psibar <- b (psibar + w), read from `Pc`, written to `Pn`; inverse H on
+// the interior: H^{n-1/2} = H^{n+1/2} + S curl E^n; adjoint E:
+// Ebar -= S C^T Hbar, CPML wrapped.
 __global__ __launch_bounds__(256) void k_bwd_b(Grid g, Fields F, Fields A, Psi Pc, Psi Pn, int do_inv,
                                               int do_adj)
 {
@@ -248,7 +248,7 @@ __global__ __launch_bounds__(256) void k_bwd_b(Grid g, Fields F, Fields A, Psi P
     if (i >= g.nx || j >= g.ny) return;
     const long long c = cidx(g, i, j, k);
     if (do_adj && g.p > 0) {
-        // E-type psibar: own cell, before Ebar changes
+        // E-type psibar of this cell into the next buffer, before Ebar changes
         const bool hq[3] = {held_ex(i, j, k), held_ey(i, j, k), held_ez(i, j, k)};
         const float ce = g.ce[c];
         const int cc[3] = {i, j, k};
@@ -260,14 +260,10 @@ __global__ __launch_bounds__(256) void k_bwd_b(Grid g, Fields F, Fields A, Psi P
             const float b = g.prof[0][ax][0][cc[ax]];
             // idx 0: E comp (ax+1)%3, sign -, idx 1: E comp (ax+2)%3, sign +
             const int q0 = (ax + 1) % 3, q1 = (ax + 2) % 3;
-            if (!hq[q0]) {
-                const float w = -1.f * (ce * A.c[q0][c]);
-                Pc.a[ax][0][si] = b * (Pc.a[ax][0][si] + w);
-            }
-            if (!hq[q1]) {
-                const float w = 1.f * (ce * A.c[q1][c]);
-                Pc.a[ax][1][si] = b * (Pc.a[ax][1][si] + w);
-            }
+            const float w0 = -1.f * (ce * A.c[q0][c]);
+            const float w1 = 1.f * (ce * A.c[q1][c]);
+            Pn.a[ax][0][si] = hq[q0] ? Pc.a[ax][0][si] : b * (Pc.a[ax][0][si] + w0);
+            Pn.a[ax][1][si] = hq[q1] ? Pc.a[ax][1][si] : b * (Pc.a[ax][1][si] + w1);
         }
     }
     if (do_inv && in_interior(g, i, j, k)) {

@@ -1,0 +1,496 @@
+// Fused reverse step as a z-march: the inverse update of the interior (arXiv
+// 2412.12360, section 2.2) together with the hand-written adjoint of the
+// forward step, the detector adjoint source and the replay of the interface
+// record, in one pass over the grid per reverse step.
+//
+// Reverse step n maps the forward state s_{n+1} = (E^{n+1}, H^{n+1/2}) to s_n
+// on the interior I = [p, n-p)^3 and the adjoint of s_{n+1} to the adjoint of
+// s_n.  Per cell it is the same arithmetic, in the same order, as the
+// per-cell phases k_bwd_a / k_bwd_b (and bitwise equal to them):
+//   phase A: dJ/dd += Ebar' . curl H^{n+1/2};  E^n = E^{n+1} - src_n - S/eps curl H^{n+1/2};
+//            Hbar += C(S/eps Ebar') with the transposed CPML (coefficients Q)
+//   phase B: psibar_E <- b (psibar_E + w);  H^{n-1/2} = H^{n+1/2} + S curl E^n;
+//            Ebar -= S C^T Hbar with the transposed CPML (coefficients R);
+//            psibar_H <- b (psibar_H + w)
+// Phase A at a cell reads H at -1 and Q at +1; phase B reads E^n at +1 and R
+// at -1, so a workgroup computes a tile with a 2-cell halo and marches up in
+// z with phase A one plane behind the fetch and phase B two planes behind.
+// The four x/y exchanges of a plane (H, Q, E^n, R) share one LDS round.
+// Record values replace the fields on the PML-side layers (H on the low
+// faces from step n, E^n on the high faces from step n-1) as they are read.
+// All state is read from one buffer set and written to the other.
+#include "fdtd_internal.h"
+
+namespace {
+
+constexpr int EX = 64;
+constexpr int W = 16;
+constexpr int EY = W;
+constexpr int HALO = 2;
+
+__device__ __forceinline__ int remap_xcd_r(int b, int nb)
+{
+    const int q = nb / 8, rem = nb % 8;
+    const int xcd = b % 8, slot = b / 8;
+    return xcd < rem ? xcd * (q + 1) + slot : rem * (q + 1) + (xcd - rem) * q + slot;
+}
+
+template <bool XP, bool YP> struct PsiB {
+    float z[4];
+    float x[XP ? 4 : 1];
+    float y[YP ? 4 : 1];
+};
+
+// one plane of inputs of a column
+template <bool XP, bool YP> struct RPlane {
+    float e[3], h[3], ce, ae[3], ah[3];
+    PsiB<XP, YP> pb;
+};
+
+template <bool XP, bool YP>
+__global__ __launch_bounds__(EX *W) void k_tb_reverse(RevArgs A)
+{
+    __shared__ float sH[3][EY][EX];
+    __shared__ float sQ[4][EY][EX];
+    __shared__ float sEn[3][EY][EX];
+    __shared__ float sR[4][EY][EX];
+    __shared__ float sGz[2 * 64][6];
+
+    const Grid &g = A.g;
+    const int nx = g.nx, ny = g.ny, nz = g.nz, p = g.p;
+    const unsigned nxy = (unsigned)g.nxy;
+    const float S = g.S;
+    for (int e = threadIdx.x; e < 2 * p; e += blockDim.x) {
+        const int kk = e < p ? e : nz - 2 * p + e;
+        const float4 gE = A.profv[2][2 * kk], gH = A.profv[2][2 * kk + 1];
+        sGz[e][0] = gE.x; sGz[e][1] = gE.y; sGz[e][2] = gE.z;
+        sGz[e][3] = gH.x; sGz[e][4] = gH.y; sGz[e][5] = gH.z;
+    }
+    __syncthreads();
+
+    int b = blockIdx.x;
+    if (A.xcd_remap) b = remap_xcd_r(b, gridDim.x);
+    const int4 tl = A.tiles[2 * b], tz = A.tiles[2 * b + 1];
+    const int x0 = tl.x, x1 = tl.y, y0 = tl.z, y1 = tl.w, z0 = tz.x, z1 = tz.y;
+    const int lane = threadIdx.x & (EX - 1);
+    const int row = threadIdx.x / EX;
+    const int x = x0 - HALO + lane;
+    const int y = y0 - HALO + row;
+    const bool incol = x >= 0 && x < nx && y >= 0 && y < ny;
+    const bool own = x >= x0 && x < x1 && y >= y0 && y < y1;
+    const int xc = x < 0 ? 0 : (x >= nx ? nx - 1 : x);
+    const int yc = y < 0 ? 0 : (y >= ny ? ny - 1 : y);
+    const unsigned off = (unsigned)yc * (unsigned)nx + (unsigned)xc;
+    const bool icol = p == 0 ? incol : (x >= p && x < nx - p && y >= p && y < ny - p);
+    const bool wx = x >= p && x < nx - p, wy = y >= p && y < ny - p;
+    const int sx = (XP && incol) ? slab_coord(x, nx, p) : -1;
+    const int sy = (YP && incol) ? slab_coord(y, ny, p) : -1;
+    const unsigned soff_x = sx >= 0 ? (unsigned)yc * (unsigned)(2 * p) + (unsigned)sx : 0u;
+    const unsigned soff_y = sy >= 0 ? (unsigned)sy * (unsigned)nx + (unsigned)xc : 0u;
+    float4 gxE = make_float4(1.f, 0.f, 1.f, 0.f), gxH = gxE, gyE = gxE, gyH = gxE;
+    if constexpr (XP) {
+        if (sx >= 0) { gxE = A.profv[0][2 * x]; gxH = A.profv[0][2 * x + 1]; }
+    }
+    if constexpr (YP) {
+        if (sy >= 0) { gyE = A.profv[1][2 * y]; gyH = A.profv[1][2 * y + 1]; }
+    }
+    const bool in_design_xy = x >= A.dlo.x && x < A.dhi.x && y >= A.dlo.y && y < A.dhi.y;
+    const int ddx = A.dhi.x - A.dlo.x, ddy = A.dhi.y - A.dlo.y;
+
+    // ---------------------------------------------------------- plane fetch
+    auto load = [&](int t, RPlane<XP, YP> &P) {
+        const bool tin = t >= 0 && t < nz;
+        const bool v = tin && incol;
+        const unsigned c = ((unsigned)(tin ? t : 0) * nxy + off) * 4u;
+        auto ld = [&](const float *base) { return *(const float *)((const char *)base + c); };
+#pragma unroll
+        for (int q = 0; q < 3; q++) {
+            const float e = ld(A.fin.c[q]), h = ld(A.fin.c[3 + q]);
+            P.e[q] = v ? e : 0.f;
+            P.h[q] = v ? h : 0.f;
+        }
+        {
+            const float cc = ld(g.ce);
+            P.ce = v ? cc : 0.f;
+        }
+        if (A.do_adj) {
+#pragma unroll
+            for (int q = 0; q < 3; q++) {
+                const float e = ld(A.ain.c[q]), h = ld(A.ain.c[3 + q]);
+                P.ae[q] = v ? e : 0.f;
+                P.ah[q] = v ? h : 0.f;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 3; q++) { P.ae[q] = 0.f; P.ah[q] = 0.f; }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; q++) P.pb.z[q] = 0.f;
+        if constexpr (XP) {
+#pragma unroll
+            for (int q = 0; q < 4; q++) P.pb.x[q] = 0.f;
+        }
+        if constexpr (YP) {
+#pragma unroll
+            for (int q = 0; q < 4; q++) P.pb.y[q] = 0.f;
+        }
+        if (A.do_adj && p > 0 && tin) {
+            const int szt = slab_coord(t, nz, p);
+            if (szt >= 0) {
+                const unsigned zi = (unsigned)szt * nxy + off;
+#pragma unroll
+                for (int q = 0; q < 4; q++) P.pb.z[q] = A.pin.a[2][q][zi];
+            }
+            if constexpr (XP) {
+                const unsigned xi = (unsigned)t * (unsigned)ny * (unsigned)(2 * p) + soff_x;
+#pragma unroll
+                for (int q = 0; q < 4; q++) P.pb.x[q] = A.pin.a[0][q][xi];
+            }
+            if constexpr (YP) {
+                const unsigned yi = (unsigned)t * (unsigned)(2 * p) * (unsigned)nx + soff_y;
+#pragma unroll
+                for (int q = 0; q < 4; q++) P.pb.y[q] = A.pin.a[1][q][yi];
+            }
+        }
+        // H^{n+1/2} on the low-face layers comes from the record of step n
+        if (A.rec_h && v && t >= p - 1 && t < nz - p) {
+            const bool wz = t >= p;
+            if (t == p - 1 && wx && wy) {
+                const long long e = A.R.off[4] + (long long)(y - p) * A.R.Lu[2] + (x - p);
+                const long long fs = (long long)A.R.Lu[2] * A.R.Lv[2];
+                P.h[0] = A.rec_h[e];
+                P.h[1] = A.rec_h[e + fs];
+            }
+            if (wz && x == p - 1 && wy) {
+                const long long e = A.R.off[0] + (long long)(t - p) * A.R.Lu[0] + (y - p);
+                const long long fs = (long long)A.R.Lu[0] * A.R.Lv[0];
+                P.h[1] = A.rec_h[e];
+                P.h[2] = A.rec_h[e + fs];
+            }
+            if (wz && y == p - 1 && wx) {
+                const long long e = A.R.off[2] + (long long)(t - p) * A.R.Lu[1] + (x - p);
+                const long long fs = (long long)A.R.Lu[1] * A.R.Lv[1];
+                P.h[2] = A.rec_h[e];
+                P.h[0] = A.rec_h[e + fs];
+            }
+        }
+        // detector adjoint source: dJ/dE^{n+1}, dJ/dH^{n+1/2}
+        if (A.do_adj && A.with_det && v) {
+            for (int m = 0; m < A.D.ndet; m++) {
+                if (t != A.D.k[m] || x < A.D.i0[m] || x >= A.D.i1[m] || y < A.D.j0[m] || y >= A.D.j1[m]) continue;
+                const float sw = A.wS[m];
+                P.ae[0] = fmaf(sw, P.h[1], P.ae[0]);
+                P.ae[1] = fmaf(-sw, P.h[0], P.ae[1]);
+                P.ah[1] = fmaf(sw, P.e[0], P.ah[1]);
+                P.ah[0] = fmaf(-sw, P.e[1], P.ah[0]);
+            }
+        }
+    };
+
+    // adjoint coefficients of the six E pairs of a column at plane k:
+    // 0: Ey along z (+), 1: Ez along y (-), 2: Ex along z (-), 3: Ez along x (+),
+    // 4: Ex along y (+), 5: Ey along x (-)
+    auto qcoef = [&](const RPlane<XP, YP> &P, int k, float Q[6]) {
+        const bool live = incol && k >= 0 && k < nz;
+        const bool hex = y == 0 || k == 0, hey = x == 0 || k == 0, hez = x == 0 || y == 0;
+        const float cex = P.ce * P.ae[0], cey = P.ce * P.ae[1], cez = P.ce * P.ae[2];
+        float q0 = 1.f * cey, q1 = -1.f * cez, q2 = -1.f * cex, q3 = 1.f * cez, q4 = 1.f * cex, q5 = -1.f * cey;
+        const int sz = (p > 0 && k >= 0 && k < nz) ? slab_coord(k, nz, p) : -1;
+        if (sz >= 0) {
+            const float a = sGz[sz][1], kv = sGz[sz][2];
+            q0 = cpml_adj_coef(q0, P.pb.z[1], a, kv);
+            q2 = cpml_adj_coef(q2, P.pb.z[0], a, kv);
+        }
+        if constexpr (XP) {
+            if (sx >= 0) {
+                q3 = cpml_adj_coef(q3, P.pb.x[1], gxE.y, gxE.z);
+                q5 = cpml_adj_coef(q5, P.pb.x[0], gxE.y, gxE.z);
+            }
+        }
+        if constexpr (YP) {
+            if (sy >= 0) {
+                q1 = cpml_adj_coef(q1, P.pb.y[0], gyE.y, gyE.z);
+                q4 = cpml_adj_coef(q4, P.pb.y[1], gyE.y, gyE.z);
+            }
+        }
+        Q[0] = (live && !hey) ? q0 : 0.f;
+        Q[1] = (live && !hez) ? q1 : 0.f;
+        Q[2] = (live && !hex) ? q2 : 0.f;
+        Q[3] = (live && !hez) ? q3 : 0.f;
+        Q[4] = (live && !hex) ? q4 : 0.f;
+        Q[5] = (live && !hey) ? q5 : 0.f;
+    };
+
+    // adjoint coefficients of the six H pairs: 0: Hy along z (-S), 1: Hz along y (+S),
+    // 2: Hz along x (-S), 3: Hx along z (+S), 4: Hx along y (-S), 5: Hy along x (+S)
+    auto rcoef = [&](const float ah[3], const PsiB<XP, YP> &pb, int k, float Rr[6]) {
+        const bool live = incol && k >= 0 && k < nz;
+        const float sx_ = S * ah[0], sy_ = S * ah[1], sz_ = S * ah[2];
+        float r0 = -1.f * sy_, r1 = 1.f * sz_, r2 = -1.f * sz_, r3 = 1.f * sx_, r4 = -1.f * sx_, r5 = 1.f * sy_;
+        const int sz = (p > 0 && k >= 0 && k < nz) ? slab_coord(k, nz, p) : -1;
+        if (sz >= 0) {
+            const float a = sGz[sz][4], kv = sGz[sz][5];
+            r0 = cpml_adj_coef(r0, pb.z[3], a, kv);
+            r3 = cpml_adj_coef(r3, pb.z[2], a, kv);
+        }
+        if constexpr (XP) {
+            if (sx >= 0) {
+                r2 = cpml_adj_coef(r2, pb.x[3], gxH.y, gxH.z);
+                r5 = cpml_adj_coef(r5, pb.x[2], gxH.y, gxH.z);
+            }
+        }
+        if constexpr (YP) {
+            if (sy >= 0) {
+                r1 = cpml_adj_coef(r1, pb.y[2], gyH.y, gyH.z);
+                r4 = cpml_adj_coef(r4, pb.y[3], gyH.y, gyH.z);
+            }
+        }
+        Rr[0] = live ? r0 : 0.f; Rr[1] = live ? r1 : 0.f; Rr[2] = live ? r2 : 0.f;
+        Rr[3] = live ? r3 : 0.f; Rr[4] = live ? r4 : 0.f; Rr[5] = live ? r5 : 0.f;
+    };
+
+    // ------------------------------------------------------------ pipeline
+    // Pa: inputs of plane a = t-1; b*: plane b = t-2 (E^n, H^{n+1/2}, Ebar',
+    // Hbar_new, S/eps, psibar); Rz: R of plane b-1 (z pairs); Hm: H^{n+1/2}
+    // x,y of plane a-1.  Q of plane a and R of plane b are recomputed from
+    // these rather than carried, which keeps the march within 128 VGPRs.
+    RPlane<XP, YP> Pa;
+    float bEn[3] = {0.f, 0.f, 0.f}, bH[3] = {0.f, 0.f, 0.f}, bAe[3] = {0.f, 0.f, 0.f}, bAh[3] = {0.f, 0.f, 0.f};
+    float bCe = 0.f;
+    PsiB<XP, YP> bPb;
+#pragma unroll
+    for (int q = 0; q < 4; q++) bPb.z[q] = 0.f;
+    if constexpr (XP) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) bPb.x[q] = 0.f;
+    }
+    if constexpr (YP) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) bPb.y[q] = 0.f;
+    }
+    float Rz0 = 0.f, Rz3 = 0.f;     // R of plane b-1: Hy along z, Hx along z
+    float Hm0 = 0.f, Hm1 = 0.f;     // Hx, Hy of plane a-1
+
+    const int zs = z0 - HALO;
+    load(zs - 1, Pa);               // plane a = zs - 1 (zero unless in the grid)
+
+    for (int t = zs; t < z1 + HALO; t++) {
+        const int a = t - 1, bpl = t - 2;
+        RPlane<XP, YP> L;
+        load(t, L);
+        float Qa[6], bR[6];
+        qcoef(Pa, a, Qa);
+        rcoef(bAh, bPb, bpl, bR);
+
+        // ---- one LDS round: H(a), Q(a), E^n(b), R(b)
+#pragma unroll
+        for (int q = 0; q < 3; q++) sH[q][row][lane] = Pa.h[q];
+        sQ[0][row][lane] = Qa[1];   // Ez along y
+        sQ[1][row][lane] = Qa[3];   // Ez along x
+        sQ[2][row][lane] = Qa[4];   // Ex along y
+        sQ[3][row][lane] = Qa[5];   // Ey along x
+#pragma unroll
+        for (int q = 0; q < 3; q++) sEn[q][row][lane] = bEn[q];
+        sR[0][row][lane] = bR[1];   // Hz along y
+        sR[1][row][lane] = bR[2];   // Hz along x
+        sR[2][row][lane] = bR[4];   // Hx along y
+        sR[3][row][lane] = bR[5];   // Hy along x
+        __syncthreads();
+        const int ru = row + 1 < EY ? row + 1 : row, rd = row > 0 ? row - 1 : row;
+        const int lr = lane + 1 < EX ? lane + 1 : lane, ll = lane > 0 ? lane - 1 : lane;
+
+        // ---------------------------------------------------- phase A at plane a
+        float aEn[3], aAh[3];
+        {
+            const bool kin = a >= 0 && a < nz;
+            const bool interior = icol && kin && (p == 0 || (a >= p && a < nz - p));
+            const float hx = Pa.h[0], hy = Pa.h[1], hz = Pa.h[2];
+            const float hz_y = sH[2][rd][lane], hx_y = sH[0][rd][lane];
+            const float hz_x = sH[2][row][ll], hy_x = sH[1][row][ll];
+            const float dy_hz = hz - hz_y, dz_hy = hy - Hm1;
+            const float dz_hx = hx - Hm0, dx_hz = hz - hz_x;
+            const float dx_hy = hy - hy_x, dy_hx = hx - hx_y;
+            const bool hex = y == 0 || a == 0, hey = x == 0 || a == 0, hez = x == 0 || y == 0;
+            if (A.do_inv && interior) {
+                if (A.do_adj && A.gacc && own && a >= z0 && a < z1 && in_design_xy && a >= A.dlo.z && a < A.dhi.z) {
+                    const long long dc = ((long long)(a - A.dlo.z) * ddy + (y - A.dlo.y)) * ddx + (x - A.dlo.x);
+                    float acc = A.gacc[dc];
+                    if (!hex) acc = fmaf(Pa.ae[0], dy_hz - dz_hy, acc);
+                    if (!hey) acc = fmaf(Pa.ae[1], dz_hx - dx_hz, acc);
+                    if (!hez) acc = fmaf(Pa.ae[2], dx_hy - dy_hx, acc);
+                    A.gacc[dc] = acc;
+                }
+                float ex = Pa.e[0], ey = Pa.e[1], ez = Pa.e[2];
+                for (int s = 0; s < g.nsrc; s++) {
+                    if (a != g.sk[s]) continue;
+                    if (g.skind[s] == 0 && (x != g.si[s] || y != g.sj[s])) continue;
+                    const float Am = g.samp[s][A.n];
+                    if (g.scomp[s] == 0 && !hex) ex = ex - Am;
+                    if (g.scomp[s] == 1 && !hey) ey = ey - Am;
+                    if (g.scomp[s] == 2 && !hez) ez = ez - Am;
+                }
+                const float ce = Pa.ce;
+                if (!hex) ex = e_unupdate(ex, ce, dy_hz, dz_hy);
+                if (!hey) ey = e_unupdate(ey, ce, dz_hx, dx_hz);
+                if (!hez) ez = e_unupdate(ez, ce, dx_hy, dy_hx);
+                aEn[0] = ex; aEn[1] = ey; aEn[2] = ez;
+            } else {
+                aEn[0] = Pa.e[0]; aEn[1] = Pa.e[1]; aEn[2] = Pa.e[2];
+                if (A.do_inv && p > 0 && incol && kin) {
+                    // E^n on the high-face layers from the record of step n-1 (E^0 = 0)
+                    const bool wz = a >= p && a < nz - p;
+                    if (a == nz - p && wx && wy) {
+                        const long long e = A.R.off[5] + (long long)(y - p) * A.R.Lu[2] + (x - p);
+                        const long long fs = (long long)A.R.Lu[2] * A.R.Lv[2];
+                        aEn[0] = A.rec_e ? A.rec_e[e] : 0.f;
+                        aEn[1] = A.rec_e ? A.rec_e[e + fs] : 0.f;
+                    }
+                    if (wz && x == nx - p && wy) {
+                        const long long e = A.R.off[1] + (long long)(a - p) * A.R.Lu[0] + (y - p);
+                        const long long fs = (long long)A.R.Lu[0] * A.R.Lv[0];
+                        aEn[1] = A.rec_e ? A.rec_e[e] : 0.f;
+                        aEn[2] = A.rec_e ? A.rec_e[e + fs] : 0.f;
+                    }
+                    if (wz && y == ny - p && wx) {
+                        const long long e = A.R.off[3] + (long long)(a - p) * A.R.Lu[1] + (x - p);
+                        const long long fs = (long long)A.R.Lu[1] * A.R.Lv[1];
+                        aEn[2] = A.rec_e ? A.rec_e[e] : 0.f;
+                        aEn[0] = A.rec_e ? A.rec_e[e + fs] : 0.f;
+                    }
+                }
+            }
+            if (!(incol && kin)) { aEn[0] = aEn[1] = aEn[2] = 0.f; }
+            if (A.do_adj) {
+                float Qt[6];
+                qcoef(L, t, Qt);
+                const float qa = Qa[0] - Qt[0];
+                const float qb = Qa[1] - sQ[0][ru][lane];
+                const float qc = Qa[2] - Qt[2];
+                const float qd = Qa[3] - sQ[1][row][lr];
+                const float qe = Qa[4] - sQ[2][ru][lane];
+                const float qf = Qa[5] - sQ[3][row][lr];
+                aAh[0] = Pa.ah[0] + (qa + qb);
+                aAh[1] = Pa.ah[1] + (qc + qd);
+                aAh[2] = Pa.ah[2] + (qe + qf);
+            } else {
+                aAh[0] = aAh[1] = aAh[2] = 0.f;
+            }
+        }
+
+        // ---------------------------------------------------- phase B at plane b
+        {
+            const bool kin = bpl >= 0 && bpl < nz;
+            const bool interior = icol && kin && (p == 0 || (bpl >= p && bpl < nz - p));
+            const bool hex = y == 0 || bpl == 0, hey = x == 0 || bpl == 0, hez = x == 0 || y == 0;
+            const bool store = own && bpl >= z0 && bpl < z1;
+            if (store) {
+                const unsigned c = ((unsigned)bpl * nxy + off) * 4u;
+                auto st = [&](float *base, float v) { *(float *)((char *)base + c) = v; };
+                if (A.do_inv && interior) {
+                    const float ex = bEn[0], ey = bEn[1], ez = bEn[2];
+                    const float ey_x = sEn[1][row][lr], ez_x = sEn[2][row][lr];
+                    const float ex_y = sEn[0][ru][lane], ez_y = sEn[2][ru][lane];
+                    const float ex_z = aEn[0], ey_z = aEn[1];
+#pragma unroll
+                    for (int q = 0; q < 3; q++) st(A.fout.c[q], bEn[q]);
+                    st(A.fout.c[3], h_unupdate(bH[0], S, ez_y - ez, ey_z - ey));
+                    st(A.fout.c[4], h_unupdate(bH[1], S, ex_z - ex, ez_x - ez));
+                    st(A.fout.c[5], h_unupdate(bH[2], S, ey_x - ey, ex_y - ex));
+                }
+                if (A.do_adj) {
+                    // adjoint E with the transposed H pairs
+                    float ex = bAe[0], ey = bAe[1], ez = bAe[2];
+                    if (!hex) {
+                        const float ra = Rz0 - bR[0];
+                        const float rb = sR[0][rd][lane] - bR[1];
+                        ex = ex + (ra + rb);
+                    }
+                    if (!hey) {
+                        const float ra = sR[1][row][ll] - bR[2];
+                        const float rb = Rz3 - bR[3];
+                        ey = ey + (ra + rb);
+                    }
+                    if (!hez) {
+                        const float ra = sR[2][rd][lane] - bR[4];
+                        const float rb = sR[3][row][ll] - bR[5];
+                        ez = ez + (ra + rb);
+                    }
+                    st(A.aout.c[0], ex); st(A.aout.c[1], ey); st(A.aout.c[2], ez);
+#pragma unroll
+                    for (int q = 0; q < 3; q++) st(A.aout.c[3 + q], bAh[q]);
+                    // psibar updates of the slab cells
+                    if (p > 0) {
+                        const float ce = bCe;
+                        const int szb = slab_coord(bpl, nz, p);
+                        if (szb >= 0) {
+                            const unsigned zi = (unsigned)szb * nxy + off;
+                            const float bE = sGz[szb][0], bHh = sGz[szb][3];
+                            // z idx 0: Ex (-), idx 1: Ey (+); idx 2: Hx (+S), idx 3: Hy (-S)
+                            const float w0 = -1.f * (ce * bAe[0]), w1 = 1.f * (ce * bAe[1]);
+                            A.pout.a[2][0][zi] = hex ? bPb.z[0] : bE * (bPb.z[0] + w0);
+                            A.pout.a[2][1][zi] = hey ? bPb.z[1] : bE * (bPb.z[1] + w1);
+                            A.pout.a[2][2][zi] = bHh * (bPb.z[2] + 1.f * (S * bAh[0]));
+                            A.pout.a[2][3][zi] = bHh * (bPb.z[3] + -1.f * (S * bAh[1]));
+                        }
+                        if constexpr (XP) {
+                            if (sx >= 0) {
+                                const unsigned xi = (unsigned)bpl * (unsigned)ny * (unsigned)(2 * p) + soff_x;
+                                // x idx 0: Ey (-), idx 1: Ez (+); idx 2: Hy (+S), idx 3: Hz (-S)
+                                const float w0 = -1.f * (ce * bAe[1]), w1 = 1.f * (ce * bAe[2]);
+                                A.pout.a[0][0][xi] = hey ? bPb.x[0] : gxE.x * (bPb.x[0] + w0);
+                                A.pout.a[0][1][xi] = hez ? bPb.x[1] : gxE.x * (bPb.x[1] + w1);
+                                A.pout.a[0][2][xi] = gxH.x * (bPb.x[2] + 1.f * (S * bAh[1]));
+                                A.pout.a[0][3][xi] = gxH.x * (bPb.x[3] + -1.f * (S * bAh[2]));
+                            }
+                        }
+                        if constexpr (YP) {
+                            if (sy >= 0) {
+                                const unsigned yi = (unsigned)bpl * (unsigned)(2 * p) * (unsigned)nx + soff_y;
+                                // y idx 0: Ez (-), idx 1: Ex (+); idx 2: Hz (+S), idx 3: Hx (-S)
+                                const float w0 = -1.f * (ce * bAe[2]), w1 = 1.f * (ce * bAe[0]);
+                                A.pout.a[1][0][yi] = hez ? bPb.y[0] : gyE.x * (bPb.y[0] + w0);
+                                A.pout.a[1][1][yi] = hex ? bPb.y[1] : gyE.x * (bPb.y[1] + w1);
+                                A.pout.a[1][2][yi] = gyH.x * (bPb.y[2] + 1.f * (S * bAh[2]));
+                                A.pout.a[1][3][yi] = gyH.x * (bPb.y[3] + -1.f * (S * bAh[0]));
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+
+        // ------------------------------------------------------------ rotate
+        Rz0 = bR[0];
+        Rz3 = bR[3];
+#pragma unroll
+        for (int q = 0; q < 3; q++) {
+            bEn[q] = aEn[q];
+            bH[q] = Pa.h[q];
+            bAe[q] = Pa.ae[q];
+            bAh[q] = aAh[q];
+        }
+        bCe = Pa.ce;
+        bPb = Pa.pb;
+        Hm0 = Pa.h[0];
+        Hm1 = Pa.h[1];
+        Pa = L;
+    }
+}
+
+}  // namespace
+
+int rev_halo() { return HALO; }
+
+hipError_t launch_tb_reverse_class(const RevArgs &a, int cls, hipStream_t s)
+{
+    if (a.ntiles <= 0) return hipSuccess;
+    constexpr int threads = EX * W;
+    switch (cls) {
+    case 0: hipLaunchKernelGGL((k_tb_reverse<false, false>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_tb_reverse<true, false>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_tb_reverse<false, true>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_tb_reverse<true, true>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
+    }
+    return hipGetLastError();
+}

@@ -80,3 +80,39 @@ def test_tb_parity_with_oracle(K, monkeypatch):
     assert np.linalg.norm(f - st[:6]) / np.linalg.norm(st[:6]) <= 1e-4
     assert np.linalg.norm(tr.cpu().numpy() - trace) / np.linalg.norm(trace) <= 1e-4
     assert abs(float(Jg.item()) - J) <= 1e-4 * abs(J)
+
+
+def grad_run(pr, naive, monkeypatch):
+    monkeypatch.setenv("FDTD_NAIVE", "1" if naive else "0")
+    s = _solver(pr, record=True)
+    _, J = s.forward()
+    g, r = s.grad()
+    torch.cuda.synchronize()
+    return J.clone(), g.clone(), r.clone()
+
+
+@pytest.mark.parametrize("shape,p,T,d", [((70, 45, 38), 5, 40, 8), ((33, 61, 70), 6, 33, 10), ((16, 16, 16), 3, 60, 4)])
+def test_fused_reverse_bitwise_equal_to_per_cell(shape, p, T, d, monkeypatch):
+    """The fused reverse z-march (inverse + adjoint + record replay + detector
+    source in one pass) gives the per-cell reverse step's bits."""
+    pr = W.small_cpml(nx=shape[0], ny=shape[1], nz=shape[2], p=p, T=T, d=d, seed=31)
+    announce(f"fused reverse bitwise {shape} p={p} T={T}")
+    J0, g0, r0 = grad_run(pr, True, monkeypatch)
+    J1, g1, r1 = grad_run(pr, False, monkeypatch)
+    assert torch.equal(J0, J1)
+    assert torch.equal(g0, g1)
+    assert torch.equal(r0, r1)
+
+
+def test_fused_inverse_bitwise_equal_to_per_cell(monkeypatch):
+    pr = W.small_cpml(nx=70, ny=45, nz=38, p=5, T=50)
+    outs = []
+    for naive in (True, False):
+        monkeypatch.setenv("FDTD_NAIVE", "1" if naive else "0")
+        s = _solver(pr, record=True)
+        s.forward()
+        s.inverse(30)
+        torch.cuda.synchronize()
+        f = torch.stack([x.clone() for x in s.fields()])
+        outs.append(f[:, p:-p, p:-p, p:-p] if (p := pr.p) else f)
+    assert torch.equal(outs[0], outs[1])
