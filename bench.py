@@ -81,6 +81,20 @@ def cpu_baseline(pr, target_s: float = 12.0):
             "sample": f"{pr.nx}x{pr.ny}x{pr.nz} grid, {n} FP64 time steps (steps 1..{n}) of the same problem"}
 
 
+def copy_calibration(torch, nbytes: int = 1 << 30, reps: int = 4):
+    """Plain device kernels of known traffic: an elementwise negation reads
+    and writes `nbytes` (and a runtime copy does the same); their per-dispatch
+    HBM counters (FETCH_SIZE, WRITE_SIZE) against `nbytes` give the counters'
+    scale factor."""
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        torch.neg(a, out=b)
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": nbytes, "reps": reps}), flush=True)
+
+
 def serving_bench(count: int, torch, seed_rate: float = 0.8):
     """Serving mix: `count` requests of the Poisson mix recipe (edges U{64..256},
     50% forward / 50% gradient, T = 8 x max edge, CPML 8).  Measures saturation
@@ -142,6 +156,10 @@ def main():
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving", type=int, default=0, help="requests of the serving mix to run (0 = skip)")
+    ap.add_argument("--solve-steps", type=int, default=0,
+                    help="profiling runs only: time steps per solve instead of the workload's (0 = workload)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="profiling runs only: run a plain 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -152,8 +170,11 @@ def main():
     from paper_2412_12360_amd import workloads as W
     from paper_2412_12360_amd.fdtd import Solver
 
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
     rank = int(os.environ.get("RANK", "0"))
-    pr = W.config2()
+    pr = W.config2(T=args.solve_steps) if args.solve_steps else W.config2()
     s = Solver(pr, record=False, time_block=args.time_block)
     K = s.time_block
     for _ in range(args.warmup):
@@ -184,6 +205,7 @@ def main():
             "workload": "256^3 Yee grid, 10-cell CPML, 2000 steps forward, ramped Ex plane-wave sheet, "
                         "flux detector, eps_r 2.25 with a 128^3 cube U[2.25,12.25] (seed 2)",
             "grid": [pr.nx, pr.ny, pr.nz], "steps_per_solve": pr.T, "time_block": K,
+            **({"profiling_run": "steps per solve overridden"} if args.solve_steps else {}),
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_GBS, "unit": "GB/s",
@@ -196,7 +218,7 @@ def main():
     torch.cuda.empty_cache()
 
     if not args.no_grad:
-        pg = W.config3()
+        pg = W.config3(T=args.solve_steps) if args.solve_steps else W.config3()
         g = Solver(pg, record=True, time_block=args.time_block)
         g.reset()
         g.forward()

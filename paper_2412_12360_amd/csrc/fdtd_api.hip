@@ -81,6 +81,7 @@ struct fdtd_ctx {
     int nparts_cap = 0;
     int4 *tiles = nullptr;                 // tile tables of every K' <= K, two classes each
     int tb_off[5][4], tb_cnt[5][4];
+    unsigned fstride, pstride[3];   // z-march addressing: bytes between arrays of one set
     float4 *profv[3];
     bool naive = false;                    // per-cell kernels instead of the z-march
     hipStream_t side[3] = {nullptr, nullptr, nullptr};   // concurrent tile classes (default priority)
@@ -198,12 +199,13 @@ void geometry(const fdtd_desc *d, const fdtd_flux_detector *det, int ndet, Geome
     for (int a = 0; a < 3; a++) G.design_cells *= (d->design_hi[a] - d->design_lo[a]);
 }
 
-// z-march variant: ones digit = workgroup shape (0: 16 waves x 1 row, 1: 8 x 2),
-// tens digit = planes fetched ahead (1..3)
+// forward z-march workgroup shape: 0: 16 waves of 64-lane rows (64 x 16
+// tile), 1: 8 waves of 32-lane rows (32 x 16 tile, two workgroups per CU;
+// measured faster on the 256^3 benchmark grid)
 int tb_shape()
 {
     if (const char *e = getenv("FDTD_TB_SHAPE")) return atoi(e);
-    return 0;
+    return 1;
 }
 
 int choose_K(const fdtd_desc *d)
@@ -236,7 +238,7 @@ int zchunk(const Geometry &G, int K)
         const int v = atoi(e);
         if (v > 0) return std::min(v, G.nz);
     }
-    const long long tx = (long long)split_axis(G.nx, tb_tile_x(K)).size();
+    const long long tx = (long long)split_axis(G.nx, tb_tile_x(K, tb_shape())).size();
     const long long ty = (long long)split_axis(G.ny, tb_tile_y(K, tb_shape())).size();
     // short marches: the work per workgroup is serial, so many short
     // marches balance better than few long ones (16 planes measured best)
@@ -244,16 +246,21 @@ int zchunk(const Geometry &G, int K)
     return std::min(16, G.nz);
 }
 
-// Tile tables of the z-march kernel for K' = 1..K, four classes each: bit 0
-// = an x CPML slab inside the halo-extended footprint, bit 1 = a y slab.
+// Tile tables of the z-march kernels, four classes each (bit 0 = an x CPML
+// slab inside the halo-extended footprint, bit 1 = a y slab): slot 0 for the
+// fused reverse march, slot K' for a forward sweep of K' = 1..K steps.
 void build_tiles(const Geometry &G, int K, std::vector<int4> &out, int off[5][4], int cnt[5][4])
 {
     out.clear();
     for (int kk = 0; kk < 5; kk++)
         for (int c = 0; c < 4; c++) off[kk][c] = cnt[kk][c] = 0;
-    for (int kk = 1; kk <= std::max(K, rev_halo()); kk++) {
-        const int ZC = zchunk(G, kk);
-        const auto xs = split_axis(G.nx, tb_tile_x(kk)), ys = split_axis(G.ny, tb_tile_y(kk, tb_shape()));
+    // slot 0: the reverse march (halo rev_halo()); slots 1..K: forward, halo kk
+    for (int kk = 0; kk <= K; kk++) {
+        const int halo = kk == 0 ? rev_halo() : kk;
+        const int ZC = zchunk(G, halo);
+        const int tx = kk == 0 ? rev_tile_x() : tb_tile_x(kk, tb_shape());
+        const int ty = kk == 0 ? rev_tile_y() : tb_tile_y(kk, tb_shape());
+        const auto xs = split_axis(G.nx, tx), ys = split_axis(G.ny, ty);
         std::vector<int4> cls[4];
         for (int z0 = 0; z0 < G.nz; z0 += ZC)
             for (const auto &yt : ys)
@@ -261,11 +268,11 @@ void build_tiles(const Geometry &G, int K, std::vector<int4> &out, int off[5][4]
                     const int z1 = std::min(z0 + ZC, G.nz);
                     int c = 0;
                     if (G.p > 0) {
-                        if (xt.first - kk < G.p || xt.second + kk > G.nx - G.p) c |= 1;
-                        if (yt.first - kk < G.p || yt.second + kk > G.ny - G.p) c |= 2;
+                        if (xt.first - halo < G.p || xt.second + halo > G.nx - G.p) c |= 1;
+                        if (yt.first - halo < G.p || yt.second + halo > G.ny - G.p) c |= 2;
                     }
                     cls[c].push_back(make_int4(xt.first, xt.second, yt.first, yt.second));
-                    cls[c].push_back(make_int4(z0, z1, 0, 0));
+                    cls[c].push_back(make_int4(z0, z1, c, 0));
                 }
         for (int c = 0; c < 4; c++) {
             off[kk][c] = (int)out.size() / 2;
@@ -449,6 +456,8 @@ fdtd_status steps_tb(fdtd_ctx *h, int n0, int kk, int with_src, int with_rec, in
     a.D = G.D;
     a.xcd_remap = 1;
     for (int ax = 0; ax < 3; ax++) a.profv[ax] = h->profv[ax];
+    a.fstride = h->fstride;
+    for (int ax = 0; ax < 3; ax++) a.pstride[ax] = h->pstride[ax];
     // The four tile classes are independent (all read buffer cur, write
     // disjoint cells of buffer cur^1): classes 1..3 run on side streams that
     // fork from and join back into the handle's stream, so a small class
@@ -544,7 +553,7 @@ fdtd_status reverse_fused(fdtd_ctx *h, int n, int do_inv, int do_adj, int with_d
     a.dhi = make_int3(h->desc.design_hi[0], h->desc.design_hi[1], h->desc.design_hi[2]);
     for (int ax = 0; ax < 3; ax++) a.profv[ax] = h->profv[ax];
     a.xcd_remap = 1;
-    const int kt = rev_halo();   // the tile tables of halo K = 2 fit the reverse march
+    const int kt = 0;   // tile table slot of the reverse march
     const bool par = h->side[0] != nullptr;
     if (par) HIPCHK(h, hipEventRecord(h->fork, h->stream));
     for (int c = 0; c < 4; c++) {
@@ -628,6 +637,30 @@ fdtd_status fdtd_create(const fdtd_desc *desc, const fdtd_source *src, int32_t n
         return fail(nullptr, FDTD_E_NOMEM, "workspace %zu bytes < footprint %zu", workspace_bytes, need);
     }
     plan(h, desc, h->geo, h->K, workspace);
+    // the z-march kernel addresses a field set, and the four auxiliaries of a
+    // slab axis, from one base with 32-bit byte offsets
+    {
+        auto stride_of = [](float *const *v, int n, unsigned &st) {
+            const uintptr_t d = (uintptr_t)v[1] - (uintptr_t)v[0];
+            for (int q = 1; q < n; q++)
+                if ((uintptr_t)v[q] - (uintptr_t)v[q - 1] != d) return false;
+            if ((unsigned long long)d * (unsigned long long)n >= (1ull << 32)) return false;
+            st = (unsigned)d;
+            return true;
+        };
+        unsigned f0 = 0, f1 = 0;
+        bool ok = stride_of(h->fld[0], 6, f0) && stride_of(h->fld[1], 6, f1) && f0 == f1;
+        h->fstride = f0;
+        for (int a = 0; a < 3; a++) {
+            h->pstride[a] = 0;
+            if (h->geo.p > 0) {
+                unsigned p0 = 0, p1 = 0;
+                ok = ok && stride_of(h->psi[0][a], 4, p0) && stride_of(h->psi[1][a], 4, p1) && p0 == p1;
+                h->pstride[a] = p0;
+            }
+        }
+        if (!ok) h->naive = true;
+    }
 
     // device problem description
     const Geometry &G = h->geo;

@@ -159,13 +159,17 @@ struct TbArgs {
     RecGeom R;
     float *planes;          // detector flux planes of step n0 (or nullptr); + s*D.per_step
     Detectors D;
-    const int4 *tiles;      // per tile two int4: (x0, x1, y0, y1), (z0, z1, 0, 0) owned box
+    const int4 *tiles;      // per tile two int4: (x0, x1, y0, y1), (z0, z1, class, 0) owned box
     int ntiles;
     const float4 *profv[3]; // per axis, per index: (b, a, 1/kappa) at E then H positions
     int xcd_remap;          // 1: map consecutive tiles to one XCD
+    unsigned fstride;       // bytes from component q to q+1 of a field set (in and out alike)
+    unsigned pstride[3];    // bytes from CPML auxiliary q to q+1 of axis a (pin and pout alike)
 };
+// one sweep of K steps over the tiles of class cls (bit 0: an x CPML slab in
+// the halo-extended footprint, bit 1: a y slab)
 hipError_t launch_tb_forward_class(const TbArgs &a, int K, int cls, int shape, hipStream_t s);
-int tb_tile_x(int K);
+int tb_tile_x(int K, int shape);
 int tb_tile_y(int K, int shape);
 int tb_max_pml();
 
@@ -191,3 +195,5 @@ struct RevArgs {
 };
 hipError_t launch_tb_reverse_class(const RevArgs &a, int cls, hipStream_t s);
 int rev_halo();
+int rev_tile_x();
+int rev_tile_y();

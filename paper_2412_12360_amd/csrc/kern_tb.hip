@@ -28,7 +28,6 @@
 
 namespace {
 
-constexpr int EX = 64;
 constexpr int TB_MAXP = 64;   // largest CPML thickness the z-march kernel stages
 
 
@@ -85,10 +84,13 @@ __device__ __forceinline__ float cpml_term_h(float d, float &psi, float b, float
     return fmaf(d, kinv, psi);
 }
 
-template <int K, bool XP, bool YP, int PD, int W, int R>
-__global__ __launch_bounds__(EX *W) void k_tb_forward(TbArgs A)
+// TX lanes of a wave row span x; W waves; R rows per thread.  The register
+// budget allows 4 waves per SIMD (two workgroups per CU at 512 threads).
+template <int K, bool XP, bool YP, int PD, int W, int R, int TX>
+__global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
 {
-    constexpr int EY = W * R;
+    constexpr int EX = TX;
+    constexpr int EY = (64 * W / TX) * R;
     __shared__ float sE[3][EY][EX];
     __shared__ float sH[3][EY][EX];
     // z grading of the 2p slab planes (E b, a, 1/k, H b, a, 1/k) and the
@@ -115,7 +117,7 @@ __global__ __launch_bounds__(EX *W) void k_tb_forward(TbArgs A)
     if (A.xcd_remap) b = remap_xcd(b, gridDim.x);
     const int4 tl = A.tiles[2 * b], tz = A.tiles[2 * b + 1];
     const int x0 = tl.x, x1 = tl.y, y0 = tl.z, y1 = tl.w, z0 = tz.x, z1 = tz.y;
-    const int lane = threadIdx.x & (EX - 1);
+    const int lane = threadIdx.x % EX;
     const int wv = threadIdx.x / EX;
     const int x = x0 - K + lane;
     const bool inx = x >= 0 && x < nx;
@@ -154,13 +156,11 @@ __global__ __launch_bounds__(EX *W) void k_tb_forward(TbArgs A)
         }
     }
 
-    const float *__restrict__ iEx = A.in.c[0];
-    const float *__restrict__ iEy = A.in.c[1];
-    const float *__restrict__ iEz = A.in.c[2];
-    const float *__restrict__ iHx = A.in.c[3];
-    const float *__restrict__ iHy = A.in.c[4];
-    const float *__restrict__ iHz = A.in.c[5];
+    // one base per buffer set: component q of a field set at q * fs bytes,
+    // CPML auxiliary q of axis a at q * A.pstride[a] bytes (32-bit offsets)
+    const float *__restrict__ iF = A.in.c[0];
     const float *__restrict__ ice = A.g.ce;
+    const unsigned fs = A.fstride;
 
     auto load_plane = [&](int t, Plane<R, XP, YP> &P) {
         const bool tin = t >= 0 && t < nz;
@@ -168,41 +168,53 @@ __global__ __launch_bounds__(EX *W) void k_tb_forward(TbArgs A)
 #pragma unroll
         for (int r = 0; r < R; r++) {
             const unsigned c = (base + off[r]) * 4u;
-            const bool v = tin && incol[r];
-            const float e0 = ldo(iEx, c), e1 = ldo(iEy, c), e2 = ldo(iEz, c);
-            const float h0 = ldo(iHx, c), h1 = ldo(iHy, c), h2 = ldo(iHz, c);
-            const float cc = ldo(ice, c);
-            P.e[r][0] = v ? e0 : 0.f; P.e[r][1] = v ? e1 : 0.f; P.e[r][2] = v ? e2 : 0.f;
-            P.h[r][0] = v ? h0 : 0.f; P.h[r][1] = v ? h1 : 0.f; P.h[r][2] = v ? h2 : 0.f;
-            P.ce[r] = v ? cc : 0.f;
+            // raw values: columns and planes outside the grid are zeroed where
+            // the plane is consumed, so the fetch stays in flight until then
+            P.e[r][0] = ldo(iF, c); P.e[r][1] = ldo(iF, c + fs); P.e[r][2] = ldo(iF, c + 2 * fs);
+            P.h[r][0] = ldo(iF, c + 3 * fs); P.h[r][1] = ldo(iF, c + 4 * fs); P.h[r][2] = ldo(iF, c + 5 * fs);
+            P.ce[r] = ldo(ice, c);
             psi_zero<XP, YP>(P.p[r]);
         }
         if (p > 0 && tin) {
             const int szt = slab_coord(t, nz, p);
             if (szt >= 0) {
                 const unsigned zb = (unsigned)szt * nxy;
+                const unsigned ps = A.pstride[2];
 #pragma unroll
                 for (int r = 0; r < R; r++) {
+                    const unsigned o = (zb + off[r]) * 4u;
 #pragma unroll
-                    for (int q = 0; q < 4; q++) P.p[r].z[q] = A.pin.a[2][q][zb + off[r]];
+                    for (int q = 0; q < 4; q++) P.p[r].z[q] = ldo(A.pin.a[2][0], o + q * ps);
                 }
             }
             if constexpr (XP) {
                 const unsigned xb = (unsigned)t * (unsigned)ny * (unsigned)(2 * p);
+                const unsigned ps = A.pstride[0];
 #pragma unroll
-                for (int r = 0; r < R; r++)
+                for (int r = 0; r < R; r++) {
+                    const unsigned o = (xb + soff_x[r]) * 4u;
 #pragma unroll
-                    for (int q = 0; q < 4; q++) P.p[r].x[q] = A.pin.a[0][q][xb + soff_x[r]];
+                    for (int q = 0; q < 4; q++) P.p[r].x[q] = ldo(A.pin.a[0][0], o + q * ps);
+                }
             }
             if constexpr (YP) {
                 const unsigned yb = (unsigned)t * (unsigned)(2 * p) * (unsigned)nx;
+                const unsigned ps = A.pstride[1];
 #pragma unroll
-                for (int r = 0; r < R; r++)
+                for (int r = 0; r < R; r++) {
+                    const unsigned o = (yb + soff_y[r]) * 4u;
 #pragma unroll
-                    for (int q = 0; q < 4; q++) P.p[r].y[q] = A.pin.a[1][q][yb + soff_y[r]];
+                    for (int q = 0; q < 4; q++) P.p[r].y[q] = ldo(A.pin.a[1][0], o + q * ps);
+                }
             }
         }
     };
+
+    // source planes (uniform; -2^31 for an absent source), hoisted so the
+    // per-level test issues no scalar memory load
+    int skq[FD_MAXSRC];
+#pragma unroll
+    for (int q = 0; q < FD_MAXSRC; q++) skq[q] = (A.with_src && q < A.g.nsrc) ? A.g.sk[q] : (-2147483647 - 1);
 
     // pipeline registers: Eo[s], Ho[s]/Hc[s], Po[s] = output of level s at the
     // plane level s+1 works on next; Ho[K] = last Hx, Hy of level K; cd[s] =
@@ -228,14 +240,19 @@ __global__ __launch_bounds__(EX *W) void k_tb_forward(TbArgs A)
     auto body = [&](const int t, const Plane<R, XP, YP> &cur) {
         float nE[R][3], nH[R][3];
         PsiReg<XP, YP> nP[R];
+        const bool tin = t >= 0 && t < nz;
 #pragma unroll
         for (int r = 0; r < R; r++) {
+            const bool v = tin && incol[r];
 #pragma unroll
-            for (int q = 0; q < 3; q++) { nE[r][q] = cur.e[r][q]; nH[r][q] = cur.h[r][q]; }
+            for (int q = 0; q < 3; q++) {
+                nE[r][q] = v ? cur.e[r][q] : 0.f;
+                nH[r][q] = v ? cur.h[r][q] : 0.f;
+            }
             nP[r] = cur.p[r];
 #pragma unroll
             for (int s = K; s > 0; s--) cd[s][r] = cd[s - 1][r];
-            cd[0][r] = cur.ce[r];
+            cd[0][r] = v ? cur.ce[r] : 0.f;
         }
 #pragma unroll
         for (int s = 1; s <= K; s++) {
@@ -334,22 +351,23 @@ __global__ __launch_bounds__(EX *W) void k_tb_forward(TbArgs A)
                     mE[r][1] = live ? ey : 0.f;
                     mE[r][2] = live ? ez : 0.f;
                 }
-                // ---- sources (uniform plane test)
-                if (A.with_src) {
-                    for (int q = 0; q < A.g.nsrc; q++) {
-                        if (k != A.g.sk[q]) continue;
+                // ---- sources (uniform plane test against the hoisted source
+                // planes: no scalar memory load on a plane without a source)
+#pragma unroll
+                for (int q = 0; q < FD_MAXSRC; q++) {
+                    if (k == skq[q]) {
                         const float am = sAmp[q][s - 1];
                         const int comp = A.g.scomp[q];
 #pragma unroll
                         for (int r = 0; r < R; r++) {
                             const bool hit = incol[r] && kin &&
                                              (A.g.skind[q] == 1 || (x == A.g.si[q] && ys[r] == A.g.sj[q]));
-                            const float mask = comp == 0 ? mex[r] * mk : comp == 1 ? mey[r] * mk : mez[r];
-                            if (hit && mask != 0.f) {
-                                if (comp == 0) mE[r][0] = mE[r][0] + am;
-                                if (comp == 1) mE[r][1] = mE[r][1] + am;
-                                if (comp == 2) mE[r][2] = mE[r][2] + am;
-                            }
+                            // one select per component, no component-indexed
+                            // array (which the compiler would place in scratch);
+                            // a held component takes no source
+                            mE[r][0] = (hit && comp == 0 && mex[r] * mk != 0.f) ? mE[r][0] + am : mE[r][0];
+                            mE[r][1] = (hit && comp == 1 && mey[r] * mk != 0.f) ? mE[r][1] + am : mE[r][1];
+                            mE[r][2] = (hit && comp == 2 && mez[r] != 0.f) ? mE[r][2] + am : mE[r][2];
                         }
                     }
                 }
@@ -436,45 +454,52 @@ __global__ __launch_bounds__(EX *W) void k_tb_forward(TbArgs A)
         }
         if (kK >= z0 && kK < z1) {
             const unsigned base = (unsigned)kK * nxy;
+            float *__restrict__ oF = A.out.c[0];
 #pragma unroll
             for (int r = 0; r < R; r++) {
                 if (!own[r]) continue;
                 const unsigned c = (base + off[r]) * 4u;
 #pragma unroll
                 for (int q = 0; q < 3; q++) {
-                    sto(A.out.c[q], c, nE[r][q]);
-                    sto(A.out.c[3 + q], c, nH[r][q]);
+                    sto(oF, c + q * fs, nE[r][q]);
+                    sto(oF, c + (3 + q) * fs, nH[r][q]);
                 }
             }
             if (p > 0) {
                 const int szo = slab_coord(kK, nz, p);
                 if (szo >= 0) {
                     const unsigned zb = (unsigned)szo * nxy;
+                    const unsigned ps = A.pstride[2];
 #pragma unroll
                     for (int r = 0; r < R; r++)
                         if (own[r]) {
+                            const unsigned o = (zb + off[r]) * 4u;
 #pragma unroll
-                            for (int q = 0; q < 4; q++) A.pout.a[2][q][zb + off[r]] = nP[r].z[q];
+                            for (int q = 0; q < 4; q++) sto(A.pout.a[2][0], o + q * ps, nP[r].z[q]);
                         }
                 }
                 if constexpr (XP) {
                     if (sx >= 0) {
                         const unsigned xb = (unsigned)kK * (unsigned)ny * (unsigned)(2 * p);
+                        const unsigned ps = A.pstride[0];
 #pragma unroll
                         for (int r = 0; r < R; r++)
                             if (own[r]) {
+                                const unsigned o = (xb + soff_x[r]) * 4u;
 #pragma unroll
-                                for (int q = 0; q < 4; q++) A.pout.a[0][q][xb + soff_x[r]] = nP[r].x[q];
+                                for (int q = 0; q < 4; q++) sto(A.pout.a[0][0], o + q * ps, nP[r].x[q]);
                             }
                     }
                 }
                 if constexpr (YP) {
                     const unsigned yb = (unsigned)kK * (unsigned)(2 * p) * (unsigned)nx;
+                    const unsigned ps = A.pstride[1];
 #pragma unroll
                     for (int r = 0; r < R; r++)
                         if (own[r] && sy[r] >= 0) {
+                            const unsigned o = (yb + soff_y[r]) * 4u;
 #pragma unroll
-                            for (int q = 0; q < 4; q++) A.pout.a[1][q][yb + soff_y[r]] = nP[r].y[q];
+                            for (int q = 0; q < 4; q++) sto(A.pout.a[1][0], o + q * ps, nP[r].y[q]);
                         }
                 }
             }
@@ -498,51 +523,50 @@ __global__ __launch_bounds__(EX *W) void k_tb_forward(TbArgs A)
     }
 }
 
-template <int K, int W, int R, int PD>
+template <int K, int W, int R, int PD, int TX>
 hipError_t launch_kwrp(const TbArgs &a, int cls, hipStream_t s)
 {
-    constexpr int threads = EX * W;
+    constexpr int threads = 64 * W;
     if (a.ntiles <= 0) return hipSuccess;
     switch (cls) {
-    case 0: hipLaunchKernelGGL((k_tb_forward<K, false, false, PD, W, R>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
-    case 1: hipLaunchKernelGGL((k_tb_forward<K, true, false, PD, W, R>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_tb_forward<K, false, true, PD, W, R>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_tb_forward<K, true, true, PD, W, R>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
+    case 0: hipLaunchKernelGGL((k_tb_forward<K, false, false, PD, W, R, TX>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_tb_forward<K, true, false, PD, W, R, TX>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_tb_forward<K, false, true, PD, W, R, TX>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_tb_forward<K, true, true, PD, W, R, TX>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
     }
     return hipGetLastError();
 }
 
-// workgroup shapes (waves x rows per thread) and plane-prefetch depths
+// workgroup shapes: waves, lanes per wave row along x (one row per thread)
+//   0: 16 waves of 64-lane rows, a 64 x 16 tile, one workgroup per CU
+//   1: 8 waves of 32-lane rows, a 32 x 16 tile, two workgroups per CU
 constexpr int NSHAPE = 2;
 constexpr int SHAPE_W[NSHAPE] = {16, 8};
-constexpr int SHAPE_R[NSHAPE] = {1, 2};
+constexpr int SHAPE_TX[NSHAPE] = {64, 32};
 
 template <int K>
 hipError_t launch_k(const TbArgs &a, int cls, int shape, hipStream_t s)
 {
-    const int sh = shape % 10, pd = shape / 10;
-    if (sh == 1) {
-        if (pd == 2) return launch_kwrp<K, 8, 2, 2>(a, cls, s);
-        return launch_kwrp<K, 8, 2, 1>(a, cls, s);
-    }
-    if (pd == 2) return launch_kwrp<K, 16, 1, 2>(a, cls, s);
-    if (pd == 3) return launch_kwrp<K, 16, 1, 3>(a, cls, s);
-    return launch_kwrp<K, 16, 1, 1>(a, cls, s);
+    if (shape == 0) return launch_kwrp<K, 16, 1, 1, 64>(a, cls, s);
+    return launch_kwrp<K, 8, 1, 1, 32>(a, cls, s);
 }
+
+int shape_index(int shape) { return shape >= 0 && shape < NSHAPE ? shape : 1; }
 
 }  // namespace
 
-int tb_tile_x(int K) { return EX - 2 * K; }
+int tb_tile_x(int K, int shape) { return SHAPE_TX[shape_index(shape)] - 2 * K; }
 int tb_max_pml() { return TB_MAXP; }
 int tb_tile_y(int K, int shape)
 {
-    const int sh = (shape % 10) < NSHAPE ? shape % 10 : 0;
-    return SHAPE_W[sh] * SHAPE_R[sh] - 2 * K;
+    const int sh = shape_index(shape);
+    return 64 * SHAPE_W[sh] / SHAPE_TX[sh] - 2 * K;
 }
 
 // Tiles of class cls: bit 0 = x CPML slab in the extended footprint, bit 1 = y.
 hipError_t launch_tb_forward_class(const TbArgs &a, int K, int cls, int shape, hipStream_t s)
 {
+    shape = shape_index(shape);
     switch (K) {
     case 1: return launch_k<1>(a, cls, shape, s);
     case 2: return launch_k<2>(a, cls, shape, s);

@@ -481,6 +481,8 @@ __global__ __launch_bounds__(EX *W) void k_tb_reverse(RevArgs A)
 }  // namespace
 
 int rev_halo() { return HALO; }
+int rev_tile_x() { return EX - 2 * HALO; }
+int rev_tile_y() { return EY - 2 * HALO; }
 
 hipError_t launch_tb_reverse_class(const RevArgs &a, int cls, hipStream_t s)
 {
