@@ -200,12 +200,13 @@ void geometry(const fdtd_desc *d, const fdtd_flux_detector *det, int ndet, Geome
 }
 
 // forward z-march workgroup shape: 0: 16 waves of 64-lane rows (64 x 16
-// tile), 1: 8 waves of 32-lane rows (32 x 16 tile, two workgroups per CU;
-// measured faster on the 256^3 benchmark grid)
+// tile), 1: 8 waves of 32-lane rows (32 x 16 tile, two workgroups per CU),
+// 2 / 3: rows of 32 + 2K lanes whose owned part is one aligned 128-byte line,
+// 16 / 8 waves.  3 measured fastest on the 256^3 benchmark grid.
 int tb_shape()
 {
     if (const char *e = getenv("FDTD_TB_SHAPE")) return atoi(e);
-    return 1;
+    return 3;
 }
 
 int choose_K(const fdtd_desc *d)
@@ -227,6 +228,14 @@ std::vector<std::pair<int, int>> split_axis(int n, int w)
     const int m = (mid + w - 1) / w;
     for (int i = 0; i < m; i++) v.push_back({w + (int)((long long)mid * i / m), w + (int)((long long)mid * (i + 1) / m)});
     v.push_back({n - w, n});
+    return v;
+}
+
+// Split [0, n) into consecutive tiles of w cells (the last one shorter).
+std::vector<std::pair<int, int>> split_uniform(int n, int w)
+{
+    std::vector<std::pair<int, int>> v;
+    for (int a = 0; a < n; a += w) v.push_back({a, std::min(n, a + w)});
     return v;
 }
 
@@ -260,7 +269,9 @@ void build_tiles(const Geometry &G, int K, std::vector<int4> &out, int off[5][4]
         const int ZC = zchunk(G, halo);
         const int tx = kk == 0 ? rev_tile_x() : tb_tile_x(kk, tb_shape());
         const int ty = kk == 0 ? rev_tile_y() : tb_tile_y(kk, tb_shape());
-        const auto xs = split_axis(G.nx, tx), ys = split_axis(G.ny, ty);
+        // line-aligned shapes cut x into whole lines from x = 0
+        const auto xs = (kk > 0 && tb_tile_aligned(tb_shape())) ? split_uniform(G.nx, tx) : split_axis(G.nx, tx);
+        const auto ys = split_axis(G.ny, ty);
         std::vector<int4> cls[4];
         for (int z0 = 0; z0 < G.nz; z0 += ZC)
             for (const auto &yt : ys)
@@ -553,6 +564,8 @@ fdtd_status reverse_fused(fdtd_ctx *h, int n, int do_inv, int do_adj, int with_d
     a.dhi = make_int3(h->desc.design_hi[0], h->desc.design_hi[1], h->desc.design_hi[2]);
     for (int ax = 0; ax < 3; ax++) a.profv[ax] = h->profv[ax];
     a.xcd_remap = 1;
+    a.fstride = h->fstride;
+    for (int ax = 0; ax < 3; ax++) a.pstride[ax] = h->pstride[ax];
     const int kt = 0;   // tile table slot of the reverse march
     const bool par = h->side[0] != nullptr;
     if (par) HIPCHK(h, hipEventRecord(h->fork, h->stream));
@@ -648,14 +661,24 @@ fdtd_status fdtd_create(const fdtd_desc *desc, const fdtd_source *src, int32_t n
             st = (unsigned)d;
             return true;
         };
+        // (the adjoint sets, when present, must have the same spacing: the
+        // fused reverse march addresses them the same way)
         unsigned f0 = 0, f1 = 0;
         bool ok = stride_of(h->fld[0], 6, f0) && stride_of(h->fld[1], 6, f1) && f0 == f1;
+        if (desc->record) {
+            unsigned a0 = 0, a1 = 0;
+            ok = ok && stride_of(h->adj[0], 6, a0) && stride_of(h->adj[1], 6, a1) && a0 == f0 && a1 == f0;
+        }
         h->fstride = f0;
         for (int a = 0; a < 3; a++) {
             h->pstride[a] = 0;
             if (h->geo.p > 0) {
                 unsigned p0 = 0, p1 = 0;
                 ok = ok && stride_of(h->psi[0][a], 4, p0) && stride_of(h->psi[1][a], 4, p1) && p0 == p1;
+                if (desc->record) {
+                    unsigned b0 = 0, b1 = 0;
+                    ok = ok && stride_of(h->pb[0][a], 4, b0) && stride_of(h->pb[1][a], 4, b1) && b0 == p0 && b1 == p0;
+                }
                 h->pstride[a] = p0;
             }
         }

@@ -171,6 +171,7 @@ struct TbArgs {
 hipError_t launch_tb_forward_class(const TbArgs &a, int K, int cls, int shape, hipStream_t s);
 int tb_tile_x(int K, int shape);
 int tb_tile_y(int K, int shape);
+bool tb_tile_aligned(int shape);   // x tiles start on 128-byte lines (uniform split)
 int tb_max_pml();
 
 // fused reverse step (inverse + adjoint) as a z-march, tile halo rev_halo()
@@ -192,6 +193,8 @@ struct RevArgs {
     int ntiles;
     const float4 *profv[3];
     int xcd_remap;
+    unsigned fstride;        // bytes from component q to q+1 of a field or adjoint set
+    unsigned pstride[3];     // bytes from auxiliary q to q+1 of axis a (pin and pout alike)
 };
 hipError_t launch_tb_reverse_class(const RevArgs &a, int cls, hipStream_t s);
 int rev_halo();

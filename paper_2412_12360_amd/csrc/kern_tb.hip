@@ -91,8 +91,10 @@ __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
 {
     constexpr int EX = TX;
     constexpr int EY = (64 * W / TX) * R;
-    __shared__ float sE[3][EY][EX];
-    __shared__ float sH[3][EY][EX];
+    // (one spare row for the threads beyond the last full row when TX does
+    // not divide the workgroup: they compute on it and write nothing)
+    __shared__ float sE[3][EY + 1][EX];
+    __shared__ float sH[3][EY + 1][EX];
     // z grading of the 2p slab planes (E b, a, 1/k, H b, a, 1/k) and the
     // source amplitudes of the K steps of this sweep, staged once so the
     // march never waits on a vector load other than its own plane fetches
@@ -117,10 +119,11 @@ __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
     if (A.xcd_remap) b = remap_xcd(b, gridDim.x);
     const int4 tl = A.tiles[2 * b], tz = A.tiles[2 * b + 1];
     const int x0 = tl.x, x1 = tl.y, y0 = tl.z, y1 = tl.w, z0 = tz.x, z1 = tz.y;
-    const int lane = threadIdx.x % EX;
-    const int wv = threadIdx.x / EX;
+    const bool active = (int)threadIdx.x < EX * (EY / R);
+    const int lane = active ? (int)threadIdx.x % EX : 0;
+    const int wv = active ? (int)threadIdx.x / EX : EY / R;
     const int x = x0 - K + lane;
-    const bool inx = x >= 0 && x < nx;
+    const bool inx = active && x >= 0 && x < nx;
     const int xc = x < 0 ? 0 : (x >= nx ? nx - 1 : x);
     const int sx = (XP && inx) ? slab_coord(x, nx, p) : -1;
 
@@ -537,31 +540,41 @@ hipError_t launch_kwrp(const TbArgs &a, int cls, hipStream_t s)
     return hipGetLastError();
 }
 
-// workgroup shapes: waves, lanes per wave row along x (one row per thread)
+// workgroup shapes (one row per thread):
 //   0: 16 waves of 64-lane rows, a 64 x 16 tile, one workgroup per CU
 //   1: 8 waves of 32-lane rows, a 32 x 16 tile, two workgroups per CU
-constexpr int NSHAPE = 2;
-constexpr int SHAPE_W[NSHAPE] = {16, 8};
-constexpr int SHAPE_TX[NSHAPE] = {64, 32};
+//   2: 16 waves as rows of 32 + 2K lanes (28 rows at K = 2): the owned part
+//      of each row is one whole 128-byte line, line aligned, so no two
+//      workgroups write parts of the same line
+//   3: as 2 with 8 waves (two workgroups per CU)
+constexpr int NSHAPE = 4;
+constexpr int SHAPE_W[NSHAPE] = {16, 8, 16, 8};
+constexpr int ALIGN_X = 32;   // floats per 128-byte line
+__host__ __device__ constexpr int shape_tx(int sh, int K) { return sh == 0 ? 64 : sh == 1 ? 32 : ALIGN_X + 2 * K; }
 
 template <int K>
 hipError_t launch_k(const TbArgs &a, int cls, int shape, hipStream_t s)
 {
-    if (shape == 0) return launch_kwrp<K, 16, 1, 1, 64>(a, cls, s);
-    return launch_kwrp<K, 8, 1, 1, 32>(a, cls, s);
+    switch (shape) {
+    case 0: return launch_kwrp<K, 16, 1, 1, 64>(a, cls, s);
+    case 2: return launch_kwrp<K, 16, 1, 1, ALIGN_X + 2 * K>(a, cls, s);
+    case 3: return launch_kwrp<K, 8, 1, 1, ALIGN_X + 2 * K>(a, cls, s);
+    default: return launch_kwrp<K, 8, 1, 1, 32>(a, cls, s);
+    }
 }
 
 int shape_index(int shape) { return shape >= 0 && shape < NSHAPE ? shape : 1; }
 
 }  // namespace
 
-int tb_tile_x(int K, int shape) { return SHAPE_TX[shape_index(shape)] - 2 * K; }
+int tb_tile_x(int K, int shape) { return shape_tx(shape_index(shape), K) - 2 * K; }
 int tb_max_pml() { return TB_MAXP; }
 int tb_tile_y(int K, int shape)
 {
     const int sh = shape_index(shape);
-    return 64 * SHAPE_W[sh] / SHAPE_TX[sh] - 2 * K;
+    return 64 * SHAPE_W[sh] / shape_tx(sh, K) - 2 * K;
 }
+bool tb_tile_aligned(int shape) { return shape_index(shape) >= 2; }
 
 // Tiles of class cls: bit 0 = x CPML slab in the extended footprint, bit 1 = y.
 hipError_t launch_tb_forward_class(const TbArgs &a, int K, int cls, int shape, hipStream_t s)

@@ -24,6 +24,11 @@
 namespace {
 
 constexpr int EX = 64;
+
+// every pointer here addresses device global memory; saying so keeps the
+// loads and stores on global (not flat) instructions
+#define GLOBAL __attribute__((address_space(1)))
+__device__ __forceinline__ float gld(const float *p) { return *(const GLOBAL float *)p; }
 constexpr int W = 16;
 constexpr int EY = W;
 constexpr int HALO = 2;
@@ -55,6 +60,7 @@ __global__ __launch_bounds__(EX *W) void k_tb_reverse(RevArgs A)
     __shared__ float sEn[3][EY][EX];
     __shared__ float sR[4][EY][EX];
     __shared__ float sGz[2 * 64][6];
+    __shared__ float sAmp[FD_MAXSRC];   // source amplitudes of step n
 
     const Grid &g = A.g;
     const int nx = g.nx, ny = g.ny, nz = g.nz, p = g.p;
@@ -66,7 +72,24 @@ __global__ __launch_bounds__(EX *W) void k_tb_reverse(RevArgs A)
         sGz[e][0] = gE.x; sGz[e][1] = gE.y; sGz[e][2] = gE.z;
         sGz[e][3] = gH.x; sGz[e][4] = gH.y; sGz[e][5] = gH.z;
     }
+    if ((int)threadIdx.x < FD_MAXSRC) sAmp[threadIdx.x] = (int)threadIdx.x < g.nsrc ? g.samp[threadIdx.x][A.n] : 0.f;
     __syncthreads();
+    // source and detector planes (uniform; -2^31 when absent), hoisted so the
+    // per-plane tests issue no scalar memory load
+    constexpr int NONE = -2147483647 - 1;
+    int skq[FD_MAXSRC], dkq[FD_MAXDET];
+#pragma unroll
+    for (int q = 0; q < FD_MAXSRC; q++) skq[q] = q < g.nsrc ? g.sk[q] : NONE;
+#pragma unroll
+    for (int m = 0; m < FD_MAXDET; m++) dkq[m] = (A.do_adj && A.with_det && m < A.D.ndet) ? A.D.k[m] : NONE;
+    // Arguments used only on rare planes (record layers, detector, source)
+    // are read through a copy of the argument pointer that is made opaque on
+    // every plane, so they are fetched where used instead of being held in
+    // scalar registers for the whole march.
+    // (the argument block is the kernel's only parameter, at offset 0 of the
+    // kernel-argument segment)
+    typedef const __attribute__((address_space(4))) RevArgs KArgs;
+    KArgs *Kp = (KArgs *)__builtin_amdgcn_kernarg_segment_ptr();
 
     int b = blockIdx.x;
     if (A.xcd_remap) b = remap_xcd_r(b, gridDim.x);
@@ -94,6 +117,7 @@ __global__ __launch_bounds__(EX *W) void k_tb_reverse(RevArgs A)
     if constexpr (YP) {
         if (sy >= 0) { gyE = A.profv[1][2 * y]; gyH = A.profv[1][2 * y + 1]; }
     }
+    const unsigned fs = A.fstride;   // bytes between the components of a field or adjoint set
     const bool in_design_xy = x >= A.dlo.x && x < A.dhi.x && y >= A.dlo.y && y < A.dhi.y;
     const int ddx = A.dhi.x - A.dlo.x, ddy = A.dhi.y - A.dlo.y;
 
@@ -102,21 +126,21 @@ __global__ __launch_bounds__(EX *W) void k_tb_reverse(RevArgs A)
         const bool tin = t >= 0 && t < nz;
         const bool v = tin && incol;
         const unsigned c = ((unsigned)(tin ? t : 0) * nxy + off) * 4u;
-        auto ld = [&](const float *base) { return *(const float *)((const char *)base + c); };
+        auto ld = [&](const float *base, unsigned o) { return *(const GLOBAL float *)((const GLOBAL char *)base + o); };
 #pragma unroll
         for (int q = 0; q < 3; q++) {
-            const float e = ld(A.fin.c[q]), h = ld(A.fin.c[3 + q]);
+            const float e = ld(A.fin.c[0], c + q * fs), h = ld(A.fin.c[0], c + (3 + q) * fs);
             P.e[q] = v ? e : 0.f;
             P.h[q] = v ? h : 0.f;
         }
         {
-            const float cc = ld(g.ce);
+            const float cc = ld(g.ce, c);
             P.ce = v ? cc : 0.f;
         }
         if (A.do_adj) {
 #pragma unroll
             for (int q = 0; q < 3; q++) {
-                const float e = ld(A.ain.c[q]), h = ld(A.ain.c[3 + q]);
+                const float e = ld(A.ain.c[0], c + q * fs), h = ld(A.ain.c[0], c + (3 + q) * fs);
                 P.ae[q] = v ? e : 0.f;
                 P.ah[q] = v ? h : 0.f;
             }
@@ -139,50 +163,53 @@ __global__ __launch_bounds__(EX *W) void k_tb_reverse(RevArgs A)
             if (szt >= 0) {
                 const unsigned zi = (unsigned)szt * nxy + off;
 #pragma unroll
-                for (int q = 0; q < 4; q++) P.pb.z[q] = A.pin.a[2][q][zi];
+                for (int q = 0; q < 4; q++) P.pb.z[q] = ld(A.pin.a[2][0], zi * 4u + q * A.pstride[2]);
             }
             if constexpr (XP) {
                 const unsigned xi = (unsigned)t * (unsigned)ny * (unsigned)(2 * p) + soff_x;
 #pragma unroll
-                for (int q = 0; q < 4; q++) P.pb.x[q] = A.pin.a[0][q][xi];
+                for (int q = 0; q < 4; q++) P.pb.x[q] = ld(A.pin.a[0][0], xi * 4u + q * A.pstride[0]);
             }
             if constexpr (YP) {
                 const unsigned yi = (unsigned)t * (unsigned)(2 * p) * (unsigned)nx + soff_y;
 #pragma unroll
-                for (int q = 0; q < 4; q++) P.pb.y[q] = A.pin.a[1][q][yi];
+                for (int q = 0; q < 4; q++) P.pb.y[q] = ld(A.pin.a[1][0], yi * 4u + q * A.pstride[1]);
             }
         }
         // H^{n+1/2} on the low-face layers comes from the record of step n
         if (A.rec_h && v && t >= p - 1 && t < nz - p) {
             const bool wz = t >= p;
             if (t == p - 1 && wx && wy) {
-                const long long e = A.R.off[4] + (long long)(y - p) * A.R.Lu[2] + (x - p);
-                const long long fs = (long long)A.R.Lu[2] * A.R.Lv[2];
-                P.h[0] = A.rec_h[e];
-                P.h[1] = A.rec_h[e + fs];
+                const long long e = Kp->R.off[4] + (long long)(y - p) * Kp->R.Lu[2] + (x - p);
+                const long long fsr = (long long)Kp->R.Lu[2] * Kp->R.Lv[2];
+                P.h[0] = gld(Kp->rec_h + e);
+                P.h[1] = gld(Kp->rec_h + e + fsr);
             }
             if (wz && x == p - 1 && wy) {
-                const long long e = A.R.off[0] + (long long)(t - p) * A.R.Lu[0] + (y - p);
-                const long long fs = (long long)A.R.Lu[0] * A.R.Lv[0];
-                P.h[1] = A.rec_h[e];
-                P.h[2] = A.rec_h[e + fs];
+                const long long e = Kp->R.off[0] + (long long)(t - p) * Kp->R.Lu[0] + (y - p);
+                const long long fsr = (long long)Kp->R.Lu[0] * Kp->R.Lv[0];
+                P.h[1] = gld(Kp->rec_h + e);
+                P.h[2] = gld(Kp->rec_h + e + fsr);
             }
             if (wz && y == p - 1 && wx) {
-                const long long e = A.R.off[2] + (long long)(t - p) * A.R.Lu[1] + (x - p);
-                const long long fs = (long long)A.R.Lu[1] * A.R.Lv[1];
-                P.h[2] = A.rec_h[e];
-                P.h[0] = A.rec_h[e + fs];
+                const long long e = Kp->R.off[2] + (long long)(t - p) * Kp->R.Lu[1] + (x - p);
+                const long long fsr = (long long)Kp->R.Lu[1] * Kp->R.Lv[1];
+                P.h[2] = gld(Kp->rec_h + e);
+                P.h[0] = gld(Kp->rec_h + e + fsr);
             }
         }
-        // detector adjoint source: dJ/dE^{n+1}, dJ/dH^{n+1/2}
-        if (A.do_adj && A.with_det && v) {
-            for (int m = 0; m < A.D.ndet; m++) {
-                if (t != A.D.k[m] || x < A.D.i0[m] || x >= A.D.i1[m] || y < A.D.j0[m] || y >= A.D.j1[m]) continue;
-                const float sw = A.wS[m];
-                P.ae[0] = fmaf(sw, P.h[1], P.ae[0]);
-                P.ae[1] = fmaf(-sw, P.h[0], P.ae[1]);
-                P.ah[1] = fmaf(sw, P.e[0], P.ah[1]);
-                P.ah[0] = fmaf(-sw, P.e[1], P.ah[0]);
+        // detector adjoint source: dJ/dE^{n+1}, dJ/dH^{n+1/2} (uniform plane
+        // test against the hoisted detector planes)
+#pragma unroll
+        for (int m = 0; m < FD_MAXDET; m++) {
+            if (t == dkq[m]) {
+                if (v && x >= Kp->D.i0[m] && x < Kp->D.i1[m] && y >= Kp->D.j0[m] && y < Kp->D.j1[m]) {
+                    const float sw = Kp->wS[m];
+                    P.ae[0] = fmaf(sw, P.h[1], P.ae[0]);
+                    P.ae[1] = fmaf(-sw, P.h[0], P.ae[1]);
+                    P.ah[1] = fmaf(sw, P.e[0], P.ah[1]);
+                    P.ah[0] = fmaf(-sw, P.e[1], P.ah[0]);
+                }
             }
         }
     };
@@ -275,6 +302,7 @@ __global__ __launch_bounds__(EX *W) void k_tb_reverse(RevArgs A)
     load(zs - 1, Pa);               // plane a = zs - 1 (zero unless in the grid)
 
     for (int t = zs; t < z1 + HALO; t++) {
+        asm volatile("" : "+s"(Kp));
         const int a = t - 1, bpl = t - 2;
         RPlane<XP, YP> L;
         load(t, L);
@@ -314,20 +342,25 @@ __global__ __launch_bounds__(EX *W) void k_tb_reverse(RevArgs A)
             if (A.do_inv && interior) {
                 if (A.do_adj && A.gacc && own && a >= z0 && a < z1 && in_design_xy && a >= A.dlo.z && a < A.dhi.z) {
                     const long long dc = ((long long)(a - A.dlo.z) * ddy + (y - A.dlo.y)) * ddx + (x - A.dlo.x);
-                    float acc = A.gacc[dc];
+                    float acc = gld(A.gacc + dc);
                     if (!hex) acc = fmaf(Pa.ae[0], dy_hz - dz_hy, acc);
                     if (!hey) acc = fmaf(Pa.ae[1], dz_hx - dx_hz, acc);
                     if (!hez) acc = fmaf(Pa.ae[2], dx_hy - dy_hx, acc);
-                    A.gacc[dc] = acc;
+                    *(GLOBAL float *)(A.gacc + dc) = acc;
                 }
                 float ex = Pa.e[0], ey = Pa.e[1], ez = Pa.e[2];
-                for (int s = 0; s < g.nsrc; s++) {
-                    if (a != g.sk[s]) continue;
-                    if (g.skind[s] == 0 && (x != g.si[s] || y != g.sj[s])) continue;
-                    const float Am = g.samp[s][A.n];
-                    if (g.scomp[s] == 0 && !hex) ex = ex - Am;
-                    if (g.scomp[s] == 1 && !hey) ey = ey - Am;
-                    if (g.scomp[s] == 2 && !hez) ez = ez - Am;
+                // sources, in order (uniform plane test against the hoisted
+                // source planes; one select per component)
+#pragma unroll
+                for (int q = 0; q < FD_MAXSRC; q++) {
+                    if (a == skq[q]) {
+                        const bool hit = Kp->g.skind[q] != 0 || (x == Kp->g.si[q] && y == Kp->g.sj[q]);
+                        const float Am = sAmp[q];
+                        const int comp = Kp->g.scomp[q];
+                        ex = (hit && comp == 0 && !hex) ? ex - Am : ex;
+                        ey = (hit && comp == 1 && !hey) ? ey - Am : ey;
+                        ez = (hit && comp == 2 && !hez) ? ez - Am : ez;
+                    }
                 }
                 const float ce = Pa.ce;
                 if (!hex) ex = e_unupdate(ex, ce, dy_hz, dz_hy);
@@ -340,22 +373,22 @@ __global__ __launch_bounds__(EX *W) void k_tb_reverse(RevArgs A)
                     // E^n on the high-face layers from the record of step n-1 (E^0 = 0)
                     const bool wz = a >= p && a < nz - p;
                     if (a == nz - p && wx && wy) {
-                        const long long e = A.R.off[5] + (long long)(y - p) * A.R.Lu[2] + (x - p);
-                        const long long fs = (long long)A.R.Lu[2] * A.R.Lv[2];
-                        aEn[0] = A.rec_e ? A.rec_e[e] : 0.f;
-                        aEn[1] = A.rec_e ? A.rec_e[e + fs] : 0.f;
+                        const long long e = Kp->R.off[5] + (long long)(y - p) * Kp->R.Lu[2] + (x - p);
+                        const long long fsr = (long long)Kp->R.Lu[2] * Kp->R.Lv[2];
+                        aEn[0] = A.rec_e ? gld(Kp->rec_e + e) : 0.f;
+                        aEn[1] = A.rec_e ? gld(Kp->rec_e + e + fsr) : 0.f;
                     }
                     if (wz && x == nx - p && wy) {
-                        const long long e = A.R.off[1] + (long long)(a - p) * A.R.Lu[0] + (y - p);
-                        const long long fs = (long long)A.R.Lu[0] * A.R.Lv[0];
-                        aEn[1] = A.rec_e ? A.rec_e[e] : 0.f;
-                        aEn[2] = A.rec_e ? A.rec_e[e + fs] : 0.f;
+                        const long long e = Kp->R.off[1] + (long long)(a - p) * Kp->R.Lu[0] + (y - p);
+                        const long long fsr = (long long)Kp->R.Lu[0] * Kp->R.Lv[0];
+                        aEn[1] = A.rec_e ? gld(Kp->rec_e + e) : 0.f;
+                        aEn[2] = A.rec_e ? gld(Kp->rec_e + e + fsr) : 0.f;
                     }
                     if (wz && y == ny - p && wx) {
-                        const long long e = A.R.off[3] + (long long)(a - p) * A.R.Lu[1] + (x - p);
-                        const long long fs = (long long)A.R.Lu[1] * A.R.Lv[1];
-                        aEn[2] = A.rec_e ? A.rec_e[e] : 0.f;
-                        aEn[0] = A.rec_e ? A.rec_e[e + fs] : 0.f;
+                        const long long e = Kp->R.off[3] + (long long)(a - p) * Kp->R.Lu[1] + (x - p);
+                        const long long fsr = (long long)Kp->R.Lu[1] * Kp->R.Lv[1];
+                        aEn[2] = A.rec_e ? gld(Kp->rec_e + e) : 0.f;
+                        aEn[0] = A.rec_e ? gld(Kp->rec_e + e + fsr) : 0.f;
                     }
                 }
             }
@@ -385,17 +418,17 @@ __global__ __launch_bounds__(EX *W) void k_tb_reverse(RevArgs A)
             const bool store = own && bpl >= z0 && bpl < z1;
             if (store) {
                 const unsigned c = ((unsigned)bpl * nxy + off) * 4u;
-                auto st = [&](float *base, float v) { *(float *)((char *)base + c) = v; };
+                auto st = [&](float *base, unsigned o, float v) { *(GLOBAL float *)((GLOBAL char *)base + o) = v; };
                 if (A.do_inv && interior) {
                     const float ex = bEn[0], ey = bEn[1], ez = bEn[2];
                     const float ey_x = sEn[1][row][lr], ez_x = sEn[2][row][lr];
                     const float ex_y = sEn[0][ru][lane], ez_y = sEn[2][ru][lane];
                     const float ex_z = aEn[0], ey_z = aEn[1];
 #pragma unroll
-                    for (int q = 0; q < 3; q++) st(A.fout.c[q], bEn[q]);
-                    st(A.fout.c[3], h_unupdate(bH[0], S, ez_y - ez, ey_z - ey));
-                    st(A.fout.c[4], h_unupdate(bH[1], S, ex_z - ex, ez_x - ez));
-                    st(A.fout.c[5], h_unupdate(bH[2], S, ey_x - ey, ex_y - ex));
+                    for (int q = 0; q < 3; q++) st(A.fout.c[0], c + q * fs, bEn[q]);
+                    st(A.fout.c[0], c + 3 * fs, h_unupdate(bH[0], S, ez_y - ez, ey_z - ey));
+                    st(A.fout.c[0], c + 4 * fs, h_unupdate(bH[1], S, ex_z - ex, ez_x - ez));
+                    st(A.fout.c[0], c + 5 * fs, h_unupdate(bH[2], S, ey_x - ey, ex_y - ex));
                 }
                 if (A.do_adj) {
                     // adjoint E with the transposed H pairs
@@ -415,9 +448,9 @@ __global__ __launch_bounds__(EX *W) void k_tb_reverse(RevArgs A)
                         const float rb = sR[3][row][ll] - bR[5];
                         ez = ez + (ra + rb);
                     }
-                    st(A.aout.c[0], ex); st(A.aout.c[1], ey); st(A.aout.c[2], ez);
+                    st(A.aout.c[0], c, ex); st(A.aout.c[0], c + fs, ey); st(A.aout.c[0], c + 2 * fs, ez);
 #pragma unroll
-                    for (int q = 0; q < 3; q++) st(A.aout.c[3 + q], bAh[q]);
+                    for (int q = 0; q < 3; q++) st(A.aout.c[0], c + (3 + q) * fs, bAh[q]);
                     // psibar updates of the slab cells
                     if (p > 0) {
                         const float ce = bCe;
@@ -427,20 +460,20 @@ __global__ __launch_bounds__(EX *W) void k_tb_reverse(RevArgs A)
                             const float bE = sGz[szb][0], bHh = sGz[szb][3];
                             // z idx 0: Ex (-), idx 1: Ey (+); idx 2: Hx (+S), idx 3: Hy (-S)
                             const float w0 = -1.f * (ce * bAe[0]), w1 = 1.f * (ce * bAe[1]);
-                            A.pout.a[2][0][zi] = hex ? bPb.z[0] : bE * (bPb.z[0] + w0);
-                            A.pout.a[2][1][zi] = hey ? bPb.z[1] : bE * (bPb.z[1] + w1);
-                            A.pout.a[2][2][zi] = bHh * (bPb.z[2] + 1.f * (S * bAh[0]));
-                            A.pout.a[2][3][zi] = bHh * (bPb.z[3] + -1.f * (S * bAh[1]));
+                            st(A.pout.a[2][0], zi * 4u + 0 * A.pstride[2], hex ? bPb.z[0] : bE * (bPb.z[0] + w0));
+                            st(A.pout.a[2][0], zi * 4u + 1 * A.pstride[2], hey ? bPb.z[1] : bE * (bPb.z[1] + w1));
+                            st(A.pout.a[2][0], zi * 4u + 2 * A.pstride[2], bHh * (bPb.z[2] + 1.f * (S * bAh[0])));
+                            st(A.pout.a[2][0], zi * 4u + 3 * A.pstride[2], bHh * (bPb.z[3] + -1.f * (S * bAh[1])));
                         }
                         if constexpr (XP) {
                             if (sx >= 0) {
                                 const unsigned xi = (unsigned)bpl * (unsigned)ny * (unsigned)(2 * p) + soff_x;
                                 // x idx 0: Ey (-), idx 1: Ez (+); idx 2: Hy (+S), idx 3: Hz (-S)
                                 const float w0 = -1.f * (ce * bAe[1]), w1 = 1.f * (ce * bAe[2]);
-                                A.pout.a[0][0][xi] = hey ? bPb.x[0] : gxE.x * (bPb.x[0] + w0);
-                                A.pout.a[0][1][xi] = hez ? bPb.x[1] : gxE.x * (bPb.x[1] + w1);
-                                A.pout.a[0][2][xi] = gxH.x * (bPb.x[2] + 1.f * (S * bAh[1]));
-                                A.pout.a[0][3][xi] = gxH.x * (bPb.x[3] + -1.f * (S * bAh[2]));
+                                st(A.pout.a[0][0], xi * 4u + 0 * A.pstride[0], hey ? bPb.x[0] : gxE.x * (bPb.x[0] + w0));
+                                st(A.pout.a[0][0], xi * 4u + 1 * A.pstride[0], hez ? bPb.x[1] : gxE.x * (bPb.x[1] + w1));
+                                st(A.pout.a[0][0], xi * 4u + 2 * A.pstride[0], gxH.x * (bPb.x[2] + 1.f * (S * bAh[1])));
+                                st(A.pout.a[0][0], xi * 4u + 3 * A.pstride[0], gxH.x * (bPb.x[3] + -1.f * (S * bAh[2])));
                             }
                         }
                         if constexpr (YP) {
@@ -448,10 +481,10 @@ __global__ __launch_bounds__(EX *W) void k_tb_reverse(RevArgs A)
                                 const unsigned yi = (unsigned)bpl * (unsigned)(2 * p) * (unsigned)nx + soff_y;
                                 // y idx 0: Ez (-), idx 1: Ex (+); idx 2: Hz (+S), idx 3: Hx (-S)
                                 const float w0 = -1.f * (ce * bAe[2]), w1 = 1.f * (ce * bAe[0]);
-                                A.pout.a[1][0][yi] = hez ? bPb.y[0] : gyE.x * (bPb.y[0] + w0);
-                                A.pout.a[1][1][yi] = hex ? bPb.y[1] : gyE.x * (bPb.y[1] + w1);
-                                A.pout.a[1][2][yi] = gyH.x * (bPb.y[2] + 1.f * (S * bAh[2]));
-                                A.pout.a[1][3][yi] = gyH.x * (bPb.y[3] + -1.f * (S * bAh[0]));
+                                st(A.pout.a[1][0], yi * 4u + 0 * A.pstride[1], hez ? bPb.y[0] : gyE.x * (bPb.y[0] + w0));
+                                st(A.pout.a[1][0], yi * 4u + 1 * A.pstride[1], hex ? bPb.y[1] : gyE.x * (bPb.y[1] + w1));
+                                st(A.pout.a[1][0], yi * 4u + 2 * A.pstride[1], gyH.x * (bPb.y[2] + 1.f * (S * bAh[2])));
+                                st(A.pout.a[1][0], yi * 4u + 3 * A.pstride[1], gyH.x * (bPb.y[3] + -1.f * (S * bAh[0])));
                             }
                         }
                     }
