@@ -269,8 +269,9 @@ void build_tiles(const Geometry &G, int K, std::vector<int4> &out, int off[5][4]
         const int ZC = zchunk(G, halo);
         const int tx = kk == 0 ? rev_tile_x() : tb_tile_x(kk, tb_shape());
         const int ty = kk == 0 ? rev_tile_y() : tb_tile_y(kk, tb_shape());
-        // line-aligned shapes cut x into whole lines from x = 0
-        const auto xs = (kk > 0 && tb_tile_aligned(tb_shape())) ? split_uniform(G.nx, tx) : split_axis(G.nx, tx);
+        // line-aligned shapes (and the reverse march) cut x into whole lines
+        // from x = 0
+        const auto xs = (kk == 0 || tb_tile_aligned(tb_shape())) ? split_uniform(G.nx, tx) : split_axis(G.nx, tx);
         const auto ys = split_axis(G.ny, ty);
         std::vector<int4> cls[4];
         for (int z0 = 0; z0 < G.nz; z0 += ZC)

@@ -23,15 +23,21 @@
 
 namespace {
 
-constexpr int EX = 64;
+// Workgroup: W waves as rows of EX = 32 + 2*HALO lanes; the owned part of
+// a row is one whole 128-byte line, line aligned (x tiles are cut into whole
+// lines), so no two workgroups write parts of the same line.  The threads
+// beyond the last full row (1024 - 28*36 = 16) work on a spare LDS row and
+// write nothing.
+constexpr int HALO = 2;
+constexpr int EX = 32 + 2 * HALO;
+constexpr int W = 16;
+constexpr int NT = 64 * W;
+constexpr int EY = NT / EX;
 
 // every pointer here addresses device global memory; saying so keeps the
 // loads and stores on global (not flat) instructions
 #define GLOBAL __attribute__((address_space(1)))
 __device__ __forceinline__ float gld(const float *p) { return *(const GLOBAL float *)p; }
-constexpr int W = 16;
-constexpr int EY = W;
-constexpr int HALO = 2;
 
 __device__ __forceinline__ int remap_xcd_r(int b, int nb)
 {
@@ -53,12 +59,12 @@ template <bool XP, bool YP> struct RPlane {
 };
 
 template <bool XP, bool YP>
-__global__ __launch_bounds__(EX *W) void k_tb_reverse(RevArgs A)
+__global__ __launch_bounds__(NT) void k_tb_reverse(RevArgs A)
 {
-    __shared__ float sH[3][EY][EX];
-    __shared__ float sQ[4][EY][EX];
-    __shared__ float sEn[3][EY][EX];
-    __shared__ float sR[4][EY][EX];
+    __shared__ float sH[3][EY + 1][EX];
+    __shared__ float sQ[4][EY + 1][EX];
+    __shared__ float sEn[3][EY + 1][EX];
+    __shared__ float sR[4][EY + 1][EX];
     __shared__ float sGz[2 * 64][6];
     __shared__ float sAmp[FD_MAXSRC];   // source amplitudes of step n
 
@@ -95,16 +101,17 @@ __global__ __launch_bounds__(EX *W) void k_tb_reverse(RevArgs A)
     if (A.xcd_remap) b = remap_xcd_r(b, gridDim.x);
     const int4 tl = A.tiles[2 * b], tz = A.tiles[2 * b + 1];
     const int x0 = tl.x, x1 = tl.y, y0 = tl.z, y1 = tl.w, z0 = tz.x, z1 = tz.y;
-    const int lane = threadIdx.x & (EX - 1);
-    const int row = threadIdx.x / EX;
+    const bool active = (int)threadIdx.x < EX * EY;
+    const int lane = active ? (int)threadIdx.x % EX : 0;
+    const int row = active ? (int)threadIdx.x / EX : EY;
     const int x = x0 - HALO + lane;
     const int y = y0 - HALO + row;
-    const bool incol = x >= 0 && x < nx && y >= 0 && y < ny;
+    const bool incol = active && x >= 0 && x < nx && y >= 0 && y < ny;
     const bool own = x >= x0 && x < x1 && y >= y0 && y < y1;
     const int xc = x < 0 ? 0 : (x >= nx ? nx - 1 : x);
     const int yc = y < 0 ? 0 : (y >= ny ? ny - 1 : y);
     const unsigned off = (unsigned)yc * (unsigned)nx + (unsigned)xc;
-    const bool icol = p == 0 ? incol : (x >= p && x < nx - p && y >= p && y < ny - p);
+    const bool icol = p == 0 ? incol : (active && x >= p && x < nx - p && y >= p && y < ny - p);
     const bool wx = x >= p && x < nx - p, wy = y >= p && y < ny - p;
     const int sx = (XP && incol) ? slab_coord(x, nx, p) : -1;
     const int sy = (YP && incol) ? slab_coord(y, ny, p) : -1;
@@ -520,7 +527,7 @@ int rev_tile_y() { return EY - 2 * HALO; }
 hipError_t launch_tb_reverse_class(const RevArgs &a, int cls, hipStream_t s)
 {
     if (a.ntiles <= 0) return hipSuccess;
-    constexpr int threads = EX * W;
+    constexpr int threads = NT;
     switch (cls) {
     case 0: hipLaunchKernelGGL((k_tb_reverse<false, false>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
     case 1: hipLaunchKernelGGL((k_tb_reverse<true, false>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
