@@ -8,9 +8,11 @@ every face and T = 2000 (forward only).  The line also carries:
   - fwd_grad: the 200^3 gradient problem (CPML 10, 64^3 design cube,
     T = 1500): forward with the interface record, then the time-reversed
     adjoint pass, rated as N*T / (t_fwd + t_bwd);
-  - roofline: the forward pass (all tile classes of one K-step sweep)
-    against the 8 TB/s HBM peak, with algorithmic bytes 52 B per cell plus
-    32 B per CPML slab cell and slab axis, per time step;
+  - roofline: the forward sweep (the tile-class kernels of one K-step
+    sweep, timed on the same grid without the detector so no reduction
+    kernel is inside the events) against the 8 TB/s HBM peak, with
+    algorithmic bytes 52 B per cell plus 32 B per CPML slab cell and slab
+    axis, per time step; traffic from the committed counter summary;
   - cpu_baseline: the FP64 oracle on the host cores, timed on a bounded
     sample (the same 256^3 grid, a few time steps).
 Prints one JSON line.
@@ -18,9 +20,12 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import dataclasses
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -30,6 +35,36 @@ if ROOT not in sys.path:
 
 METRIC = "Mcell-updates/s fwd and fwd+grad (FP32, % HBM roofline); p99 latency in serving mix"
 PEAK_GBS = 8000.0
+# rocprofv3 counter summary of the forward sweep on this workload: HBM bytes
+# per sweep (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy kernel's
+# counters) and the hashes of the sources it was taken on
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "fdtd_forward_zmarch_256cube_hbm_traffic.md")
+TRAFFIC_SOURCES = ("paper_2412_12360_amd/csrc/kern_tb.hip", "paper_2412_12360_amd/csrc/fdtd_api.hip")
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(K: int):
+    """HBM bytes per K-step sweep from the committed counter summary, or None
+    when it is missing, was taken at another K, or the kernel or its host
+    tiling has changed since."""
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            text = f.read()
+    except OSError:
+        return None
+    b = re.search(r"traffic_bytes_per_sweep:\s*(\d+)", text)
+    k = re.search(r"time_block:\s*(\d+)", text)
+    h = re.search(r"sources_sha256:\s*([0-9a-f]{64})", text)
+    if not (b and k and h) or int(k.group(1)) != K or h.group(1) != source_hash():
+        return None
+    return int(b.group(1))
 
 
 def slab_cell_axes(pr) -> int:
@@ -60,6 +95,37 @@ def time_solves(solver, count: int, torch):
     e1.record(st)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1)
+
+
+def fwd_grad_run(pg, Solver, torch, time_block: int, workload: str):
+    """One warm-up solve, then a timed forward (with the interface record)
+    and gradient on the solver's stream: N*T / (t_fwd + t_bwd)."""
+    g = Solver(pg, record=True, time_block=time_block)
+    g.reset()
+    g.forward()
+    g.grad()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e2 = torch.cuda.Event(enable_timing=True)
+    e0.record(g.stream)
+    g.reset()
+    g.forward()
+    e1.record(g.stream)
+    dg, recon = g.grad()
+    e2.record(g.stream)
+    torch.cuda.synchronize()
+    tf, tb = e0.elapsed_time(e1), e1.elapsed_time(e2)
+    res = {
+        "workload": workload,
+        "value": round(pg.N * pg.T / ((tf + tb) / 1e3) / 1e6, 1), "unit": "Mcell-steps/s",
+        "fwd_ms": round(tf, 2), "bwd_ms": round(tb, 2),
+        "recon_err": float(recon.item()),
+        "hbm_footprint_gb": round(g.footprint / 1e9, 2),
+    }
+    del g
+    torch.cuda.empty_cache()
+    return res
 
 
 def cpu_baseline(pr, target_s: float = 12.0):
@@ -95,7 +161,7 @@ def copy_calibration(torch, nbytes: int = 1 << 30, reps: int = 4):
     print(json.dumps({"copy_calibration_bytes": nbytes, "reps": reps}), flush=True)
 
 
-def serving_bench(count: int, torch, seed_rate: float = 0.8):
+def serving_bench(count: int, torch, seed_rate: float = 0.8, budget_gb: float = 0.0):
     """Serving mix: `count` requests of the Poisson mix recipe (edges U{64..256},
     50% forward / 50% gradient, T = 8 x max edge, CPML 8).  Measures saturation
     throughput one-at-a-time and with continuous batching (all queued at t=0),
@@ -106,7 +172,7 @@ def serving_bench(count: int, torch, seed_rate: float = 0.8):
     descs = W.serving_mix(count=count, rate_hz=None)
     probs = {rid: W.serving_request(e, k == "gradient", seed=1000 + rid, p=8, rid=rid) for (rid, e, k, _) in descs}
     kinds = {rid: k for (rid, _, k, _) in descs}
-    budget = int(torch.cuda.mem_get_info()[0] * 0.8)
+    budget = int(budget_gb * 1e9) if budget_gb > 0 else int(torch.cuda.mem_get_info()[0] * 0.8)
 
     def run(max_active, streams, arrivals=None):
         reqs = [serve.Request(rid=rid, kind=kinds[rid], problem=probs[rid],
@@ -144,6 +210,7 @@ def serving_bench(count: int, torch, seed_rate: float = 0.8):
         "one_at_a_time_open": {"p50_s": r(seq_open["p50_latency_s"]), "p99_s": r(seq_open["p99_latency_s"])},
         "batched_open": {"p50_s": r(bat_open["p50_latency_s"]), "p99_s": r(bat_open["p99_latency_s"])},
         "speedup_throughput": r(bat["throughput_mcell_steps_s"] / seq["throughput_mcell_steps_s"]),
+        "hbm_budget_gb": round(budget / 1e9, 1),
     }
 
 
@@ -158,6 +225,10 @@ def main():
     ap.add_argument("--serving", type=int, default=0, help="requests of the serving mix to run (0 = skip)")
     ap.add_argument("--solve-steps", type=int, default=0,
                     help="profiling runs only: time steps per solve instead of the workload's (0 = workload)")
+    ap.add_argument("--large", action="store_true",
+                    help="also run the 640x640x400 forward+gradient problem (CPML 12, 4000 steps)")
+    ap.add_argument("--serving-budget-gb", type=float, default=0.0,
+                    help="HBM budget for the serving mix (0 = 80%% of free memory)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="profiling runs only: run a plain 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -184,8 +255,28 @@ def main():
     ms = time_solves(s, args.steps, torch)
     cells = pr.N * pr.T * args.steps
     value = cells / (ms / 1e3) / 1e6
-    passes = math.ceil(pr.T / K)
-    pass_ms = ms / args.steps / passes
+    del s
+    torch.cuda.empty_cache()
+    # The dominant kernel: one K-step sweep (the tile-class kernels, run
+    # concurrently and joined on the solver's stream).  Timed on the same grid
+    # without the flux detector, so that no reduction kernel falls inside the
+    # events; the sweep kernels are the same ones.
+    ps = dataclasses.replace(pr, detectors=[])
+    sw = Solver(ps, record=False, time_block=args.time_block)
+    sw.reset()
+    sw.forward()
+    sw.reset()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(sw.stream)
+    sw.forward()
+    ev1.record(sw.stream)
+    torch.cuda.synchronize()
+    passes = math.ceil(ps.T / K)
+    pass_ms = ev0.elapsed_time(ev1) / passes
+    del sw
+    torch.cuda.empty_cache()
     alg = alg_bytes_fwd_step(pr) * K
     achieved = alg / (pass_ms / 1e3) / 1e9
     out = {
@@ -209,45 +300,28 @@ def main():
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_GBS, 4), "traffic": None,
-            "kernel": f"forward z-march sweep (K={K} steps, all tile classes)",
+            "frac": round(achieved / PEAK_GBS, 4), "traffic": measured_traffic(K),
+            "kernel": f"forward z-march sweep (K={K} steps, the concurrent tile-class kernels)",
             "alg_bytes_per_launch": alg, "avg_launch_ms": round(pass_ms, 5),
+            "launches_timed": passes,
         },
     }
-    del s
-    torch.cuda.empty_cache()
 
     if not args.no_grad:
         pg = W.config3(T=args.solve_steps) if args.solve_steps else W.config3()
-        g = Solver(pg, record=True, time_block=args.time_block)
-        g.reset()
-        g.forward()
-        g.grad()
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e2 = torch.cuda.Event(enable_timing=True)
-        e0.record(g.stream)
-        g.reset()
-        g.forward()
-        e1.record(g.stream)
-        dg, recon = g.grad()
-        e2.record(g.stream)
-        torch.cuda.synchronize()
-        tf, tb = e0.elapsed_time(e1), e1.elapsed_time(e2)
-        out["fwd_grad"] = {
-            "workload": "200^3 grid, CPML 10, 64^3 design cube rho~U[0,1] (seed 3), eps_r = 2.25 + 10 rho, "
-                        "1500 steps, objective = time-integrated flux; forward with interface record, "
-                        "then inverse-step + adjoint backward",
-            "value": round(pg.N * pg.T / ((tf + tb) / 1e3) / 1e6, 1), "unit": "Mcell-steps/s",
-            "fwd_ms": round(tf, 2), "bwd_ms": round(tb, 2),
-            "recon_err": float(recon.item()),
-        }
-        del g
-        torch.cuda.empty_cache()
+        out["fwd_grad"] = fwd_grad_run(pg, Solver, torch, args.time_block,
+                                       "200^3 grid, CPML 10, 64^3 design cube rho~U[0,1] (seed 3), eps_r = 2.25 + 10 rho, "
+                                       "1500 steps, objective = time-integrated flux; forward with interface record, "
+                                       "then inverse-step + adjoint backward")
+
+    if args.large and not args.no_grad:
+        out["fwd_grad_large"] = fwd_grad_run(W.config4(T=args.solve_steps) if args.solve_steps else W.config4(),
+                                             Solver, torch, args.time_block,
+                                             "640x640x400 grid, CPML 12, 256x256x128 design box (blurred binary rho, "
+                                             "seed 5), eps_r = 2.25 + 10 rho, 4000 steps, interface record in HBM")
 
     if args.serving > 0:
-        out["serving"] = serving_bench(args.serving, torch)
+        out["serving"] = serving_bench(args.serving, torch, budget_gb=args.serving_budget_gb)
 
     if rank == 0 and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pr)
