@@ -547,7 +547,9 @@ fdtd_status reverse_fused(fdtd_ctx *h, int n, int do_inv, int do_adj, int with_d
     a.g = h->g;
     a.fin = fields_of(h, h->cur);
     a.fout = fields_of(h, h->cur ^ 1);
-    a.ain = do_adj ? adj_of(h, h->acur) : Fields{};
+    // without an adjoint the march still issues its adjoint loads (from the
+    // forward input set, a readable buffer of the same size) and drops them
+    a.ain = do_adj ? adj_of(h, h->acur) : fields_of(h, h->cur);
     a.aout = do_adj ? adj_of(h, h->acur ^ 1) : Fields{};
     a.pin = psibar_of(h, h->apar);
     a.pout = psibar_of(h, h->apar ^ 1);

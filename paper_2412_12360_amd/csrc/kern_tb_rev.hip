@@ -129,31 +129,25 @@ __global__ __launch_bounds__(NT) void k_tb_reverse(RevArgs A)
     const int ddx = A.dhi.x - A.dlo.x, ddy = A.dhi.y - A.dlo.y;
 
     // ---------------------------------------------------------- plane fetch
-    auto load = [&](int t, RPlane<XP, YP> &P) {
+    // load_raw issues the loads of plane t; finish (one iteration later, so
+    // the fetch overlaps a whole plane of work) zeroes what lies outside the
+    // grid, replays the record and adds the detector adjoint source.
+    auto load_raw = [&](int t, RPlane<XP, YP> &P) __attribute__((always_inline)) {
         const bool tin = t >= 0 && t < nz;
-        const bool v = tin && incol;
         const unsigned c = ((unsigned)(tin ? t : 0) * nxy + off) * 4u;
         auto ld = [&](const float *base, unsigned o) { return *(const GLOBAL float *)((const GLOBAL char *)base + o); };
 #pragma unroll
         for (int q = 0; q < 3; q++) {
-            const float e = ld(A.fin.c[0], c + q * fs), h = ld(A.fin.c[0], c + (3 + q) * fs);
-            P.e[q] = v ? e : 0.f;
-            P.h[q] = v ? h : 0.f;
+            P.e[q] = ld(A.fin.c[0], c + q * fs);
+            P.h[q] = ld(A.fin.c[0], c + (3 + q) * fs);
         }
-        {
-            const float cc = ld(g.ce, c);
-            P.ce = v ? cc : 0.f;
-        }
-        if (A.do_adj) {
+        P.ce = ld(g.ce, c);
+        // (issued on every path, so the compiler's wait counts stay exact;
+        // without an adjoint, ain points at a readable set and finish drops it)
 #pragma unroll
-            for (int q = 0; q < 3; q++) {
-                const float e = ld(A.ain.c[0], c + q * fs), h = ld(A.ain.c[0], c + (3 + q) * fs);
-                P.ae[q] = v ? e : 0.f;
-                P.ah[q] = v ? h : 0.f;
-            }
-        } else {
-#pragma unroll
-            for (int q = 0; q < 3; q++) { P.ae[q] = 0.f; P.ah[q] = 0.f; }
+        for (int q = 0; q < 3; q++) {
+            P.ae[q] = ld(A.ain.c[0], c + q * fs);
+            P.ah[q] = ld(A.ain.c[0], c + (3 + q) * fs);
         }
 #pragma unroll
         for (int q = 0; q < 4; q++) P.pb.z[q] = 0.f;
@@ -183,6 +177,20 @@ __global__ __launch_bounds__(NT) void k_tb_reverse(RevArgs A)
                 for (int q = 0; q < 4; q++) P.pb.y[q] = ld(A.pin.a[1][0], yi * 4u + q * A.pstride[1]);
             }
         }
+    };
+    auto finish = [&](int t, const RPlane<XP, YP> &R, RPlane<XP, YP> &P) __attribute__((always_inline)) {
+        const bool tin = t >= 0 && t < nz;
+        const bool v = tin && incol;
+        const bool va = v && A.do_adj;
+#pragma unroll
+        for (int q = 0; q < 3; q++) {
+            P.e[q] = v ? R.e[q] : 0.f;
+            P.h[q] = v ? R.h[q] : 0.f;
+            P.ae[q] = va ? R.ae[q] : 0.f;
+            P.ah[q] = va ? R.ah[q] : 0.f;
+        }
+        P.ce = v ? R.ce : 0.f;
+        P.pb = R.pb;
         // H^{n+1/2} on the low-face layers comes from the record of step n
         if (A.rec_h && v && t >= p - 1 && t < nz - p) {
             const bool wz = t >= p;
@@ -306,13 +314,14 @@ __global__ __launch_bounds__(NT) void k_tb_reverse(RevArgs A)
     float Hm0 = 0.f, Hm1 = 0.f;     // Hx, Hy of plane a-1
 
     const int zs = z0 - HALO;
-    load(zs - 1, Pa);               // plane a = zs - 1 (zero unless in the grid)
-
-    for (int t = zs; t < z1 + HALO; t++) {
-        asm volatile("" : "+s"(Kp));
+    {
+        RPlane<XP, YP> R;
+        load_raw(zs - 1, R);        // plane a = zs - 1 (zero unless in the grid)
+        finish(zs - 1, R, Pa);
+    }
+    // one step of the march; L = the finished plane t
+    auto body = [&](const int t, const RPlane<XP, YP> &L) __attribute__((always_inline)) {
         const int a = t - 1, bpl = t - 2;
-        RPlane<XP, YP> L;
-        load(t, L);
         float Qa[6], bR[6];
         qcoef(Pa, a, Qa);
         rcoef(bAh, bPb, bpl, bR);
@@ -515,6 +524,40 @@ __global__ __launch_bounds__(NT) void k_tb_reverse(RevArgs A)
         Hm0 = Pa.h[0];
         Hm1 = Pa.h[1];
         Pa = L;
+    };
+    if constexpr (!XP && !YP) {
+        // Interior tiles: plane t+1 is fetched while plane t is worked on;
+        // two raw plane buffers used alternately (a copy of a plane in flight
+        // would be a use and stall on it).  An odd count gets one more step,
+        // which stores nothing: its planes lie beyond the owned range.
+        RPlane<XP, YP> R0, R1;
+        load_raw(zs, R0);
+        for (int t = zs; t < z1 + HALO; t += 2) {
+            {
+                asm volatile("" : "+s"(Kp));
+                load_raw(t + 1, R1);
+                RPlane<XP, YP> L;
+                finish(t, R0, L);
+                body(t, L);
+            }
+            {
+                asm volatile("" : "+s"(Kp));
+                load_raw(t + 2, R0);
+                RPlane<XP, YP> L;
+                finish(t + 1, R1, L);
+                body(t + 1, L);
+            }
+        }
+    } else {
+        // slab tiles carry the auxiliaries too and have no registers for a
+        // second plane in flight: fetch and use
+        for (int t = zs; t < z1 + HALO; t++) {
+            asm volatile("" : "+s"(Kp));
+            RPlane<XP, YP> R, L;
+            load_raw(t, R);
+            finish(t, R, L);
+            body(t, L);
+        }
     }
 }
 
