@@ -39,7 +39,7 @@ PEAK_GBS = 8000.0
 # per sweep (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy kernel's
 # counters) and the hashes of the sources it was taken on
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "fdtd_forward_zmarch_256cube_hbm_traffic.md")
-TRAFFIC_SOURCES = ("paper_2412_12360_amd/csrc/kern_tb.hip", "paper_2412_12360_amd/csrc/fdtd_api.hip")
+TRAFFIC_SOURCES = ("paper_2412_12360_amd/csrc/kern_tb.hip",)
 
 
 def source_hash() -> str:
@@ -52,8 +52,8 @@ def source_hash() -> str:
 
 def measured_traffic(K: int):
     """HBM bytes per K-step sweep from the committed counter summary, or None
-    when it is missing, was taken at another K, or the kernel or its host
-    tiling has changed since."""
+    when it is missing, was taken at another K, or the forward kernel source
+    has changed since."""
     try:
         with open(TRAFFIC_PROFILE) as f:
             text = f.read()
