@@ -7,7 +7,8 @@ flux detector.  The default workload is a 256^3 grid with a 10-cell CPML on
 every face and T = 2000 (forward only).  The line also carries:
   - fwd_grad: the 200^3 gradient problem (CPML 10, 64^3 design cube,
     T = 1500): forward with the interface record, then the time-reversed
-    adjoint pass, rated as N*T / (t_fwd + t_bwd);
+    adjoint pass, rated as N*T / (t_fwd + t_bwd); beside it the same
+    gradient by checkpointing (the method time reversal replaces);
   - roofline: the forward sweep (the tile-class kernels of one K-step
     sweep, timed on the same grid without the detector so no reduction
     kernel is inside the events) against the 8 TB/s HBM peak, with
@@ -97,7 +98,7 @@ def time_solves(solver, count: int, torch):
     return e0.elapsed_time(e1)
 
 
-def fwd_grad_run(pg, Solver, torch, time_block: int, workload: str):
+def fwd_grad_run(pg, Solver, torch, time_block: int, workload: str, checkpoint: bool = False):
     """One warm-up solve, then a timed forward (with the interface record)
     and gradient on the solver's stream: N*T / (t_fwd + t_bwd)."""
     g = Solver(pg, record=True, time_block=time_block)
@@ -123,6 +124,28 @@ def fwd_grad_run(pg, Solver, torch, time_block: int, workload: str):
         "recon_err": float(recon.item()),
         "hbm_footprint_gb": round(g.footprint / 1e9, 2),
     }
+    if checkpoint:
+        # the baseline the time reversal replaces: checkpoints every sqrt(T)
+        # steps, each segment recomputed and kept, adjoint-only reverse steps
+        seg = max(1, int(round(math.sqrt(pg.T))))
+        store = torch.empty(g.checkpoint_bytes(seg), dtype=torch.uint8, device=g.device)
+        g.grad_checkpointed(seg, store=store)
+        torch.cuda.synchronize()
+        c0 = torch.cuda.Event(enable_timing=True)
+        c1 = torch.cuda.Event(enable_timing=True)
+        c0.record(g.stream)
+        dck, _ = g.grad_checkpointed(seg, store=store)
+        c1.record(g.stream)
+        torch.cuda.synchronize()
+        tc = c0.elapsed_time(c1)
+        res["checkpointed"] = {
+            "what": f"forward + gradient by checkpointing every {seg} steps (segments recomputed and kept)",
+            "value": round(pg.N * pg.T / (tc / 1e3) / 1e6, 1), "unit": "Mcell-steps/s", "ms": round(tc, 2),
+            "extra_hbm_gb": round(store.numel() / 1e9, 2),
+            "time_reversal_speedup": round(tc / (tf + tb), 3),
+            "grad_rel_diff_vs_time_reversal": float(((dck - dg).norm() / dg.norm()).item()),
+        }
+        del store
     del g
     torch.cuda.empty_cache()
     return res
@@ -312,7 +335,7 @@ def main():
         out["fwd_grad"] = fwd_grad_run(pg, Solver, torch, args.time_block,
                                        "200^3 grid, CPML 10, 64^3 design cube rho~U[0,1] (seed 3), eps_r = 2.25 + 10 rho, "
                                        "1500 steps, objective = time-integrated flux; forward with interface record, "
-                                       "then inverse-step + adjoint backward")
+                                       "then inverse-step + adjoint backward", checkpoint=True)
 
     if args.large and not args.no_grad:
         out["fwd_grad_large"] = fwd_grad_run(W.config4(T=args.solve_steps) if args.solve_steps else W.config4(),

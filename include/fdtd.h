@@ -134,6 +134,27 @@ fdtd_status fdtd_inverse(fdtd_handle h, int32_t n_steps);
  * arithmetic) over the RMS of the interior fields at t = T. */
 fdtd_status fdtd_grad(fdtd_handle h, float *dJ_deps, float *recon_err);
 
+/* Gradient by checkpointing, the baseline the time-reversal gradient is
+ * measured against (section 2.2 compares the two): runs the forward pass from
+ * zero fields, keeping the complete state (fields and CPML auxiliaries) at
+ * the start of every segment of `segment` steps, then walks the segments
+ * backwards: restores the segment's first state, recomputes the segment one
+ * step at a time keeping the fields after each step, and applies the adjoint
+ * steps (no inverse) to the kept states.  Same dJ/deps as fdtd_grad up to the
+ * rounding of the time reversal.
+ *   store: caller-owned device memory, 256-byte aligned, of at least
+ *          fdtd_checkpoint_bytes(h, segment) bytes (ceil(T/segment) full
+ *          states + segment field states); the library does not allocate.
+ *   dJ_deps: device, design cells; J: device [1] or NULL (the objective).
+ * Needs a handle created with record = 1 (for the adjoint state; the record
+ * itself is not used) on the z-march path.  Any t on entry; t = 0 on return
+ * with zeroed fields.  Errors: E_STATE without record, E_UNSUPPORTED on the
+ * per-cell fallback, E_INVALID for a segment outside [1, T] or NULL/unaligned
+ * pointers, E_NOMEM when store_bytes is too small. */
+fdtd_status fdtd_checkpoint_bytes(fdtd_handle h, int32_t segment, size_t *bytes);
+fdtd_status fdtd_grad_checkpointed(fdtd_handle h, int32_t segment, void *store, size_t store_bytes,
+                                   float *dJ_deps, float *J);
+
 /* Replace 1/eps_r (device, N values) and the per-cell update coefficients;
  * allowed when t = 0. */
 fdtd_status fdtd_set_inv_eps(fdtd_handle h, const float *inv_eps);

@@ -540,12 +540,13 @@ fdtd_status reverse_step(fdtd_ctx *h, int n, int do_adj)
 
 // one reverse step n with the fused z-march kernel (all state ping-pong);
 // do_inv = 0 applies only the adjoint of the source-free step map
-fdtd_status reverse_fused(fdtd_ctx *h, int n, int do_inv, int do_adj, int with_det, float *gacc)
+fdtd_status reverse_fused(fdtd_ctx *h, int n, int do_inv, int do_adj, int with_det, float *gacc,
+                          const Fields *fin = nullptr)
 {
     const Geometry &G = h->geo;
     RevArgs a;
     a.g = h->g;
-    a.fin = fields_of(h, h->cur);
+    a.fin = fin ? *fin : fields_of(h, h->cur);
     a.fout = fields_of(h, h->cur ^ 1);
     // without an adjoint the march still issues its adjoint loads (from the
     // forward input set, a readable buffer of the same size) and drops them
@@ -865,6 +866,148 @@ fdtd_status fdtd_grad(fdtd_handle h, float *dJ_deps, float *recon_err)
     }
     HIPCHK(h, launch_interior_sumsq(h->g, fields_of(h, h->cur), h->parts[1], &np, h->stream));
     if (recon_err) HIPCHK(h, launch_recon(h->parts[0], h->parts[1], np, recon_err, h->stream));
+    HIPCHK(h, launch_deps(h->gacc, h->d_design, G.design_cells, h->desc.courant, dJ_deps, h->stream));
+    st = zero_forward(h);
+    if (st != FDTD_OK) return st;
+    HIPCHK(h, launch_fill(h->trace, (long long)h->T * std::max(1, G.D.ndet), 0.f, h->stream));
+    h->t = 0;
+    return FDTD_OK;
+}
+
+// ----------------------------------------------------------------------
+// Checkpointed gradient (a comparator for the time-reversal gradient): the
+// store holds nseg complete forward states (fields and CPML auxiliaries,
+// one per segment start) followed by the fields after each step of one
+// segment.
+namespace {
+
+struct CkptPlan {
+    int C, nseg;
+    size_t snap_bytes, step_bytes, total;
+};
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+CkptPlan ckpt_plan(const fdtd_ctx *h, int C)
+{
+    CkptPlan P;
+    P.C = C;
+    P.nseg = (h->T + C - 1) / C;
+    const Geometry &G = h->geo;
+    P.step_bytes = 6 * align256((size_t)G.N * 4);
+    P.snap_bytes = P.step_bytes;
+    if (G.p > 0)
+        for (int a = 0; a < 3; a++) P.snap_bytes += 4 * align256((size_t)G.slab_n[a] * 4);
+    P.total = (size_t)P.nseg * P.snap_bytes + (size_t)C * P.step_bytes;
+    return P;
+}
+
+// the 6 field arrays and (if snap) the 12 auxiliaries of one stored state
+void ckpt_arrays(const fdtd_ctx *h, char *base, float *fld[6], float *psi[3][4])
+{
+    const Geometry &G = h->geo;
+    size_t off = 0;
+    for (int q = 0; q < 6; q++) {
+        fld[q] = (float *)(base + off);
+        off += align256((size_t)G.N * 4);
+    }
+    if (psi)
+        for (int a = 0; a < 3; a++)
+            for (int q = 0; q < 4; q++) {
+                psi[a][q] = G.p > 0 ? (float *)(base + off) : nullptr;
+                if (G.p > 0) off += align256((size_t)G.slab_n[a] * 4);
+            }
+}
+
+fdtd_status copy_state(fdtd_ctx *h, float *const dfld[6], float *const dpsi[3][4], float *const sfld[6],
+                       float *const spsi[3][4])
+{
+    const Geometry &G = h->geo;
+    for (int q = 0; q < 6; q++) HIPCHK(h, launch_copy(dfld[q], sfld[q], G.N, h->stream));
+    if (dpsi && spsi && G.p > 0)
+        for (int a = 0; a < 3; a++)
+            for (int q = 0; q < 4; q++) HIPCHK(h, launch_copy(dpsi[a][q], spsi[a][q], G.slab_n[a], h->stream));
+    return FDTD_OK;
+}
+
+}  // namespace
+
+fdtd_status fdtd_checkpoint_bytes(fdtd_handle h, int32_t segment, size_t *bytes)
+{
+    if (!h || !bytes) return fail(h, FDTD_E_INVALID, "NULL argument");
+    if (segment < 1 || segment > h->T) return fail(h, FDTD_E_INVALID, "segment %d not in [1, T]", segment);
+    *bytes = ckpt_plan(h, segment).total;
+    return FDTD_OK;
+}
+
+fdtd_status fdtd_grad_checkpointed(fdtd_handle h, int32_t segment, void *store, size_t store_bytes,
+                                   float *dJ_deps, float *J)
+{
+    if (!h) return fail(nullptr, FDTD_E_INVALID, "handle is NULL");
+    if (!h->desc.record) return fail(h, FDTD_E_STATE, "the checkpointed gradient needs the adjoint state (record = 1)");
+    if (h->naive) return fail(h, FDTD_E_UNSUPPORTED, "the checkpointed gradient runs on the z-march path only");
+    if (segment < 1 || segment > h->T) return fail(h, FDTD_E_INVALID, "segment %d not in [1, T]", segment);
+    if (!store || !dJ_deps) return fail(h, FDTD_E_INVALID, "store or dJ_deps is NULL");
+    if (((uintptr_t)store & 255) != 0) return fail(h, FDTD_E_INVALID, "store not 256-byte aligned");
+    const CkptPlan P = ckpt_plan(h, segment);
+    if (store_bytes < P.total) return fail(h, FDTD_E_NOMEM, "store %zu bytes < %zu", store_bytes, P.total);
+    // the reverse march addresses a kept field set from its first array at
+    // the workspace's component spacing: the store must use the same one
+    if ((size_t)h->fstride != align256((size_t)h->geo.N * 4))
+        return fail(h, FDTD_E_UNSUPPORTED, "field spacing %u differs from the store's", h->fstride);
+    const Geometry &G = h->geo;
+    char *base = (char *)store;
+    auto snap = [&](int sidx, float *fld[6], float *psi[3][4]) { ckpt_arrays(h, base + (size_t)sidx * P.snap_bytes, fld, psi); };
+    auto kept = [&](int j, float *fld[6]) { ckpt_arrays(h, base + (size_t)P.nseg * P.snap_bytes + (size_t)j * P.step_bytes, fld, nullptr); };
+
+    // forward from zero fields, keeping the state at every segment start
+    fdtd_status st = zero_forward(h);
+    if (st != FDTD_OK) return st;
+    HIPCHK(h, launch_fill(h->trace, (long long)h->T * std::max(1, G.D.ndet), 0.f, h->stream));
+    for (int sidx = 0; sidx < P.nseg; sidx++) {
+        float *sf[6], *sp[3][4];
+        snap(sidx, sf, sp);
+        st = copy_state(h, sf, sp, h->fld[h->cur], h->psi[h->cur]);
+        if (st != FDTD_OK) return st;
+        const int n0 = sidx * P.C, cnt = std::min(P.C, h->T - n0);
+        st = advance(h, n0, cnt, 1, 0, 1);
+        if (st != FDTD_OK) return st;
+    }
+    if (J) {
+        if (G.D.ndet > 0)
+            HIPCHK(h, launch_objective(h->trace, h->T, G.D.ndet, h->wdev, h->desc.courant, J, h->stream));
+        else
+            HIPCHK(h, launch_fill(J, 1, 0.f, h->stream));
+    }
+
+    // backwards over the segments: restore, recompute keeping every step's
+    // fields, then the adjoint steps (no inverse) on the kept states
+    st = zero_adjoint(h);
+    if (st != FDTD_OK) return st;
+    HIPCHK(h, launch_fill(h->gacc, G.design_cells, 0.f, h->stream));
+    for (int sidx = P.nseg - 1; sidx >= 0; sidx--) {
+        const int n0 = sidx * P.C, n1 = std::min(h->T, n0 + P.C);
+        float *sf[6], *sp[3][4];
+        snap(sidx, sf, sp);
+        st = copy_state(h, h->fld[h->cur], h->psi[h->cur], sf, sp);
+        if (st != FDTD_OK) return st;
+        for (int n = n0; n < n1; n++) {
+            st = advance(h, n, 1, 1, 0, 0);
+            if (st != FDTD_OK) return st;
+            float *kf[6];
+            kept(n - n0, kf);
+            st = copy_state(h, kf, nullptr, h->fld[h->cur], nullptr);
+            if (st != FDTD_OK) return st;
+        }
+        for (int n = n1 - 1; n >= n0; n--) {
+            float *kf[6];
+            kept(n - n0, kf);
+            Fields F;
+            for (int q = 0; q < 6; q++) F.c[q] = kf[q];
+            st = reverse_fused(h, n, 0, 1, 1, h->gacc, &F);
+            if (st != FDTD_OK) return st;
+        }
+    }
     HIPCHK(h, launch_deps(h->gacc, h->d_design, G.design_cells, h->desc.courant, dJ_deps, h->stream));
     st = zero_forward(h);
     if (st != FDTD_OK) return st;

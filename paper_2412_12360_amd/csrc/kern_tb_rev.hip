@@ -355,15 +355,18 @@ __global__ __launch_bounds__(NT) void k_tb_reverse(RevArgs A)
             const float dz_hx = hx - Hm0, dx_hz = hz - hz_x;
             const float dx_hy = hy - hy_x, dy_hx = hx - hx_y;
             const bool hex = y == 0 || a == 0, hey = x == 0 || a == 0, hez = x == 0 || y == 0;
+            // dJ/dd += Ebar' . curl H^{n+1/2} (also in the adjoint-only mode,
+            // where the forward state comes from storage instead of the inverse)
+            if (interior && A.do_adj && A.gacc && own && a >= z0 && a < z1 && in_design_xy && a >= A.dlo.z &&
+                a < A.dhi.z) {
+                const long long dc = ((long long)(a - A.dlo.z) * ddy + (y - A.dlo.y)) * ddx + (x - A.dlo.x);
+                float acc = gld(A.gacc + dc);
+                if (!hex) acc = fmaf(Pa.ae[0], dy_hz - dz_hy, acc);
+                if (!hey) acc = fmaf(Pa.ae[1], dz_hx - dx_hz, acc);
+                if (!hez) acc = fmaf(Pa.ae[2], dx_hy - dy_hx, acc);
+                *(GLOBAL float *)(A.gacc + dc) = acc;
+            }
             if (A.do_inv && interior) {
-                if (A.do_adj && A.gacc && own && a >= z0 && a < z1 && in_design_xy && a >= A.dlo.z && a < A.dhi.z) {
-                    const long long dc = ((long long)(a - A.dlo.z) * ddy + (y - A.dlo.y)) * ddx + (x - A.dlo.x);
-                    float acc = gld(A.gacc + dc);
-                    if (!hex) acc = fmaf(Pa.ae[0], dy_hz - dz_hy, acc);
-                    if (!hey) acc = fmaf(Pa.ae[1], dz_hx - dx_hz, acc);
-                    if (!hez) acc = fmaf(Pa.ae[2], dx_hy - dy_hx, acc);
-                    *(GLOBAL float *)(A.gacc + dc) = acc;
-                }
                 float ex = Pa.e[0], ey = Pa.e[1], ez = Pa.e[2];
                 // sources, in order (uniform plane test against the hoisted
                 // source planes; one select per component)

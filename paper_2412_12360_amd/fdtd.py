@@ -51,7 +51,8 @@ class fdtd_flux_detector(C.Structure):
 ENTRY_POINTS = [
     "fdtd_footprint", "fdtd_create", "fdtd_forward", "fdtd_inverse", "fdtd_grad", "fdtd_set_inv_eps",
     "fdtd_reset", "fdtd_destroy", "fdtd_time", "fdtd_last_error", "fdtd_field_ptr", "fdtd_state_arrays",
-    "fdtd_linear_steps", "fdtd_record_ptr", "fdtd_time_block",
+    "fdtd_linear_steps", "fdtd_record_ptr", "fdtd_time_block", "fdtd_checkpoint_bytes",
+    "fdtd_grad_checkpointed",
 ]
 
 _lib = None
@@ -77,6 +78,8 @@ def lib():
     L.fdtd_forward.argtypes = [H, C.c_int32, fp, fp]
     L.fdtd_inverse.argtypes = [H, C.c_int32]
     L.fdtd_grad.argtypes = [H, fp, fp]
+    L.fdtd_checkpoint_bytes.argtypes = [H, C.c_int32, C.POINTER(C.c_size_t)]
+    L.fdtd_grad_checkpointed.argtypes = [H, C.c_int32, C.c_void_p, C.c_size_t, fp, fp]
     L.fdtd_set_inv_eps.argtypes = [H, fp]
     L.fdtd_reset.argtypes = [H]
     L.fdtd_destroy.argtypes = [H]
@@ -244,6 +247,28 @@ class Solver:
         r = self.torch.zeros(1, dtype=self.torch.float32, device=self.device)
         self.fdtd_grad(g, r)
         return g, r
+
+    def checkpoint_bytes(self, segment: int) -> int:
+        """Device bytes the checkpointed gradient keeps for this segment length."""
+        v = C.c_size_t(0)
+        check(lib().fdtd_checkpoint_bytes(self.handle, int(segment), C.byref(v)), self.handle)
+        return int(v.value)
+
+    def grad_checkpointed(self, segment: int, store=None):
+        """The checkpointed gradient (comparator of grad()): runs the forward
+        pass itself; returns dJ/deps_r over the design box [dz, dy, dx] and J.
+        `store`: optional preallocated uint8 device tensor of at least
+        checkpoint_bytes(segment) bytes (256-byte aligned)."""
+        nbytes = self.checkpoint_bytes(segment)
+        if store is None:
+            store = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.device)
+        g = self.torch.empty(self.prob.design_shape(), dtype=self.torch.float32, device=self.device)
+        J = self.torch.zeros(1, dtype=self.torch.float32, device=self.device)
+        check(lib().fdtd_grad_checkpointed(self.handle, int(segment), C.c_void_p(store.data_ptr()),
+                                           C.c_size_t(store.numel() * store.element_size()),
+                                           C.c_void_p(g.data_ptr()), C.c_void_p(J.data_ptr())), self.handle)
+        self._keep_store = store
+        return g, J
 
     def fdtd_set_inv_eps(self, inv_eps):
         self._keep = inv_eps

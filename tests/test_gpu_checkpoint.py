@@ -1,0 +1,70 @@
+"""The checkpointed gradient (the baseline of the time-reversal gradient,
+arXiv 2412.12360 section 2.2): same objective bit for bit, the same dJ/deps
+as the time-reversal gradient up to the rounding of the reversal, and the
+FP64 oracle's stored-history gradient within the gradient tolerance; for a
+segment that divides T, one that does not (a ragged last segment), one step
+and all T steps per segment."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle.oracle import Oracle
+from paper_2412_12360_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GRAD_TOL = 1e-3
+
+
+def announce(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("shape,p,T,d", [((40, 36, 44), 6, 160, 8), ((70, 45, 38), 5, 90, 8)])
+def test_checkpointed_gradient_matches_reversal_and_oracle(shape, p, T, d):
+    from paper_2412_12360_amd.fdtd import Solver
+    pr = W.small_cpml(nx=shape[0], ny=shape[1], nz=shape[2], p=p, T=T, d=d, seed=21)
+    announce(f"checkpointed gradient {shape} p={p} T={T}")
+    o = Oracle(pr)
+    g_ref, J_ref, _ = o.grad_history()
+    ref = o.deps_design(g_ref)
+    s = Solver(pr, record=True)
+    _, J_rev = s.forward()
+    g_rev, _ = s.grad()
+    torch.cuda.synchronize()
+    g_rev = g_rev.cpu().numpy()
+    J_rev = float(J_rev.item())
+    assert np.linalg.norm(ref) > 1e-8 * abs(J_ref)   # the signal reaches the detector
+    assert rel_l2(g_rev, ref) <= GRAD_TOL
+    for seg in (7, T // 2 + 1, 1, T):
+        announce(f"checkpointed gradient {shape} segment={seg}")
+        g_ck, J_ck = s.grad_checkpointed(seg)
+        torch.cuda.synchronize()
+        g_ck = g_ck.cpu().numpy()
+        assert float(J_ck.item()) == J_rev          # the same forward kernels, any segmenting
+        assert rel_l2(g_ck, ref) <= GRAD_TOL
+        assert rel_l2(g_ck, g_rev) <= 1e-4         # time reversal only adds its rounding
+        assert s.t == 0
+    # the handle is left reset: the time-reversal gradient still works
+    s.forward()
+    g2, _ = s.grad()
+    torch.cuda.synchronize()
+    assert np.array_equal(g2.cpu().numpy(), g_rev)
+
+
+def test_checkpoint_store_too_small_is_rejected():
+    from paper_2412_12360_amd.fdtd import Solver, FdtdError
+    pr = W.small_cpml(nx=40, ny=36, nz=30, p=4, T=12, d=6, seed=22)
+    announce("checkpoint store too small")
+    s = Solver(pr, record=True)
+    need = s.checkpoint_bytes(4)
+    small = torch.empty(need - 256, dtype=torch.uint8, device=s.device)
+    with pytest.raises(FdtdError):
+        s.grad_checkpointed(4, store=small)
+    with pytest.raises(FdtdError):
+        s.checkpoint_bytes(0)
