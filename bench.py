@@ -14,6 +14,9 @@ every face and T = 2000 (forward only).  The line also carries:
     kernel is inside the events) against the 8 TB/s HBM peak, with
     algorithmic bytes 52 B per cell plus 32 B per CPML slab cell and slab
     axis, per time step; traffic from the committed counter summary;
+  - serving: the first requests of the serving mix (12 by default), one at
+    a time and with continuous batching: throughput, and p50/p99 latency
+    under Poisson arrivals at 0.8x the one-at-a-time rate;
   - cpu_baseline: the FP64 oracle on the host cores, timed on a bounded
     sample (the same 256^3 grid, a few time steps).
 Prints one JSON line.
@@ -245,7 +248,8 @@ def main():
     ap.add_argument("--time-block", type=int, default=0)
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serving", type=int, default=0, help="requests of the serving mix to run (0 = skip)")
+    ap.add_argument("--serving", type=int, default=12,
+                    help="requests of the serving mix to run (0 = skip; the first requests of the 500-request mix)")
     ap.add_argument("--solve-steps", type=int, default=0,
                     help="profiling runs only: time steps per solve instead of the workload's (0 = workload)")
     ap.add_argument("--large", action="store_true",
