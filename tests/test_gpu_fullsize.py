@@ -90,3 +90,36 @@ def test_adjoint_transpose_full_size(which):
     rhs = sum(dot(a, b) for a, b in zip(x0, Mty))
     scale = np.sqrt(sum(dot(a, a) for a in Mx) * sum(dot(b, b) for b in y0))
     assert abs(lhs - rhs) <= 2e-6 * scale
+
+
+def test_directional_fd_full_size_c3():
+    """200^3, CPML 10, 1500 steps: the time-reversal gradient against a
+    central difference of the GPU objective in eps_r along the gradient's
+    own direction (by Cauchy-Schwarz the two agree only if the computed
+    gradient is parallel to the true one and of the right length) and along
+    its restriction to the lower half of the design cube.  A random direction
+    is not resolvable here: it moves J by about one float32 ulp.  The step is
+    chosen so that J changes by about 1e-3 of itself, in the linear regime."""
+    from paper_2412_12360_amd.fdtd import Solver
+    from paper_2412_12360_amd.autograd import objective
+    pr = W.config3()
+    announce("full-size directional finite difference c3")
+    s = Solver(pr, record=True)
+    eps = torch.tensor(W.eps_from_rho(pr.rho), dtype=torch.float32, device=s.device).requires_grad_(True)
+    J = objective(eps, s)
+    J.backward()
+    g = eps.grad.detach().double()
+    J0 = float(J.item())
+    half = g.clone()
+    half[g.shape[0] // 2:] = 0.0
+    for name, v in (("gradient", g.clone()), ("lower half", half)):
+        v = v / v.norm()
+        dJ = float((g * v).sum().item())
+        h = min(2.0, 1e-3 * abs(J0) / max(abs(dJ), 1e-30))
+        with torch.no_grad():
+            Jp = float(objective((eps.double() + h * v).float(), s).item())
+            Jm = float(objective((eps.double() - h * v).float(), s).item())
+        fd = (Jp - Jm) / (2 * h)
+        print(f"[gpu-case] {name}: J {J0:.6e} h {h:.3e} adjoint {dJ:.6e} fd {fd:.6e}", flush=True)
+        assert abs(Jp - Jm) > 1e-5 * abs(J0)          # resolvable in float32 (about 90 ulps of J)
+        assert abs(fd - dJ) <= 2e-2 * abs(dJ)
