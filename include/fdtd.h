@@ -53,7 +53,7 @@ typedef enum {
     FDTD_E_NOMEM = 2,        /* workspace smaller than fdtd_footprint()        */
     FDTD_E_DEVICE = 3,       /* a HIP call or kernel launch failed             */
     FDTD_E_STATE = 4,        /* call not allowed in the handle's current state */
-    FDTD_E_UNSUPPORTED = 5   /* valid request this build does not implement    */
+    FDTD_E_UNSUPPORTED = 5   /* valid request this library does not implement  */
 } fdtd_status;
 
 enum { FDTD_EX = 0, FDTD_EY, FDTD_EZ, FDTD_HX, FDTD_HY, FDTD_HZ };

@@ -5,7 +5,10 @@
     detector on, against the FP64 oracle on the whole grid;
   - 200^3 and 640x640x400: the adjoint (fused reverse kernel) is the exact
     transpose of the forward step map, <M x, y> = <x, M^T y>, on random states
-    including every CPML auxiliary array.
+    including every CPML auxiliary array;
+  - 200^3, 1500 steps: the time-reversal gradient against central differences
+    of the GPU objective along the gradient direction and along its restriction
+    to the lower half of the design box.
 """
 import numpy as np
 import pytest

@@ -4,7 +4,9 @@ Each test would fail on a plausible mistake in the oracle: a dropped curl
 term, a wrong sign, a transposed difference, a misplaced boundary, a wrong
 Courant scaling, a broken record or inverse, a non-transposed adjoint.
 """
+import decimal
 import math
+import pathlib
 
 import numpy as np
 import pytest
@@ -42,21 +44,43 @@ def random_state(prob, seed, with_psi=False):
 
 # ---------------------------------------------------- P13: step-count rule
 
-def test_step_counts_match_paper():
-    """Section 3.1 Table 2 (200 fs at 25/20/10/5/2.5 nm), section 3.2 (5245 steps
-    at 20 nm, same 200 fs) and section 3.3 (1574 steps at 100 nm, 300 fs)."""
-    for dx_nm, steps in [(25, 4196), (20, 5245), (10, 10490), (5, 20980), (2.5, 41960)]:
-        assert W.steps_for(200e-15, dx_nm * 1e-9) == steps
-    assert W.steps_for(300e-15, 100e-9) == 1574
+GOLDEN = pathlib.Path(__file__).parent / "golden" / "paper_step_and_cell_counts.txt"
 
 
-def test_cell_counts_match_paper():
-    """Domain / dx reproduces the printed cell counts (section 3.1, 3.2, 3.3)."""
-    cells = lambda dims, dx: int(np.prod([round(d / dx) for d in dims]))
-    assert cells((6000, 4000, 1500), 25) == 2_304_000
-    assert cells((6000, 4000, 1500), 2.5) == 2_304_000_000
-    assert cells((4000, 4000, 1500), 20) == 3_000_000
-    assert cells((40000, 17000, 10000), 100) == 6_800_000
+def printed_counts():
+    rows = []
+    for line in GOLDEN.read_text().splitlines():
+        if line.strip() and not line.startswith("#"):
+            f = line.split()
+            rows.append(dict(dx_nm=float(f[0]), L_um=tuple(float(v) for v in f[1:4]),
+                             fs=float(f[4]), cells=decimal.Decimal(f[5]), steps=int(f[6]),
+                             where=f[7]))
+    return rows
+
+
+def test_golden_table_is_complete():
+    """Table 2 has five resolutions; sections 3.2 and 3.3 one scene each."""
+    where = [r["where"] for r in printed_counts()]
+    assert where.count("Table2") == 5 and "Sec3.2" in where and "Sec3.3" in where
+
+
+@pytest.mark.parametrize("row", printed_counts(), ids=lambda r: f"{r['where']}-{r['dx_nm']}nm")
+def test_step_counts_match_paper(row):
+    """The 0.99 Courant factor on the 3D limit, rounded to nearest, gives every
+    printed step count (section 3.1 Table 2, sections 3.2 and 3.3)."""
+    assert W.steps_for(row["fs"] * 1e-15, row["dx_nm"] * 1e-9) == row["steps"]
+
+
+@pytest.mark.parametrize("row", printed_counts(), ids=lambda r: f"{r['where']}-{r['dx_nm']}nm")
+def test_cell_counts_match_paper(row):
+    """Volume / dx^3 gives the printed cell count to its last printed digit."""
+    cells = 1
+    for L in row["L_um"]:
+        n = L * 1000.0 / row["dx_nm"]
+        assert abs(n - round(n)) < 1e-9          # the volume is a whole number of cells
+        cells *= int(round(n))
+    unit = decimal.Decimal(1).scaleb(row["cells"].as_tuple().exponent)
+    assert abs(decimal.Decimal(cells) - row["cells"]) <= unit / 2
 
 
 # ------------------------------------------------- P1: discrete energy
