@@ -20,8 +20,11 @@
  *     written in its plain recursive form for every (component, derivative axis)
  *     pair; psi arrays exist on the whole grid and stay exactly 0 where the
  *     profile is zero (b = 1, a = 0, kappa = 1).
- *   - additive ("soft") E sources, a non-interpolated Poynting-flux detector on
- *     a z-normal plane and the objective J = S * sum_n w * P[n] (section 2.1,
+ *   - additive sources on any field component, at one cell or on a whole
+ *     z-normal plane: E sources after the E half step, H sources after the H
+ *     half step (a total-field/scattered-field plane is one E and one H plane
+ *     source, see oracle.py); a non-interpolated Poynting-flux detector on a
+ *     z-normal plane and the objective J = S * sum_n w * P[n] (section 2.1,
  *     detectors without interpolation).
  *   - the interface record (section 2.2): every step, tangential H^{n+1/2} on
  *     the PML-side layer p-1 of the three low faces and tangential E^{n+1} on
@@ -55,7 +58,7 @@ typedef struct {
     const double *d;                /* N values of 1/eps_r */
     int nsrc;
     int src_kind[OR_MAXSRC];        /* 0 = point, 1 = full z-normal plane */
-    int src_comp[OR_MAXSRC];        /* 0,1,2 = Ex,Ey,Ez */
+    int src_comp[OR_MAXSRC];        /* 0..5 = Ex,Ey,Ez,Hx,Hy,Hz */
     int src_i[OR_MAXSRC], src_j[OR_MAXSRC], src_k[OR_MAXSRC];
     const double *src_amp[OR_MAXSRC];   /* amplitude per step, length >= T */
     int ndet;
@@ -207,30 +210,34 @@ static void e_sweep(const or_problem *P, double *st, const or_prof *PE)
             }
 }
 
-static void add_sources(const or_problem *P, double *st, int n, double sign)
+/* sources on the E components (hfield = 0) or on the H components (hfield = 1);
+ * held E cells take no source */
+static void add_sources(const or_problem *P, double *st, int n, double sign, int hfield)
 {
     for (int s = 0; s < P->nsrc; s++) {
         int q = P->src_comp[s];
+        if ((q >= 3) != hfield) continue;
         double A = sign * P->src_amp[s][n];
         double *F = slot(st, P, q);
         if (P->src_kind[s] == 0) {
             int i = P->src_i[s], j = P->src_j[s], k = P->src_k[s];
-            if (!e_held(q, i, j, k)) F[idx(P, i, j, k)] += A;
+            if (q >= 3 || !e_held(q, i, j, k)) F[idx(P, i, j, k)] += A;
         } else {
             int k = P->src_k[s];
             for (int j = 0; j < P->ny; j++)
                 for (int i = 0; i < P->nx; i++)
-                    if (!e_held(q, i, j, k)) F[idx(P, i, j, k)] += A;
+                    if (q >= 3 || !e_held(q, i, j, k)) F[idx(P, i, j, k)] += A;
         }
     }
 }
 
 /* inverse-step variant: subtract only on interior cells */
-static void sub_sources_interior(const or_problem *P, double *st, int n)
+static void sub_sources_interior(const or_problem *P, double *st, int n, int hfield)
 {
     int p = P->p;
     for (int s = 0; s < P->nsrc; s++) {
         int q = P->src_comp[s];
+        if ((q >= 3) != hfield) continue;
         double A = P->src_amp[s][n];
         double *F = slot(st, P, q);
         for (int k = p; k < P->nz - p; k++)
@@ -239,7 +246,7 @@ static void sub_sources_interior(const or_problem *P, double *st, int n)
                     int hit = P->src_kind[s] == 0
                                   ? (i == P->src_i[s] && j == P->src_j[s] && k == P->src_k[s])
                                   : (k == P->src_k[s]);
-                    if (hit && !e_held(q, i, j, k)) F[idx(P, i, j, k)] -= A;
+                    if (hit && (q >= 3 || !e_held(q, i, j, k))) F[idx(P, i, j, k)] -= A;
                 }
     }
 }
@@ -303,16 +310,17 @@ static void record_io(const or_problem *P, double *st, double *rec, int which, i
     }
 }
 
-/* one forward step n: psi_H, H, psi_E, E, sources, detectors, record */
+/* one forward step n: psi_H, H, H sources, psi_E, E, E sources, detectors, record */
 /* trow (ndet values, may be NULL) receives this step's fluxes; rec (may be
  * NULL) this step's record. */
 static void step_fwd(const or_problem *P, double *st, int n, const or_prof *PE, const or_prof *PH,
                      double *trow, double *rec, int with_src)
 {
     h_sweep(P, st, PH);
+    if (with_src) add_sources(P, st, n, 1.0, 1);
     if (rec) record_io(P, st, rec, 0, 0);
     e_sweep(P, st, PE);
-    if (with_src) add_sources(P, st, n, 1.0);
+    if (with_src) add_sources(P, st, n, 1.0, 0);
     if (rec) record_io(P, st, rec, 1, 0);
     if (trow)
         for (int m = 0; m < P->ndet; m++) trow[m] = det_flux(P, st, m);
@@ -347,7 +355,8 @@ void or_step_linear(const or_problem *P, double *st, int T)
 
 /* ----------------------------------------------------------- inverse step
  * Undo step n on the interior I = [p, n-p)^3 (the whole box when p == 0):
- * E^n = E^{n+1} - src_n - S*D*C^T H^{n+1/2}, then H^{n-1/2} = H^{n+1/2} + S*C E^n.
+ * E^n = E^{n+1} - srcE_n - S*D*C^T H^{n+1/2}, then
+ * H^{n-1/2} = H^{n+1/2} - srcH_n + S*C E^n.
  * Before each half the out-of-interior neighbours are written from the record:
  * H^{n+1/2} on the low faces from rec_n, E^n on the high faces from rec_{n-1}
  * (E^0 = 0).  PML cells are not reconstructed. */
@@ -357,7 +366,7 @@ static void inverse_step(const or_problem *P, double *st, int n, const double *r
     int p = P->p;
     size_t rf = or_record_floats(P);
     if (p > 0) record_io(P, st, (double *)(rec + (size_t)n * rf), 0, 1);
-    sub_sources_interior(P, st, n);
+    sub_sources_interior(P, st, n, 0);
     double *H[3] = {slot(st, P, 3), slot(st, P, 4), slot(st, P, 5)};
     double *E[3] = {slot(st, P, 0), slot(st, P, 1), slot(st, P, 2)};
 #pragma omp parallel for schedule(static)
@@ -381,6 +390,7 @@ static void inverse_step(const or_problem *P, double *st, int n, const double *r
             free(zero);
         }
     }
+    sub_sources_interior(P, st, n, 1);
 #pragma omp parallel for schedule(static)
     for (int k = p; k < P->nz - p; k++)
         for (int j = p; j < P->ny - p; j++)

@@ -79,6 +79,61 @@ def _load():
     return _lib
 
 
+def tfsf_incident(S: float, d: float, amp: np.ndarray, pol: int):
+    """Incident fields of a one-sided total-field/scattered-field plane along +z
+    (section 2.1 names the source type; the formulation here is the textbook
+    one for a Yee grid).
+
+    A 1D Yee line along z carries the incident wave, with the grid's Courant
+    number S and the plane's 1/eps_r d, so that for a wave uniform in x and y
+    it is exactly the 3D update restricted to z.  E lives on its nodes, H
+    between them.  Node 0 is driven, E_0^{n+1} = amp[n] (a hard source), one
+    cell below the plane; node 1 is the first total-field E plane k0.  At step n
+    the 3D curl across the boundary misses the incident part on each side:
+      - the scattered-field H layer k0-1 reads total E at k0, so after its H
+        half step it takes +S E_1^n (Hy, Ex polarisation) or -S E_1^n (Hx, Ey);
+      - the total-field E plane k0 reads scattered H at k0-1, so after its E
+        half step it takes +S d H_0^{n+1/2} (on the polarisation component).
+    The line has T/2 + 8 nodes and a conducting far end, which a wave from
+    node 0 cannot reach and return from within T steps (a Yee update moves
+    information at most one cell per step).
+
+    Returns (aE, aH, E_line, H_line): the two amplitude series and the line
+    after len(amp) steps."""
+    T = len(amp)
+    L = T // 2 + 8
+    E = np.zeros(L)
+    H = np.zeros(L - 1)
+    aE = np.zeros(T)
+    aH = np.zeros(T)
+    sg = 1.0 if pol == 0 else -1.0
+    for n in range(T):
+        aH[n] = sg * S * E[1]
+        H -= S * (E[1:] - E[:-1])
+        aE[n] = S * d * H[0]
+        E[1:-1] -= S * d * (H[1:] - H[:-1])
+        E[0] = float(amp[n])
+    return aE, aH, E, H
+
+
+def expand_sources(prob, d: np.ndarray):
+    """The problem's sources as plain additive sources (kind 0 point, kind 1
+    plane; components 0..5): a TFSF source becomes its E plane source on k0 and
+    its H plane source on k0-1, fed by tfsf_incident with 1/eps_r of the plane's
+    centre cell."""
+    out = []
+    for src in prob.sources:
+        if src.kind != 2:
+            out.append((src.kind, src.comp, src.i, src.j, src.k, np.asarray(src.amp, np.float64)))
+            continue
+        assert src.comp in (0, 1)
+        dc = float(d[src.k, prob.ny // 2, prob.nx // 2])
+        aE, aH, _, _ = tfsf_incident(float(prob.S), dc, np.asarray(src.amp, np.float64), src.comp)
+        out.append((1, src.comp, 0, 0, src.k, aE))
+        out.append((1, 4 if src.comp == 0 else 3, 0, 0, src.k - 1, aH))
+    return out
+
+
 def _ptr(a: np.ndarray):
     assert a.dtype == np.float64 and a.flags.c_contiguous
     return a.ctypes.data_as(C.POINTER(C.c_double))
@@ -100,15 +155,17 @@ class Oracle:
         s.m, s.sigma_max = float(prob.pml_m), float(prob.pml_sigma_max)
         s.kappa_max, s.alpha_max = float(prob.pml_kappa_max), float(prob.pml_alpha_max)
         s.d = _ptr(self.d)
-        assert len(prob.sources) <= MAXSRC and len(prob.detectors) <= MAXDET
+        srcs = expand_sources(prob, self.d)
+        assert len(srcs) <= MAXSRC and len(prob.detectors) <= MAXDET
         self._amps = []
-        s.nsrc = len(prob.sources)
-        for i, src in enumerate(prob.sources):
-            a = np.ascontiguousarray(src.amp, dtype=np.float64)
+        s.nsrc = len(srcs)
+        for i, (kind, comp, si, sj, sk, amp) in enumerate(srcs):
+            a = np.ascontiguousarray(amp, dtype=np.float64)
             self._amps.append(a)
-            s.src_kind[i], s.src_comp[i] = src.kind, src.comp
-            s.src_i[i], s.src_j[i], s.src_k[i] = src.i, src.j, src.k
+            s.src_kind[i], s.src_comp[i] = kind, comp
+            s.src_i[i], s.src_j[i], s.src_k[i] = si, sj, sk
             s.src_amp[i] = _ptr(a)
+        self.sources = srcs
         s.ndet = len(prob.detectors)
         for i, det in enumerate(prob.detectors):
             s.det_k[i] = det.k

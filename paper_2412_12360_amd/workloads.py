@@ -42,12 +42,12 @@ def steps_for(duration_s: float, dx_m: float) -> int:
 
 @dataclasses.dataclass
 class Source:
-    kind: int            # 0 = point, 1 = whole z-normal plane
-    comp: int            # 0, 1, 2 = Ex, Ey, Ez
+    kind: int            # 0 = point, 1 = whole z-normal plane, 2 = TFSF plane wave along +z
+    comp: int            # 0..5 = Ex, Ey, Ez, Hx, Hy, Hz; kind 2: 0 (Ex) or 1 (Ey) polarisation
     i: int
     j: int
-    k: int
-    amp: np.ndarray      # float32, one value per step
+    k: int               # kind 2: the first total-field E plane
+    amp: np.ndarray      # float32, one value per step (kind 2: the incident waveform)
 
 
 @dataclasses.dataclass
@@ -147,6 +147,16 @@ def _sheet_problem(name, nx, ny, nz, p, T, eps, eps_bg, design_lo, design_hi, rh
     return Problem(name=name, nx=nx, ny=ny, nz=nz, S=S, p=p, pml_m=m, pml_sigma_max=sig,
                    pml_kappa_max=kap, pml_alpha_max=alp, inv_eps=inv, sources=[src],
                    detectors=[det], design_lo=design_lo, design_hi=design_hi, T=T, rho=rho)
+
+
+def with_tfsf(prob: Problem, k: Optional[int] = None, comp: int = 0) -> Problem:
+    """The same problem with its first source replaced by a one-sided
+    total-field/scattered-field plane wave along +z (section 2.1 names this
+    source type) with the same waveform, on the plane k (default: that
+    source's plane)."""
+    s0 = prob.sources[0]
+    src = Source(kind=2, comp=comp, i=0, j=0, k=s0.k if k is None else k, amp=s0.amp)
+    return dataclasses.replace(prob, name=prob.name + "_tfsf", sources=[src] + list(prob.sources[1:]))
 
 
 def config1(T: int = 500, n: int = 32) -> Problem:

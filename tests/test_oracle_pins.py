@@ -11,7 +11,7 @@ import pathlib
 import numpy as np
 import pytest
 
-from oracle.oracle import NSLOT, Oracle
+from oracle.oracle import NSLOT, Oracle, tfsf_incident
 from paper_2412_12360_amd import workloads as W
 
 
@@ -179,14 +179,16 @@ def test_resonance_converges_to_continuum():
 
 # ------------------------------------------ P4: forward then inverse
 
-def test_inverse_recovers_pec_state():
+@pytest.mark.parametrize("comp", [2, 4])
+def test_inverse_recovers_pec_state(comp):
     """On a closed conducting box the whole update is reversible (section 2.2):
-    T forward steps with a source, then T inverse steps, recover the start."""
+    T forward steps with a source (on E, or on H), then T inverse steps,
+    recover the start."""
     nx, ny, nz = 14, 12, 10
     rng = np.random.default_rng(7)
     d = 1.0 / rng.uniform(1.0, 12.25, size=(nz, ny, nx))
     T = 80
-    src = W.Source(kind=0, comp=2, i=7, j=6, k=5, amp=W.gaussian_pulse(T, 20, 6))
+    src = W.Source(kind=0, comp=comp, i=7, j=6, k=5, amp=W.gaussian_pulse(T, 20, 6))
     pr = pec_problem(nx, ny, nz, d=d, sources=[src], T=T)
     o = Oracle(pr)
     st = random_state(pr, 8)
@@ -197,10 +199,13 @@ def test_inverse_recovers_pec_state():
     assert np.max(np.abs(st[:6] - s0[:6])) < 1e-12 * np.max(np.abs(s0[:6])) * T
 
 
-def test_inverse_recovers_cpml_interior_with_record():
+@pytest.mark.parametrize("tfsf", [False, True])
+def test_inverse_recovers_cpml_interior_with_record(tfsf):
     """With CPML only the interior is reversible; the six face records (2
-    tangential components each) make the interior exactly recoverable."""
+    tangential components each) make the interior exactly recoverable (with
+    the sheet source, and with the TFSF plane's E and H sources)."""
     pr = W.small_cpml(nx=26, ny=24, nz=28, p=5, T=120)
+    pr = W.with_tfsf(pr) if tfsf else pr
     o = Oracle(pr)
     st = o.new_state()
     # a nonzero start inside the interior
@@ -251,9 +256,11 @@ def tiny_grad_problem(T=60):
     return W.small_cpml(nx=16, ny=16, nz=16, p=3, T=T, d=4, seed=12, name="tiny")
 
 
-def test_history_gradient_equals_reversed_gradient():
+@pytest.mark.parametrize("tfsf", [False, True])
+def test_history_gradient_equals_reversed_gradient(tfsf):
     """Time reversal reaches exactly the plain stored-history VJP (section 2.2)."""
     pr = W.small_cpml(nx=22, ny=20, nz=24, p=4, T=90, d=6, seed=13)
+    pr = W.with_tfsf(pr) if tfsf else pr
     o = Oracle(pr)
     g1, J1, tr1 = o.grad_history(seg=7)
     g2, J2, tr2, recon = o.grad_reversed()
@@ -266,10 +273,12 @@ def test_history_gradient_equals_reversed_gradient():
     assert np.linalg.norm(g1 - g3) <= 1e-13 * np.linalg.norm(g1)
 
 
-def test_gradient_matches_central_differences_all_design_cells():
+@pytest.mark.parametrize("tfsf", [False, True])
+def test_gradient_matches_central_differences_all_design_cells(tfsf):
     """Central differences in rho (h = 1e-3) against the adjoint dJ/drho = 10 dJ/deps
-    on every design cell of a tiny CPML problem."""
+    on every design cell of a tiny CPML problem (sheet source, or TFSF plane)."""
     pr = tiny_grad_problem()
+    pr = W.with_tfsf(pr) if tfsf else pr
     o = Oracle(pr)
     g, J, _ = o.grad_history()
     # dJ/drho = dJ/deps * 10 with eps = 2.25 + 10 rho, evaluated at the exact float64 d
@@ -419,3 +428,95 @@ def test_plane_wave_flux_is_positive_upward():
     pr2 = dataclasses.replace(pr, detectors=[below])
     _, J2, _, _ = Oracle(pr2).run()
     assert J2 < 0
+
+
+# ------------------------------------ P14: total-field/scattered-field plane
+
+def tfsf_box(T, k0, pol, n_extra=10):
+    """A conducting box wide enough that no column within T+3 cells of the
+    centre can see a side wall within T steps (a Yee update moves information
+    at most one cell per step), and tall enough that the incident wave does not
+    reach the top wall; eps_r = 2.25 everywhere."""
+    n = 2 * T + n_extra
+    nz = k0 + T + 6
+    inv = np.full((nz, n, n), 1.0 / 2.25, np.float32)
+    amp = W.ramped_sine(T, W.courant(), lambda0=12.0, periods=1)
+    src = W.Source(kind=2, comp=pol, i=0, j=0, k=k0, amp=amp)
+    return pec_problem(n, n, nz, d=inv, sources=[src], T=T), amp
+
+
+@pytest.mark.parametrize("pol", [0, 1])
+def test_tfsf_total_field_is_the_incident_line_scattered_field_is_zero(pol):
+    """Away from the side walls a plane wave along z is exactly a 1D problem:
+    above the plane the 3D field equals the incident line (E on its nodes, the
+    matching H between them), below it every component stays zero.  A wrong
+    sign, a wrong time level of either correction or a line with other
+    coefficients than the grid leaks 0.3-1.5 of the field below the plane."""
+    T, k0 = 24, 6
+    pr, amp = tfsf_box(T, k0, pol)
+    o = Oracle(pr)
+    st = o.new_state()
+    o.forward(st, T)
+    n = pr.nx
+    _, _, El, Hl = tfsf_incident(pr.S, float(o.d[k0, n // 2, n // 2]), amp.astype(np.float64), pol)
+    c = slice(T + 3, n - T - 3)
+    assert c.stop > c.start
+    Ecomp = st[pol][:, c, c]
+    Hcomp = st[4 if pol == 0 else 3][:, c, c]
+    hsign = 1.0 if pol == 0 else -1.0
+    scale = np.max(np.abs(El))
+    assert scale > 0.1
+    j = np.arange(k0, pr.nz) - (k0 - 1)          # line node of each total-field plane
+    Eref = np.array([El[q] if q < len(El) else 0.0 for q in j])
+    Href = np.array([Hl[q] if q < len(Hl) else 0.0 for q in j])
+    assert np.max(np.abs(Ecomp[k0:] - Eref[:, None, None])) <= 1e-13 * scale
+    assert np.max(np.abs(Hcomp[k0:] - hsign * Href[:, None, None])) <= 1e-13 * scale
+    for q in range(6):
+        assert np.max(np.abs(st[q][:k0, c, c])) <= 1e-14 * scale
+    for q in {0, 1, 2, 3, 4, 5} - {pol, 4 if pol == 0 else 3}:
+        assert np.max(np.abs(st[q][:, c, c])) == 0.0
+
+
+@pytest.mark.parametrize("lam,d", [(20.0, 1 / 2.25), (12.0, 1.0), (30.0, 1 / 12.25)])
+def test_tfsf_line_obeys_discrete_dispersion(lam, d):
+    """The incident line is a 1D Yee grid: behind the switched-on front its
+    field is a sinusoid whose wavenumber kk obeys the closed-form discrete
+    dispersion sin(w/2) = S sqrt(d) sin(kk/2), so E[k-1] + E[k+1] = 2 cos(kk) E[k].
+    The continuum value cos(w / (S sqrt(d))) differs by 2e-3 to 1e-2."""
+    S = W.courant()
+    T = 1200
+    amp = W.ramped_sine(T, S, lambda0=lam, periods=2).astype(np.float64)
+    w = 2 * math.pi * S / lam
+    _, _, E, _ = tfsf_incident(S, d, amp, 0)
+    v = S * math.sqrt(d)
+    settled = int(0.8 * v * (T - round(2 * 2 * math.pi / w)))
+    k = np.arange(2, settled)
+    c_fit = np.sum((E[k - 1] + E[k + 1]) * E[k]) / (2 * np.sum(E[k] ** 2))
+    c_discrete = 1 - 2 * (math.sin(w / 2) / v) ** 2
+    c_continuum = math.cos(w / v)
+    assert abs(c_fit - c_discrete) <= 1e-4
+    assert abs(c_fit - c_continuum) >= 1e-3
+
+
+def test_tfsf_is_one_sided_sheet_is_not():
+    """In a CPML box the TFSF plane radiates only upward: the flux through a
+    plane below it is below 1e-6 of the flux above (8e-9 measured), while the
+    soft sheet radiates as much downward as upward."""
+    S = W.courant()
+    n, nz, p, T, k0 = 40, 64, 8, 260, 24
+    m, sig, kap, alp = W.pml_grading(S, 2.25)
+    inv = np.full((nz, n, n), 1.0 / 2.25, np.float32)
+    amp = W.ramped_sine(T, S, lambda0=16.0, periods=2)
+    dets = [W.Detector(k=k0 - 6, i0=p, i1=n - p, j0=p, j1=n - p), W.Detector(k=k0 + 14, i0=p, i1=n - p, j0=p, j1=n - p)]
+    ratio = {}
+    for kind in (1, 2):
+        src = W.Source(kind=kind, comp=0, i=0, j=0, k=k0, amp=amp)
+        pr = W.Problem(name="one_sided", nx=n, ny=n, nz=nz, S=S, p=p, pml_m=m, pml_sigma_max=sig,
+                       pml_kappa_max=kap, pml_alpha_max=alp, inv_eps=inv, sources=[src], detectors=dets,
+                       design_lo=(16, 16, 34), design_hi=(24, 24, 40), T=T)
+        _, _, trace, _ = Oracle(pr).run()
+        up = np.sum(trace[:, 1])
+        assert up > 0
+        ratio[kind] = abs(np.sum(trace[:, 0])) / up
+    assert ratio[2] < 1e-6
+    assert ratio[1] > 0.5
