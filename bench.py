@@ -101,6 +101,38 @@ def time_solves(solver, count: int, torch):
     return e0.elapsed_time(e1)
 
 
+def tfsf_run(pr, Solver, torch, time_block: int, steps: int, W):
+    """The headline forward workload with the one-sided total-field/scattered-
+    field plane (Ex polarised, same plane) in place of the soft sheet: full
+    solves timed like the headline value, and the material upload that reruns
+    the plane's incident line (fdtd_set_inv_eps) timed on the solver's stream."""
+    pt = W.with_tfsf(pr)
+    s = Solver(pt, record=False, time_block=time_block)
+    s.reset()
+    s.forward()
+    ms = time_solves(s, steps, torch)
+    s.reset()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s.stream)
+    s.set_inv_eps(s.inv_eps)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    line_ms = e0.elapsed_time(e1)
+    del s
+    torch.cuda.empty_cache()
+    return {
+        "workload": "the same grid, materials, detector and waveform with a one-sided TFSF plane wave "
+                    f"(Ex, first total-field plane k = {pt.sources[0].k}) instead of the sheet",
+        "value": round(pt.N * pt.T * steps / (ms / 1e3) / 1e6, 1),
+        "unit": "Mcell-updates/s",
+        "ms_per_solve": round(ms / steps, 3),
+        "incident_line_ms": round(line_ms, 3),
+        "incident_line_note": f"material upload plus the {pt.T}-step incident line, once per create or set_inv_eps",
+    }
+
+
 def fwd_grad_run(pg, Solver, torch, time_block: int, workload: str, checkpoint: bool = False):
     """One warm-up solve, then a timed forward (with the interface record)
     and gradient on the solver's stream: N*T / (t_fwd + t_bwd)."""
@@ -247,6 +279,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--time-block", type=int, default=0)
     ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--no-tfsf", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving", type=int, default=12,
                     help="requests of the serving mix to run (0 = skip; the first requests of the 500-request mix)")
@@ -333,6 +366,9 @@ def main():
             "launches_timed": passes,
         },
     }
+
+    if not args.no_tfsf:
+        out["tfsf"] = tfsf_run(pr, Solver, torch, args.time_block, args.steps, W)
 
     if not args.no_grad:
         pg = W.config3(T=args.solve_steps) if args.solve_steps else W.config3()

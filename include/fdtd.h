@@ -78,10 +78,23 @@ typedef struct {
                                  /* 1..4); results are bitwise independent of K    */
 } fdtd_desc;
 
-/* Additive E source (section 2.1 uses total-field/scattered-field injection;
- * this is the soft variant): after each E update, E_comp += amp[n] at one cell
- * (kind 0) or on every cell of the z-normal plane k (kind 1).  Held PEC cells
- * are skipped.  amp: device, n_steps floats (copied at create). */
+/* Sources (section 2.1).
+ * kind 0 / 1, additive ("soft"): after the half step of step n that updates
+ *   component comp (0..5 = Ex, Ey, Ez, Hx, Hy, Hz), that component gains amp[n]
+ *   at the cell (i, j, k) (kind 0) or on every cell of the z-normal plane k
+ *   (kind 1).  Held PEC cells of E components are skipped.
+ * kind 2, one-sided total-field/scattered-field plane wave along +z (the
+ *   source type section 2.1 names): comp = polarisation (0 = Ex, 1 = Ey);
+ *   k = the first total-field E plane, p+1 <= k < nz-p, with the layers k-1
+ *   and k outside the design box's z range; amp = the incident waveform,
+ *   imposed on a 1D incident line one cell below the plane.  The library runs
+ *   that line (the grid's S, eps_r of the plane's centre cell) at create and
+ *   at fdtd_set_inv_eps, and adds its two corrections every step: S/eps H_inc
+ *   to the polarisation component on plane k, +-S E_inc to Hy (Ex) or Hx (Ey)
+ *   on layer k-1.  For normal incidence the line is exact, so below the plane
+ *   the grid holds only the field scattered back.  Takes two of the
+ *   FDTD_MAX_SOURCES slots; i, j are ignored.
+ * amp: device, n_steps floats (copied at create). */
 typedef struct {
     int32_t kind, comp, i, j, k;
     const float *amp;

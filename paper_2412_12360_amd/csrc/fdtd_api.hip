@@ -74,7 +74,13 @@ struct fdtd_ctx {
     int acur = 0, apar = 0;
     float *ce = nullptr, *inv_eps = nullptr, *d_design = nullptr;
     float *prof[2][3][3];
-    float *amps[FDTD_MAX_SOURCES];
+    float *amps[FDTD_MAX_SOURCES];         // per internal source (see expand_sources)
+    // total-field/scattered-field planes: their waveforms and the incident line
+    int ntfsf = 0;
+    int tfsf_pub[FD_MAXSRC / 2];           // public source index of each plane
+    int tfsf_slot[FD_MAXSRC / 2][2];       // internal E and H source slots
+    float *twave[FD_MAXSRC / 2];
+    float *tline = nullptr;
     float *red = nullptr;
     float *trace = nullptr, *planes = nullptr, *wdev = nullptr, *rec = nullptr, *gacc = nullptr;
     float *parts[2] = {nullptr, nullptr};
@@ -113,6 +119,32 @@ fdtd_status fail(fdtd_ctx *h, fdtd_status st, const char *fmt, ...)
 
 int dim_of(const fdtd_desc *d, int a) { return a == 0 ? d->nx : a == 1 ? d->ny : d->nz; }
 
+// The kernels see plain additive sources only (kind 0 point, kind 1 z-plane,
+// components 0..5).  A total-field/scattered-field plane (public kind 2) is
+// two of them: its E correction on plane k (component = polarisation) and its
+// H correction on layer k-1 (Hy for Ex, Hx for Ey), both fed by the incident
+// line.  Returns the number of internal sources (may exceed FD_MAXSRC).
+struct IntSrc {
+    int kind, comp, i, j, k;
+    int pub;       // public source index
+    int role;      // 0: the caller's amplitude, 1: TFSF E correction, 2: TFSF H correction
+};
+int expand_sources(const fdtd_source *src, int nsrc, IntSrc *out, int cap)
+{
+    int n = 0;
+    auto put = [&](IntSrc v) { if (n < cap) out[n] = v; n++; };
+    for (int s = 0; s < nsrc; s++) {
+        const fdtd_source &q = src[s];
+        if (q.kind != 2) {
+            put({q.kind, q.comp, q.i, q.j, q.k, s, 0});
+        } else {
+            put({1, q.comp, 0, 0, q.k, s, 1});
+            put({1, q.comp == 0 ? 4 : 3, 0, 0, q.k - 1, s, 2});
+        }
+    }
+    return n;
+}
+
 fdtd_status validate(fdtd_ctx *h, const fdtd_desc *d, const fdtd_source *src, int nsrc,
                      const fdtd_flux_detector *det, int ndet)
 {
@@ -138,12 +170,27 @@ fdtd_status validate(fdtd_ctx *h, const fdtd_desc *d, const fdtd_source *src, in
     if (ndet > 0 && !det) return fail(h, FDTD_E_INVALID, "detectors NULL");
     for (int s = 0; s < nsrc; s++) {
         const fdtd_source &q = src[s];
-        if (q.kind != 0 && q.kind != 1) return fail(h, FDTD_E_INVALID, "source %d: kind must be 0 or 1", s);
-        if (q.comp < 0 || q.comp > 2) return fail(h, FDTD_E_INVALID, "source %d: comp must be 0..2", s);
+        if (q.kind < 0 || q.kind > 2) return fail(h, FDTD_E_INVALID, "source %d: kind must be 0, 1 or 2", s);
+        if (q.kind != 2 && (q.comp < 0 || q.comp > 5)) return fail(h, FDTD_E_INVALID, "source %d: comp must be 0..5", s);
+        if (q.kind == 2 && q.comp != 0 && q.comp != 1)
+            return fail(h, FDTD_E_INVALID, "source %d: TFSF polarisation must be 0 (Ex) or 1 (Ey)", s);
         if (q.k < 0 || q.k >= d->nz) return fail(h, FDTD_E_INVALID, "source %d: k out of range", s);
         if (q.kind == 0 && (q.i < 0 || q.i >= d->nx || q.j < 0 || q.j >= d->ny))
             return fail(h, FDTD_E_INVALID, "source %d: (i,j) out of range", s);
+        if (q.kind == 2) {
+            // both layers in the z interior, and outside the design box's z range
+            // (the incident line takes the plane's material as given)
+            if (q.k < p + 1 || q.k >= d->nz - p)
+                return fail(h, FDTD_E_INVALID, "source %d: TFSF plane k must lie in [p+1, nz-p)", s);
+            if (q.k - 1 < d->design_hi[2] && d->design_lo[2] <= q.k)
+                return fail(h, FDTD_E_INVALID, "source %d: TFSF layers k-1, k meet the design box", s);
+        }
         if (!q.amp) return fail(h, FDTD_E_INVALID, "source %d: amp is NULL", s);
+    }
+    {
+        IntSrc tmp[2 * FDTD_MAX_SOURCES];
+        if (expand_sources(src, nsrc, tmp, 2 * FDTD_MAX_SOURCES) > FD_MAXSRC)
+            return fail(h, FDTD_E_INVALID, "sources need more than %d slots (a TFSF plane takes two)", FD_MAXSRC);
     }
     const bool rec = d->record == 1;
     auto inside = [&](int lo, int hi, int a) {
@@ -316,6 +363,8 @@ size_t plan(fdtd_ctx *h, const fdtd_desc *d, const Geometry &G, int K, void *bas
         for (int a = 0; a < 3; a++)
             for (int f = 0; f < 3; f++) h->prof[t][a][f] = B.take(n[a]);
     for (int s = 0; s < FDTD_MAX_SOURCES; s++) h->amps[s] = B.take(d->n_steps);
+    for (int t = 0; t < FD_MAXSRC / 2; t++) h->twave[t] = t < h->ntfsf ? B.take(d->n_steps) : nullptr;
+    h->tline = h->ntfsf > 0 ? B.take(2 * (size_t)tfsf_line_nodes(d->n_steps)) : nullptr;
     h->trace = B.take((size_t)d->n_steps * std::max(1, G.D.ndet));
     h->planes = B.take((size_t)std::max(1, K) * std::max<long long>(1, G.D.per_step));
     h->wdev = B.take(FDTD_MAX_DETECTORS);
@@ -433,7 +482,7 @@ fdtd_status step_naive(fdtd_ctx *h, int n, int with_src, int with_rec, int with_
     Fields F = fields_of(h, h->cur);
     Psi P = psi_of(h, h->cur);
     const Geometry &G = h->geo;
-    HIPCHK(h, launch_h_naive(h->g, F, P, h->stream));
+    HIPCHK(h, launch_h_naive(h->g, F, P, n, with_src, h->stream));
     if (with_rec && h->rec && G.R.per_step > 0)
         HIPCHK(h, launch_record(h->g, F, G.R, h->rec + (size_t)n * G.R.per_step, 0, 0, h->stream));
     HIPCHK(h, launch_e_naive(h->g, F, P, n, with_src, h->stream));
@@ -533,7 +582,7 @@ fdtd_status reverse_step(fdtd_ctx *h, int n, int do_adj)
     Psi Pc = psibar_of(h, h->apar), Pn = psibar_of(h, h->apar ^ 1);
     HIPCHK(h, launch_bwd_a(h->g, F, A, Pc, n, 1, do_adj, do_adj ? h->gacc : nullptr, h->desc.design_lo,
                            h->desc.design_hi, h->stream));
-    HIPCHK(h, launch_bwd_b(h->g, F, A, Pc, Pn, 1, do_adj, h->stream));
+    HIPCHK(h, launch_bwd_b(h->g, F, A, Pc, Pn, n, 1, do_adj, h->stream));
     if (do_adj) h->apar ^= 1;
     return FDTD_OK;
 }
@@ -598,7 +647,22 @@ fdtd_status upload_materials(fdtd_ctx *h, const float *inv_eps)
     const Geometry &G = h->geo;
     HIPCHK(h, launch_scale_ce(inv_eps, h->desc.courant, h->ce, G.N, h->stream));
     HIPCHK(h, launch_gather_box(inv_eps, h->g, h->desc.design_lo, h->desc.design_hi, h->d_design, h->stream));
+    // incident line of each TFSF plane, with S/eps_r of the plane's centre cell
+    for (int t = 0; t < h->ntfsf; t++) {
+        const fdtd_source &q = h->src[h->tfsf_pub[t]];
+        const float *ce_at = h->ce + ((long long)q.k * G.ny + G.ny / 2) * G.nx + G.nx / 2;
+        HIPCHK(h, launch_tfsf_line(h->twave[t], h->T, h->desc.courant, ce_at, q.comp == 0 ? 1.f : -1.f, h->tline,
+                                   h->amps[h->tfsf_slot[t][0]], h->amps[h->tfsf_slot[t][1]], h->stream));
+    }
     return FDTD_OK;
+}
+
+// number of TFSF planes among the public sources
+int count_tfsf(const fdtd_source *src, int nsrc)
+{
+    int c = 0;
+    for (int s = 0; s < nsrc; s++) c += src[s].kind == 2;
+    return c;
 }
 
 }  // namespace
@@ -617,6 +681,7 @@ fdtd_status fdtd_footprint(const fdtd_desc *desc, const fdtd_source *src, int32_
     if (!tmp) return fail(nullptr, FDTD_E_NOMEM, "host allocation failed");
     Geometry G;
     geometry(desc, det, ndet, G);
+    tmp->ntfsf = count_tfsf(src, nsrc);
     *bytes = plan(tmp, desc, G, choose_K(desc), nullptr);
     delete tmp;
     return FDTD_OK;
@@ -638,6 +703,17 @@ fdtd_status fdtd_create(const fdtd_desc *desc, const fdtd_source *src, int32_t n
     h->nsrc = nsrc;
     h->ndet = ndet;
     for (int s = 0; s < nsrc; s++) h->src[s] = src[s];
+    IntSrc isrc[FD_MAXSRC];
+    const int nint = expand_sources(src, nsrc, isrc, FD_MAXSRC);
+    h->ntfsf = 0;
+    for (int q = 0; q < nint; q++) {
+        if (isrc[q].role == 1) {
+            h->tfsf_pub[h->ntfsf] = isrc[q].pub;
+            h->tfsf_slot[h->ntfsf][0] = q;
+            h->tfsf_slot[h->ntfsf][1] = q + 1;   // the H correction follows its E correction
+            h->ntfsf++;
+        }
+    }
     for (int m = 0; m < ndet; m++) h->det[m] = det[m];
     h->stream = (hipStream_t)stream;
     h->T = desc->n_steps;
@@ -700,11 +776,11 @@ fdtd_status fdtd_create(const fdtd_desc *desc, const fdtd_source *src, int32_t n
         for (int a = 0; a < 3; a++)
             for (int f = 0; f < 3; f++) g.prof[t][a][f] = h->prof[t][a][f];
     for (int a = 0; a < 3; a++) g.slab_n[a] = G.slab_n[a];
-    g.nsrc = nsrc;
+    g.nsrc = nint;
     for (int s = 0; s < FD_MAXSRC; s++) {
-        const bool on = s < nsrc;
-        g.skind[s] = on ? src[s].kind : 0; g.scomp[s] = on ? src[s].comp : 0;
-        g.si[s] = on ? src[s].i : 0; g.sj[s] = on ? src[s].j : 0; g.sk[s] = on ? src[s].k : -1;
+        const bool on = s < nint;
+        g.skind[s] = on ? isrc[s].kind : 0; g.scomp[s] = on ? isrc[s].comp : 0;
+        g.si[s] = on ? isrc[s].i : 0; g.sj[s] = on ? isrc[s].j : 0; g.sk[s] = on ? isrc[s].k : -1;
         g.samp[s] = h->amps[s];
     }
 
@@ -770,8 +846,15 @@ fdtd_status fdtd_create(const fdtd_desc *desc, const fdtd_source *src, int32_t n
                                       hipMemcpyHostToDevice, h->stream);
         if (e != hipSuccess) { fdtd_status r = fail(nullptr, FDTD_E_DEVICE, "tiles: %s", hipGetErrorString(e)); delete h; return r; }
     }
-    for (int s = 0; s < nsrc; s++) {
-        hipError_t e = hipMemcpyAsync(h->amps[s], src[s].amp, sizeof(float) * desc->n_steps,
+    // the caller's amplitudes: plain sources into their slots, TFSF waveforms
+    // into the workspace (upload_materials runs their incident lines)
+    for (int q = 0; q < nint; q++) {
+        if (isrc[q].role == 2) continue;
+        float *dst = h->amps[q];
+        if (isrc[q].role == 1)
+            for (int t = 0; t < h->ntfsf; t++)
+                if (h->tfsf_slot[t][0] == q) dst = h->twave[t];
+        hipError_t e = hipMemcpyAsync(dst, src[isrc[q].pub].amp, sizeof(float) * desc->n_steps,
                                       hipMemcpyDeviceToDevice, h->stream);
         if (e != hipSuccess) { fdtd_status r = fail(nullptr, FDTD_E_DEVICE, "amp copy: %s", hipGetErrorString(e)); delete h; return r; }
     }
@@ -1103,7 +1186,7 @@ fdtd_status fdtd_linear_steps(fdtd_handle h, int32_t n, int32_t adjoint)
             Fields F = fields_of(h, h->cur), A = adj_of(h, h->acur);
             Psi Pc = psibar_of(h, h->apar), Pn = psibar_of(h, h->apar ^ 1);
             HIPCHK(h, launch_bwd_a(h->g, F, A, Pc, 0, 0, 1, nullptr, h->desc.design_lo, h->desc.design_hi, h->stream));
-            HIPCHK(h, launch_bwd_b(h->g, F, A, Pc, Pn, 0, 1, h->stream));
+            HIPCHK(h, launch_bwd_b(h->g, F, A, Pc, Pn, 0, 0, 1, h->stream));
             h->apar ^= 1;
             st = FDTD_OK;
         }

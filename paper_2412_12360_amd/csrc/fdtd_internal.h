@@ -110,7 +110,7 @@ __device__ __forceinline__ bool held_ez(int i, int j, int k) { (void)k; return i
 // ------------------------------------------------------------------ launchers
 // All return hipSuccess or the launch error.
 
-hipError_t launch_h_naive(const Grid &g, const Fields &F, const Psi &P, hipStream_t s);
+hipError_t launch_h_naive(const Grid &g, const Fields &F, const Psi &P, int n, int with_src, hipStream_t s);
 hipError_t launch_e_naive(const Grid &g, const Fields &F, const Psi &P, int n, int with_src, hipStream_t s);
 
 // phase A of a reverse step: inverse E (interior), dJ/dd accumulation, adjoint H
@@ -119,7 +119,13 @@ hipError_t launch_bwd_a(const Grid &g, const Fields &F, const Fields &A, const P
                         hipStream_t s);
 // phase B: inverse H (interior), adjoint E, psi-bar updates (H-type ping-pong)
 hipError_t launch_bwd_b(const Grid &g, const Fields &F, const Fields &A, const Psi &Pb_cur,
-                        const Psi &Pb_next, int do_inv, int do_adj, hipStream_t s);
+                        const Psi &Pb_next, int n, int do_inv, int do_adj, hipStream_t s);
+
+// incident-field line of a TFSF plane: nodes for T steps (scratch 2*nodes - 1
+// floats), and the launch writing the E and H correction series (T each)
+int tfsf_line_nodes(int T);
+hipError_t launch_tfsf_line(const float *amp, int T, float S, const float *ce_at, float hsign, float *line,
+                            float *outE, float *outH, hipStream_t s);
 
 hipError_t launch_record(const Grid &g, const Fields &F, const RecGeom &R, float *rec_step,
                          int side, int restore, hipStream_t s);

@@ -168,6 +168,41 @@ __global__ __launch_bounds__(NT) void k_deps(const float *gacc, const float *dd,
     out[t] = -(d * d) * (S * gacc[t]);
 }
 
+// Incident fields of a one-sided total-field/scattered-field plane along +z
+// (section 2.1 names the source type).  A 1D Yee line along z with the grid's
+// S and the plane's S/eps_r carries the incident wave; for a wave uniform in
+// x and y it is the 3D update restricted to z, here with the same update
+// expressions (zero transverse differences).  Node 0 is driven,
+// E_0^{n+1} = amp[n]; node 1 is the first total-field E plane k0.  Step n
+// writes the two corrections the grid's curl misses across the plane:
+//     outH[n] = hsign * S * E_1^n       (after the H half step, layer k0-1)
+//     outE[n] = S/eps * H_0^{n+1/2}     (after the E half step, plane k0)
+// The line has L nodes (E) and L-1 edges (H) in `line` and a conducting far
+// end; with L >= T/2 + 8 no wave from node 0 returns from it within T steps
+// (an update moves information at most one cell per step).  One workgroup.
+constexpr int LINE_NT = 1024;
+__global__ __launch_bounds__(LINE_NT) void k_tfsf_line(const float *amp, int T, float S, const float *ce_at,
+                                                       float hsign, float *line, int L, float *outE, float *outH)
+{
+    float *E = line, *H = line + L;
+    const float ce = *ce_at;
+    for (int c = threadIdx.x; c < 2 * L - 1; c += LINE_NT) line[c] = 0.f;
+    __syncthreads();
+    for (int n = 0; n < T; n++) {
+        // H phase: reads E only
+        if (threadIdx.x == 0) outH[n] = hsign * (S * E[1]);
+        for (int c = threadIdx.x; c < L - 1; c += LINE_NT) H[c] = h_update(H[c], S, E[c + 1] - E[c], 0.f);
+        __syncthreads();
+        // E phase: reads H only; node L-1 stays 0
+        if (threadIdx.x == 0) {
+            outE[n] = ce * H[0];
+            E[0] = amp[n];
+        }
+        for (int c = 1 + threadIdx.x; c < L - 1; c += LINE_NT) E[c] = e_update(E[c], ce, 0.f, H[c] - H[c - 1]);
+        __syncthreads();
+    }
+}
+
 __global__ __launch_bounds__(NT) void k_fill(float *p, long long n, float v)
 {
     const long long t = (long long)blockIdx.x * NT + threadIdx.x;
@@ -284,6 +319,16 @@ hipError_t launch_deps(const float *gacc, const float *dd, long long D, float S,
 {
     if (D == 0) return hipSuccess;
     hipLaunchKernelGGL(k_deps, dim3(nblk(D)), dim3(NT), 0, s, gacc, dd, D, S, out);
+    return hipGetLastError();
+}
+
+int tfsf_line_nodes(int T) { return T / 2 + 8; }
+
+hipError_t launch_tfsf_line(const float *amp, int T, float S, const float *ce_at, float hsign, float *line,
+                            float *outE, float *outH, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_tfsf_line, dim3(1), dim3(LINE_NT), 0, s, amp, T, S, ce_at, hsign, line,
+                       tfsf_line_nodes(T), outE, outH);
     return hipGetLastError();
 }
 

@@ -15,7 +15,7 @@ __device__ __forceinline__ long long cidx(const Grid &g, int i, int j, int k)
 }
 
 // ----------------------------------------------------------- forward, H half
-__global__ __launch_bounds__(256) void k_h_naive(Grid g, Fields F, Psi P)
+__global__ __launch_bounds__(256) void k_h_naive(Grid g, Fields F, Psi P, int n, int with_src)
 {
     const int i = blockIdx.x * BX + threadIdx.x;
     const int j = blockIdx.y * BY + threadIdx.y;
@@ -58,9 +58,21 @@ __global__ __launch_bounds__(256) void k_h_naive(Grid g, Fields F, Psi P)
             P.a[2][2][s] = p2; P.a[2][3][s] = p3;
         }
     }
-    F.c[3][c] = h_update(F.c[3][c], g.S, dy_ez, dz_ey);
-    F.c[4][c] = h_update(F.c[4][c], g.S, dz_ex, dx_ez);
-    F.c[5][c] = h_update(F.c[5][c], g.S, dx_ey, dy_ex);
+    float hx = h_update(F.c[3][c], g.S, dy_ez, dz_ey);
+    float hy = h_update(F.c[4][c], g.S, dz_ex, dx_ez);
+    float hz = h_update(F.c[5][c], g.S, dx_ey, dy_ex);
+    // H sources (components 3..5), after the H half step
+    if (with_src) {
+        for (int s = 0; s < g.nsrc; s++) {
+            if (k != g.sk[s] || g.scomp[s] < 3) continue;
+            if (g.skind[s] == 0 && (i != g.si[s] || j != g.sj[s])) continue;
+            const float A = g.samp[s][n];
+            if (g.scomp[s] == 3) hx = hx + A;
+            if (g.scomp[s] == 4) hy = hy + A;
+            if (g.scomp[s] == 5) hz = hz + A;
+        }
+    }
+    F.c[3][c] = hx; F.c[4][c] = hy; F.c[5][c] = hz;
 }
 
 // ----------------------------------------------------------- forward, E half
@@ -237,9 +249,9 @@ __global__ __launch_bounds__(256) void k_bwd_a(Grid g, Fields F, Fields A, Psi P
 
 // ---------------------------------------------------------- reverse, phase B
 // psibar <- b (psibar + w), read from `Pc`, written to `Pn`; inverse H on
-// the interior: H^{n-1/2} = H^{n+1/2} + S curl E^n; adjoint E:
+// the interior: H^{n-1/2} = H^{n+1/2} - srcH_n + S curl E^n; adjoint E:
 // Ebar -= S C^T Hbar, CPML wrapped.
-__global__ __launch_bounds__(256) void k_bwd_b(Grid g, Fields F, Fields A, Psi Pc, Psi Pn, int do_inv,
+__global__ __launch_bounds__(256) void k_bwd_b(Grid g, Fields F, Fields A, Psi Pc, Psi Pn, int n, int do_inv,
                                               int do_adj)
 {
     const int i = blockIdx.x * BX + threadIdx.x;
@@ -273,9 +285,18 @@ __global__ __launch_bounds__(256) void k_bwd_b(Grid g, Fields F, Fields A, Psi P
         const float ey_x = xi ? Ey[c + 1] : 0.f, ez_x = xi ? Ez[c + 1] : 0.f;
         const float ex_y = yj ? Ex[c + g.nx] : 0.f, ez_y = yj ? Ez[c + g.nx] : 0.f;
         const float ex_z = zk ? Ex[c + g.nxy] : 0.f, ey_z = zk ? Ey[c + g.nxy] : 0.f;
-        F.c[3][c] = h_unupdate(F.c[3][c], g.S, ez_y - ez, ey_z - ey);
-        F.c[4][c] = h_unupdate(F.c[4][c], g.S, ex_z - ex, ez_x - ez);
-        F.c[5][c] = h_unupdate(F.c[5][c], g.S, ey_x - ey, ex_y - ex);
+        float hx = F.c[3][c], hy = F.c[4][c], hz = F.c[5][c];
+        for (int s = 0; s < g.nsrc; s++) {
+            if (k != g.sk[s] || g.scomp[s] < 3) continue;
+            if (g.skind[s] == 0 && (i != g.si[s] || j != g.sj[s])) continue;
+            const float Am = g.samp[s][n];
+            if (g.scomp[s] == 3) hx = hx - Am;
+            if (g.scomp[s] == 4) hy = hy - Am;
+            if (g.scomp[s] == 5) hz = hz - Am;
+        }
+        F.c[3][c] = h_unupdate(hx, g.S, ez_y - ez, ey_z - ey);
+        F.c[4][c] = h_unupdate(hy, g.S, ex_z - ex, ez_x - ez);
+        F.c[5][c] = h_unupdate(hz, g.S, ey_x - ey, ex_y - ex);
     }
     if (do_adj) {
         // Ebar_x: Hy along z (-S, z idx 3), Hz along y (+S, y idx 2)
@@ -321,9 +342,9 @@ dim3 cell_grid(const Grid &g) { return dim3((g.nx + BX - 1) / BX, (g.ny + BY - 1
 
 }  // namespace
 
-hipError_t launch_h_naive(const Grid &g, const Fields &F, const Psi &P, hipStream_t s)
+hipError_t launch_h_naive(const Grid &g, const Fields &F, const Psi &P, int n, int with_src, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_h_naive, cell_grid(g), dim3(BX, BY), 0, s, g, F, P);
+    hipLaunchKernelGGL(k_h_naive, cell_grid(g), dim3(BX, BY), 0, s, g, F, P, n, with_src);
     return hipGetLastError();
 }
 
@@ -342,8 +363,8 @@ hipError_t launch_bwd_a(const Grid &g, const Fields &F, const Fields &A, const P
 }
 
 hipError_t launch_bwd_b(const Grid &g, const Fields &F, const Fields &A, const Psi &Pc, const Psi &Pn,
-                        int do_inv, int do_adj, hipStream_t s)
+                        int n, int do_inv, int do_adj, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_bwd_b, cell_grid(g), dim3(BX, BY), 0, s, g, F, A, Pc, Pn, do_inv, do_adj);
+    hipLaunchKernelGGL(k_bwd_b, cell_grid(g), dim3(BX, BY), 0, s, g, F, A, Pc, Pn, n, do_inv, do_adj);
     return hipGetLastError();
 }

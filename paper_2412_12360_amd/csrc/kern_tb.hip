@@ -218,6 +218,13 @@ __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
     int skq[FD_MAXSRC];
 #pragma unroll
     for (int q = 0; q < FD_MAXSRC; q++) skq[q] = (A.with_src && q < A.g.nsrc) ? A.g.sk[q] : (-2147483647 - 1);
+    // The other source arguments are read through a copy of the argument
+    // pointer that is made opaque on every plane, so they are fetched on a
+    // source plane instead of being held in scalar registers for the whole
+    // march (the argument block is the kernel's only parameter, at offset 0
+    // of the kernel-argument segment).
+    typedef const __attribute__((address_space(4))) TbArgs KArgs;
+    KArgs *Kp = (KArgs *)__builtin_amdgcn_kernarg_segment_ptr();
 
     // pipeline registers: Eo[s], Ho[s]/Hc[s], Po[s] = output of level s at the
     // plane level s+1 works on next; Ho[K] = last Hx, Hy of level K; cd[s] =
@@ -311,6 +318,26 @@ __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
                     mH[r][0] = live ? h_update(Ho[s - 1][r][0], S, dy_ez, dz_ey) : 0.f;
                     mH[r][1] = live ? h_update(Ho[s - 1][r][1], S, dz_ex, dx_ez) : 0.f;
                     mH[r][2] = live ? h_update(Hc[s - 1][r], S, dx_ey, dy_ex) : 0.f;
+                }
+                // ---- H sources (components 3..5), before any E update reads
+                // this plane's H; same uniform plane test as the E sources
+#pragma unroll
+                for (int q = 0; q < FD_MAXSRC; q++) {
+                    if (k == skq[q]) {
+                        const float am = sAmp[q][s - 1];
+                        const int comp = Kp->g.scomp[q];
+#pragma unroll
+                        for (int r = 0; r < R; r++) {
+                            const bool hit = incol[r] && kin &&
+                                             (Kp->g.skind[q] == 1 || (x == Kp->g.si[q] && ys[r] == Kp->g.sj[q]));
+                            mH[r][0] = (hit && comp == 3) ? mH[r][0] + am : mH[r][0];
+                            mH[r][1] = (hit && comp == 4) ? mH[r][1] + am : mH[r][1];
+                            mH[r][2] = (hit && comp == 5) ? mH[r][2] + am : mH[r][2];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < R; r++) {
                     sH[0][row[r]][lane] = mH[r][0];
                     sH[1][row[r]][lane] = mH[r][1];
                     sH[2][row[r]][lane] = mH[r][2];
@@ -354,17 +381,17 @@ __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
                     mE[r][1] = live ? ey : 0.f;
                     mE[r][2] = live ? ez : 0.f;
                 }
-                // ---- sources (uniform plane test against the hoisted source
+                // ---- E sources (uniform plane test against the hoisted source
                 // planes: no scalar memory load on a plane without a source)
 #pragma unroll
                 for (int q = 0; q < FD_MAXSRC; q++) {
                     if (k == skq[q]) {
                         const float am = sAmp[q][s - 1];
-                        const int comp = A.g.scomp[q];
+                        const int comp = Kp->g.scomp[q];
 #pragma unroll
                         for (int r = 0; r < R; r++) {
                             const bool hit = incol[r] && kin &&
-                                             (A.g.skind[q] == 1 || (x == A.g.si[q] && ys[r] == A.g.sj[q]));
+                                             (Kp->g.skind[q] == 1 || (x == Kp->g.si[q] && ys[r] == Kp->g.sj[q]));
                             // one select per component, no component-indexed
                             // array (which the compiler would place in scratch);
                             // a held component takes no source
@@ -520,6 +547,7 @@ __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
             if (t < zend) {
                 const Plane<R, XP, YP> cur = ring[u];
                 load_plane(t + PD, ring[u]);
+                asm volatile("" : "+s"(Kp));
                 body(t, cur);
             }
         }

@@ -7,9 +7,9 @@
 // on the interior I = [p, n-p)^3 and the adjoint of s_{n+1} to the adjoint of
 // s_n.  Per cell it is the same arithmetic, in the same order, as the
 // per-cell phases k_bwd_a / k_bwd_b (and bitwise equal to them):
-//   phase A: dJ/dd += Ebar' . curl H^{n+1/2};  E^n = E^{n+1} - src_n - S/eps curl H^{n+1/2};
+//   phase A: dJ/dd += Ebar' . curl H^{n+1/2};  E^n = E^{n+1} - srcE_n - S/eps curl H^{n+1/2};
 //            Hbar += C(S/eps Ebar') with the transposed CPML (coefficients Q)
-//   phase B: psibar_E <- b (psibar_E + w);  H^{n-1/2} = H^{n+1/2} + S curl E^n;
+//   phase B: psibar_E <- b (psibar_E + w);  H^{n-1/2} = H^{n+1/2} - srcH_n + S curl E^n;
 //            Ebar -= S C^T Hbar with the transposed CPML (coefficients R);
 //            psibar_H <- b (psibar_H + w)
 // Phase A at a cell reads H at -1 and Q at +1; phase B reads E^n at +1 and R
@@ -445,9 +445,22 @@ __global__ __launch_bounds__(NT) void k_tb_reverse(RevArgs A)
                     const float ex_z = aEn[0], ey_z = aEn[1];
 #pragma unroll
                     for (int q = 0; q < 3; q++) st(A.fout.c[0], c + q * fs, bEn[q]);
-                    st(A.fout.c[0], c + 3 * fs, h_unupdate(bH[0], S, ez_y - ez, ey_z - ey));
-                    st(A.fout.c[0], c + 4 * fs, h_unupdate(bH[1], S, ex_z - ex, ez_x - ez));
-                    st(A.fout.c[0], c + 5 * fs, h_unupdate(bH[2], S, ey_x - ey, ex_y - ex));
+                    // H sources of step n, in order, before the un-update
+                    float hx = bH[0], hy = bH[1], hz = bH[2];
+#pragma unroll
+                    for (int q = 0; q < FD_MAXSRC; q++) {
+                        if (bpl == skq[q]) {
+                            const bool hit = Kp->g.skind[q] != 0 || (x == Kp->g.si[q] && y == Kp->g.sj[q]);
+                            const float Am = sAmp[q];
+                            const int comp = Kp->g.scomp[q];
+                            hx = (hit && comp == 3) ? hx - Am : hx;
+                            hy = (hit && comp == 4) ? hy - Am : hy;
+                            hz = (hit && comp == 5) ? hz - Am : hz;
+                        }
+                    }
+                    st(A.fout.c[0], c + 3 * fs, h_unupdate(hx, S, ez_y - ez, ey_z - ey));
+                    st(A.fout.c[0], c + 4 * fs, h_unupdate(hy, S, ex_z - ex, ez_x - ez));
+                    st(A.fout.c[0], c + 5 * fs, h_unupdate(hz, S, ey_x - ey, ex_y - ex));
                 }
                 if (A.do_adj) {
                     // adjoint E with the transposed H pairs

@@ -92,7 +92,7 @@ def test_bad_source_and_create_arguments():
     pr = W.small_cpml()
     d = F.make_desc(pr, 1)
     src = F.make_sources(pr, [1])
-    src[0].comp = 4
+    src[0].comp = 6
     out = C.c_size_t(0)
     assert F.lib().fdtd_footprint(C.byref(d), src, 1, F.make_detectors(pr), 1, C.byref(out)) == F.FDTD_E_INVALID
     # a too-small workspace is refused before any device work
@@ -101,3 +101,50 @@ def test_bad_source_and_create_arguments():
                              C.c_void_p(256), C.c_size_t(1024), None, C.byref(h))
     assert st == F.FDTD_E_NOMEM and not h.value
     assert F.lib().fdtd_forward(None, 1, None, None) == F.FDTD_E_INVALID
+
+
+def _status(pr, record=False):
+    F = _F()
+    d = F.make_desc(pr, 1, record=record)
+    out = C.c_size_t(0)
+    st = F.lib().fdtd_footprint(C.byref(d), F.make_sources(pr, [1] * len(pr.sources)), len(pr.sources),
+                                F.make_detectors(pr), len(pr.detectors), C.byref(out))
+    return st, int(out.value)
+
+
+def test_h_sources_and_tfsf_accepted():
+    F = _F()
+    pr = W.small_cpml(nx=40, ny=36, nz=44, p=6, T=100)
+    amp = pr.sources[0].amp
+    for comp in range(6):
+        q = W.Source(kind=0, comp=comp, i=20, j=18, k=22, amp=amp)
+        assert _status(W.dataclasses.replace(pr, sources=[q]))[0] == F.FDTD_OK
+    st, fp_tfsf = _status(W.with_tfsf(pr), record=True)
+    assert st == F.FDTD_OK
+    # the TFSF waveform and its incident line live in the workspace
+    assert fp_tfsf > _status(pr, record=True)[1]
+
+
+@pytest.mark.parametrize("change,what", [
+    (dict(comp=2), "polarisation"),       # only Ex or Ey
+    (dict(k=6), "[p+1, nz-p)"),           # H layer k-1 inside the CPML
+    (dict(k=38), "[p+1, nz-p)"),          # E plane inside the CPML
+    (dict(k=19), "design box"),           # layer k-1 = 18 is the design box's first layer
+])
+def test_tfsf_placement_validated(change, what):
+    F = _F()
+    pr = W.with_tfsf(W.small_cpml(nx=40, ny=36, nz=44, p=6, T=100))   # design z in [18, 26)
+    src = W.dataclasses.replace(pr.sources[0], **change)
+    st, _ = _status(W.dataclasses.replace(pr, sources=[src]))
+    assert st == F.FDTD_E_INVALID
+    assert what.lower() in F.lib().fdtd_last_error(None).decode().lower()
+
+
+def test_tfsf_takes_two_source_slots():
+    F = _F()
+    pr = W.with_tfsf(W.small_cpml(nx=40, ny=36, nz=44, p=6, T=100))
+    extra = [W.Source(kind=0, comp=2, i=20, j=18, k=30, amp=pr.sources[0].amp)] * 3
+    assert _status(W.dataclasses.replace(pr, sources=pr.sources + extra[:2]))[0] == F.FDTD_OK
+    st, _ = _status(W.dataclasses.replace(pr, sources=pr.sources + extra))
+    assert st == F.FDTD_E_INVALID
+    assert "slots" in F.lib().fdtd_last_error(None).decode()
