@@ -26,6 +26,9 @@
  *     source, see oracle.py); a non-interpolated Poynting-flux detector on a
  *     z-normal plane and the objective J = S * sum_n w * P[n] (section 2.1,
  *     detectors without interpolation).
+ *   - the interpolated flux of section 2.1 (forward only): Ex, Ey, Hx, Hy each
+ *     averaged onto the point (i+1/2, j+1/2, k) of the detector plane at time
+ *     n+1/2 (E of steps n and n+1; H^{n+1/2} of layers k-1 and k).
  *   - the interface record (section 2.2): every step, tangential H^{n+1/2} on
  *     the PML-side layer p-1 of the three low faces and tangential E^{n+1} on
  *     layer n_a-p of the three high faces, over the interior window.
@@ -65,6 +68,7 @@ typedef struct {
     int det_k[OR_MAXDET];
     int det_i0[OR_MAXDET], det_i1[OR_MAXDET], det_j0[OR_MAXDET], det_j1[OR_MAXDET];
     double det_w[OR_MAXDET];
+    int det_interp[OR_MAXDET];      /* 1: co-located (interpolated) flux, forward only */
     int dlo[3], dhi[3];             /* half-open design box */
 } or_problem;
 
@@ -265,6 +269,34 @@ static double det_flux(const or_problem *P, const double *st, int m)
     return s;
 }
 
+/* Interpolated flux of detector m (section 2.1: composite metrics need the
+ * components at one point in space and time).  Target point (i+1/2, j+1/2, k)
+ * at time n+1/2.  Ex(i+1/2, j, k) is averaged over j, j+1 and over the steps
+ * n, n+1; Ey(i, j+1/2, k) over i, i+1 and the two steps; Hx(i, j+1/2, k+-1/2)
+ * over i, i+1 and the layers k-1, k; Hy(i+1/2, j, k+-1/2) over j, j+1 and the
+ * two layers; H^{n+1/2} is already at time n+1/2.  eprev holds Ex^n then Ey^n
+ * of plane k, [ny][nx] each; st holds E^{n+1}, H^{n+1/2}. */
+static double det_flux_interp(const or_problem *P, const double *st, const double *eprev, int m)
+{
+    size_t N = ncell(P), A = (size_t)P->nx * P->ny;
+    const double *Ex = st, *Ey = st + N, *Hx = st + 3 * N, *Hy = st + 4 * N;
+    const double *Px = eprev, *Py = eprev + A;
+    int k = P->det_k[m];
+    double s = 0.0;
+    for (int j = P->det_j0[m]; j < P->det_j1[m]; j++)
+        for (int i = P->det_i0[m]; i < P->det_i1[m]; i++) {
+            size_t p00 = (size_t)j * P->nx + i, p01 = p00 + P->nx, p10 = p00 + 1;
+            double ex = 0.25 * (Px[p00] + Px[p01] + Ex[idx(P, i, j, k)] + Ex[idx(P, i, j + 1, k)]);
+            double ey = 0.25 * (Py[p00] + Py[p10] + Ey[idx(P, i, j, k)] + Ey[idx(P, i + 1, j, k)]);
+            double hx = 0.25 * (Hx[idx(P, i, j, k - 1)] + Hx[idx(P, i + 1, j, k - 1)] +
+                                Hx[idx(P, i, j, k)] + Hx[idx(P, i + 1, j, k)]);
+            double hy = 0.25 * (Hy[idx(P, i, j, k - 1)] + Hy[idx(P, i, j + 1, k - 1)] +
+                                Hy[idx(P, i, j, k)] + Hy[idx(P, i, j + 1, k)]);
+            s += ex * hy - ey * hx;
+        }
+    return s;
+}
+
 /* ------------------------------------------------------- interface record
  * Face f = 2a + side.  side 0 (low): tangential H at layer p-1; side 1 (high):
  * tangential E at layer n_a - p.  Components (a+1)%3 then (a+2)%3.  Window over
@@ -316,6 +348,17 @@ static void record_io(const or_problem *P, double *st, double *rec, int which, i
 static void step_fwd(const or_problem *P, double *st, int n, const or_prof *PE, const or_prof *PH,
                      double *trow, double *rec, int with_src)
 {
+    /* E^n of the interpolated detectors' planes, before the step */
+    double *eprev = NULL;
+    size_t A = (size_t)P->nx * P->ny;
+    if (trow)
+        for (int m = 0; m < P->ndet; m++)
+            if (P->det_interp[m]) {
+                if (!eprev) eprev = malloc(sizeof(double) * 2 * A * OR_MAXDET);
+                for (int q = 0; q < 2; q++)
+                    memcpy(eprev + (2 * (size_t)m + q) * A, slot(st, P, q) + (size_t)P->det_k[m] * A,
+                           sizeof(double) * A);
+            }
     h_sweep(P, st, PH);
     if (with_src) add_sources(P, st, n, 1.0, 1);
     if (rec) record_io(P, st, rec, 0, 0);
@@ -323,7 +366,9 @@ static void step_fwd(const or_problem *P, double *st, int n, const or_prof *PE, 
     if (with_src) add_sources(P, st, n, 1.0, 0);
     if (rec) record_io(P, st, rec, 1, 0);
     if (trow)
-        for (int m = 0; m < P->ndet; m++) trow[m] = det_flux(P, st, m);
+        for (int m = 0; m < P->ndet; m++)
+            trow[m] = P->det_interp[m] ? det_flux_interp(P, st, eprev + 2 * (size_t)m * A, m) : det_flux(P, st, m);
+    free(eprev);
 }
 
 /* Advance st by T steps starting at step n0.  trace: [T][ndet] or NULL.
@@ -426,6 +471,7 @@ static void adjoint_step(const or_problem *P, double *adj, const double *fwd, do
         const double *Ex = fwd, *Ey = fwd + N, *Hx = fwd + 3 * N, *Hy = fwd + 4 * N;
         double *aEx = adj, *aEy = adj + N, *aHx = adj + 3 * N, *aHy = adj + 4 * N;
         for (int m = 0; m < P->ndet; m++) {
+            if (P->det_interp[m]) continue;   /* forward only: its weight must be 0 in a gradient */
             double sw = S * P->det_w[m];
             int k = P->det_k[m];
             for (int j = P->det_j0[m]; j < P->det_j1[m]; j++)

@@ -58,6 +58,7 @@ class Detector:
     j0: int
     j1: int
     weight: float = 1.0
+    interpolate: bool = False   # co-located (interpolated) flux, forward only
 
 
 @dataclasses.dataclass

@@ -4,6 +4,7 @@ Each test would fail on a plausible mistake in the oracle: a dropped curl
 term, a wrong sign, a transposed difference, a misplaced boundary, a wrong
 Courant scaling, a broken record or inverse, a non-transposed adjoint.
 """
+import dataclasses
 import decimal
 import math
 import pathlib
@@ -520,3 +521,92 @@ def test_tfsf_is_one_sided_sheet_is_not():
         ratio[kind] = abs(np.sum(trace[:, 0])) / up
     assert ratio[2] < 1e-6
     assert ratio[1] > 0.5
+
+
+# ------------------------------------------- P15: interpolated flux detector
+
+OFFSETS = {0: (0.5, 0.0, 0.0), 1: (0.0, 0.5, 0.0), 3: (0.0, 0.5, 0.5), 4: (0.5, 0.0, 0.5)}   # Ex, Ey, Hx, Hy
+
+
+def trilinear(F, off, x, y, z):
+    """A staggered component F[z, y, x] whose node (i, j, k) sits at
+    (i, j, k) + off, interpolated trilinearly at (x, y, z)."""
+    axes = []
+    for u, o in zip((x, y, z), off):
+        t = u - o
+        lo = math.floor(t)
+        w = t - lo
+        axes.append([(lo, 1.0 - w), (lo + 1, w)])
+    v = 0.0
+    for i, wi in axes[0]:
+        for j, wj in axes[1]:
+            for k, wk in axes[2]:
+                if wi * wj * wk != 0.0:
+                    v += wi * wj * wk * F[k, j, i]
+    return v
+
+
+def test_interpolated_flux_is_the_colocated_product():
+    """Section 2.1: composite metrics need all components at one point and
+    time.  Against a generic trilinear interpolation of each component from
+    its own Yee position (E at integer steps, H at half steps) onto the points
+    (i+1/2, j+1/2, k) at time n+1/2, on random CPML states stepped with a
+    source: a wrong axis, layer, neighbour or time level fails it."""
+    pr = W.small_cpml(nx=14, ny=13, nz=12, p=3, T=6, d=4, seed=41)
+    k = 6
+    pr = dataclasses.replace(pr, detectors=[
+        W.Detector(k=k, i0=2, i1=12, j0=1, j1=11, weight=0.0, interpolate=True),
+        W.Detector(k=k, i0=2, i1=12, j0=1, j1=11, weight=0.0)])
+    o = Oracle(pr)
+    st = random_state(pr, 42, with_psi=True)
+    for n in range(pr.T):
+        before = st.copy()
+        _, trace, _ = o.forward(st, 1, n0=n)
+        got = trace[0, 0]
+        want = plain = 0.0
+        for j in range(1, 11):
+            for i in range(2, 12):
+                x, y = i + 0.5, j + 0.5
+                ex = 0.5 * (trilinear(before[0], OFFSETS[0], x, y, k) + trilinear(st[0], OFFSETS[0], x, y, k))
+                ey = 0.5 * (trilinear(before[1], OFFSETS[1], x, y, k) + trilinear(st[1], OFFSETS[1], x, y, k))
+                hx = trilinear(st[3], OFFSETS[3], x, y, k)
+                hy = trilinear(st[4], OFFSETS[4], x, y, k)
+                want += ex * hy - ey * hx
+                plain += st[0][k, j, i] * st[4][k, j, i] - st[1][k, j, i] * st[3][k, j, i]
+        assert abs(got - want) <= 1e-12 * max(1.0, abs(want))
+        assert abs(trace[0, 1] - plain) <= 1e-12 * max(1.0, abs(plain))
+        assert abs(got - plain) > 1e-3 * abs(want)
+
+
+def test_interpolated_flux_of_a_plane_wave_is_in_phase():
+    """A steady plane wave (TFSF in a conducting box, central columns that
+    cannot see a side wall): the co-located flux is C sin^2(w(n+1/2) - phase),
+    so its oscillation equals its mean, with C = cos(w/2) cos(kk/2) / sqrt(d)
+    from the discrete dispersion (E amplitude 1).  The non-interpolated flux,
+    whose E and H sit half a step and half a cell apart, oscillates 1.2 times
+    its mean and turns negative."""
+    S = W.courant()
+    T, k0, lam = 80, 6, 8.0
+    n, nz = 2 * T + 10, k0 + T + 6
+    d = 1.0 / 2.25
+    inv = np.full((nz, n, n), d, np.float32)
+    src = W.Source(kind=2, comp=0, i=0, j=0, k=k0, amp=W.ramped_sine(T, S, lambda0=lam, periods=2))
+    c0, c1 = T + 3, n - T - 4
+    dets = [W.Detector(k=k0 + 3, i0=c0, i1=c1, j0=c0, j1=c1, interpolate=True),
+            W.Detector(k=k0 + 3, i0=c0, i1=c1, j0=c0, j1=c1)]
+    pr = pec_problem(n, n, nz, d=inv, sources=[src], detectors=dets, T=T)
+    _, _, trace, _ = Oracle(pr).run()
+    cells = (c1 - c0) ** 2
+    w = 2 * math.pi * S / lam
+    kk = 2 * math.asin(math.sin(w / 2) / (S * math.sqrt(d)))
+    C = math.cos(w / 2) * math.cos(kk / 2) / math.sqrt(d)
+    steady = np.arange(45, T)
+    X = np.stack([np.ones(len(steady)), np.cos(2 * w * steady), np.sin(2 * w * steady)], 1)
+    fit = lambda P: np.linalg.lstsq(X, P[steady] / cells, rcond=None)[0]
+    a, b, c = fit(trace[:, 0])
+    assert abs(a - C / 2) <= 2e-3 * C
+    assert abs(math.hypot(b, c) - a) <= 2e-3 * a
+    assert np.min(trace[steady, 0]) >= -1e-3 * C * cells
+    ap, bp, cp = fit(trace[:, 1])
+    assert math.hypot(bp, cp) > 1.1 * ap
+    assert np.min(trace[steady, 1]) < -0.05 * C * cells
