@@ -133,6 +133,26 @@ def tfsf_run(pr, Solver, torch, time_block: int, steps: int, W):
     }
 
 
+def interp_detector_run(pr, Solver, torch, time_block: int, steps: int):
+    """The headline forward workload with its flux detector in the
+    interpolated (co-located) mode: raw planes written by the sweep kernels,
+    E^n gathered before each sweep, the co-located density formed after it."""
+    pi = dataclasses.replace(pr, detectors=[dataclasses.replace(d, interpolate=True) for d in pr.detectors])
+    s = Solver(pi, record=False, time_block=time_block)
+    s.reset()
+    s.forward()
+    ms = time_solves(s, steps, torch)
+    del s
+    torch.cuda.empty_cache()
+    return {
+        "workload": "the same solve with the flux detector interpolated (all components co-located at "
+                    "(i+1/2, j+1/2, k) and time n+1/2)",
+        "value": round(pi.N * pi.T * steps / (ms / 1e3) / 1e6, 1),
+        "unit": "Mcell-updates/s",
+        "ms_per_solve": round(ms / steps, 3),
+    }
+
+
 def fwd_grad_run(pg, Solver, torch, time_block: int, workload: str, checkpoint: bool = False):
     """One warm-up solve, then a timed forward (with the interface record)
     and gradient on the solver's stream: N*T / (t_fwd + t_bwd)."""
@@ -279,7 +299,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--time-block", type=int, default=0)
     ap.add_argument("--no-grad", action="store_true")
-    ap.add_argument("--no-tfsf", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the TFSF-source and interpolated-detector variants of the forward workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving", type=int, default=12,
                     help="requests of the serving mix to run (0 = skip; the first requests of the 500-request mix)")
@@ -367,8 +388,9 @@ def main():
         },
     }
 
-    if not args.no_tfsf:
+    if not args.no_variants:
         out["tfsf"] = tfsf_run(pr, Solver, torch, args.time_block, args.steps, W)
+        out["interpolated_detector"] = interp_detector_run(pr, Solver, torch, args.time_block, args.steps)
 
     if not args.no_grad:
         pg = W.config3(T=args.solve_steps) if args.solve_steps else W.config3()

@@ -100,13 +100,22 @@ typedef struct {
     const float *amp;
 } fdtd_source;
 
-/* Non-interpolated Poynting flux through the z-normal plane k over the window
- * [i0,i1) x [j0,j1) (section 2.1, detectors without interpolation):
- *     P[n] = sum Ex*Hy - Ey*Hx   with E^{n+1} and H^{n+1/2}
- * and the objective J = S * sum_n weight * P[n]. */
+/* Poynting flux through the z-normal plane k over the window [i0,i1) x [j0,j1)
+ * (section 2.1), and the objective J = S * sum_n weight * P[n].
+ * interpolate = 0 (the default of the paper's optimisation runs): the
+ *     components as they lie on the Yee grid,
+ *         P[n] = sum Ex*Hy - Ey*Hx   with E^{n+1} and H^{n+1/2} at index (i,j,k).
+ * interpolate = 1 (the paper's evaluation mode): every component averaged
+ *     onto the point (i+1/2, j+1/2, k) at time n+1/2 -- Ex over j, j+1 and the
+ *     steps n, n+1; Ey over i, i+1 and the two steps; Hx over i, i+1 and the
+ *     layers k-1, k; Hy over j, j+1 and the two layers -- then the same sum.
+ *     Needs k >= 1, i1 < nx, j1 < ny.  Forward only: fdtd_grad and
+ *     fdtd_grad_checkpointed return FDTD_E_UNSUPPORTED when such a detector
+ *     has a nonzero weight. */
 typedef struct {
     int32_t k, i0, i1, j0, j1;
     float weight;
+    int32_t interpolate;
 } fdtd_flux_detector;
 
 #define FDTD_MAX_SOURCES 4

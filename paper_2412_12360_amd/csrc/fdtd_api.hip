@@ -81,6 +81,7 @@ struct fdtd_ctx {
     int tfsf_slot[FD_MAXSRC / 2][2];       // internal E and H source slots
     float *twave[FD_MAXSRC / 2];
     float *tline = nullptr;
+    float *raw = nullptr, *eprev = nullptr;  // interpolated detectors: K raw plane sets, E^n planes
     float *red = nullptr;
     float *trace = nullptr, *planes = nullptr, *wdev = nullptr, *rec = nullptr, *gacc = nullptr;
     float *parts[2] = {nullptr, nullptr};
@@ -204,6 +205,11 @@ fdtd_status validate(fdtd_ctx *h, const fdtd_desc *d, const fdtd_source *src, in
             (rec && (q.k < p || q.k >= d->nz - p)))
             return fail(h, FDTD_E_INVALID, "detector %d outside the %s", m, rec ? "interior" : "grid");
         if (!std::isfinite(q.weight)) return fail(h, FDTD_E_INVALID, "detector %d: weight not finite", m);
+        if (q.interpolate != 0 && q.interpolate != 1)
+            return fail(h, FDTD_E_INVALID, "detector %d: interpolate must be 0 or 1", m);
+        // the co-located flux reads layer k-1 and the cells at i1, j1
+        if (q.interpolate && (q.k < 1 || q.i1 > d->nx - 1 || q.j1 > d->ny - 1))
+            return fail(h, FDTD_E_INVALID, "detector %d: interpolation needs k >= 1, i1 < nx, j1 < ny", m);
     }
     for (int a = 0; a < 3; a++)
         if (!inside(d->design_lo[a], d->design_hi[a], a))
@@ -229,19 +235,30 @@ void geometry(const fdtd_desc *d, const fdtd_flux_detector *det, int ndet, Geome
     }
     G.R.per_step = off;
     G.D.ndet = ndet;
-    long long doff = 0;
+    long long doff = 0, roff = 0, eoff = 0;
     for (int m = 0; m < FDTD_MAX_DETECTORS; m++) {
+        G.D.roff[m] = roff;
+        G.D.eoff[m] = eoff;
         if (m < ndet) {
             G.D.k[m] = det[m].k; G.D.i0[m] = det[m].i0; G.D.i1[m] = det[m].i1;
             G.D.j0[m] = det[m].j0; G.D.j1[m] = det[m].j1;
             G.D.off[m] = doff;
             doff += (long long)(det[m].i1 - det[m].i0) * (det[m].j1 - det[m].j0);
+            G.D.interp[m] = det[m].interpolate ? 1 : 0;
+            if (G.D.interp[m]) {
+                const long long L = (long long)(det[m].i1 - det[m].i0 + 1) * (det[m].j1 - det[m].j0 + 1);
+                roff += 6 * L;
+                eoff += 2 * L;
+            }
         } else {
             G.D.k[m] = G.D.i0[m] = G.D.i1[m] = G.D.j0[m] = G.D.j1[m] = 0;
             G.D.off[m] = doff;
+            G.D.interp[m] = 0;
         }
     }
     G.D.per_step = doff;
+    G.D.raw_per_step = roff;
+    G.D.eprev_floats = eoff;
     G.design_cells = 1;
     for (int a = 0; a < 3; a++) G.design_cells *= (d->design_hi[a] - d->design_lo[a]);
 }
@@ -367,6 +384,8 @@ size_t plan(fdtd_ctx *h, const fdtd_desc *d, const Geometry &G, int K, void *bas
     h->tline = h->ntfsf > 0 ? B.take(2 * (size_t)tfsf_line_nodes(d->n_steps)) : nullptr;
     h->trace = B.take((size_t)d->n_steps * std::max(1, G.D.ndet));
     h->planes = B.take((size_t)std::max(1, K) * std::max<long long>(1, G.D.per_step));
+    h->raw = G.D.raw_per_step > 0 ? B.take((size_t)std::max(1, K) * G.D.raw_per_step) : nullptr;
+    h->eprev = G.D.eprev_floats > 0 ? B.take(G.D.eprev_floats) : nullptr;
     h->wdev = B.take(FDTD_MAX_DETECTORS);
     {
         long long rs = 1;
@@ -482,6 +501,8 @@ fdtd_status step_naive(fdtd_ctx *h, int n, int with_src, int with_rec, int with_
     Fields F = fields_of(h, h->cur);
     Psi P = psi_of(h, h->cur);
     const Geometry &G = h->geo;
+    const bool interp = with_det && h->raw;
+    if (interp) HIPCHK(h, launch_det_eprev(h->g, F, G.D, h->eprev, h->stream));
     HIPCHK(h, launch_h_naive(h->g, F, P, n, with_src, h->stream));
     if (with_rec && h->rec && G.R.per_step > 0)
         HIPCHK(h, launch_record(h->g, F, G.R, h->rec + (size_t)n * G.R.per_step, 0, 0, h->stream));
@@ -490,6 +511,10 @@ fdtd_status step_naive(fdtd_ctx *h, int n, int with_src, int with_rec, int with_
         HIPCHK(h, launch_record(h->g, F, G.R, h->rec + (size_t)n * G.R.per_step, 1, 0, h->stream));
     if (with_det && G.D.ndet > 0) {
         HIPCHK(h, launch_det_planes(h->g, F, G.D, h->planes, h->stream));
+        if (interp) {
+            HIPCHK(h, launch_det_raw(h->g, F, G.D, h->raw, h->stream));
+            HIPCHK(h, launch_det_interp(G.D, h->raw, h->eprev, 1, h->planes, h->stream));
+        }
         for (int m = 0; m < G.D.ndet; m++) {
             const long long L = (long long)(G.D.i1[m] - G.D.i0[m]) * (G.D.j1[m] - G.D.j0[m]);
             HIPCHK(h, launch_reduce_rows2(h->planes + G.D.off[m], L, 1, G.D.per_step,
@@ -514,7 +539,11 @@ fdtd_status steps_tb(fdtd_ctx *h, int n0, int kk, int with_src, int with_rec, in
     a.rec = (with_rec && h->rec && G.R.per_step > 0) ? h->rec + (size_t)n0 * G.R.per_step : nullptr;
     a.R = G.R;
     a.planes = (with_det && G.D.ndet > 0) ? h->planes : nullptr;
+    a.raw = h->raw;
     a.D = G.D;
+    // E^n of the interpolated detectors' planes (the sweep reads buffer cur
+    // and writes the other one, so this gather may run beside it)
+    if (a.planes && h->raw) HIPCHK(h, launch_det_eprev(h->g, a.in, G.D, h->eprev, h->stream));
     a.xcd_remap = 1;
     for (int ax = 0; ax < 3; ax++) a.profv[ax] = h->profv[ax];
     a.fstride = h->fstride;
@@ -538,6 +567,7 @@ fdtd_status steps_tb(fdtd_ctx *h, int n0, int kk, int with_src, int with_rec, in
         }
     }
     h->cur ^= 1;
+    if (a.planes && h->raw) HIPCHK(h, launch_det_interp(G.D, h->raw, h->eprev, kk, h->planes, h->stream));
     if (a.planes)
         for (int m = 0; m < G.D.ndet; m++) {
             const long long L = (long long)(G.D.i1[m] - G.D.i0[m]) * (G.D.j1[m] - G.D.j0[m]);
@@ -931,10 +961,20 @@ fdtd_status fdtd_inverse(fdtd_handle h, int32_t n_steps)
     return FDTD_OK;
 }
 
+// an interpolated detector that enters the objective (its adjoint is not built)
+static bool interp_weighted(const fdtd_ctx *h)
+{
+    for (int m = 0; m < h->ndet; m++)
+        if (h->det[m].interpolate && h->det[m].weight != 0.f) return true;
+    return false;
+}
+
 fdtd_status fdtd_grad(fdtd_handle h, float *dJ_deps, float *recon_err)
 {
     if (!h) return fail(nullptr, FDTD_E_INVALID, "handle is NULL");
     if (!h->desc.record) return fail(h, FDTD_E_STATE, "fdtd_grad needs record = 1");
+    if (interp_weighted(h))
+        return fail(h, FDTD_E_UNSUPPORTED, "interpolated detectors are forward only: give them weight 0 in a gradient");
     if (h->t != h->T) return fail(h, FDTD_E_STATE, "fdtd_grad needs t = T (t = %d, T = %d)", h->t, h->T);
     if (!dJ_deps) return fail(h, FDTD_E_INVALID, "dJ_deps is NULL");
     const Geometry &G = h->geo;
@@ -1028,6 +1068,8 @@ fdtd_status fdtd_grad_checkpointed(fdtd_handle h, int32_t segment, void *store, 
 {
     if (!h) return fail(nullptr, FDTD_E_INVALID, "handle is NULL");
     if (!h->desc.record) return fail(h, FDTD_E_STATE, "the checkpointed gradient needs the adjoint state (record = 1)");
+    if (interp_weighted(h))
+        return fail(h, FDTD_E_UNSUPPORTED, "interpolated detectors are forward only: give them weight 0 in a gradient");
     if (h->naive) return fail(h, FDTD_E_UNSUPPORTED, "the checkpointed gradient runs on the z-march path only");
     if (segment < 1 || segment > h->T) return fail(h, FDTD_E_INVALID, "segment %d not in [1, T]", segment);
     if (!store || !dJ_deps) return fail(h, FDTD_E_INVALID, "store or dJ_deps is NULL");

@@ -61,6 +61,14 @@ struct Detectors {
     int k[FD_MAXDET], i0[FD_MAXDET], i1[FD_MAXDET], j0[FD_MAXDET], j1[FD_MAXDET];
     long long off[FD_MAXDET];      // offset of the detector's window in a flux plane set
     long long per_step;            // floats of all windows for one step
+    // interpolated (co-located) detectors: per step the six raw planes Ex, Ey
+    // (E^{n+1}, plane k), Hx, Hy (H^{n+1/2}, layer k-1), Hx, Hy (layer k) over
+    // the window extended by one cell in x and y; and E^n of plane k (Ex, Ey)
+    int interp[FD_MAXDET];
+    long long roff[FD_MAXDET];     // offset of the detector's six raw planes in a raw set
+    long long raw_per_step;        // floats of all raw planes for one step
+    long long eoff[FD_MAXDET];     // offset of the detector's two E^n planes
+    long long eprev_floats;
 };
 
 // ------------------------------------------------------------ device helpers
@@ -127,6 +135,14 @@ int tfsf_line_nodes(int T);
 hipError_t launch_tfsf_line(const float *amp, int T, float S, const float *ce_at, float hsign, float *line,
                             float *outE, float *outH, hipStream_t s);
 
+// interpolated detectors: E^n of their planes before a sweep (or step); the
+// raw planes of one step from the fields (per-cell path); the co-located flux
+// density of `levels` steps from the raw planes into the flux planes
+hipError_t launch_det_eprev(const Grid &g, const Fields &F, const Detectors &D, float *eprev, hipStream_t s);
+hipError_t launch_det_raw(const Grid &g, const Fields &F, const Detectors &D, float *raw, hipStream_t s);
+hipError_t launch_det_interp(const Detectors &D, const float *raw, const float *eprev, int levels, float *planes,
+                             hipStream_t s);
+
 hipError_t launch_record(const Grid &g, const Fields &F, const RecGeom &R, float *rec_step,
                          int side, int restore, hipStream_t s);
 hipError_t launch_record_zero_e(const Grid &g, const Fields &F, const RecGeom &R, hipStream_t s);
@@ -164,6 +180,7 @@ struct TbArgs {
     float *rec;             // record of step n0 (or nullptr); step n0+s at rec + s*per_step
     RecGeom R;
     float *planes;          // detector flux planes of step n0 (or nullptr); + s*D.per_step
+    float *raw;             // raw planes of the interpolated detectors, step n0; + s*D.raw_per_step
     Detectors D;
     const int4 *tiles;      // per tile two int4: (x0, x1, y0, y1), (z0, z1, class, 0) owned box
     int ntiles;

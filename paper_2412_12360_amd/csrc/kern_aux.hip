@@ -62,6 +62,82 @@ __global__ __launch_bounds__(NT) void k_det_planes(Grid g, Fields F, Detectors D
     planes[t] = flux_density(F.c[0][c], F.c[1][c], F.c[3][c], F.c[4][c]);
 }
 
+// Interpolated detectors (section 2.1: composite metrics need all components
+// at one point and time).  Cell t of detector m's extended window
+// [i0, i1] x [j0, j1] (one more cell in x and y than the flux window).
+__device__ __forceinline__ bool ext_cell(const Detectors &D, long long t, int &m, int &i, int &j, long long &e,
+                                         long long &L)
+{
+    long long base = 0;
+    for (m = 0; m < D.ndet; m++) {
+        if (!D.interp[m]) continue;
+        const int w = D.i1[m] - D.i0[m] + 1;
+        L = (long long)w * (D.j1[m] - D.j0[m] + 1);
+        if (t < base + L) {
+            e = t - base;
+            j = D.j0[m] + (int)(e / w);
+            i = D.i0[m] + (int)(e - (long long)(j - D.j0[m]) * w);
+            return true;
+        }
+        base += L;
+    }
+    return false;
+}
+
+// E^n (Ex, Ey) of the interpolated detectors' planes, before the step
+__global__ __launch_bounds__(NT) void k_det_eprev(Grid g, Fields F, Detectors D, float *eprev, long long total)
+{
+    const long long t = (long long)blockIdx.x * NT + threadIdx.x;
+    if (t >= total) return;
+    int m, i, j;
+    long long e, L;
+    if (!ext_cell(D, t, m, i, j, e, L)) return;
+    const long long c = cidx(g, i, j, D.k[m]);
+    eprev[D.eoff[m] + e] = F.c[0][c];
+    eprev[D.eoff[m] + L + e] = F.c[1][c];
+}
+
+// the six raw planes of one step from the fields (per-cell path)
+__global__ __launch_bounds__(NT) void k_det_raw(Grid g, Fields F, Detectors D, float *raw, long long total)
+{
+    const long long t = (long long)blockIdx.x * NT + threadIdx.x;
+    if (t >= total) return;
+    int m, i, j;
+    long long e, L;
+    if (!ext_cell(D, t, m, i, j, e, L)) return;
+    const long long c = cidx(g, i, j, D.k[m]), cm = c - g.nxy;
+    float *r = raw + D.roff[m] + e;
+    r[0] = F.c[0][c];
+    r[L] = F.c[1][c];
+    r[2 * L] = F.c[3][cm];
+    r[3 * L] = F.c[4][cm];
+    r[4 * L] = F.c[3][c];
+    r[5 * L] = F.c[4][c];
+}
+
+// co-located flux density of detector m at step level s: E of steps n, n+1
+// (from eprev for s = 0, else from the raw planes of level s-1) and
+// H^{n+1/2} of layers k-1, k, each averaged onto (i+1/2, j+1/2, k)
+__global__ __launch_bounds__(NT) void k_det_interp(Detectors D, int m, int s, const float *raw, const float *eprev,
+                                                   float *planes)
+{
+    const long long e = (long long)blockIdx.x * NT + threadIdx.x;
+    const int w = D.i1[m] - D.i0[m];
+    const long long n = (long long)w * (D.j1[m] - D.j0[m]);
+    if (e >= n) return;
+    const int jj = (int)(e / w), ii = (int)(e - (long long)jj * w);
+    const int wx = w + 1;
+    const long long L = (long long)wx * (D.j1[m] - D.j0[m] + 1);
+    const long long p00 = (long long)jj * wx + ii, p10 = p00 + 1, p01 = p00 + wx;
+    const float *Rb = raw + s * D.raw_per_step + D.roff[m];
+    const float *Ea = s == 0 ? eprev + D.eoff[m] : raw + (s - 1) * D.raw_per_step + D.roff[m];
+    const float ex = 0.25f * ((Ea[p00] + Ea[p01]) + (Rb[p00] + Rb[p01]));
+    const float ey = 0.25f * ((Ea[L + p00] + Ea[L + p10]) + (Rb[L + p00] + Rb[L + p10]));
+    const float hx = 0.25f * ((Rb[2 * L + p00] + Rb[2 * L + p10]) + (Rb[4 * L + p00] + Rb[4 * L + p10]));
+    const float hy = 0.25f * ((Rb[3 * L + p00] + Rb[3 * L + p01]) + (Rb[5 * L + p00] + Rb[5 * L + p01]));
+    planes[s * D.per_step + D.off[m] + e] = flux_density(ex, ey, hx, hy);
+}
+
 // dJ/dE^{n+1} and dJ/dH^{n+1/2} of J += S w sum (Ex Hy - Ey Hx)
 __global__ __launch_bounds__(NT) void k_det_adjoint(Grid g, Fields F, Fields A, Detectors D, int m, float sw)
 {
@@ -320,6 +396,45 @@ hipError_t launch_deps(const float *gacc, const float *dd, long long D, float S,
     if (D == 0) return hipSuccess;
     hipLaunchKernelGGL(k_deps, dim3(nblk(D)), dim3(NT), 0, s, gacc, dd, D, S, out);
     return hipGetLastError();
+}
+
+long long ext_total(const Detectors &D)
+{
+    long long tot = 0;
+    for (int m = 0; m < D.ndet; m++)
+        if (D.interp[m]) tot += (long long)(D.i1[m] - D.i0[m] + 1) * (D.j1[m] - D.j0[m] + 1);
+    return tot;
+}
+
+hipError_t launch_det_eprev(const Grid &g, const Fields &F, const Detectors &D, float *eprev, hipStream_t s)
+{
+    const long long tot = ext_total(D);
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_det_eprev, dim3(nblk(tot)), dim3(NT), 0, s, g, F, D, eprev, tot);
+    return hipGetLastError();
+}
+
+hipError_t launch_det_raw(const Grid &g, const Fields &F, const Detectors &D, float *raw, hipStream_t s)
+{
+    const long long tot = ext_total(D);
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_det_raw, dim3(nblk(tot)), dim3(NT), 0, s, g, F, D, raw, tot);
+    return hipGetLastError();
+}
+
+hipError_t launch_det_interp(const Detectors &D, const float *raw, const float *eprev, int levels, float *planes,
+                             hipStream_t s)
+{
+    for (int m = 0; m < D.ndet; m++) {
+        if (!D.interp[m]) continue;
+        const long long n = (long long)(D.i1[m] - D.i0[m]) * (D.j1[m] - D.j0[m]);
+        for (int l = 0; l < levels; l++) {
+            hipLaunchKernelGGL(k_det_interp, dim3(nblk(n)), dim3(NT), 0, s, D, m, l, raw, eprev, planes);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
 }
 
 int tfsf_line_nodes(int T) { return T / 2 + 8; }

@@ -405,6 +405,28 @@ __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
                 if (A.planes && k >= z0 && k < z1) {
                     for (int m = 0; m < A.D.ndet; m++) {
                         if (k != A.D.k[m]) continue;
+                        if (A.D.interp[m]) {
+                            // co-located flux: the raw components over the window
+                            // extended by one cell in x and y (E^{n+1} of plane k,
+                            // H^{n+1/2} of layers k-1 and k), combined after the sweep
+                            const int wx = A.D.i1[m] - A.D.i0[m] + 1;
+                            const long long L = (long long)wx * (A.D.j1[m] - A.D.j0[m] + 1);
+#pragma unroll
+                            for (int r = 0; r < R; r++) {
+                                const int yy = ys[r];
+                                if (own[r] && x >= A.D.i0[m] && x <= A.D.i1[m] && yy >= A.D.j0[m] && yy <= A.D.j1[m]) {
+                                    float *rw = A.raw + (long long)(s - 1) * A.D.raw_per_step + A.D.roff[m] +
+                                                (long long)(yy - A.D.j0[m]) * wx + (x - A.D.i0[m]);
+                                    rw[0] = mE[r][0];
+                                    rw[L] = mE[r][1];
+                                    rw[2 * L] = Ho[s][r][0];
+                                    rw[3 * L] = Ho[s][r][1];
+                                    rw[4 * L] = mH[r][0];
+                                    rw[5 * L] = mH[r][1];
+                                }
+                            }
+                            continue;
+                        }
 #pragma unroll
                         for (int r = 0; r < R; r++) {
                             const int yy = ys[r];

@@ -148,3 +148,14 @@ def test_tfsf_takes_two_source_slots():
     st, _ = _status(W.dataclasses.replace(pr, sources=pr.sources + extra))
     assert st == F.FDTD_E_INVALID
     assert "slots" in F.lib().fdtd_last_error(None).decode()
+
+
+@pytest.mark.parametrize("change", [dict(k=0), dict(i1=40), dict(j1=36), dict(interpolate=2)])
+def test_interpolated_detector_placement_validated(change):
+    F = _F()
+    pr = W.small_cpml(nx=40, ny=36, nz=44, p=0, T=50)
+    det = W.Detector(k=10, i0=0, i1=39, j0=0, j1=35, interpolate=True)
+    assert _status(W.dataclasses.replace(pr, detectors=[det]))[0] == F.FDTD_OK
+    bad = W.dataclasses.replace(det, **change)
+    st, _ = _status(W.dataclasses.replace(pr, detectors=[bad]))
+    assert st == F.FDTD_E_INVALID
