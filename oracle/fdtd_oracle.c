@@ -26,9 +26,9 @@
  *     source, see oracle.py); a non-interpolated Poynting-flux detector on a
  *     z-normal plane and the objective J = S * sum_n w * P[n] (section 2.1,
  *     detectors without interpolation).
- *   - the interpolated flux of section 2.1 (forward only): Ex, Ey, Hx, Hy each
- *     averaged onto the point (i+1/2, j+1/2, k) of the detector plane at time
- *     n+1/2 (E of steps n and n+1; H^{n+1/2} of layers k-1 and k).
+ *   - the interpolated flux of section 2.1: Ex, Ey, Hx, Hy each averaged onto
+ *     the point (i+1/2, j+1/2, k) of the detector plane at time n+1/2 (E of
+ *     steps n and n+1; H^{n+1/2} of layers k-1 and k), and its adjoint source.
  *   - the interface record (section 2.2): every step, tangential H^{n+1/2} on
  *     the PML-side layer p-1 of the three low faces and tangential E^{n+1} on
  *     layer n_a-p of the three high faces, over the interior window.
@@ -68,7 +68,7 @@ typedef struct {
     int det_k[OR_MAXDET];
     int det_i0[OR_MAXDET], det_i1[OR_MAXDET], det_j0[OR_MAXDET], det_j1[OR_MAXDET];
     double det_w[OR_MAXDET];
-    int det_interp[OR_MAXDET];      /* 1: co-located (interpolated) flux, forward only */
+    int det_interp[OR_MAXDET];      /* 1: co-located (interpolated) flux */
     int dlo[3], dhi[3];             /* half-open design box */
 } or_problem;
 
@@ -373,20 +373,106 @@ static void step_fwd(const or_problem *P, double *st, int n, const or_prof *PE, 
 
 /* Advance st by T steps starting at step n0.  trace: [T][ndet] or NULL.
  * rec: [T][or_record_floats] or NULL.  Returns J = S * sum w * P over the run. */
-double or_forward(const or_problem *P, double *st, int n0, int T, double *trace, double *rec)
+/* Adjoint of the interpolated flux.  The gradient passes keep, per step n and
+ * interpolated detector m, the planes the co-located flux of step n reads:
+ * E^{n+1} x, y of plane k, H^{n+1/2} x, y of layer k-1, H^{n+1/2} x, y of
+ * layer k (six [ny][nx] planes), and E^0 x, y of plane k. */
+static size_t dstore_floats(const or_problem *P, int T)
+{
+    return (size_t)T * P->ndet * 6 * (size_t)P->nx * P->ny;
+}
+
+static int any_interp(const or_problem *P)
+{
+    for (int m = 0; m < P->ndet; m++)
+        if (P->det_interp[m]) return 1;
+    return 0;
+}
+
+static void dstore_planes(const or_problem *P, const double *st, double *dst, int m, int e_only)
+{
+    size_t A = (size_t)P->nx * P->ny;
+    int k = P->det_k[m];
+    const int comp[6] = {0, 1, 3, 4, 3, 4};
+    const int layer[6] = {k, k, k - 1, k - 1, k, k};
+    for (int q = 0; q < (e_only ? 2 : 6); q++)
+        memcpy(dst + q * A, slot((double *)st, P, comp[q]) + (size_t)layer[q] * A, sizeof(double) * A);
+}
+
+/* Before reverse step n: add dJ/dE^{n+1} and dJ/dH^{n+1/2} of the interpolated
+ * detectors, J = S sum_n w P[n] with P[n] the co-located sum.  E^{n+1} enters
+ * P[n] (as the later of its two steps) and P[n+1] (as the earlier); H^{n+1/2}
+ * enters P[n] only.  Each co-located value is a quarter of four nodes, so each
+ * node receives a quarter of the partner value of every cell it enters. */
+static void det_interp_adjoint(const or_problem *P, double *adj, const double *store, const double *e0, int n,
+                               int T)
+{
+    size_t N = ncell(P), A = (size_t)P->nx * P->ny;
+    for (int m = 0; m < P->ndet; m++) {
+        if (!P->det_interp[m]) continue;
+        double sw = P->S * P->det_w[m];
+        if (sw == 0.0) continue;
+        int k = P->det_k[m];
+        const double *R = store + ((size_t)n * P->ndet + m) * 6 * A;
+        const double *Ep = n == 0 ? e0 + (size_t)m * 2 * A : store + ((size_t)(n - 1) * P->ndet + m) * 6 * A;
+        const double *R1 = n + 1 < T ? store + ((size_t)(n + 1) * P->ndet + m) * 6 * A : NULL;
+        for (int j = P->det_j0[m]; j < P->det_j1[m]; j++)
+            for (int i = P->det_i0[m]; i < P->det_i1[m]; i++) {
+                size_t p00 = (size_t)j * P->nx + i, p01 = p00 + P->nx, p10 = p00 + 1;
+                double exc = 0.25 * (Ep[p00] + Ep[p01] + R[p00] + R[p01]);
+                double eyc = 0.25 * (Ep[A + p00] + Ep[A + p10] + R[A + p00] + R[A + p10]);
+                double hxc = 0.25 * (R[2 * A + p00] + R[2 * A + p10] + R[4 * A + p00] + R[4 * A + p10]);
+                double hyc = 0.25 * (R[3 * A + p00] + R[3 * A + p01] + R[5 * A + p00] + R[5 * A + p01]);
+                double hxc1 = 0.0, hyc1 = 0.0;
+                if (R1) {
+                    hxc1 = 0.25 * (R1[2 * A + p00] + R1[2 * A + p10] + R1[4 * A + p00] + R1[4 * A + p10]);
+                    hyc1 = 0.25 * (R1[3 * A + p00] + R1[3 * A + p01] + R1[5 * A + p00] + R1[5 * A + p01]);
+                }
+                double *aEx = adj, *aEy = adj + N, *aHx = adj + 3 * N, *aHy = adj + 4 * N;
+                double gx = 0.25 * sw * (hyc + hyc1), gy = -0.25 * sw * (hxc + hxc1);
+                aEx[idx(P, i, j, k)] += gx;
+                aEx[idx(P, i, j + 1, k)] += gx;
+                aEy[idx(P, i, j, k)] += gy;
+                aEy[idx(P, i + 1, j, k)] += gy;
+                double ghy = 0.25 * sw * exc, ghx = -0.25 * sw * eyc;
+                for (int kk = k - 1; kk <= k; kk++) {
+                    aHy[idx(P, i, j, kk)] += ghy;
+                    aHy[idx(P, i, j + 1, kk)] += ghy;
+                    aHx[idx(P, i, j, kk)] += ghx;
+                    aHx[idx(P, i + 1, j, kk)] += ghx;
+                }
+            }
+    }
+}
+
+/* forward loop shared by or_forward and the gradients; store/e0 (may be NULL)
+ * receive the interpolated detectors' planes */
+static double forward_run(const or_problem *P, double *st, int n0, int T, double *trace, double *rec,
+                          double *store, double *e0)
 {
     or_prof PE, PH;
     prof_make(P, &PE, &PH);
-    size_t rf = rec ? or_record_floats(P) : 0;
+    size_t rf = rec ? or_record_floats(P) : 0, A = (size_t)P->nx * P->ny;
     double J = 0.0;
     double *tr = trace ? trace : malloc(sizeof(double) * (size_t)(T > 0 ? T : 1) * (P->ndet > 0 ? P->ndet : 1));
+    if (e0)
+        for (int m = 0; m < P->ndet; m++)
+            if (P->det_interp[m]) dstore_planes(P, st, e0 + (size_t)m * 2 * A, m, 1);
     for (int n = 0; n < T; n++) {
         step_fwd(P, st, n0 + n, &PE, &PH, tr + (size_t)n * P->ndet, rec ? rec + (size_t)n * rf : NULL, 1);
         for (int m = 0; m < P->ndet; m++) J += P->S * P->det_w[m] * tr[(size_t)n * P->ndet + m];
+        if (store)
+            for (int m = 0; m < P->ndet; m++)
+                if (P->det_interp[m]) dstore_planes(P, st, store + ((size_t)n * P->ndet + m) * 6 * A, m, 0);
     }
     if (!trace) free(tr);
     prof_free(&PE); prof_free(&PH);
     return J;
+}
+
+double or_forward(const or_problem *P, double *st, int n0, int T, double *trace, double *rec)
+{
+    return forward_run(P, st, n0, T, trace, rec, NULL, NULL);
 }
 
 /* the linear step map M (no source, no detector), T times */
@@ -471,7 +557,7 @@ static void adjoint_step(const or_problem *P, double *adj, const double *fwd, do
         const double *Ex = fwd, *Ey = fwd + N, *Hx = fwd + 3 * N, *Hy = fwd + 4 * N;
         double *aEx = adj, *aEy = adj + N, *aHx = adj + 3 * N, *aHy = adj + 4 * N;
         for (int m = 0; m < P->ndet; m++) {
-            if (P->det_interp[m]) continue;   /* forward only: its weight must be 0 in a gradient */
+            if (P->det_interp[m]) continue;   /* its adjoint source: det_interp_adjoint */
             double sw = S * P->det_w[m];
             int k = P->det_k[m];
             for (int j = P->det_j0[m]; j < P->det_j1[m]; j++)
@@ -604,10 +690,19 @@ double or_grad_history(const or_problem *P, int T, int seg, double *g, double *t
     prof_make(P, &PE, &PH);
     double J = 0.0;
     double *tr = malloc(sizeof(double) * (size_t)(T > 0 ? T : 1) * (P->ndet > 0 ? P->ndet : 1));
+    size_t A = (size_t)P->nx * P->ny;
+    double *store = any_interp(P) ? calloc(dstore_floats(P, T) + 1, sizeof(double)) : NULL;
+    double *e0 = any_interp(P) ? calloc((size_t)P->ndet * 2 * A, sizeof(double)) : NULL;
+    if (e0)
+        for (int m = 0; m < P->ndet; m++)
+            if (P->det_interp[m]) dstore_planes(P, st, e0 + (size_t)m * 2 * A, m, 1);
     for (int n = 0; n < T; n++) {
         if (n % seg == 0) memcpy(ck + (size_t)(n / seg) * SZ, st, sizeof(double) * SZ);
         step_fwd(P, st, n, &PE, &PH, tr + (size_t)n * P->ndet, NULL, 1);
         for (int m = 0; m < P->ndet; m++) J += P->S * P->det_w[m] * tr[(size_t)n * P->ndet + m];
+        if (store)
+            for (int m = 0; m < P->ndet; m++)
+                if (P->det_interp[m]) dstore_planes(P, st, store + ((size_t)n * P->ndet + m) * 6 * A, m, 0);
     }
     if (trace) memcpy(trace, tr, sizeof(double) * (size_t)T * P->ndet);
     double *adj = calloc(SZ, sizeof(double));
@@ -620,10 +715,12 @@ double or_grad_history(const or_problem *P, int T, int seg, double *g, double *t
             memcpy(buf + (size_t)(m + 1) * SZ, buf + (size_t)m * SZ, sizeof(double) * SZ);
             step_fwd(P, buf + (size_t)(m + 1) * SZ, s0 + m, &PE, &PH, NULL, NULL, 1);
         }
-        for (int m = len - 1; m >= 0; m--)
+        for (int m = len - 1; m >= 0; m--) {
+            if (store) det_interp_adjoint(P, adj, store, e0, s0 + m, T);
             adjoint_step(P, adj, buf + (size_t)(m + 1) * SZ, g, 1, &PE, &PH, tmp);
+        }
     }
-    free(ck); free(buf); free(st); free(adj); free(tmp); free(tr);
+    free(ck); free(buf); free(st); free(adj); free(tmp); free(tr); free(store); free(e0);
     prof_free(&PE); prof_free(&PH);
     return J;
 }
@@ -638,7 +735,10 @@ double or_grad_reversed(const or_problem *P, int T, double *g, double *trace, do
     size_t N = ncell(P), SZ = OR_NSLOT * N, rf = or_record_floats(P);
     double *st = calloc(SZ, sizeof(double));
     double *rec = P->p > 0 ? malloc(sizeof(double) * (size_t)(T > 0 ? T : 1) * rf) : NULL;
-    double J = or_forward(P, st, 0, T, trace, rec);
+    size_t A = (size_t)P->nx * P->ny;
+    double *store = any_interp(P) ? calloc(dstore_floats(P, T) + 1, sizeof(double)) : NULL;
+    double *e0 = any_interp(P) ? calloc((size_t)P->ndet * 2 * A, sizeof(double)) : NULL;
+    double J = forward_run(P, st, 0, T, trace, rec, store, e0);
     int p = P->p;
     double nT = 0.0;
     for (int f = 0; f < 6; f++)
@@ -651,6 +751,7 @@ double or_grad_reversed(const or_problem *P, int T, double *g, double *trace, do
     double *tmp = malloc(sizeof(double) * 6 * N);
     memset(g, 0, sizeof(double) * N);
     for (int n = T - 1; n >= 0; n--) {
+        if (store) det_interp_adjoint(P, adj, store, e0, n, T);
         adjoint_step(P, adj, st, g, 1, &PE, &PH, tmp);
         inverse_step(P, st, n, rec);
     }
@@ -662,7 +763,7 @@ double or_grad_reversed(const or_problem *P, int T, double *g, double *trace, do
                     for (int i = p; i < P->nx - p; i++) { double v = st[(size_t)f * N + idx(P, i, j, k)]; n0 += v * v; }
         *recon = nT > 0.0 ? sqrt(n0 / nT) : 0.0;
     }
-    free(st); free(rec); free(adj); free(tmp);
+    free(st); free(rec); free(adj); free(tmp); free(store); free(e0);
     prof_free(&PE); prof_free(&PH);
     return J;
 }

@@ -225,14 +225,8 @@ class Oracle:
         self.L.or_adjoint_linear(C.byref(self.s), _ptr(adj), T)
 
     # ----------------------------------------------------------- gradients
-    def _check_grad(self):
-        for det in self.prob.detectors:
-            assert not (getattr(det, "interpolate", False) and det.weight != 0.0), \
-                "interpolated detectors are forward only: weight 0 in a gradient"
-
     def grad_history(self, T: int | None = None, seg: int | None = None):
         """dJ/dd over the grid by the stored-history VJP; returns (g, J, trace)."""
-        self._check_grad()
         T = self.prob.T if T is None else T
         self._check_T(0, T)
         seg = seg or max(1, int(np.ceil(np.sqrt(T))))
@@ -244,7 +238,6 @@ class Oracle:
 
     def grad_reversed(self, T: int | None = None):
         """dJ/dd by time reversal; returns (g, J, trace, recon)."""
-        self._check_grad()
         T = self.prob.T if T is None else T
         self._check_T(0, T)
         g = np.zeros(self.prob.shape, np.float64)
