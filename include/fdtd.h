@@ -109,9 +109,10 @@ typedef struct {
  *     onto the point (i+1/2, j+1/2, k) at time n+1/2 -- Ex over j, j+1 and the
  *     steps n, n+1; Ey over i, i+1 and the two steps; Hx over i, i+1 and the
  *     layers k-1, k; Hy over j, j+1 and the two layers -- then the same sum.
- *     Needs k >= 1, i1 < nx, j1 < ny.  Forward only: fdtd_grad and
- *     fdtd_grad_checkpointed return FDTD_E_UNSUPPORTED when such a detector
- *     has a nonzero weight. */
+ *     Needs k >= 1, i1 < nx, j1 < ny.  With record = 1 the library keeps the
+ *     six planes such a detector reads (E^{n+1} of plane k, H^{n+1/2} of
+ *     layers k-1 and k; 24 B per cell of the window extended by one cell in
+ *     x and y, per step) so that the gradients can apply its adjoint source. */
 typedef struct {
     int32_t k, i0, i1, j0, j1;
     float weight;

@@ -95,6 +95,8 @@ struct fdtd_ctx {
     hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
     int shape = 0;                         // z-march workgroup shape
     float wS[FDTD_MAX_DETECTORS];
+    float wS_plain[FDTD_MAX_DETECTORS];   // wS with the interpolated detectors' entries zero
+    float *drec = nullptr, *drec_e0 = nullptr;  // interpolated detectors' planes of every step (gradients)
     std::vector<float> host_tables;        // kept alive for async uploads
     std::vector<int4> host_tiles;
 };
@@ -386,6 +388,11 @@ size_t plan(fdtd_ctx *h, const fdtd_desc *d, const Geometry &G, int K, void *bas
     h->planes = B.take((size_t)std::max(1, K) * std::max<long long>(1, G.D.per_step));
     h->raw = G.D.raw_per_step > 0 ? B.take((size_t)std::max(1, K) * G.D.raw_per_step) : nullptr;
     h->eprev = G.D.eprev_floats > 0 ? B.take(G.D.eprev_floats) : nullptr;
+    // with the adjoint state, the interpolated detectors' planes of every step
+    // (their adjoint source reads steps n-1, n, n+1) and of step 0
+    const bool keep = d->record && G.D.raw_per_step > 0;
+    h->drec = keep ? B.take((size_t)d->n_steps * G.D.raw_per_step) : nullptr;
+    h->drec_e0 = keep ? B.take(G.D.eprev_floats) : nullptr;
     h->wdev = B.take(FDTD_MAX_DETECTORS);
     {
         long long rs = 1;
@@ -502,7 +509,9 @@ fdtd_status step_naive(fdtd_ctx *h, int n, int with_src, int with_rec, int with_
     Psi P = psi_of(h, h->cur);
     const Geometry &G = h->geo;
     const bool interp = with_det && h->raw;
+    float *rawt = h->drec ? h->drec + (size_t)n * G.D.raw_per_step : h->raw;
     if (interp) HIPCHK(h, launch_det_eprev(h->g, F, G.D, h->eprev, h->stream));
+    if (interp && h->drec && n == 0) HIPCHK(h, launch_det_eprev(h->g, F, G.D, h->drec_e0, h->stream));
     HIPCHK(h, launch_h_naive(h->g, F, P, n, with_src, h->stream));
     if (with_rec && h->rec && G.R.per_step > 0)
         HIPCHK(h, launch_record(h->g, F, G.R, h->rec + (size_t)n * G.R.per_step, 0, 0, h->stream));
@@ -512,8 +521,8 @@ fdtd_status step_naive(fdtd_ctx *h, int n, int with_src, int with_rec, int with_
     if (with_det && G.D.ndet > 0) {
         HIPCHK(h, launch_det_planes(h->g, F, G.D, h->planes, h->stream));
         if (interp) {
-            HIPCHK(h, launch_det_raw(h->g, F, G.D, h->raw, h->stream));
-            HIPCHK(h, launch_det_interp(G.D, h->raw, h->eprev, 1, h->planes, h->stream));
+            HIPCHK(h, launch_det_raw(h->g, F, G.D, rawt, h->stream));
+            HIPCHK(h, launch_det_interp(G.D, rawt, h->eprev, 1, h->planes, h->stream));
         }
         for (int m = 0; m < G.D.ndet; m++) {
             const long long L = (long long)(G.D.i1[m] - G.D.i0[m]) * (G.D.j1[m] - G.D.j0[m]);
@@ -539,11 +548,12 @@ fdtd_status steps_tb(fdtd_ctx *h, int n0, int kk, int with_src, int with_rec, in
     a.rec = (with_rec && h->rec && G.R.per_step > 0) ? h->rec + (size_t)n0 * G.R.per_step : nullptr;
     a.R = G.R;
     a.planes = (with_det && G.D.ndet > 0) ? h->planes : nullptr;
-    a.raw = h->raw;
+    a.raw = h->drec ? h->drec + (size_t)n0 * G.D.raw_per_step : h->raw;
     a.D = G.D;
     // E^n of the interpolated detectors' planes (the sweep reads buffer cur
     // and writes the other one, so this gather may run beside it)
     if (a.planes && h->raw) HIPCHK(h, launch_det_eprev(h->g, a.in, G.D, h->eprev, h->stream));
+    if (a.planes && h->drec && n0 == 0) HIPCHK(h, launch_det_eprev(h->g, a.in, G.D, h->drec_e0, h->stream));
     a.xcd_remap = 1;
     for (int ax = 0; ax < 3; ax++) a.profv[ax] = h->profv[ax];
     a.fstride = h->fstride;
@@ -567,7 +577,7 @@ fdtd_status steps_tb(fdtd_ctx *h, int n0, int kk, int with_src, int with_rec, in
         }
     }
     h->cur ^= 1;
-    if (a.planes && h->raw) HIPCHK(h, launch_det_interp(G.D, h->raw, h->eprev, kk, h->planes, h->stream));
+    if (a.planes && h->raw) HIPCHK(h, launch_det_interp(G.D, a.raw, h->eprev, kk, h->planes, h->stream));
     if (a.planes)
         for (int m = 0; m < G.D.ndet; m++) {
             const long long L = (long long)(G.D.i1[m] - G.D.i0[m]) * (G.D.j1[m] - G.D.j0[m]);
@@ -608,7 +618,7 @@ fdtd_status reverse_step(fdtd_ctx *h, int n, int do_adj)
             HIPCHK(h, launch_record_zero_e(h->g, F, G.R, h->stream));
     }
     Fields A = do_adj ? adj_of(h, h->acur) : Fields{};
-    if (do_adj && G.D.ndet > 0) HIPCHK(h, launch_det_adjoint(h->g, F, A, G.D, h->wS, h->stream));
+    if (do_adj && G.D.ndet > 0) HIPCHK(h, launch_det_adjoint(h->g, F, A, G.D, h->wS_plain, h->stream));
     Psi Pc = psibar_of(h, h->apar), Pn = psibar_of(h, h->apar ^ 1);
     HIPCHK(h, launch_bwd_a(h->g, F, A, Pc, n, 1, do_adj, do_adj ? h->gacc : nullptr, h->desc.design_lo,
                            h->desc.design_hi, h->stream));
@@ -641,7 +651,7 @@ fdtd_status reverse_fused(fdtd_ctx *h, int n, int do_inv, int do_adj, int with_d
     a.rec_e = (do_inv && G.p > 0 && n > 0) ? h->rec + (size_t)(n - 1) * G.R.per_step : nullptr;
     a.R = G.R;
     a.D = G.D;
-    for (int m = 0; m < FD_MAXDET; m++) a.wS[m] = h->wS[m];
+    for (int m = 0; m < FD_MAXDET; m++) a.wS[m] = h->wS_plain[m];
     a.gacc = gacc;
     a.dlo = make_int3(h->desc.design_lo[0], h->desc.design_lo[1], h->desc.design_lo[2]);
     a.dhi = make_int3(h->desc.design_hi[0], h->desc.design_hi[1], h->desc.design_hi[2]);
@@ -851,6 +861,7 @@ fdtd_status fdtd_create(const fdtd_desc *desc, const fdtd_source *src, int32_t n
     for (int m2 = 0; m2 < FDTD_MAX_DETECTORS; m2++) {
         const float w = m2 < ndet ? det[m2].weight : 0.f;
         h->wS[m2] = desc->courant * w;
+        h->wS_plain[m2] = (m2 < ndet && det[m2].interpolate) ? 0.f : h->wS[m2];
         h->host_tables.push_back(w);
     }
     {
@@ -961,20 +972,10 @@ fdtd_status fdtd_inverse(fdtd_handle h, int32_t n_steps)
     return FDTD_OK;
 }
 
-// an interpolated detector that enters the objective (its adjoint is not built)
-static bool interp_weighted(const fdtd_ctx *h)
-{
-    for (int m = 0; m < h->ndet; m++)
-        if (h->det[m].interpolate && h->det[m].weight != 0.f) return true;
-    return false;
-}
-
 fdtd_status fdtd_grad(fdtd_handle h, float *dJ_deps, float *recon_err)
 {
     if (!h) return fail(nullptr, FDTD_E_INVALID, "handle is NULL");
     if (!h->desc.record) return fail(h, FDTD_E_STATE, "fdtd_grad needs record = 1");
-    if (interp_weighted(h))
-        return fail(h, FDTD_E_UNSUPPORTED, "interpolated detectors are forward only: give them weight 0 in a gradient");
     if (h->t != h->T) return fail(h, FDTD_E_STATE, "fdtd_grad needs t = T (t = %d, T = %d)", h->t, h->T);
     if (!dJ_deps) return fail(h, FDTD_E_INVALID, "dJ_deps is NULL");
     const Geometry &G = h->geo;
@@ -984,6 +985,9 @@ fdtd_status fdtd_grad(fdtd_handle h, float *dJ_deps, float *recon_err)
     if (st != FDTD_OK) return st;
     HIPCHK(h, launch_fill(h->gacc, G.design_cells, 0.f, h->stream));
     for (int n = h->T - 1; n >= 0; n--) {
+        if (h->drec)
+            HIPCHK(h, launch_det_interp_adjoint(h->g, G.D, h->drec, h->drec_e0, n, h->T, h->wS, adj_of(h, h->acur),
+                                                h->stream));
         st = h->naive ? reverse_step(h, n, 1) : reverse_fused(h, n, 1, 1, 1, h->gacc);
         if (st != FDTD_OK) return st;
     }
@@ -1068,8 +1072,6 @@ fdtd_status fdtd_grad_checkpointed(fdtd_handle h, int32_t segment, void *store, 
 {
     if (!h) return fail(nullptr, FDTD_E_INVALID, "handle is NULL");
     if (!h->desc.record) return fail(h, FDTD_E_STATE, "the checkpointed gradient needs the adjoint state (record = 1)");
-    if (interp_weighted(h))
-        return fail(h, FDTD_E_UNSUPPORTED, "interpolated detectors are forward only: give them weight 0 in a gradient");
     if (h->naive) return fail(h, FDTD_E_UNSUPPORTED, "the checkpointed gradient runs on the z-march path only");
     if (segment < 1 || segment > h->T) return fail(h, FDTD_E_INVALID, "segment %d not in [1, T]", segment);
     if (!store || !dJ_deps) return fail(h, FDTD_E_INVALID, "store or dJ_deps is NULL");
@@ -1129,6 +1131,9 @@ fdtd_status fdtd_grad_checkpointed(fdtd_handle h, int32_t segment, void *store, 
             kept(n - n0, kf);
             Fields F;
             for (int q = 0; q < 6; q++) F.c[q] = kf[q];
+            if (h->drec)
+                HIPCHK(h, launch_det_interp_adjoint(h->g, G.D, h->drec, h->drec_e0, n, h->T, h->wS,
+                                                    adj_of(h, h->acur), h->stream));
             st = reverse_fused(h, n, 0, 1, 1, h->gacc, &F);
             if (st != FDTD_OK) return st;
         }

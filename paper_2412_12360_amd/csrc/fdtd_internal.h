@@ -142,6 +142,10 @@ hipError_t launch_det_eprev(const Grid &g, const Fields &F, const Detectors &D, 
 hipError_t launch_det_raw(const Grid &g, const Fields &F, const Detectors &D, float *raw, hipStream_t s);
 hipError_t launch_det_interp(const Detectors &D, const float *raw, const float *eprev, int levels, float *planes,
                              hipStream_t s);
+// their adjoint source before reverse step n (drec: raw planes of every step,
+// e0: E planes of step 0; wS[m] = S * weight, zero weights skipped)
+hipError_t launch_det_interp_adjoint(const Grid &g, const Detectors &D, const float *drec, const float *e0, int n,
+                                    int T, const float *wS, const Fields &A, hipStream_t s);
 
 hipError_t launch_record(const Grid &g, const Fields &F, const RecGeom &R, float *rec_step,
                          int side, int restore, hipStream_t s);

@@ -138,6 +138,63 @@ __global__ __launch_bounds__(NT) void k_det_interp(Detectors D, int m, int s, co
     planes[s * D.per_step + D.off[m] + e] = flux_density(ex, ey, hx, hy);
 }
 
+// Adjoint source of interpolated detector m before reverse step n, for
+// J = S sum_n w P[n] with P[n] the co-located sum: E^{n+1} enters P[n] (as the
+// later of its two steps) and P[n+1] (as the earlier), H^{n+1/2} enters P[n].
+// Each co-located value is a quarter of four nodes, so a node receives a
+// quarter of the partner value of every cell it enters.  drec holds the six
+// raw planes of every step, e0 the E planes of step 0.  One thread per node of
+// the extended window gathers its (at most two) cells: no two threads write
+// one address, and the order of the sums is fixed.
+struct CoVals {
+    float exc, eyc, hxc, hyc, hxc1, hyc1;
+};
+__device__ __forceinline__ CoVals co_vals(const float *Ep, const float *R, const float *R1, long long L, int wx, int ci,
+                                          int cj)
+{
+    const long long p00 = (long long)cj * wx + ci, p10 = p00 + 1, p01 = p00 + wx;
+    CoVals v;
+    v.exc = 0.25f * ((Ep[p00] + Ep[p01]) + (R[p00] + R[p01]));
+    v.eyc = 0.25f * ((Ep[L + p00] + Ep[L + p10]) + (R[L + p00] + R[L + p10]));
+    v.hxc = 0.25f * ((R[2 * L + p00] + R[2 * L + p10]) + (R[4 * L + p00] + R[4 * L + p10]));
+    v.hyc = 0.25f * ((R[3 * L + p00] + R[3 * L + p01]) + (R[5 * L + p00] + R[5 * L + p01]));
+    v.hxc1 = R1 ? 0.25f * ((R1[2 * L + p00] + R1[2 * L + p10]) + (R1[4 * L + p00] + R1[4 * L + p10])) : 0.f;
+    v.hyc1 = R1 ? 0.25f * ((R1[3 * L + p00] + R1[3 * L + p01]) + (R1[5 * L + p00] + R1[5 * L + p01])) : 0.f;
+    return v;
+}
+
+__global__ __launch_bounds__(NT) void k_det_interp_adjoint(Grid g, Detectors D, int m, const float *drec,
+                                                           const float *e0, int n, int T, float sw, Fields A)
+{
+    const int w = D.i1[m] - D.i0[m], h = D.j1[m] - D.j0[m], wx = w + 1;
+    const long long L = (long long)wx * (h + 1);
+    const long long t = (long long)blockIdx.x * NT + threadIdx.x;
+    if (t >= L) return;
+    const int jj = (int)(t / wx), ii = (int)(t - (long long)jj * wx);
+    const float *R = drec + (long long)n * D.raw_per_step + D.roff[m];
+    const float *Ep = n == 0 ? e0 + D.eoff[m] : drec + (long long)(n - 1) * D.raw_per_step + D.roff[m];
+    const float *R1 = n + 1 < T ? drec + (long long)(n + 1) * D.raw_per_step + D.roff[m] : nullptr;
+    const bool in00 = ii < w && jj < h, in0m = ii < w && jj >= 1, inm0 = ii >= 1 && jj < h;
+    CoVals c00{}, c0m{}, cm0{};
+    if (in00) c00 = co_vals(Ep, R, R1, L, wx, ii, jj);
+    if (in0m) c0m = co_vals(Ep, R, R1, L, wx, ii, jj - 1);
+    if (inm0) cm0 = co_vals(Ep, R, R1, L, wx, ii - 1, jj);
+    // Ex node (cells (i,j), (i,j-1)), Ey node (cells (i,j), (i-1,j)), Hy nodes
+    // of both layers (cells (i,j), (i,j-1)), Hx nodes (cells (i,j), (i-1,j))
+    const float gx = (c00.hyc + c00.hyc1) + (c0m.hyc + c0m.hyc1);
+    const float gy = (c00.hxc + c00.hxc1) + (cm0.hxc + cm0.hxc1);
+    const float ghy = c00.exc + c0m.exc;
+    const float ghx = c00.eyc + cm0.eyc;
+    const float q = 0.25f * sw;
+    const long long c = cidx(g, D.i0[m] + ii, D.j0[m] + jj, D.k[m]), cm = c - g.nxy;
+    A.c[0][c] = fmaf(q, gx, A.c[0][c]);
+    A.c[1][c] = fmaf(-q, gy, A.c[1][c]);
+    A.c[4][cm] = fmaf(q, ghy, A.c[4][cm]);
+    A.c[4][c] = fmaf(q, ghy, A.c[4][c]);
+    A.c[3][cm] = fmaf(-q, ghx, A.c[3][cm]);
+    A.c[3][c] = fmaf(-q, ghx, A.c[3][c]);
+}
+
 // dJ/dE^{n+1} and dJ/dH^{n+1/2} of J += S w sum (Ex Hy - Ey Hx)
 __global__ __launch_bounds__(NT) void k_det_adjoint(Grid g, Fields F, Fields A, Detectors D, int m, float sw)
 {
@@ -433,6 +490,19 @@ hipError_t launch_det_interp(const Detectors &D, const float *raw, const float *
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_det_interp_adjoint(const Grid &g, const Detectors &D, const float *drec, const float *e0, int n,
+                                    int T, const float *wS, const Fields &A, hipStream_t s)
+{
+    for (int m = 0; m < D.ndet; m++) {
+        if (!D.interp[m] || wS[m] == 0.f) continue;
+        const long long L = (long long)(D.i1[m] - D.i0[m] + 1) * (D.j1[m] - D.j0[m] + 1);
+        hipLaunchKernelGGL(k_det_interp_adjoint, dim3(nblk(L)), dim3(NT), 0, s, g, D, m, drec, e0, n, T, wS[m], A);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }

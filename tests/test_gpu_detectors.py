@@ -5,8 +5,10 @@ time; the paper evaluates finished designs this way), through the C ABI:
     and a plain detector on the same plane and an interpolated one elsewhere,
     on ragged multi-tile grids;
   - the z-march at every time-block size gives the per-cell path's bits;
-  - interpolated detectors are forward only: with weight 0 the gradient is
-    bitwise the one without them, with a nonzero weight it is refused.
+  - with an interpolated detector in the objective: the time-reversal
+    gradient against the oracle's, the fused reverse against the per-cell
+    reverse bit for bit, the checkpointed gradient against the time-reversal
+    one; with weight 0 the gradient is bitwise the one without it.
 Tolerance as in the other parity tests: rel-L2 <= 1e-4.
 """
 import dataclasses
@@ -82,10 +84,67 @@ def test_interpolated_detector_bitwise_all_K(shape, p, T, monkeypatch):
         assert torch.equal(J, outs[0][1])
 
 
-def test_interpolated_detector_is_forward_only():
-    from paper_2412_12360_amd.fdtd import FdtdError, FDTD_E_UNSUPPORTED
+def grad_problem(shape=(40, 36, 44), p=6, T=160, seed=12):
+    """Objective: the plain flux (weight 0.3) and the interpolated flux
+    (weight 1) of one window."""
+    pr = W.small_cpml(nx=shape[0], ny=shape[1], nz=shape[2], p=p, T=T, d=8, seed=seed)
+    d = pr.detectors[0]
+    return dataclasses.replace(pr, detectors=[dataclasses.replace(d, weight=0.3),
+                                              dataclasses.replace(d, weight=1.0, interpolate=True)])
+
+
+def test_interpolated_objective_gradient_parity():
+    pr = grad_problem()
+    announce("interpolated objective gradient 40x36x44 p=6 T=160")
+    o = Oracle(pr)
+    g, J, _ = o.grad_history()
+    ref = o.deps_design(g)
+    s = _solver(pr, record=True)
+    _, Jg = s.forward()
+    dg, recon = s.grad()
+    torch.cuda.synchronize()
+    assert abs(float(Jg.item()) - J) <= FIELD_TOL * abs(J)
+    assert rel_l2(dg.cpu().numpy(), ref) <= 1e-3
+    assert float(recon.item()) < 1e-3
+    # the interpolated detector's adjoint source matters
+    g0, _, _ = Oracle(dataclasses.replace(pr, detectors=pr.detectors[:1])).grad_history()
+    assert rel_l2(o.deps_design(g0), ref) > 0.1
+
+
+@pytest.mark.parametrize("shape,p,T", [((70, 45, 38), 5, 40), ((16, 16, 16), 3, 60)])
+def test_interpolated_objective_fused_reverse_bitwise(shape, p, T, monkeypatch):
+    pr = grad_problem(shape, p, T, seed=31)
+    outs = []
+    for naive in (True, False):
+        announce(f"interpolated objective reverse bitwise {shape} naive={naive}")
+        monkeypatch.setenv("FDTD_NAIVE", "1" if naive else "0")
+        s = _solver(pr, record=True)
+        _, J = s.forward()
+        g, r = s.grad()
+        torch.cuda.synchronize()
+        outs.append((J.clone(), g.clone(), r.clone()))
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
+
+
+def test_interpolated_objective_checkpointed_matches_reversal():
+    pr = grad_problem((40, 36, 44), 6, 160, seed=21)
+    announce("interpolated objective checkpointed 40x36x44")
+    s = _solver(pr, record=True)
+    _, J = s.forward()
+    g, _ = s.grad()
+    torch.cuda.synchronize()
+    J, g = J.clone(), g.clone()
+    for seg in (7, 160):
+        gc, Jc = s.grad_checkpointed(seg)
+        torch.cuda.synchronize()
+        assert torch.equal(Jc, J)
+        assert rel_l2(gc.cpu().numpy(), g.cpu().numpy().astype(np.float64)) <= 1e-4
+
+
+def test_zero_weight_interpolated_detector_leaves_gradient():
     base = W.small_cpml(nx=40, ny=36, nz=44, p=6, T=120, d=8, seed=12)
-    announce("interpolated detector in a gradient")
+    announce("zero-weight interpolated detector in a gradient")
     grads = []
     for pr in (base, with_interp(base, w_interp=0.0)):
         s = _solver(pr, record=True)
@@ -95,8 +154,3 @@ def test_interpolated_detector_is_forward_only():
         grads.append((J.clone(), g.clone()))
     assert torch.equal(grads[0][0], grads[1][0])
     assert torch.equal(grads[0][1], grads[1][1])
-    s = _solver(with_interp(base, w_interp=1.0), record=True)
-    s.forward()
-    with pytest.raises(FdtdError) as ei:
-        s.grad()
-    assert ei.value.status == FDTD_E_UNSUPPORTED
