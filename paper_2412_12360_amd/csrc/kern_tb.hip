@@ -139,7 +139,7 @@ __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
     float4 gyE[YP ? R : 1], gyH[YP ? R : 1];
 #pragma unroll
     for (int r = 0; r < R; r++) {
-        row[r] = wv * R + r;
+        row[r] = active ? wv * R + r : EY;   // idle threads share the spare row
         ys[r] = y0 - K + row[r];
         incol[r] = inx && ys[r] >= 0 && ys[r] < ny;
         own[r] = x >= x0 && x < x1 && ys[r] >= y0 && ys[r] < y1;
@@ -597,8 +597,12 @@ hipError_t launch_kwrp(const TbArgs &a, int cls, hipStream_t s)
 //      of each row is one whole 128-byte line, line aligned, so no two
 //      workgroups write parts of the same line
 //   3: as 2 with 8 waves (two workgroups per CU)
+// (two rows per thread with 8 waves, 24 owned rows at K = 2, needs about 170
+// to 220 registers, so 2-3 waves per SIMD and one workgroup per CU: measured
+// 2.8 times slower than shape 3, not kept)
 constexpr int NSHAPE = 4;
 constexpr int SHAPE_W[NSHAPE] = {16, 8, 16, 8};
+constexpr int SHAPE_R[NSHAPE] = {1, 1, 1, 1};
 constexpr int ALIGN_X = 32;   // floats per 128-byte line
 __host__ __device__ constexpr int shape_tx(int sh, int K) { return sh == 0 ? 64 : sh == 1 ? 32 : ALIGN_X + 2 * K; }
 
@@ -622,7 +626,7 @@ int tb_max_pml() { return TB_MAXP; }
 int tb_tile_y(int K, int shape)
 {
     const int sh = shape_index(shape);
-    return 64 * SHAPE_W[sh] / shape_tx(sh, K) - 2 * K;
+    return (64 * SHAPE_W[sh] / shape_tx(sh, K)) * SHAPE_R[sh] - 2 * K;
 }
 bool tb_tile_aligned(int shape) { return shape_index(shape) >= 2; }
 
