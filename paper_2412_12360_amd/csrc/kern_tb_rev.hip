@@ -128,7 +128,9 @@ __global__ __launch_bounds__(NT, 4) void k_tb_reverse(RevArgs A)
     }
     const unsigned fs = A.fstride;   // bytes between the components of a field or adjoint set
     const bool in_design_xy = x >= A.dlo.x && x < A.dhi.x && y >= A.dlo.y && y < A.dhi.y;
-    const int ddx = A.dhi.x - A.dlo.x, ddy = A.dhi.y - A.dlo.y;
+    // dJ/dd index of this column within a design plane, and the plane size
+    const int dxy = in_design_xy ? (y - A.dlo.y) * (A.dhi.x - A.dlo.x) + (x - A.dlo.x) : 0;
+    const int dplane = (A.dhi.x - A.dlo.x) * (A.dhi.y - A.dlo.y);
 
     // ---------------------------------------------------------- plane fetch
     // load_raw issues the loads of plane t; finish (one iteration later, so
@@ -361,12 +363,12 @@ __global__ __launch_bounds__(NT, 4) void k_tb_reverse(RevArgs A)
             // where the forward state comes from storage instead of the inverse)
             if (interior && A.do_adj && A.gacc && own && a >= z0 && a < z1 && in_design_xy && a >= A.dlo.z &&
                 a < A.dhi.z) {
-                const long long dc = ((long long)(a - A.dlo.z) * ddy + (y - A.dlo.y)) * ddx + (x - A.dlo.x);
-                float acc = gld(A.gacc + dc);
+                const long long dc = (long long)(a - A.dlo.z) * dplane + dxy;
+                float acc = gld(Kp->gacc + dc);
                 if (!hex) acc = fmaf(Pa.ae[0], dy_hz - dz_hy, acc);
                 if (!hey) acc = fmaf(Pa.ae[1], dz_hx - dx_hz, acc);
                 if (!hez) acc = fmaf(Pa.ae[2], dx_hy - dy_hx, acc);
-                *(GLOBAL float *)(A.gacc + dc) = acc;
+                *(GLOBAL float *)(Kp->gacc + dc) = acc;
             }
             if (A.do_inv && interior) {
                 float ex = Pa.e[0], ey = Pa.e[1], ez = Pa.e[2];
