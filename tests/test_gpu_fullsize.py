@@ -6,9 +6,10 @@
   - 200^3 and 640x640x400: the adjoint (fused reverse kernel) is the exact
     transpose of the forward step map, <M x, y> = <x, M^T y>, on random states
     including every CPML auxiliary array;
-  - 200^3, 1500 steps: the time-reversal gradient against central differences
-    of the GPU objective along the gradient direction and along its restriction
-    to the lower half of the design box.
+  - 200^3 (1500 steps) and 640x640x400 (4000 steps): the time-reversal
+    gradient against central differences of the GPU objective along the
+    gradient direction and along its restriction to the lower half of the
+    design box.
 """
 import numpy as np
 import pytest
@@ -95,8 +96,10 @@ def test_adjoint_transpose_full_size(which):
     assert abs(lhs - rhs) <= 2e-6 * scale
 
 
-def test_directional_fd_full_size_c3():
-    """200^3, CPML 10, 1500 steps: the time-reversal gradient against a
+@pytest.mark.parametrize("which", ["c3", "c4"])
+def test_directional_fd_full_size(which):
+    """c3 (200^3, CPML 10, 1500 steps) and c4 (640x640x400, CPML 12, 4000
+    steps, 54 GB of interface record): the time-reversal gradient against a
     central difference of the GPU objective in eps_r along the gradient's
     own direction (by Cauchy-Schwarz the two agree only if the computed
     gradient is parallel to the true one and of the right length) and along
@@ -105,8 +108,8 @@ def test_directional_fd_full_size_c3():
     chosen so that J changes by about 1e-3 of itself, in the linear regime."""
     from paper_2412_12360_amd.fdtd import Solver
     from paper_2412_12360_amd.autograd import objective
-    pr = W.config3()
-    announce("full-size directional finite difference c3")
+    pr = W.config3() if which == "c3" else W.config4()
+    announce(f"full-size directional finite difference {which}")
     s = Solver(pr, record=True)
     eps = torch.tensor(W.eps_from_rho(pr.rho), dtype=torch.float32, device=s.device).requires_grad_(True)
     J = objective(eps, s)
@@ -123,6 +126,6 @@ def test_directional_fd_full_size_c3():
             Jp = float(objective((eps.double() + h * v).float(), s).item())
             Jm = float(objective((eps.double() - h * v).float(), s).item())
         fd = (Jp - Jm) / (2 * h)
-        print(f"[gpu-case] {name}: J {J0:.6e} h {h:.3e} adjoint {dJ:.6e} fd {fd:.6e}", flush=True)
+        print(f"[gpu-case] {which} {name}: J {J0:.6e} h {h:.3e} adjoint {dJ:.6e} fd {fd:.6e}", flush=True)
         assert abs(Jp - Jm) > 1e-5 * abs(J0)          # resolvable in float32 (about 90 ulps of J)
         assert abs(fd - dJ) <= 2e-2 * abs(dJ)
