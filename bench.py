@@ -43,7 +43,7 @@ PEAK_GBS = 8000.0
 # per sweep (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy kernel's
 # counters) and the hashes of the sources it was taken on
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "fdtd_forward_zmarch_256cube_hbm_traffic.md")
-TRAFFIC_SOURCES = ("paper_2412_12360_amd/csrc/kern_tb.hip",)
+TRAFFIC_SOURCES = ("paper_2412_12360_amd/csrc/kern_tb.hip", "paper_2412_12360_amd/csrc/fdtd_api.hip")
 
 
 def source_hash() -> str:

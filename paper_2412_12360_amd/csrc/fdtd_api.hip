@@ -307,17 +307,36 @@ std::vector<std::pair<int, int>> split_uniform(int n, int w)
 
 // z extent of one workgroup's march: enough workgroups to fill the chip
 // (about 1024) without letting the 2K-plane z halo dominate.
-int zchunk(const Geometry &G, int K)
+int zchunk(const Geometry &G, int K, bool reverse)
 {
-    if (const char *e = getenv("FDTD_TB_ZC")) {
-        const int v = atoi(e);
-        if (v > 0) return std::min(v, G.nz);
+    const char *e = getenv(reverse ? "FDTD_REV_ZC" : "FDTD_TB_ZC");
+    if (e && atoi(e) > 0) return std::min(atoi(e), G.nz);
+    if (reverse) {
+        // the reverse march does about twice the work per plane: 32 or 24
+        // planes only with at least eight workgroups per slot (measured: 32
+        // best on 640x640x400, 16 on 200^3)
+        const long long tx = (long long)split_uniform(G.nx, rev_tile_x()).size();
+        const long long ty = (long long)split_axis(G.ny, rev_tile_y()).size();
+        for (int zc : {32, 24}) {
+            const long long nwg = tx * ty * ((G.nz + zc - 1) / zc);
+            if (nwg >= 8 * 2LL * 256) return std::min(zc, G.nz);
+        }
+        return std::min(16, G.nz);
     }
-    const long long tx = (long long)split_axis(G.nx, tb_tile_x(K, tb_shape())).size();
-    const long long ty = (long long)split_axis(G.ny, tb_tile_y(K, tb_shape())).size();
-    // short marches: the work per workgroup is serial, so many short
-    // marches balance better than few long ones (16 planes measured best)
-    (void)tx; (void)ty;
+    // A longer march fetches its 2K-plane z halo less often, but leaves fewer
+    // workgroups to balance over the chip (the work of one is serial).  Take
+    // the longest of 16..64 planes that still gives at least four workgroups
+    // per slot (two per CU): measured best on 200^3 (16-20 planes), 256^3 (24)
+    // and 640x640x400 (32 and up).
+    const int shape = tb_shape();
+    const long long tx = (long long)(tb_tile_aligned(shape) ? split_uniform(G.nx, tb_tile_x(K, shape))
+                                                             : split_axis(G.nx, tb_tile_x(K, shape))).size();
+    const long long ty = (long long)split_axis(G.ny, tb_tile_y(K, shape)).size();
+    const long long slots = 2LL * 256;
+    for (int zc : {64, 48, 32, 24, 20}) {
+        const long long nwg = tx * ty * ((G.nz + zc - 1) / zc);
+        if (nwg >= 4 * slots) return std::min(zc, G.nz);
+    }
     return std::min(16, G.nz);
 }
 
@@ -332,7 +351,7 @@ void build_tiles(const Geometry &G, int K, std::vector<int4> &out, int off[5][4]
     // slot 0: the reverse march (halo rev_halo()); slots 1..K: forward, halo kk
     for (int kk = 0; kk <= K; kk++) {
         const int halo = kk == 0 ? rev_halo() : kk;
-        const int ZC = zchunk(G, halo);
+        const int ZC = zchunk(G, halo, kk == 0);
         const int tx = kk == 0 ? rev_tile_x() : tb_tile_x(kk, tb_shape());
         const int ty = kk == 0 ? rev_tile_y() : tb_tile_y(kk, tb_shape());
         // line-aligned shapes (and the reverse march) cut x into whole lines
