@@ -28,7 +28,9 @@
  *     detectors without interpolation).
  *   - the interpolated flux of section 2.1: Ex, Ey, Hx, Hy each averaged onto
  *     the point (i+1/2, j+1/2, k) of the detector plane at time n+1/2 (E of
- *     steps n and n+1; H^{n+1/2} of layers k-1 and k), and its adjoint source.
+ *     steps n and n+1; H^{n+1/2} of layers k-1 and k), and its adjoint source;
+ *     the co-located energy density 1/2 (eps_r |E|^2 + |H|^2) at the same point
+ *     and time (forward only).
  *   - the interface record (section 2.2): every step, tangential H^{n+1/2} on
  *     the PML-side layer p-1 of the three low faces and tangential E^{n+1} on
  *     layer n_a-p of the three high faces, over the interior window.
@@ -69,6 +71,7 @@ typedef struct {
     int det_i0[OR_MAXDET], det_i1[OR_MAXDET], det_j0[OR_MAXDET], det_j1[OR_MAXDET];
     double det_w[OR_MAXDET];
     int det_interp[OR_MAXDET];      /* 1: co-located (interpolated) flux */
+    int det_energy[OR_MAXDET];      /* 1: co-located energy density instead of flux (forward only) */
     int dlo[3], dhi[3];             /* half-open design box */
 } or_problem;
 
@@ -297,6 +300,42 @@ static double det_flux_interp(const or_problem *P, const double *st, const doubl
     return s;
 }
 
+/* Co-located energy of detector m: 1/2 (eps_r |E|^2 + |H|^2) at the point
+ * (i+1/2, j+1/2, k) and time n+1/2, summed over the window, eps_r of cell
+ * (i,j,k).  Ex, Ey, Hx, Hy as for the interpolated flux; Ez(i, j, k+-1/2) is
+ * averaged over i, i+1, j, j+1, the layers k-1, k and the steps n, n+1;
+ * Hz(i+1/2, j+1/2, k) is already at the point.  eprev holds Ex^n, Ey^n, Ez^n
+ * of plane k and Ez^n of layer k-1, [ny][nx] each. */
+static double det_energy_interp(const or_problem *P, const double *st, const double *eprev, int m)
+{
+    size_t N = ncell(P), A = (size_t)P->nx * P->ny;
+    const double *Ex = st, *Ey = st + N, *Ez = st + 2 * N, *Hx = st + 3 * N, *Hy = st + 4 * N, *Hz = st + 5 * N;
+    const double *Px = eprev, *Py = eprev + A, *Pz = eprev + 2 * A, *Pzm = eprev + 3 * A;
+    int k = P->det_k[m];
+    double s = 0.0;
+    for (int j = P->det_j0[m]; j < P->det_j1[m]; j++)
+        for (int i = P->det_i0[m]; i < P->det_i1[m]; i++) {
+            size_t p00 = (size_t)j * P->nx + i, p01 = p00 + P->nx, p10 = p00 + 1, p11 = p01 + 1;
+            double ex = 0.25 * (Px[p00] + Px[p01] + Ex[idx(P, i, j, k)] + Ex[idx(P, i, j + 1, k)]);
+            double ey = 0.25 * (Py[p00] + Py[p10] + Ey[idx(P, i, j, k)] + Ey[idx(P, i + 1, j, k)]);
+            double ez = 0.0;
+            for (int kk = k - 1; kk <= k; kk++)
+                ez += Ez[idx(P, i, j, kk)] + Ez[idx(P, i + 1, j, kk)] + Ez[idx(P, i, j + 1, kk)] +
+                      Ez[idx(P, i + 1, j + 1, kk)];
+            const double *Q = Pz, *Qm = Pzm;
+            ez += Q[p00] + Q[p10] + Q[p01] + Q[p11] + Qm[p00] + Qm[p10] + Qm[p01] + Qm[p11];
+            ez /= 16.0;
+            double hx = 0.25 * (Hx[idx(P, i, j, k - 1)] + Hx[idx(P, i + 1, j, k - 1)] +
+                                Hx[idx(P, i, j, k)] + Hx[idx(P, i + 1, j, k)]);
+            double hy = 0.25 * (Hy[idx(P, i, j, k - 1)] + Hy[idx(P, i, j + 1, k - 1)] +
+                                Hy[idx(P, i, j, k)] + Hy[idx(P, i, j + 1, k)]);
+            double hz = Hz[idx(P, i, j, k)];
+            double eps = 1.0 / P->d[idx(P, i, j, k)];
+            s += 0.5 * (eps * (ex * ex + ey * ey + ez * ez) + hx * hx + hy * hy + hz * hz);
+        }
+    return s;
+}
+
 /* ------------------------------------------------------- interface record
  * Face f = 2a + side.  side 0 (low): tangential H at layer p-1; side 1 (high):
  * tangential E at layer n_a - p.  Components (a+1)%3 then (a+2)%3.  Window over
@@ -354,10 +393,13 @@ static void step_fwd(const or_problem *P, double *st, int n, const or_prof *PE, 
     if (trow)
         for (int m = 0; m < P->ndet; m++)
             if (P->det_interp[m]) {
-                if (!eprev) eprev = malloc(sizeof(double) * 2 * A * OR_MAXDET);
-                for (int q = 0; q < 2; q++)
-                    memcpy(eprev + (2 * (size_t)m + q) * A, slot(st, P, q) + (size_t)P->det_k[m] * A,
+                if (!eprev) eprev = malloc(sizeof(double) * 4 * A * OR_MAXDET);
+                /* Ex, Ey, Ez of plane k and Ez of layer k-1 */
+                for (int q = 0; q < 3; q++)
+                    memcpy(eprev + (4 * (size_t)m + q) * A, slot(st, P, q) + (size_t)P->det_k[m] * A,
                            sizeof(double) * A);
+                memcpy(eprev + (4 * (size_t)m + 3) * A, slot(st, P, 2) + (size_t)(P->det_k[m] - 1) * A,
+                       sizeof(double) * A);
             }
     h_sweep(P, st, PH);
     if (with_src) add_sources(P, st, n, 1.0, 1);
@@ -367,7 +409,9 @@ static void step_fwd(const or_problem *P, double *st, int n, const or_prof *PE, 
     if (rec) record_io(P, st, rec, 1, 0);
     if (trow)
         for (int m = 0; m < P->ndet; m++)
-            trow[m] = P->det_interp[m] ? det_flux_interp(P, st, eprev + 2 * (size_t)m * A, m) : det_flux(P, st, m);
+            trow[m] = !P->det_interp[m] ? det_flux(P, st, m)
+                      : P->det_energy[m] ? det_energy_interp(P, st, eprev + 4 * (size_t)m * A, m)
+                                         : det_flux_interp(P, st, eprev + 4 * (size_t)m * A, m);
     free(eprev);
 }
 
@@ -409,7 +453,7 @@ static void det_interp_adjoint(const or_problem *P, double *adj, const double *s
 {
     size_t N = ncell(P), A = (size_t)P->nx * P->ny;
     for (int m = 0; m < P->ndet; m++) {
-        if (!P->det_interp[m]) continue;
+        if (!P->det_interp[m] || P->det_energy[m]) continue;   /* energy: forward only */
         double sw = P->S * P->det_w[m];
         if (sw == 0.0) continue;
         int k = P->det_k[m];

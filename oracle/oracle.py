@@ -49,6 +49,7 @@ class _Problem(C.Structure):
         ("det_j0", C.c_int * MAXDET), ("det_j1", C.c_int * MAXDET),
         ("det_w", C.c_double * MAXDET),
         ("det_interp", C.c_int * MAXDET),
+        ("det_energy", C.c_int * MAXDET),
         ("dlo", C.c_int * 3), ("dhi", C.c_int * 3),
     ]
 
@@ -173,6 +174,8 @@ class Oracle:
             s.det_i0[i], s.det_i1[i], s.det_j0[i], s.det_j1[i] = det.i0, det.i1, det.j0, det.j1
             s.det_w[i] = float(det.weight)
             s.det_interp[i] = int(getattr(det, "interpolate", False))
+            s.det_energy[i] = int(getattr(det, "quantity", 0) == 1)
+            assert not s.det_energy[i] or s.det_interp[i], "the energy detector is co-located (interpolate)"
             if s.det_interp[i]:
                 # the co-located flux reads layer k-1 and the cells at i1, j1
                 assert det.k >= 1 and det.i1 < prob.nx and det.j1 < prob.ny
@@ -225,8 +228,14 @@ class Oracle:
         self.L.or_adjoint_linear(C.byref(self.s), _ptr(adj), T)
 
     # ----------------------------------------------------------- gradients
+    def _check_grad(self):
+        for det in self.prob.detectors:
+            assert not (getattr(det, "quantity", 0) == 1 and det.weight != 0.0), \
+                "energy detectors are forward only: weight 0 in a gradient"
+
     def grad_history(self, T: int | None = None, seg: int | None = None):
         """dJ/dd over the grid by the stored-history VJP; returns (g, J, trace)."""
+        self._check_grad()
         T = self.prob.T if T is None else T
         self._check_T(0, T)
         seg = seg or max(1, int(np.ceil(np.sqrt(T))))
@@ -238,6 +247,7 @@ class Oracle:
 
     def grad_reversed(self, T: int | None = None):
         """dJ/dd by time reversal; returns (g, J, trace, recon)."""
+        self._check_grad()
         T = self.prob.T if T is None else T
         self._check_T(0, T)
         g = np.zeros(self.prob.shape, np.float64)

@@ -58,7 +58,8 @@ class Detector:
     j0: int
     j1: int
     weight: float = 1.0
-    interpolate: bool = False   # co-located (interpolated) flux, forward only
+    interpolate: bool = False   # components co-located at (i+1/2, j+1/2, k), time n+1/2
+    quantity: int = 0           # 0 = Poynting flux, 1 = energy density (co-located, forward only)
 
 
 @dataclasses.dataclass

@@ -659,3 +659,60 @@ def test_interpolated_objective_gradient_matches_central_differences():
         fd[idx] = (vals[0] - vals[1]) / (2 * h)
     assert np.max(np.abs(adj)) > 0
     assert np.linalg.norm(fd - adj) <= 1e-6 * np.linalg.norm(adj)
+
+
+OFFSETS.update({2: (0.0, 0.0, 0.5), 5: (0.5, 0.5, 0.0)})   # Ez, Hz
+
+
+def test_colocated_energy_is_the_trilinear_interpolation():
+    """The co-located energy 1/2 (eps_r |E|^2 + |H|^2) at (i+1/2, j+1/2, k),
+    time n+1/2 (eps_r of cell (i,j,k)), against the generic trilinear
+    interpolation of all six staggered components, on random CPML states with
+    per-cell eps_r, stepped with a source."""
+    pr = W.small_cpml(nx=14, ny=13, nz=12, p=3, T=5, d=6, seed=43)
+    k = 6
+    pr = dataclasses.replace(pr, detectors=[
+        W.Detector(k=k, i0=3, i1=12, j0=2, j1=11, weight=0.0, interpolate=True, quantity=1)])
+    o = Oracle(pr)
+    eps = 1.0 / o.d
+    st = random_state(pr, 44, with_psi=True)
+    for n in range(pr.T):
+        before = st.copy()
+        _, trace, _ = o.forward(st, 1, n0=n)
+        want = 0.0
+        for j in range(2, 11):
+            for i in range(3, 12):
+                x, y = i + 0.5, j + 0.5
+                e2 = sum((0.5 * (trilinear(before[q], OFFSETS[q], x, y, k) +
+                                 trilinear(st[q], OFFSETS[q], x, y, k))) ** 2 for q in (0, 1, 2))
+                h2 = sum(trilinear(st[q], OFFSETS[q], x, y, k) ** 2 for q in (3, 4, 5))
+                want += 0.5 * (eps[k, j, i] * e2 + h2)
+        assert abs(trace[0, 0] - want) <= 1e-12 * want
+
+
+def test_colocated_energy_of_a_plane_wave():
+    """Steady plane wave (as above): E amplitude 1 and H amplitude sqrt(eps_r)
+    (from the discrete update and dispersion), so the co-located energy is
+    1/2 eps (cos^2(w/2) + cos^2(kk/2)) sin^2(w(n+1/2) - phase) per cell: mean
+    equal to its oscillation, both a quarter of eps (cos^2(w/2) + cos^2(kk/2))."""
+    S = W.courant()
+    T, k0, lam = 80, 6, 8.0
+    n, nz = 2 * T + 10, k0 + T + 6
+    d = 1.0 / 2.25
+    inv = np.full((nz, n, n), d, np.float32)
+    src = W.Source(kind=2, comp=0, i=0, j=0, k=k0, amp=W.ramped_sine(T, S, lambda0=lam, periods=2))
+    c0, c1 = T + 3, n - T - 4
+    dets = [W.Detector(k=k0 + 3, i0=c0, i1=c1, j0=c0, j1=c1, interpolate=True, quantity=1, weight=0.0)]
+    pr = pec_problem(n, n, nz, d=inv, sources=[src], detectors=dets, T=T)
+    o = Oracle(pr)
+    _, _, trace, _ = o.run()
+    cells = (c1 - c0) ** 2
+    w = 2 * math.pi * S / lam
+    kk = 2 * math.asin(math.sin(w / 2) / (S * math.sqrt(d)))
+    eps = 1.0 / float(o.d[k0 + 3, n // 2, n // 2])
+    mean = 0.25 * eps * (math.cos(w / 2) ** 2 + math.cos(kk / 2) ** 2)
+    steady = np.arange(45, T)
+    X = np.stack([np.ones(len(steady)), np.cos(2 * w * steady), np.sin(2 * w * steady)], 1)
+    a, b, c = np.linalg.lstsq(X, trace[steady, 0] / cells, rcond=None)[0]
+    assert abs(a - mean) <= 2e-3 * mean
+    assert abs(math.hypot(b, c) - a) <= 2e-3 * a
