@@ -113,10 +113,17 @@ typedef struct {
  *     six planes such a detector reads (E^{n+1} of plane k, H^{n+1/2} of
  *     layers k-1 and k; 24 B per cell of the window extended by one cell in
  *     x and y, per step) so that the gradients can apply its adjoint source. */
+/* quantity = 1 (with interpolate = 1): instead of the flux, the co-located
+ * energy density sum of 1/2 (eps_r |E|^2 + |H|^2) at the same points and
+ * time, eps_r of cell (i,j,k): Ez averaged over i, i+1, j, j+1, the layers
+ * k-1, k and the two steps; Hz lies at the point already.  Forward only:
+ * fdtd_grad and fdtd_grad_checkpointed return FDTD_E_UNSUPPORTED when an
+ * energy detector has a nonzero weight. */
 typedef struct {
     int32_t k, i0, i1, j0, j1;
     float weight;
     int32_t interpolate;
+    int32_t quantity;            /* 0 = Poynting flux, 1 = energy density */
 } fdtd_flux_detector;
 
 #define FDTD_MAX_SOURCES 4

@@ -209,6 +209,10 @@ fdtd_status validate(fdtd_ctx *h, const fdtd_desc *d, const fdtd_source *src, in
         if (!std::isfinite(q.weight)) return fail(h, FDTD_E_INVALID, "detector %d: weight not finite", m);
         if (q.interpolate != 0 && q.interpolate != 1)
             return fail(h, FDTD_E_INVALID, "detector %d: interpolate must be 0 or 1", m);
+        if (q.quantity != 0 && q.quantity != 1)
+            return fail(h, FDTD_E_INVALID, "detector %d: quantity must be 0 (flux) or 1 (energy)", m);
+        if (q.quantity == 1 && !q.interpolate)
+            return fail(h, FDTD_E_INVALID, "detector %d: the energy detector needs interpolate = 1", m);
         // the co-located flux reads layer k-1 and the cells at i1, j1
         if (q.interpolate && (q.k < 1 || q.i1 > d->nx - 1 || q.j1 > d->ny - 1))
             return fail(h, FDTD_E_INVALID, "detector %d: interpolation needs k >= 1, i1 < nx, j1 < ny", m);
@@ -247,15 +251,17 @@ void geometry(const fdtd_desc *d, const fdtd_flux_detector *det, int ndet, Geome
             G.D.off[m] = doff;
             doff += (long long)(det[m].i1 - det[m].i0) * (det[m].j1 - det[m].j0);
             G.D.interp[m] = det[m].interpolate ? 1 : 0;
+            G.D.energy[m] = det[m].quantity == 1 ? 1 : 0;
             if (G.D.interp[m]) {
                 const long long L = (long long)(det[m].i1 - det[m].i0 + 1) * (det[m].j1 - det[m].j0 + 1);
-                roff += 6 * L;
-                eoff += 2 * L;
+                roff += (G.D.energy[m] ? 9 : 6) * L;
+                eoff += (G.D.energy[m] ? 4 : 2) * L;
             }
         } else {
             G.D.k[m] = G.D.i0[m] = G.D.i1[m] = G.D.j0[m] = G.D.j1[m] = 0;
             G.D.off[m] = doff;
             G.D.interp[m] = 0;
+            G.D.energy[m] = 0;
         }
     }
     G.D.per_step = doff;
@@ -541,7 +547,7 @@ fdtd_status step_naive(fdtd_ctx *h, int n, int with_src, int with_rec, int with_
         HIPCHK(h, launch_det_planes(h->g, F, G.D, h->planes, h->stream));
         if (interp) {
             HIPCHK(h, launch_det_raw(h->g, F, G.D, rawt, h->stream));
-            HIPCHK(h, launch_det_interp(G.D, rawt, h->eprev, 1, h->planes, h->stream));
+            HIPCHK(h, launch_det_interp(h->g, G.D, rawt, h->eprev, 1, h->planes, h->stream));
         }
         for (int m = 0; m < G.D.ndet; m++) {
             const long long L = (long long)(G.D.i1[m] - G.D.i0[m]) * (G.D.j1[m] - G.D.j0[m]);
@@ -596,7 +602,7 @@ fdtd_status steps_tb(fdtd_ctx *h, int n0, int kk, int with_src, int with_rec, in
         }
     }
     h->cur ^= 1;
-    if (a.planes && h->raw) HIPCHK(h, launch_det_interp(G.D, a.raw, h->eprev, kk, h->planes, h->stream));
+    if (a.planes && h->raw) HIPCHK(h, launch_det_interp(h->g, G.D, a.raw, h->eprev, kk, h->planes, h->stream));
     if (a.planes)
         for (int m = 0; m < G.D.ndet; m++) {
             const long long L = (long long)(G.D.i1[m] - G.D.i0[m]) * (G.D.j1[m] - G.D.j0[m]);
@@ -991,10 +997,20 @@ fdtd_status fdtd_inverse(fdtd_handle h, int32_t n_steps)
     return FDTD_OK;
 }
 
+// an energy detector that enters the objective (its adjoint is not built)
+static bool energy_weighted(const fdtd_ctx *h)
+{
+    for (int m = 0; m < h->ndet; m++)
+        if (h->det[m].quantity == 1 && h->det[m].weight != 0.f) return true;
+    return false;
+}
+
 fdtd_status fdtd_grad(fdtd_handle h, float *dJ_deps, float *recon_err)
 {
     if (!h) return fail(nullptr, FDTD_E_INVALID, "handle is NULL");
     if (!h->desc.record) return fail(h, FDTD_E_STATE, "fdtd_grad needs record = 1");
+    if (energy_weighted(h))
+        return fail(h, FDTD_E_UNSUPPORTED, "energy detectors are forward only: give them weight 0 in a gradient");
     if (h->t != h->T) return fail(h, FDTD_E_STATE, "fdtd_grad needs t = T (t = %d, T = %d)", h->t, h->T);
     if (!dJ_deps) return fail(h, FDTD_E_INVALID, "dJ_deps is NULL");
     const Geometry &G = h->geo;
@@ -1091,6 +1107,8 @@ fdtd_status fdtd_grad_checkpointed(fdtd_handle h, int32_t segment, void *store, 
 {
     if (!h) return fail(nullptr, FDTD_E_INVALID, "handle is NULL");
     if (!h->desc.record) return fail(h, FDTD_E_STATE, "the checkpointed gradient needs the adjoint state (record = 1)");
+    if (energy_weighted(h))
+        return fail(h, FDTD_E_UNSUPPORTED, "energy detectors are forward only: give them weight 0 in a gradient");
     if (h->naive) return fail(h, FDTD_E_UNSUPPORTED, "the checkpointed gradient runs on the z-march path only");
     if (segment < 1 || segment > h->T) return fail(h, FDTD_E_INVALID, "segment %d not in [1, T]", segment);
     if (!store || !dJ_deps) return fail(h, FDTD_E_INVALID, "store or dJ_deps is NULL");

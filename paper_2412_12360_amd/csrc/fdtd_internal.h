@@ -65,7 +65,9 @@ struct Detectors {
     // (E^{n+1}, plane k), Hx, Hy (H^{n+1/2}, layer k-1), Hx, Hy (layer k) over
     // the window extended by one cell in x and y; and E^n of plane k (Ex, Ey)
     int interp[FD_MAXDET];
-    long long roff[FD_MAXDET];     // offset of the detector's six raw planes in a raw set
+    int energy[FD_MAXDET];         // co-located energy instead of flux: three more raw planes
+                                   // (Ez, Hz of plane k, Ez of layer k-1), E^n of Ez on k and k-1
+    long long roff[FD_MAXDET];     // offset of the detector's raw planes in a raw set
     long long raw_per_step;        // floats of all raw planes for one step
     long long eoff[FD_MAXDET];     // offset of the detector's two E^n planes
     long long eprev_floats;
@@ -140,8 +142,8 @@ hipError_t launch_tfsf_line(const float *amp, int T, float S, const float *ce_at
 // density of `levels` steps from the raw planes into the flux planes
 hipError_t launch_det_eprev(const Grid &g, const Fields &F, const Detectors &D, float *eprev, hipStream_t s);
 hipError_t launch_det_raw(const Grid &g, const Fields &F, const Detectors &D, float *raw, hipStream_t s);
-hipError_t launch_det_interp(const Detectors &D, const float *raw, const float *eprev, int levels, float *planes,
-                             hipStream_t s);
+hipError_t launch_det_interp(const Grid &g, const Detectors &D, const float *raw, const float *eprev, int levels,
+                             float *planes, hipStream_t s);
 // their adjoint source before reverse step n (drec: raw planes of every step,
 // e0: E planes of step 0; wS[m] = S * weight, zero weights skipped)
 hipError_t launch_det_interp_adjoint(const Grid &g, const Detectors &D, const float *drec, const float *e0, int n,

@@ -95,6 +95,10 @@ __global__ __launch_bounds__(NT) void k_det_eprev(Grid g, Fields F, Detectors D,
     const long long c = cidx(g, i, j, D.k[m]);
     eprev[D.eoff[m] + e] = F.c[0][c];
     eprev[D.eoff[m] + L + e] = F.c[1][c];
+    if (D.energy[m]) {   // Ez of plane k and of layer k-1
+        eprev[D.eoff[m] + 2 * L + e] = F.c[2][c];
+        eprev[D.eoff[m] + 3 * L + e] = F.c[2][c - g.nxy];
+    }
 }
 
 // the six raw planes of one step from the fields (per-cell path)
@@ -113,13 +117,18 @@ __global__ __launch_bounds__(NT) void k_det_raw(Grid g, Fields F, Detectors D, f
     r[3 * L] = F.c[4][cm];
     r[4 * L] = F.c[3][c];
     r[5 * L] = F.c[4][c];
+    if (D.energy[m]) {   // Ez, Hz of plane k, Ez of layer k-1
+        r[6 * L] = F.c[2][c];
+        r[7 * L] = F.c[5][c];
+        r[8 * L] = F.c[2][cm];
+    }
 }
 
 // co-located flux density of detector m at step level s: E of steps n, n+1
 // (from eprev for s = 0, else from the raw planes of level s-1) and
 // H^{n+1/2} of layers k-1, k, each averaged onto (i+1/2, j+1/2, k)
-__global__ __launch_bounds__(NT) void k_det_interp(Detectors D, int m, int s, const float *raw, const float *eprev,
-                                                   float *planes)
+__global__ __launch_bounds__(NT) void k_det_interp(Grid g, Detectors D, int m, int s, const float *raw,
+                                                   const float *eprev, float *planes)
 {
     const long long e = (long long)blockIdx.x * NT + threadIdx.x;
     const int w = D.i1[m] - D.i0[m];
@@ -135,7 +144,22 @@ __global__ __launch_bounds__(NT) void k_det_interp(Detectors D, int m, int s, co
     const float ey = 0.25f * ((Ea[L + p00] + Ea[L + p10]) + (Rb[L + p00] + Rb[L + p10]));
     const float hx = 0.25f * ((Rb[2 * L + p00] + Rb[2 * L + p10]) + (Rb[4 * L + p00] + Rb[4 * L + p10]));
     const float hy = 0.25f * ((Rb[3 * L + p00] + Rb[3 * L + p01]) + (Rb[5 * L + p00] + Rb[5 * L + p01]));
-    planes[s * D.per_step + D.off[m] + e] = flux_density(ex, ey, hx, hy);
+    if (!D.energy[m]) {
+        planes[s * D.per_step + D.off[m] + e] = flux_density(ex, ey, hx, hy);
+        return;
+    }
+    // energy: Ez over the four (i, j) neighbours of layers k-1, k and the two
+    // steps, Hz at the point; eps_r of cell (i,j,k) from S/eps_r
+    const long long p11 = p01 + 1;
+    const float *Ez = Rb + 6 * L, *Ezm = Rb + 8 * L;
+    const float *Pz = s == 0 ? Ea + 2 * L : Ea + 6 * L;
+    const float *Pzm = s == 0 ? Ea + 3 * L : Ea + 8 * L;
+    const float ez = 0.0625f * (((Ez[p00] + Ez[p10]) + (Ez[p01] + Ez[p11])) + ((Ezm[p00] + Ezm[p10]) + (Ezm[p01] + Ezm[p11])) +
+                                ((Pz[p00] + Pz[p10]) + (Pz[p01] + Pz[p11])) + ((Pzm[p00] + Pzm[p10]) + (Pzm[p01] + Pzm[p11])));
+    const float hz = Rb[7 * L + p00];
+    const float eps = g.S / g.ce[cidx(g, D.i0[m] + ii, D.j0[m] + jj, D.k[m])];
+    planes[s * D.per_step + D.off[m] + e] =
+        0.5f * (eps * ((ex * ex + ey * ey) + ez * ez) + ((hx * hx + hy * hy) + hz * hz));
 }
 
 // Adjoint source of interpolated detector m before reverse step n, for
@@ -479,14 +503,14 @@ hipError_t launch_det_raw(const Grid &g, const Fields &F, const Detectors &D, fl
     return hipGetLastError();
 }
 
-hipError_t launch_det_interp(const Detectors &D, const float *raw, const float *eprev, int levels, float *planes,
-                             hipStream_t s)
+hipError_t launch_det_interp(const Grid &g, const Detectors &D, const float *raw, const float *eprev, int levels,
+                             float *planes, hipStream_t s)
 {
     for (int m = 0; m < D.ndet; m++) {
         if (!D.interp[m]) continue;
         const long long n = (long long)(D.i1[m] - D.i0[m]) * (D.j1[m] - D.j0[m]);
         for (int l = 0; l < levels; l++) {
-            hipLaunchKernelGGL(k_det_interp, dim3(nblk(n)), dim3(NT), 0, s, D, m, l, raw, eprev, planes);
+            hipLaunchKernelGGL(k_det_interp, dim3(nblk(n)), dim3(NT), 0, s, g, D, m, l, raw, eprev, planes);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
@@ -498,7 +522,7 @@ hipError_t launch_det_interp_adjoint(const Grid &g, const Detectors &D, const fl
                                     int T, const float *wS, const Fields &A, hipStream_t s)
 {
     for (int m = 0; m < D.ndet; m++) {
-        if (!D.interp[m] || wS[m] == 0.f) continue;
+        if (!D.interp[m] || D.energy[m] || wS[m] == 0.f) continue;
         const long long L = (long long)(D.i1[m] - D.i0[m] + 1) * (D.j1[m] - D.j0[m] + 1);
         hipLaunchKernelGGL(k_det_interp_adjoint, dim3(nblk(L)), dim3(NT), 0, s, g, D, m, drec, e0, n, T, wS[m], A);
         hipError_t e = hipGetLastError();

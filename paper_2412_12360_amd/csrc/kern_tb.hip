@@ -404,11 +404,14 @@ __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
                 // ---- detector flux planes (uniform plane test)
                 if (A.planes && k >= z0 && k < z1) {
                     for (int m = 0; m < A.D.ndet; m++) {
-                        if (k != A.D.k[m]) continue;
+                        // an energy detector also takes Ez of the layer below its plane
+                        const bool at = k == A.D.k[m], below = A.D.energy[m] && k == A.D.k[m] - 1;
+                        if (!at && !below) continue;
                         if (A.D.interp[m]) {
                             // co-located flux: the raw components over the window
                             // extended by one cell in x and y (E^{n+1} of plane k,
-                            // H^{n+1/2} of layers k-1 and k), combined after the sweep
+                            // H^{n+1/2} of layers k-1 and k), combined after the sweep;
+                            // energy adds Ez, Hz of plane k and Ez of layer k-1
                             const int wx = A.D.i1[m] - A.D.i0[m] + 1;
                             const long long L = (long long)wx * (A.D.j1[m] - A.D.j0[m] + 1);
 #pragma unroll
@@ -417,16 +420,25 @@ __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
                                 if (own[r] && x >= A.D.i0[m] && x <= A.D.i1[m] && yy >= A.D.j0[m] && yy <= A.D.j1[m]) {
                                     float *rw = A.raw + (long long)(s - 1) * A.D.raw_per_step + A.D.roff[m] +
                                                 (long long)(yy - A.D.j0[m]) * wx + (x - A.D.i0[m]);
-                                    rw[0] = mE[r][0];
-                                    rw[L] = mE[r][1];
-                                    rw[2 * L] = Ho[s][r][0];
-                                    rw[3 * L] = Ho[s][r][1];
-                                    rw[4 * L] = mH[r][0];
-                                    rw[5 * L] = mH[r][1];
+                                    if (at) {
+                                        rw[0] = mE[r][0];
+                                        rw[L] = mE[r][1];
+                                        rw[2 * L] = Ho[s][r][0];
+                                        rw[3 * L] = Ho[s][r][1];
+                                        rw[4 * L] = mH[r][0];
+                                        rw[5 * L] = mH[r][1];
+                                        if (A.D.energy[m]) {
+                                            rw[6 * L] = mE[r][2];
+                                            rw[7 * L] = mH[r][2];
+                                        }
+                                    } else {
+                                        rw[8 * L] = mE[r][2];
+                                    }
                                 }
                             }
                             continue;
                         }
+                        if (!at) continue;
 #pragma unroll
                         for (int r = 0; r < R; r++) {
                             const int yy = ys[r];

@@ -45,7 +45,8 @@ class fdtd_source(C.Structure):
 
 class fdtd_flux_detector(C.Structure):
     _fields_ = [("k", C.c_int32), ("i0", C.c_int32), ("i1", C.c_int32), ("j0", C.c_int32),
-                ("j1", C.c_int32), ("weight", C.c_float), ("interpolate", C.c_int32)]
+                ("j1", C.c_int32), ("weight", C.c_float), ("interpolate", C.c_int32),
+                ("quantity", C.c_int32)]
 
 
 ENTRY_POINTS = [
@@ -145,6 +146,7 @@ def make_detectors(prob):
         arr[i].k, arr[i].i0, arr[i].i1, arr[i].j0, arr[i].j1 = d.k, d.i0, d.i1, d.j0, d.j1
         arr[i].weight = d.weight
         arr[i].interpolate = int(getattr(d, "interpolate", False))
+        arr[i].quantity = int(getattr(d, "quantity", 0))
     return arr
 
 

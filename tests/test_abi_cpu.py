@@ -159,3 +159,13 @@ def test_interpolated_detector_placement_validated(change):
     bad = W.dataclasses.replace(det, **change)
     st, _ = _status(W.dataclasses.replace(pr, detectors=[bad]))
     assert st == F.FDTD_E_INVALID
+
+
+@pytest.mark.parametrize("change,ok", [(dict(quantity=1), True), (dict(quantity=1, interpolate=False), False),
+                                       (dict(quantity=2), False)])
+def test_energy_detector_validated(change, ok):
+    F = _F()
+    pr = W.small_cpml(nx=40, ny=36, nz=44, p=0, T=50)
+    det = W.dataclasses.replace(W.Detector(k=10, i0=0, i1=39, j0=0, j1=35, interpolate=True), **change)
+    st, _ = _status(W.dataclasses.replace(pr, detectors=[det]))
+    assert st == (F.FDTD_OK if ok else F.FDTD_E_INVALID)

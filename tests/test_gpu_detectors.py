@@ -154,3 +154,68 @@ def test_zero_weight_interpolated_detector_leaves_gradient():
         grads.append((J.clone(), g.clone()))
     assert torch.equal(grads[0][0], grads[1][0])
     assert torch.equal(grads[0][1], grads[1][1])
+
+
+def with_energy(pr):
+    """The problem's flux detector, a co-located energy detector on the same
+    window and one on a lower plane (both weight 0: forward only)."""
+    d0 = pr.detectors[0]
+    p = pr.p
+    e1 = dataclasses.replace(d0, interpolate=True, quantity=1, weight=0.0)
+    e2 = W.Detector(k=pr.nz // 2, i0=p + 1, i1=pr.nx - p - 3, j0=p + 2, j1=pr.ny - p - 1, weight=0.0,
+                    interpolate=True, quantity=1)
+    return dataclasses.replace(pr, detectors=[d0, e1, e2])
+
+
+@pytest.mark.parametrize("shape,p,T", [((40, 36, 44), 6, 160), ((67, 29, 23), 4, 90)])
+def test_energy_detector_parity(shape, p, T):
+    pr = with_energy(W.small_cpml(nx=shape[0], ny=shape[1], nz=shape[2], p=p, T=T))
+    announce(f"energy detectors {shape} p={p} T={T}")
+    st, J, trace, _ = Oracle(pr).run()
+    s = _solver(pr)
+    tr, Jg = s.forward()
+    torch.cuda.synchronize()
+    tr = tr.cpu().numpy()
+    for m in range(3):
+        assert rel_l2(tr[:, m], trace[:, m]) <= FIELD_TOL, m
+    assert abs(float(Jg.item()) - J) <= FIELD_TOL * abs(J)
+    assert np.min(trace[:, 1:]) >= 0.0 and np.max(trace[:, 1]) > 0.0
+
+
+@pytest.mark.parametrize("shape,p,T", [((70, 45, 38), 5, 37), ((33, 61, 70), 6, 30)])
+def test_energy_detector_bitwise_all_K(shape, p, T, monkeypatch):
+    pr = with_energy(W.small_cpml(nx=shape[0], ny=shape[1], nz=shape[2], p=p, T=T))
+    outs = []
+    for K, naive in [(1, True), (1, False), (2, False), (3, False), (4, False)]:
+        announce(f"energy detectors bitwise {shape} K={K} naive={naive}")
+        monkeypatch.setenv("FDTD_NAIVE", "1" if naive else "0")
+        s = _solver(pr, time_block=K)
+        tr1, _ = s.forward(T // 2)
+        tr2, J = s.forward(T - T // 2)
+        torch.cuda.synchronize()
+        outs.append((torch.cat([tr1.clone(), tr2.clone()]), J.clone()))
+    for tr, J in outs[1:]:
+        assert torch.equal(tr, outs[0][0])
+        assert torch.equal(J, outs[0][1])
+
+
+def test_energy_detector_is_forward_only():
+    from paper_2412_12360_amd.fdtd import FdtdError, FDTD_E_UNSUPPORTED
+    base = W.small_cpml(nx=40, ny=36, nz=44, p=6, T=120, d=8, seed=12)
+    announce("energy detector in a gradient")
+    pr = with_energy(base)
+    grads = []
+    for q in (base, pr):
+        s = _solver(q, record=True)
+        _, J = s.forward()
+        g, _ = s.grad()
+        torch.cuda.synchronize()
+        grads.append((J.clone(), g.clone()))
+    assert torch.equal(grads[0][0], grads[1][0])
+    assert torch.equal(grads[0][1], grads[1][1])
+    bad = dataclasses.replace(pr, detectors=[pr.detectors[0], dataclasses.replace(pr.detectors[1], weight=1.0)])
+    s = _solver(bad, record=True)
+    s.forward()
+    with pytest.raises(FdtdError) as ei:
+        s.grad()
+    assert ei.value.status == FDTD_E_UNSUPPORTED
