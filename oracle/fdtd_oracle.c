@@ -30,7 +30,7 @@
  *     the point (i+1/2, j+1/2, k) of the detector plane at time n+1/2 (E of
  *     steps n and n+1; H^{n+1/2} of layers k-1 and k), and its adjoint source;
  *     the co-located energy density 1/2 (eps_r |E|^2 + |H|^2) at the same point
- *     and time (forward only).
+ *     and time, and its adjoint source (detector outside the design box).
  *   - the interface record (section 2.2): every step, tangential H^{n+1/2} on
  *     the PML-side layer p-1 of the three low faces and tangential E^{n+1} on
  *     layer n_a-p of the three high faces, over the interior window.
@@ -71,7 +71,7 @@ typedef struct {
     int det_i0[OR_MAXDET], det_i1[OR_MAXDET], det_j0[OR_MAXDET], det_j1[OR_MAXDET];
     double det_w[OR_MAXDET];
     int det_interp[OR_MAXDET];      /* 1: co-located (interpolated) flux */
-    int det_energy[OR_MAXDET];      /* 1: co-located energy density instead of flux (forward only) */
+    int det_energy[OR_MAXDET];      /* 1: co-located energy density instead of flux */
     int dlo[3], dhi[3];             /* half-open design box */
 } or_problem;
 
@@ -421,9 +421,12 @@ static void step_fwd(const or_problem *P, double *st, int n, const or_prof *PE, 
  * interpolated detector m, the planes the co-located flux of step n reads:
  * E^{n+1} x, y of plane k, H^{n+1/2} x, y of layer k-1, H^{n+1/2} x, y of
  * layer k (six [ny][nx] planes), and E^0 x, y of plane k. */
+#define OR_DSTORE 9   /* planes per step and detector */
+#define OR_DE0 4      /* E planes of step 0 per detector */
+
 static size_t dstore_floats(const or_problem *P, int T)
 {
-    return (size_t)T * P->ndet * 6 * (size_t)P->nx * P->ny;
+    return (size_t)T * P->ndet * OR_DSTORE * (size_t)P->nx * P->ny;
 }
 
 static int any_interp(const or_problem *P)
@@ -433,14 +436,76 @@ static int any_interp(const or_problem *P)
     return 0;
 }
 
+/* planes 0..8: Ex, Ey (plane k), Hx, Hy (layer k-1), Hx, Hy (layer k), Ez,
+ * Hz (plane k), Ez (layer k-1); with e_only the E planes Ex, Ey, Ez (k), Ez
+ * (k-1) */
 static void dstore_planes(const or_problem *P, const double *st, double *dst, int m, int e_only)
 {
     size_t A = (size_t)P->nx * P->ny;
     int k = P->det_k[m];
-    const int comp[6] = {0, 1, 3, 4, 3, 4};
-    const int layer[6] = {k, k, k - 1, k - 1, k, k};
-    for (int q = 0; q < (e_only ? 2 : 6); q++)
-        memcpy(dst + q * A, slot((double *)st, P, comp[q]) + (size_t)layer[q] * A, sizeof(double) * A);
+    const int comp[OR_DSTORE] = {0, 1, 3, 4, 3, 4, 2, 5, 2};
+    const int layer[OR_DSTORE] = {k, k, k - 1, k - 1, k, k, k, k, k - 1};
+    const int eq[OR_DE0] = {0, 1, 6, 8};
+    for (int q = 0; q < (e_only ? OR_DE0 : OR_DSTORE); q++) {
+        int qq = e_only ? eq[q] : q;
+        memcpy(dst + q * A, slot((double *)st, P, comp[qq]) + (size_t)layer[qq] * A, sizeof(double) * A);
+    }
+}
+
+/* Energy detector m, J = S sum_n w U[n] with U the co-located energy sum:
+ * dU/d(node) = eps_r * (co-located E) or (co-located H) times the node's
+ * averaging weight, for every cell the node enters (eps_r of the cell; the
+ * detector lies outside the design box, so U has no explicit eps_r term in
+ * the gradient).  E^{n+1} enters U[n] and U[n+1], H^{n+1/2} U[n]. */
+static void det_energy_adjoint(const or_problem *P, double *adj, const double *store, const double *e0, int n,
+                               int T, int m, double sw)
+{
+    size_t N = ncell(P), A = (size_t)P->nx * P->ny;
+    int k = P->det_k[m];
+    const double *R = store + ((size_t)n * P->ndet + m) * OR_DSTORE * A;
+    const double *Ep = n == 0 ? e0 + (size_t)m * OR_DE0 * A : store + ((size_t)(n - 1) * P->ndet + m) * OR_DSTORE * A;
+    const double *Epz = n == 0 ? Ep + 2 * A : Ep + 6 * A, *Epzm = n == 0 ? Ep + 3 * A : Ep + 8 * A;
+    const double *R1 = n + 1 < T ? store + ((size_t)(n + 1) * P->ndet + m) * OR_DSTORE * A : NULL;
+    double *aE[3] = {adj, adj + N, adj + 2 * N}, *aH[3] = {adj + 3 * N, adj + 4 * N, adj + 5 * N};
+    for (int j = P->det_j0[m]; j < P->det_j1[m]; j++)
+        for (int i = P->det_i0[m]; i < P->det_i1[m]; i++) {
+            size_t p00 = (size_t)j * P->nx + i, p01 = p00 + P->nx, p10 = p00 + 1, p11 = p01 + 1;
+            const size_t q4[4] = {p00, p10, p01, p11};
+            double eps = 1.0 / P->d[idx(P, i, j, k)];
+            double ex = 0.25 * (Ep[p00] + Ep[p01] + R[p00] + R[p01]);
+            double ey = 0.25 * (Ep[A + p00] + Ep[A + p10] + R[A + p00] + R[A + p10]);
+            double ez = 0.0;
+            for (int c = 0; c < 4; c++) ez += Epz[q4[c]] + Epzm[q4[c]] + R[6 * A + q4[c]] + R[8 * A + q4[c]];
+            ez /= 16.0;
+            double hx = 0.25 * (R[2 * A + p00] + R[2 * A + p10] + R[4 * A + p00] + R[4 * A + p10]);
+            double hy = 0.25 * (R[3 * A + p00] + R[3 * A + p01] + R[5 * A + p00] + R[5 * A + p01]);
+            double hz = R[7 * A + p00];
+            double ex1 = 0.0, ey1 = 0.0, ez1 = 0.0;
+            if (R1) {
+                ex1 = 0.25 * (R[p00] + R[p01] + R1[p00] + R1[p01]);
+                ey1 = 0.25 * (R[A + p00] + R[A + p10] + R1[A + p00] + R1[A + p10]);
+                for (int c = 0; c < 4; c++)
+                    ez1 += R[6 * A + q4[c]] + R[8 * A + q4[c]] + R1[6 * A + q4[c]] + R1[8 * A + q4[c]];
+                ez1 /= 16.0;
+            }
+            double gx = 0.25 * sw * eps * (ex + ex1), gy = 0.25 * sw * eps * (ey + ey1);
+            double gz = sw * eps * (ez + ez1) / 16.0;
+            aE[0][idx(P, i, j, k)] += gx;
+            aE[0][idx(P, i, j + 1, k)] += gx;
+            aE[1][idx(P, i, j, k)] += gy;
+            aE[1][idx(P, i + 1, j, k)] += gy;
+            for (int kk = k - 1; kk <= k; kk++) {
+                aE[2][idx(P, i, j, kk)] += gz;
+                aE[2][idx(P, i + 1, j, kk)] += gz;
+                aE[2][idx(P, i, j + 1, kk)] += gz;
+                aE[2][idx(P, i + 1, j + 1, kk)] += gz;
+                aH[0][idx(P, i, j, kk)] += 0.25 * sw * hx;
+                aH[0][idx(P, i + 1, j, kk)] += 0.25 * sw * hx;
+                aH[1][idx(P, i, j, kk)] += 0.25 * sw * hy;
+                aH[1][idx(P, i, j + 1, kk)] += 0.25 * sw * hy;
+            }
+            aH[2][idx(P, i, j, k)] += sw * hz;
+        }
 }
 
 /* Before reverse step n: add dJ/dE^{n+1} and dJ/dH^{n+1/2} of the interpolated
@@ -453,13 +518,17 @@ static void det_interp_adjoint(const or_problem *P, double *adj, const double *s
 {
     size_t N = ncell(P), A = (size_t)P->nx * P->ny;
     for (int m = 0; m < P->ndet; m++) {
-        if (!P->det_interp[m] || P->det_energy[m]) continue;   /* energy: forward only */
+        if (!P->det_interp[m]) continue;
         double sw = P->S * P->det_w[m];
         if (sw == 0.0) continue;
+        if (P->det_energy[m]) {
+            det_energy_adjoint(P, adj, store, e0, n, T, m, sw);
+            continue;
+        }
         int k = P->det_k[m];
-        const double *R = store + ((size_t)n * P->ndet + m) * 6 * A;
-        const double *Ep = n == 0 ? e0 + (size_t)m * 2 * A : store + ((size_t)(n - 1) * P->ndet + m) * 6 * A;
-        const double *R1 = n + 1 < T ? store + ((size_t)(n + 1) * P->ndet + m) * 6 * A : NULL;
+        const double *R = store + ((size_t)n * P->ndet + m) * OR_DSTORE * A;
+        const double *Ep = n == 0 ? e0 + (size_t)m * OR_DE0 * A : store + ((size_t)(n - 1) * P->ndet + m) * OR_DSTORE * A;
+        const double *R1 = n + 1 < T ? store + ((size_t)(n + 1) * P->ndet + m) * OR_DSTORE * A : NULL;
         for (int j = P->det_j0[m]; j < P->det_j1[m]; j++)
             for (int i = P->det_i0[m]; i < P->det_i1[m]; i++) {
                 size_t p00 = (size_t)j * P->nx + i, p01 = p00 + P->nx, p10 = p00 + 1;
@@ -501,13 +570,13 @@ static double forward_run(const or_problem *P, double *st, int n0, int T, double
     double *tr = trace ? trace : malloc(sizeof(double) * (size_t)(T > 0 ? T : 1) * (P->ndet > 0 ? P->ndet : 1));
     if (e0)
         for (int m = 0; m < P->ndet; m++)
-            if (P->det_interp[m]) dstore_planes(P, st, e0 + (size_t)m * 2 * A, m, 1);
+            if (P->det_interp[m]) dstore_planes(P, st, e0 + (size_t)m * OR_DE0 * A, m, 1);
     for (int n = 0; n < T; n++) {
         step_fwd(P, st, n0 + n, &PE, &PH, tr + (size_t)n * P->ndet, rec ? rec + (size_t)n * rf : NULL, 1);
         for (int m = 0; m < P->ndet; m++) J += P->S * P->det_w[m] * tr[(size_t)n * P->ndet + m];
         if (store)
             for (int m = 0; m < P->ndet; m++)
-                if (P->det_interp[m]) dstore_planes(P, st, store + ((size_t)n * P->ndet + m) * 6 * A, m, 0);
+                if (P->det_interp[m]) dstore_planes(P, st, store + ((size_t)n * P->ndet + m) * OR_DSTORE * A, m, 0);
     }
     if (!trace) free(tr);
     prof_free(&PE); prof_free(&PH);
@@ -736,17 +805,17 @@ double or_grad_history(const or_problem *P, int T, int seg, double *g, double *t
     double *tr = malloc(sizeof(double) * (size_t)(T > 0 ? T : 1) * (P->ndet > 0 ? P->ndet : 1));
     size_t A = (size_t)P->nx * P->ny;
     double *store = any_interp(P) ? calloc(dstore_floats(P, T) + 1, sizeof(double)) : NULL;
-    double *e0 = any_interp(P) ? calloc((size_t)P->ndet * 2 * A, sizeof(double)) : NULL;
+    double *e0 = any_interp(P) ? calloc((size_t)P->ndet * OR_DE0 * A, sizeof(double)) : NULL;
     if (e0)
         for (int m = 0; m < P->ndet; m++)
-            if (P->det_interp[m]) dstore_planes(P, st, e0 + (size_t)m * 2 * A, m, 1);
+            if (P->det_interp[m]) dstore_planes(P, st, e0 + (size_t)m * OR_DE0 * A, m, 1);
     for (int n = 0; n < T; n++) {
         if (n % seg == 0) memcpy(ck + (size_t)(n / seg) * SZ, st, sizeof(double) * SZ);
         step_fwd(P, st, n, &PE, &PH, tr + (size_t)n * P->ndet, NULL, 1);
         for (int m = 0; m < P->ndet; m++) J += P->S * P->det_w[m] * tr[(size_t)n * P->ndet + m];
         if (store)
             for (int m = 0; m < P->ndet; m++)
-                if (P->det_interp[m]) dstore_planes(P, st, store + ((size_t)n * P->ndet + m) * 6 * A, m, 0);
+                if (P->det_interp[m]) dstore_planes(P, st, store + ((size_t)n * P->ndet + m) * OR_DSTORE * A, m, 0);
     }
     if (trace) memcpy(trace, tr, sizeof(double) * (size_t)T * P->ndet);
     double *adj = calloc(SZ, sizeof(double));
@@ -781,7 +850,7 @@ double or_grad_reversed(const or_problem *P, int T, double *g, double *trace, do
     double *rec = P->p > 0 ? malloc(sizeof(double) * (size_t)(T > 0 ? T : 1) * rf) : NULL;
     size_t A = (size_t)P->nx * P->ny;
     double *store = any_interp(P) ? calloc(dstore_floats(P, T) + 1, sizeof(double)) : NULL;
-    double *e0 = any_interp(P) ? calloc((size_t)P->ndet * 2 * A, sizeof(double)) : NULL;
+    double *e0 = any_interp(P) ? calloc((size_t)P->ndet * OR_DE0 * A, sizeof(double)) : NULL;
     double J = forward_run(P, st, 0, T, trace, rec, store, e0);
     int p = P->p;
     double nT = 0.0;

@@ -229,9 +229,11 @@ class Oracle:
 
     # ----------------------------------------------------------- gradients
     def _check_grad(self):
+        lo, hi = self.prob.design_lo[2], self.prob.design_hi[2]
         for det in self.prob.detectors:
-            assert not (getattr(det, "quantity", 0) == 1 and det.weight != 0.0), \
-                "energy detectors are forward only: weight 0 in a gradient"
+            if getattr(det, "quantity", 0) == 1 and det.weight != 0.0:
+                # the energy reads eps_r: its gradient omits that explicit term
+                assert not (lo <= det.k < hi), "a weighted energy detector lies outside the design box in z"
 
     def grad_history(self, T: int | None = None, seg: int | None = None):
         """dJ/dd over the grid by the stored-history VJP; returns (g, J, trace)."""

@@ -716,3 +716,51 @@ def test_colocated_energy_of_a_plane_wave():
     a, b, c = np.linalg.lstsq(X, trace[steady, 0] / cells, rcond=None)[0]
     assert abs(a - mean) <= 2e-3 * mean
     assert abs(math.hypot(b, c) - a) <= 2e-3 * a
+
+
+def with_energy_objective(pr):
+    """Objective: the co-located energy (weight 1) on the flux detector's
+    window (outside the design box in z) plus the plain flux (weight 0.3)."""
+    d = pr.detectors[0]
+    assert not (pr.design_lo[2] <= d.k < pr.design_hi[2])
+    return dataclasses.replace(pr, detectors=[dataclasses.replace(d, weight=0.3),
+                                              dataclasses.replace(d, weight=1.0, interpolate=True, quantity=1)])
+
+
+def test_energy_objective_history_equals_reversed_gradient():
+    pr = with_energy_objective(W.small_cpml(nx=22, ny=20, nz=24, p=4, T=90, d=6, seed=13))
+    o = Oracle(pr)
+    g1, J1, _ = o.grad_history(seg=7)
+    g2, J2, _, _ = o.grad_reversed()
+    assert abs(J1 - J2) <= 1e-13 * abs(J1)
+    assert np.linalg.norm(g1 - g2) <= 1e-10 * np.linalg.norm(g1)
+    g0, _, _ = Oracle(dataclasses.replace(pr, detectors=pr.detectors[:1])).grad_history(seg=7)
+    assert np.linalg.norm(g1 - g0) > 0.1 * np.linalg.norm(g1)
+
+
+def test_energy_objective_gradient_matches_central_differences():
+    """Central differences of an objective holding the co-located energy, on
+    every design cell (the energy's adjoint source covers E^{n+1} in two energy
+    terms, Ez on two layers and all three H components)."""
+    pr = with_energy_objective(tiny_grad_problem())
+    sl = pr.design_slices()
+    o = Oracle(pr)
+    d_exact = o.d.copy()
+    d_exact[sl] = 1.0 / W.eps_from_rho(pr.rho)
+    o = Oracle(pr, d=d_exact)
+    g, J, _ = o.grad_history()
+    adj = 10.0 * o.deps_design(g)
+    h = 5e-4   # the energy is quadratic in the fields: a smaller step keeps O(h^2) below 1e-6
+    fd = np.zeros_like(adj)
+    for idx in np.ndindex(*adj.shape):
+        vals = []
+        for sgn in (1, -1):
+            rho = pr.rho.copy()
+            rho[idx] += sgn * h
+            d = d_exact.copy()
+            d[sl] = 1.0 / W.eps_from_rho(rho)
+            oo = Oracle(pr, d=d)
+            vals.append(oo.forward(oo.new_state(), pr.T)[0])
+        fd[idx] = (vals[0] - vals[1]) / (2 * h)
+    assert np.max(np.abs(adj)) > 0
+    assert np.linalg.norm(fd - adj) <= 1e-6 * np.linalg.norm(adj)
