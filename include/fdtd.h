@@ -116,9 +116,10 @@ typedef struct {
 /* quantity = 1 (with interpolate = 1): instead of the flux, the co-located
  * energy density sum of 1/2 (eps_r |E|^2 + |H|^2) at the same points and
  * time, eps_r of cell (i,j,k): Ez averaged over i, i+1, j, j+1, the layers
- * k-1, k and the two steps; Hz lies at the point already.  Forward only:
- * fdtd_grad and fdtd_grad_checkpointed return FDTD_E_UNSUPPORTED when an
- * energy detector has a nonzero weight. */
+ * k-1, k and the two steps; Hz lies at the point already.  The gradients
+ * apply its adjoint source; they return FDTD_E_UNSUPPORTED when a weighted
+ * energy detector's plane lies in the design box's z range (the energy reads
+ * eps_r there). */
 typedef struct {
     int32_t k, i0, i1, j0, j1;
     float weight;

@@ -267,6 +267,12 @@ void geometry(const fdtd_desc *d, const fdtd_flux_detector *det, int ndet, Geome
     G.D.per_step = doff;
     G.D.raw_per_step = roff;
     G.D.eprev_floats = eoff;
+    G.D.kmin = 1 << 30;
+    G.D.kmax = -1;
+    for (int m = 0; m < ndet; m++) {
+        G.D.kmin = std::min(G.D.kmin, det[m].k - (det[m].quantity == 1 ? 1 : 0));
+        G.D.kmax = std::max(G.D.kmax, det[m].k);
+    }
     G.design_cells = 1;
     for (int a = 0; a < 3; a++) G.design_cells *= (d->design_hi[a] - d->design_lo[a]);
 }
@@ -997,11 +1003,14 @@ fdtd_status fdtd_inverse(fdtd_handle h, int32_t n_steps)
     return FDTD_OK;
 }
 
-// an energy detector that enters the objective (its adjoint is not built)
-static bool energy_weighted(const fdtd_ctx *h)
+// a weighted energy detector on a plane of the design box: the energy reads
+// eps_r there, a term the adjoint does not carry
+static bool energy_in_design(const fdtd_ctx *h)
 {
     for (int m = 0; m < h->ndet; m++)
-        if (h->det[m].quantity == 1 && h->det[m].weight != 0.f) return true;
+        if (h->det[m].quantity == 1 && h->det[m].weight != 0.f && h->det[m].k >= h->desc.design_lo[2] &&
+            h->det[m].k < h->desc.design_hi[2])
+            return true;
     return false;
 }
 
@@ -1009,8 +1018,8 @@ fdtd_status fdtd_grad(fdtd_handle h, float *dJ_deps, float *recon_err)
 {
     if (!h) return fail(nullptr, FDTD_E_INVALID, "handle is NULL");
     if (!h->desc.record) return fail(h, FDTD_E_STATE, "fdtd_grad needs record = 1");
-    if (energy_weighted(h))
-        return fail(h, FDTD_E_UNSUPPORTED, "energy detectors are forward only: give them weight 0 in a gradient");
+    if (energy_in_design(h))
+        return fail(h, FDTD_E_UNSUPPORTED, "a weighted energy detector must lie outside the design box in z");
     if (h->t != h->T) return fail(h, FDTD_E_STATE, "fdtd_grad needs t = T (t = %d, T = %d)", h->t, h->T);
     if (!dJ_deps) return fail(h, FDTD_E_INVALID, "dJ_deps is NULL");
     const Geometry &G = h->geo;
@@ -1107,8 +1116,8 @@ fdtd_status fdtd_grad_checkpointed(fdtd_handle h, int32_t segment, void *store, 
 {
     if (!h) return fail(nullptr, FDTD_E_INVALID, "handle is NULL");
     if (!h->desc.record) return fail(h, FDTD_E_STATE, "the checkpointed gradient needs the adjoint state (record = 1)");
-    if (energy_weighted(h))
-        return fail(h, FDTD_E_UNSUPPORTED, "energy detectors are forward only: give them weight 0 in a gradient");
+    if (energy_in_design(h))
+        return fail(h, FDTD_E_UNSUPPORTED, "a weighted energy detector must lie outside the design box in z");
     if (h->naive) return fail(h, FDTD_E_UNSUPPORTED, "the checkpointed gradient runs on the z-march path only");
     if (segment < 1 || segment > h->T) return fail(h, FDTD_E_INVALID, "segment %d not in [1, T]", segment);
     if (!store || !dJ_deps) return fail(h, FDTD_E_INVALID, "store or dJ_deps is NULL");

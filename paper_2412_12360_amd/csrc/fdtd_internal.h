@@ -71,6 +71,7 @@ struct Detectors {
     long long raw_per_step;        // floats of all raw planes for one step
     long long eoff[FD_MAXDET];     // offset of the detector's two E^n planes
     long long eprev_floats;
+    int kmin, kmax;                // planes on which any detector emits (kmin > kmax: none)
 };
 
 // ------------------------------------------------------------ device helpers

@@ -219,6 +219,80 @@ __global__ __launch_bounds__(NT) void k_det_interp_adjoint(Grid g, Detectors D, 
     A.c[3][c] = fmaf(-q, ghx, A.c[3][c]);
 }
 
+// Adjoint source of energy detector m before reverse step n, J = S sum_n w
+// U[n] with U the co-located energy sum: a node receives eps_r (co-located E)
+// or (co-located H) times its averaging weight from every cell it enters
+// (E^{n+1} in U[n] and U[n+1], H^{n+1/2} in U[n]; the detector lies outside
+// the design box, so U adds no explicit eps_r term).  Raw planes of a step:
+// Ex, Ey (k), Hx, Hy (k-1), Hx, Hy (k), Ez, Hz (k), Ez (k-1); step 0 keeps Ex,
+// Ey, Ez (k), Ez (k-1).  One thread per node of the extended window.
+struct CoAll {
+    float ex, ey, ez, hx, hy, hz, ex1, ey1, ez1;
+};
+__device__ __forceinline__ CoAll co_all(const float *Ep, const float *Epz, const float *Epzm, const float *R,
+                                        const float *R1, long long L, int wx, int ci, int cj)
+{
+    const long long p00 = (long long)cj * wx + ci, p10 = p00 + 1, p01 = p00 + wx, p11 = p01 + 1;
+    CoAll v;
+    v.ex = 0.25f * ((Ep[p00] + Ep[p01]) + (R[p00] + R[p01]));
+    v.ey = 0.25f * ((Ep[L + p00] + Ep[L + p10]) + (R[L + p00] + R[L + p10]));
+    const float *Rz = R + 6 * L, *Rzm = R + 8 * L;
+    v.ez = 0.0625f * (((Rz[p00] + Rz[p10]) + (Rz[p01] + Rz[p11])) + ((Rzm[p00] + Rzm[p10]) + (Rzm[p01] + Rzm[p11])) +
+                      ((Epz[p00] + Epz[p10]) + (Epz[p01] + Epz[p11])) + ((Epzm[p00] + Epzm[p10]) + (Epzm[p01] + Epzm[p11])));
+    v.hx = 0.25f * ((R[2 * L + p00] + R[2 * L + p10]) + (R[4 * L + p00] + R[4 * L + p10]));
+    v.hy = 0.25f * ((R[3 * L + p00] + R[3 * L + p01]) + (R[5 * L + p00] + R[5 * L + p01]));
+    v.hz = R[7 * L + p00];
+    v.ex1 = v.ey1 = v.ez1 = 0.f;
+    if (R1) {
+        v.ex1 = 0.25f * ((R[p00] + R[p01]) + (R1[p00] + R1[p01]));
+        v.ey1 = 0.25f * ((R[L + p00] + R[L + p10]) + (R1[L + p00] + R1[L + p10]));
+        const float *Sz = R1 + 6 * L, *Szm = R1 + 8 * L;
+        v.ez1 = 0.0625f * (((Sz[p00] + Sz[p10]) + (Sz[p01] + Sz[p11])) + ((Szm[p00] + Szm[p10]) + (Szm[p01] + Szm[p11])) +
+                           ((Rz[p00] + Rz[p10]) + (Rz[p01] + Rz[p11])) + ((Rzm[p00] + Rzm[p10]) + (Rzm[p01] + Rzm[p11])));
+    }
+    return v;
+}
+
+__global__ __launch_bounds__(NT) void k_det_energy_adjoint(Grid g, Detectors D, int m, const float *drec,
+                                                           const float *e0, int n, int T, float sw, Fields A)
+{
+    const int w = D.i1[m] - D.i0[m], h = D.j1[m] - D.j0[m], wx = w + 1;
+    const long long L = (long long)wx * (h + 1);
+    const long long t = (long long)blockIdx.x * NT + threadIdx.x;
+    if (t >= L) return;
+    const int jj = (int)(t / wx), ii = (int)(t - (long long)jj * wx);
+    const float *R = drec + (long long)n * D.raw_per_step + D.roff[m];
+    const float *Ep = n == 0 ? e0 + D.eoff[m] : drec + (long long)(n - 1) * D.raw_per_step + D.roff[m];
+    const float *Epz = n == 0 ? Ep + 2 * L : Ep + 6 * L, *Epzm = n == 0 ? Ep + 3 * L : Ep + 8 * L;
+    const float *R1 = n + 1 < T ? drec + (long long)(n + 1) * D.raw_per_step + D.roff[m] : nullptr;
+    const int k = D.k[m];
+    auto eps_of = [&](int ci, int cj) { return g.S / g.ce[cidx(g, D.i0[m] + ci, D.j0[m] + cj, k)]; };
+    // the cells this node enters: (i,j), (i-1,j), (i,j-1), (i-1,j-1)
+    const bool c00 = ii < w && jj < h, cm0 = ii >= 1 && jj < h, c0m = ii < w && jj >= 1, cmm = ii >= 1 && jj >= 1;
+    CoAll v00{}, vm0{}, v0m{}, vmm{};
+    float e00 = 0.f, em0 = 0.f, e0m = 0.f, emm = 0.f;
+    if (c00) { v00 = co_all(Ep, Epz, Epzm, R, R1, L, wx, ii, jj); e00 = eps_of(ii, jj); }
+    if (cm0) { vm0 = co_all(Ep, Epz, Epzm, R, R1, L, wx, ii - 1, jj); em0 = eps_of(ii - 1, jj); }
+    if (c0m) { v0m = co_all(Ep, Epz, Epzm, R, R1, L, wx, ii, jj - 1); e0m = eps_of(ii, jj - 1); }
+    if (cmm) { vmm = co_all(Ep, Epz, Epzm, R, R1, L, wx, ii - 1, jj - 1); emm = eps_of(ii - 1, jj - 1); }
+    const float gx = e00 * (v00.ex + v00.ex1) + e0m * (v0m.ex + v0m.ex1);                       // Ex: (i,j), (i,j-1)
+    const float gy = e00 * (v00.ey + v00.ey1) + em0 * (vm0.ey + vm0.ey1);                       // Ey: (i,j), (i-1,j)
+    const float gz = (e00 * (v00.ez + v00.ez1) + em0 * (vm0.ez + vm0.ez1)) +
+                     (e0m * (v0m.ez + v0m.ez1) + emm * (vmm.ez + vmm.ez1));                       // Ez: all four
+    const float ghx = v00.hx + vm0.hx, ghy = v00.hy + v0m.hy;
+    const long long c = cidx(g, D.i0[m] + ii, D.j0[m] + jj, k), cm = c - g.nxy;
+    const float q = 0.25f * sw, q16 = 0.0625f * sw;
+    A.c[0][c] = fmaf(q, gx, A.c[0][c]);
+    A.c[1][c] = fmaf(q, gy, A.c[1][c]);
+    A.c[2][c] = fmaf(q16, gz, A.c[2][c]);
+    A.c[2][cm] = fmaf(q16, gz, A.c[2][cm]);
+    A.c[3][c] = fmaf(q, ghx, A.c[3][c]);
+    A.c[3][cm] = fmaf(q, ghx, A.c[3][cm]);
+    A.c[4][c] = fmaf(q, ghy, A.c[4][c]);
+    A.c[4][cm] = fmaf(q, ghy, A.c[4][cm]);
+    A.c[5][c] = fmaf(sw, v00.hz, A.c[5][c]);
+}
+
 // dJ/dE^{n+1} and dJ/dH^{n+1/2} of J += S w sum (Ex Hy - Ey Hx)
 __global__ __launch_bounds__(NT) void k_det_adjoint(Grid g, Fields F, Fields A, Detectors D, int m, float sw)
 {
@@ -522,9 +596,12 @@ hipError_t launch_det_interp_adjoint(const Grid &g, const Detectors &D, const fl
                                     int T, const float *wS, const Fields &A, hipStream_t s)
 {
     for (int m = 0; m < D.ndet; m++) {
-        if (!D.interp[m] || D.energy[m] || wS[m] == 0.f) continue;
+        if (!D.interp[m] || wS[m] == 0.f) continue;
         const long long L = (long long)(D.i1[m] - D.i0[m] + 1) * (D.j1[m] - D.j0[m] + 1);
-        hipLaunchKernelGGL(k_det_interp_adjoint, dim3(nblk(L)), dim3(NT), 0, s, g, D, m, drec, e0, n, T, wS[m], A);
+        if (D.energy[m])
+            hipLaunchKernelGGL(k_det_energy_adjoint, dim3(nblk(L)), dim3(NT), 0, s, g, D, m, drec, e0, n, T, wS[m], A);
+        else
+            hipLaunchKernelGGL(k_det_interp_adjoint, dim3(nblk(L)), dim3(NT), 0, s, g, D, m, drec, e0, n, T, wS[m], A);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

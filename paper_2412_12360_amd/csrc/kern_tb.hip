@@ -402,7 +402,7 @@ __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
                     }
                 }
                 // ---- detector flux planes (uniform plane test)
-                if (A.planes && k >= z0 && k < z1) {
+                if (A.planes && k >= z0 && k < z1 && k >= A.D.kmin && k <= A.D.kmax) {
                     for (int m = 0; m < A.D.ndet; m++) {
                         // an energy detector also takes Ez of the layer below its plane
                         const bool at = k == A.D.k[m], below = A.D.energy[m] && k == A.D.k[m] - 1;

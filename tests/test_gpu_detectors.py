@@ -5,10 +5,12 @@ time; the paper evaluates finished designs this way), through the C ABI:
     and a plain detector on the same plane and an interpolated one elsewhere,
     on ragged multi-tile grids;
   - the z-march at every time-block size gives the per-cell path's bits;
-  - with an interpolated detector in the objective: the time-reversal
-    gradient against the oracle's, the fused reverse against the per-cell
-    reverse bit for bit, the checkpointed gradient against the time-reversal
-    one; with weight 0 the gradient is bitwise the one without it.
+  - with an interpolated flux or a co-located energy detector in the
+    objective: the time-reversal gradient against the oracle's, the fused
+    reverse against the per-cell reverse bit for bit, the checkpointed
+    gradient against the time-reversal one; with weight 0 the gradient is
+    bitwise the one without it; an energy detector in the design box is
+    refused.
 Tolerance as in the other parity tests: rel-L2 <= 1e-4.
 """
 import dataclasses
@@ -199,21 +201,64 @@ def test_energy_detector_bitwise_all_K(shape, p, T, monkeypatch):
         assert torch.equal(J, outs[0][1])
 
 
-def test_energy_detector_is_forward_only():
-    from paper_2412_12360_amd.fdtd import FdtdError, FDTD_E_UNSUPPORTED
-    base = W.small_cpml(nx=40, ny=36, nz=44, p=6, T=120, d=8, seed=12)
-    announce("energy detector in a gradient")
-    pr = with_energy(base)
-    grads = []
-    for q in (base, pr):
-        s = _solver(q, record=True)
+def energy_grad_problem(shape=(40, 36, 44), p=6, T=160, seed=12, d=8):
+    """Objective: the plain flux (weight 0.3) and the co-located energy
+    (weight 1) of one window, outside the design box in z."""
+    pr = W.small_cpml(nx=shape[0], ny=shape[1], nz=shape[2], p=p, T=T, d=d, seed=seed)
+    det = pr.detectors[0]
+    assert not (pr.design_lo[2] <= det.k < pr.design_hi[2])
+    return dataclasses.replace(pr, detectors=[dataclasses.replace(det, weight=0.3),
+                                              dataclasses.replace(det, weight=1.0, interpolate=True, quantity=1)])
+
+
+def test_energy_objective_gradient_parity():
+    pr = energy_grad_problem()
+    announce("energy objective gradient 40x36x44 p=6 T=160")
+    o = Oracle(pr)
+    g, J, _ = o.grad_history()
+    ref = o.deps_design(g)
+    s = _solver(pr, record=True)
+    _, Jg = s.forward()
+    dg, recon = s.grad()
+    torch.cuda.synchronize()
+    assert abs(float(Jg.item()) - J) <= FIELD_TOL * abs(J)
+    assert rel_l2(dg.cpu().numpy(), ref) <= 1e-3
+    g0, _, _ = Oracle(dataclasses.replace(pr, detectors=pr.detectors[:1])).grad_history()
+    assert rel_l2(o.deps_design(g0), ref) > 0.1
+
+
+@pytest.mark.parametrize("shape,p,T,d", [((70, 45, 38), 5, 40, 8), ((16, 16, 16), 3, 60, 4)])
+def test_energy_objective_fused_reverse_bitwise(shape, p, T, d, monkeypatch):
+    pr = energy_grad_problem(shape, p, T, seed=31, d=d)
+    outs = []
+    for naive in (True, False):
+        announce(f"energy objective reverse bitwise {shape} naive={naive}")
+        monkeypatch.setenv("FDTD_NAIVE", "1" if naive else "0")
+        s = _solver(pr, record=True)
         _, J = s.forward()
-        g, _ = s.grad()
+        g, r = s.grad()
         torch.cuda.synchronize()
-        grads.append((J.clone(), g.clone()))
-    assert torch.equal(grads[0][0], grads[1][0])
-    assert torch.equal(grads[0][1], grads[1][1])
-    bad = dataclasses.replace(pr, detectors=[pr.detectors[0], dataclasses.replace(pr.detectors[1], weight=1.0)])
+        outs.append((J.clone(), g.clone(), r.clone()))
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
+
+
+def test_energy_objective_checkpointed_and_design_box_rule():
+    from paper_2412_12360_amd.fdtd import FdtdError, FDTD_E_UNSUPPORTED
+    pr = energy_grad_problem(seed=21)
+    announce("energy objective checkpointed 40x36x44")
+    s = _solver(pr, record=True)
+    _, J = s.forward()
+    g, _ = s.grad()
+    torch.cuda.synchronize()
+    J, g = J.clone(), g.clone()
+    gc, Jc = s.grad_checkpointed(11)
+    torch.cuda.synchronize()
+    assert torch.equal(Jc, J)
+    assert rel_l2(gc.cpu().numpy(), g.cpu().numpy().astype(np.float64)) <= 1e-4
+    # a weighted energy detector on a design-box plane is refused
+    d = pr.detectors[1]
+    bad = dataclasses.replace(pr, detectors=[pr.detectors[0], dataclasses.replace(d, k=pr.design_lo[2] + 1)])
     s = _solver(bad, record=True)
     s.forward()
     with pytest.raises(FdtdError) as ei:
