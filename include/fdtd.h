@@ -193,7 +193,10 @@ fdtd_status fdtd_set_inv_eps(fdtd_handle h, const float *inv_eps);
 /* Zero the fields, PML state and adjoint state; t = 0. */
 fdtd_status fdtd_reset(fdtd_handle h);
 
-/* Release host-side state.  The workspace is the caller's to free. */
+/* Release host-side state (and the handle's side streams and events).  The
+ * workspace is the caller's to free.  The handle is gone even when a HIP
+ * teardown call fails; that failure is reported as FDTD_E_DEVICE with the
+ * message in fdtd_last_error(NULL). */
 fdtd_status fdtd_destroy(fdtd_handle h);
 
 /* Current time step t (host). */

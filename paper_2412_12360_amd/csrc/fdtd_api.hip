@@ -1214,12 +1214,16 @@ fdtd_status fdtd_reset(fdtd_handle h)
 fdtd_status fdtd_destroy(fdtd_handle h)
 {
     if (!h) return FDTD_OK;
+    // release everything, then report the first failure
+    hipError_t first = hipSuccess;
+    auto keep = [&](hipError_t e) { if (first == hipSuccess) first = e; };
     for (int i = 0; i < 3; i++) {
-        if (h->side[i]) hipStreamDestroy(h->side[i]);
-        if (h->join[i]) hipEventDestroy(h->join[i]);
+        if (h->side[i]) keep(hipStreamDestroy(h->side[i]));
+        if (h->join[i]) keep(hipEventDestroy(h->join[i]));
     }
-    if (h->fork) hipEventDestroy(h->fork);
+    if (h->fork) keep(hipEventDestroy(h->fork));
     delete h;
+    if (first != hipSuccess) return fail(nullptr, FDTD_E_DEVICE, "destroy: %s", hipGetErrorString(first));
     return FDTD_OK;
 }
 
