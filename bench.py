@@ -41,16 +41,24 @@ METRIC = "Mcell-updates/s fwd and fwd+grad (FP32, % HBM roofline); p99 latency i
 PEAK_GBS = 8000.0
 # rocprofv3 counter summary of the forward sweep on this workload: HBM bytes
 # per sweep (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy kernel's
-# counters) and the hashes of the sources it was taken on
+# counters) and the hash of the sources it was taken on: the z-march kernel
+# and the tile planner block of the library (shape, time block, tiles, march
+# lengths), which together decide the sweep's traffic
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "fdtd_forward_zmarch_256cube_hbm_traffic.md")
-TRAFFIC_SOURCES = ("paper_2412_12360_amd/csrc/kern_tb.hip", "paper_2412_12360_amd/csrc/fdtd_api.hip")
+TRAFFIC_SOURCES = ("paper_2412_12360_amd/csrc/kern_tb.hip",
+                   "paper_2412_12360_amd/csrc/fdtd_api.hip [tile planner]")
+PLANNER_BEGIN = b"// ------------------------------------------------------------- tile planner"
+PLANNER_END = b"// ------------------------------------------------------ end of tile planner"
 
 
 def source_hash() -> str:
     h = hashlib.sha256()
-    for rel in TRAFFIC_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+    with open(os.path.join(ROOT, "paper_2412_12360_amd/csrc/kern_tb.hip"), "rb") as f:
+        h.update(f.read())
+    with open(os.path.join(ROOT, "paper_2412_12360_amd/csrc/fdtd_api.hip"), "rb") as f:
+        api = f.read()
+    i, j = api.index(PLANNER_BEGIN), api.index(PLANNER_END)
+    h.update(api[i:j])
     return h.hexdigest()
 
 

@@ -277,6 +277,10 @@ void geometry(const fdtd_desc *d, const fdtd_flux_detector *det, int ndet, Geome
     for (int a = 0; a < 3; a++) G.design_cells *= (d->design_hi[a] - d->design_lo[a]);
 }
 
+// ------------------------------------------------------------- tile planner
+// (the workgroup shape, time block, tiles and march lengths: together with
+// the z-march kernel they decide the sweep's memory traffic)
+
 // forward z-march workgroup shape: 0: 16 waves of 64-lane rows (64 x 16
 // tile), 1: 8 waves of 32-lane rows (32 x 16 tile, two workgroups per CU),
 // 2 / 3: rows of 32 + 2K lanes whose owned part is one aligned 128-byte line,
@@ -390,6 +394,8 @@ void build_tiles(const Geometry &G, int K, std::vector<int4> &out, int off[5][4]
         }
     }
 }
+
+// ------------------------------------------------------ end of tile planner
 
 long long interior_cells(const Geometry &G)
 {
