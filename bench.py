@@ -260,10 +260,11 @@ def serving_bench(count: int, torch, seed_rate: float = 0.8, budget_gb: float = 
     kinds = {rid: k for (rid, _, k, _) in descs}
     budget = int(budget_gb * 1e9) if budget_gb > 0 else int(torch.cuda.mem_get_info()[0] * 0.8)
 
-    def run(max_active, streams, arrivals=None):
+    def run(max_active, streams, arrivals=None, limit=None):
+        rids = sorted(probs)[:limit]
         reqs = [serve.Request(rid=rid, kind=kinds[rid], problem=probs[rid],
                               arrival=0.0 if arrivals is None else arrivals[i])
-                for i, rid in enumerate(sorted(probs))]
+                for i, rid in enumerate(rids)]
         sch = serve.Scheduler(serve.GpuExecutor(n_streams=streams), budget_bytes=budget,
                               max_active=max_active, chunk=64)
         t0 = time.perf_counter()
@@ -274,15 +275,25 @@ def serving_bench(count: int, torch, seed_rate: float = 0.8, budget_gb: float = 
         out["peak_hbm_gb"] = round(sch.peak_in_use / 1e9, 2)
         return out
 
-    run(1, 1)                                   # warm-up (code objects, allocator)
+    t_start = time.perf_counter()
+
+    def log(msg):   # one line per phase (a long mix runs for minutes)
+        print(f"[serving] {msg} ({time.perf_counter() - t_start:.0f} s)", file=sys.stderr, flush=True)
+
+    run(1, 1, limit=8)                          # warm-up (code objects, allocator)
+    log("warm-up done")
     seq = run(1, 1)
+    log(f"one at a time: {seq['req_per_s']:.3f} req/s")
     bat = run(16, 8)
+    log(f"batched: {bat['req_per_s']:.3f} req/s")
     rate = seed_rate * seq["req_per_s"]
     import numpy as np
     rng = np.random.Generator(np.random.PCG64(8))
     arr = list(np.cumsum(rng.exponential(1.0 / rate, size=count)))
     seq_open = run(1, 1, arr)
+    log(f"open loop, one at a time: p99 {seq_open['p99_latency_s']:.3f} s")
     bat_open = run(16, 8, arr)
+    log(f"open loop, batched: p99 {bat_open['p99_latency_s']:.3f} s")
     r = lambda v: None if v is None else round(v, 4)
     return {
         "workload": f"{count} requests of the serving mix (edges U{{64..256}} per axis, 50% gradient, "
