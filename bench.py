@@ -247,7 +247,8 @@ def copy_calibration(torch, nbytes: int = 1 << 30, reps: int = 4):
     print(json.dumps({"copy_calibration_bytes": nbytes, "reps": reps}), flush=True)
 
 
-def serving_bench(count: int, torch, seed_rate: float = 0.8, budget_gb: float = 0.0):
+def serving_bench(count: int, torch, seed_rate: float = 0.8, budget_gb: float = 0.0, max_active: int = 6,
+                  streams: int = 6):
     """Serving mix: `count` requests of the Poisson mix recipe (edges U{64..256},
     50% forward / 50% gradient, T = 8 x max edge, CPML 8).  Measures saturation
     throughput one-at-a-time and with continuous batching (all queued at t=0),
@@ -284,7 +285,7 @@ def serving_bench(count: int, torch, seed_rate: float = 0.8, budget_gb: float = 
     log("warm-up done")
     seq = run(1, 1)
     log(f"one at a time: {seq['req_per_s']:.3f} req/s")
-    bat = run(16, 8)
+    bat = run(max_active, streams)
     log(f"batched: {bat['req_per_s']:.3f} req/s")
     rate = seed_rate * seq["req_per_s"]
     import numpy as np
@@ -292,7 +293,7 @@ def serving_bench(count: int, torch, seed_rate: float = 0.8, budget_gb: float = 
     arr = list(np.cumsum(rng.exponential(1.0 / rate, size=count)))
     seq_open = run(1, 1, arr)
     log(f"open loop, one at a time: p99 {seq_open['p99_latency_s']:.3f} s")
-    bat_open = run(16, 8, arr)
+    bat_open = run(max_active, streams, arr)
     log(f"open loop, batched: p99 {bat_open['p99_latency_s']:.3f} s")
     r = lambda v: None if v is None else round(v, 4)
     return {
@@ -308,6 +309,7 @@ def serving_bench(count: int, torch, seed_rate: float = 0.8, budget_gb: float = 
         "batched_open": {"p50_s": r(bat_open["p50_latency_s"]), "p99_s": r(bat_open["p99_latency_s"])},
         "speedup_throughput": r(bat["throughput_mcell_steps_s"] / seq["throughput_mcell_steps_s"]),
         "hbm_budget_gb": round(budget / 1e9, 1),
+        "max_active": max_active, "streams": streams,
     }
 
 
@@ -327,6 +329,10 @@ def main():
                     help="profiling runs only: time steps per solve instead of the workload's (0 = workload)")
     ap.add_argument("--large", action="store_true",
                     help="also run the 640x640x400 forward+gradient problem (CPML 12, 4000 steps)")
+    ap.add_argument("--serving-max-active", type=int, default=6,
+                    help="requests on the GPU at once in the batched runs (6 measured best on a "
+                         "200-request mix: more sharing lengthens the largest requests)")
+    ap.add_argument("--serving-streams", type=int, default=6)
     ap.add_argument("--serving-budget-gb", type=float, default=0.0,
                     help="HBM budget for the serving mix (0 = 80%% of free memory)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -425,7 +431,8 @@ def main():
                                              "seed 5), eps_r = 2.25 + 10 rho, 4000 steps, interface record in HBM")
 
     if args.serving > 0:
-        out["serving"] = serving_bench(args.serving, torch, budget_gb=args.serving_budget_gb)
+        out["serving"] = serving_bench(args.serving, torch, budget_gb=args.serving_budget_gb,
+                                       max_active=args.serving_max_active, streams=args.serving_streams)
 
     if rank == 0 and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pr)
