@@ -161,6 +161,31 @@ def interp_detector_run(pr, Solver, torch, time_block: int, steps: int):
     }
 
 
+def shard_run(Solver, torch, time_block: int, steps: int, W, T: int = 100):
+    """The forward step on one GPU's share of a 2400x1600x600 grid cut into
+    four z-slabs (2400x1600x150, 576M cells, 12-cell CPML on all six faces):
+    the field set spans 13.8 GB, so the z-march runs with a 64-bit base per
+    component and plane.  A bounded sample of T steps per solve."""
+    pr = W.shard_slab(T=T)
+    s = Solver(pr, record=False, time_block=time_block)
+    path = s.kernel_path
+    s.reset()
+    s.forward()
+    ms = time_solves(s, steps, torch)
+    fp = s.footprint
+    del s
+    torch.cuda.empty_cache()
+    return {
+        "workload": f"{pr.nx}x{pr.ny}x{pr.nz} z-slab (one of four of a {pr.nx}x{pr.ny}x{4 * pr.nz} grid), "
+                    f"CPML {pr.p} on all six faces, Ex sheet, flux detector, {T} steps per solve",
+        "value": round(pr.N * T * steps / (ms / 1e3) / 1e6, 1),
+        "unit": "Mcell-updates/s",
+        "ms_per_step": round(ms / steps / T, 3),
+        "kernel_path": path,
+        "footprint_gb": round(fp / 1e9, 2),
+    }
+
+
 def fwd_grad_run(pg, Solver, torch, time_block: int, workload: str, checkpoint: bool = False):
     """One warm-up solve, then a timed forward (with the interface record)
     and gradient on the solver's stream: N*T / (t_fwd + t_bwd)."""
@@ -323,6 +348,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the TFSF-source and interpolated-detector variants of the forward workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-shard", action="store_true",
+                    help="skip the forward step on one z-slab of a 2400x1600x600 grid (2400x1600x150)")
     ap.add_argument("--serving", type=int, default=12,
                     help="requests of the serving mix to run (0 = skip; the first requests of the 500-request mix)")
     ap.add_argument("--solve-steps", type=int, default=0,
@@ -416,6 +443,10 @@ def main():
     if not args.no_variants:
         out["tfsf"] = tfsf_run(pr, Solver, torch, args.time_block, args.steps, W)
         out["interpolated_detector"] = interp_detector_run(pr, Solver, torch, args.time_block, args.steps)
+
+    if not args.no_shard:
+        out["shard"] = shard_run(Solver, torch, args.time_block, args.steps, W,
+                                 T=args.solve_steps if args.solve_steps else 100)
 
     if not args.no_grad:
         pg = W.config3(T=args.solve_steps) if args.solve_steps else W.config3()

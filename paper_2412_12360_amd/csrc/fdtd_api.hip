@@ -91,6 +91,7 @@ struct fdtd_ctx {
     unsigned fstride, pstride[3];   // z-march addressing: bytes between arrays of one set
     float4 *profv[3];
     bool naive = false;                    // per-cell kernels instead of the z-march
+    bool wide = false;                     // forward z-march with 64-bit component bases
     hipStream_t side[3] = {nullptr, nullptr, nullptr};   // concurrent tile classes (default priority)
     hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
     int shape = 0;                         // z-march workgroup shape
@@ -607,7 +608,7 @@ fdtd_status steps_tb(fdtd_ctx *h, int n0, int kk, int with_src, int with_rec, in
         if (a.ntiles == 0) continue;
         hipStream_t st = (par && c > 0) ? h->side[c - 1] : h->stream;
         if (st != h->stream) HIPCHK(h, hipStreamWaitEvent(st, h->fork, 0));
-        HIPCHK(h, launch_tb_forward_class(a, kk, c, h->shape, st));
+        HIPCHK(h, launch_tb_forward_class(a, kk, c, h->shape, h->wide, st));
         if (st != h->stream) {
             HIPCHK(h, hipEventRecord(h->join[c - 1], st));
             HIPCHK(h, hipStreamWaitEvent(h->stream, h->join[c - 1], 0));
@@ -821,12 +822,13 @@ fdtd_status fdtd_create(const fdtd_desc *desc, const fdtd_source *src, int32_t n
         // (the adjoint sets, when present, must have the same spacing: the
         // fused reverse march addresses them the same way)
         unsigned f0 = 0, f1 = 0;
-        bool ok = stride_of(h->fld[0], 6, f0) && stride_of(h->fld[1], 6, f1) && f0 == f1;
+        bool fok = stride_of(h->fld[0], 6, f0) && stride_of(h->fld[1], 6, f1) && f0 == f1;
         if (desc->record) {
             unsigned a0 = 0, a1 = 0;
-            ok = ok && stride_of(h->adj[0], 6, a0) && stride_of(h->adj[1], 6, a1) && a0 == f0 && a1 == f0;
+            fok = fok && stride_of(h->adj[0], 6, a0) && stride_of(h->adj[1], 6, a1) && a0 == f0 && a1 == f0;
         }
         h->fstride = f0;
+        bool ok = true;
         for (int a = 0; a < 3; a++) {
             h->pstride[a] = 0;
             if (h->geo.p > 0) {
@@ -839,7 +841,18 @@ fdtd_status fdtd_create(const fdtd_desc *desc, const fdtd_source *src, int32_t n
                 h->pstride[a] = p0;
             }
         }
-        if (!ok) h->naive = true;
+        // A field set of 4 GiB or more (above about 179M cells) runs the
+        // forward march with a 64-bit base per component and plane, offsets
+        // within one plane still 32-bit; the fused reverse march has no such
+        // instance, so a recording handle of that size, like any other
+        // addressing misfit, takes the per-cell kernels.
+        const bool wide_ok = !desc->record && tb_wide_shape(h->shape) &&
+                             (unsigned long long)h->geo.nx * (unsigned long long)h->geo.ny * 4ull < (1ull << 32);
+        const char *ew = getenv("FDTD_TB_WIDE");   // tests: the wide instance on any size
+        const bool force_wide = ew && atoi(ew) != 0 && wide_ok;
+        if (!ok || (!fok && !wide_ok)) h->naive = true;
+        else if (!fok || force_wide) h->wide = true;
+        if (h->naive) h->wide = false;
     }
 
     // device problem description
@@ -1002,7 +1015,8 @@ fdtd_status fdtd_inverse(fdtd_handle h, int32_t n_steps)
     if (n_steps < 0 || n_steps > h->t) return fail(h, FDTD_E_STATE, "cannot undo %d steps at t = %d", n_steps, h->t);
     if (h->geo.p > 0 && !h->desc.record) return fail(h, FDTD_E_STATE, "inverse with a PML needs record = 1");
     for (int s = 0; s < n_steps; s++) {
-        fdtd_status st = h->naive ? reverse_step(h, h->t - 1, 0) : reverse_fused(h, h->t - 1, 1, 0, 0, nullptr);
+        fdtd_status st = (h->naive || h->wide) ? reverse_step(h, h->t - 1, 0)
+                                               : reverse_fused(h, h->t - 1, 1, 0, 0, nullptr);
         if (st != FDTD_OK) return st;
         h->t -= 1;
     }
@@ -1312,6 +1326,13 @@ fdtd_status fdtd_time_block(fdtd_handle h, int32_t *K)
 {
     if (!h || !K) return fail(h, FDTD_E_INVALID, "NULL argument");
     *K = h->K;
+    return FDTD_OK;
+}
+
+fdtd_status fdtd_kernel_path(fdtd_handle h, int32_t *path)
+{
+    if (!h || !path) return fail(h, FDTD_E_INVALID, "NULL argument");
+    *path = h->naive ? 0 : h->wide ? 2 : 1;
     return FDTD_OK;
 }
 

@@ -198,10 +198,13 @@ struct TbArgs {
 };
 // one sweep of K steps over the tiles of class cls (bit 0: an x CPML slab in
 // the halo-extended footprint, bit 1: a y slab)
-hipError_t launch_tb_forward_class(const TbArgs &a, int K, int cls, int shape, hipStream_t s);
+// (wide: the instance with a 64-bit base per component and plane, for field
+// sets of 4 GiB or more; fstride is unused there)
+hipError_t launch_tb_forward_class(const TbArgs &a, int K, int cls, int shape, bool wide, hipStream_t s);
 int tb_tile_x(int K, int shape);
 int tb_tile_y(int K, int shape);
 bool tb_tile_aligned(int shape);   // x tiles start on 128-byte lines (uniform split)
+bool tb_wide_shape(int shape);     // the wide instance exists for this shape
 int tb_max_pml();
 
 // fused reverse step (inverse + adjoint) as a z-march, tile halo rev_halo()

@@ -19,8 +19,11 @@
 // halo-extended footprint; each class is its own instance so interior tiles
 // carry no x/y auxiliary registers.  z-slab planes are handled in every tile.
 //
-// Cost notes: cell addresses are 32-bit element offsets (one uniform plane
-// base plus one per-row offset), the conducting-wall rule is folded into the
+// Cost notes: cell addresses are 32-bit byte offsets from one base per field
+// set (one uniform plane term plus one per-row offset; grids whose field set
+// spans 4 GiB or more take the WIDE instance instead: a 64-bit uniform base
+// per component and plane, 32-bit offsets within the plane), the
+// conducting-wall rule is folded into the
 // update coefficient (a held component gets coefficient 0, which leaves it
 // bit-for-bit unchanged), and records, detectors and sources are gated by
 // uniform plane tests so the common plane pays nothing for them.
@@ -86,7 +89,7 @@ __device__ __forceinline__ float cpml_term_h(float d, float &psi, float b, float
 
 // TX lanes of a wave row span x; W waves; R rows per thread.  The register
 // budget allows 4 waves per SIMD (two workgroups per CU at 512 threads).
-template <int K, bool XP, bool YP, int PD, int W, int R, int TX>
+template <int K, bool XP, bool YP, int PD, int W, int R, int TX, bool WIDE>
 __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
 {
     constexpr int EX = TX;
@@ -165,18 +168,42 @@ __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
     const float *__restrict__ ice = A.g.ce;
     const unsigned fs = A.fstride;
 
+    // Arguments used only now and then are read through a copy of the
+    // argument pointer that is made opaque on every plane, so they are fetched
+    // where they are used instead of being held in scalar registers for the
+    // whole march (the argument block is the kernel's only parameter, at
+    // offset 0 of the kernel-argument segment): the source arguments, and the
+    // component bases of the WIDE instance.
+    typedef const __attribute__((address_space(4))) TbArgs KArgs;
+    KArgs *Kp = (KArgs *)__builtin_amdgcn_kernarg_segment_ptr();
+
     auto load_plane = [&](int t, Plane<R, XP, YP> &P) {
         const bool tin = t >= 0 && t < nz;
-        const unsigned base = (unsigned)(tin ? t : 0) * nxy;
+        if constexpr (WIDE) {
+            const size_t pb = (size_t)(tin ? t : 0) * (size_t)Kp->g.nxy;
 #pragma unroll
-        for (int r = 0; r < R; r++) {
-            const unsigned c = (base + off[r]) * 4u;
-            // raw values: columns and planes outside the grid are zeroed where
-            // the plane is consumed, so the fetch stays in flight until then
-            P.e[r][0] = ldo(iF, c); P.e[r][1] = ldo(iF, c + fs); P.e[r][2] = ldo(iF, c + 2 * fs);
-            P.h[r][0] = ldo(iF, c + 3 * fs); P.h[r][1] = ldo(iF, c + 4 * fs); P.h[r][2] = ldo(iF, c + 5 * fs);
-            P.ce[r] = ldo(ice, c);
-            psi_zero<XP, YP>(P.p[r]);
+            for (int r = 0; r < R; r++) {
+                const unsigned c = off[r] * 4u;
+#pragma unroll
+                for (int q = 0; q < 3; q++) {
+                    P.e[r][q] = ldo(Kp->in.c[q] + pb, c);
+                    P.h[r][q] = ldo(Kp->in.c[3 + q] + pb, c);
+                }
+                P.ce[r] = ldo(Kp->g.ce + pb, c);
+                psi_zero<XP, YP>(P.p[r]);
+            }
+        } else {
+            const unsigned base = (unsigned)(tin ? t : 0) * nxy;
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                const unsigned c = (base + off[r]) * 4u;
+                // raw values: columns and planes outside the grid are zeroed where
+                // the plane is consumed, so the fetch stays in flight until then
+                P.e[r][0] = ldo(iF, c); P.e[r][1] = ldo(iF, c + fs); P.e[r][2] = ldo(iF, c + 2 * fs);
+                P.h[r][0] = ldo(iF, c + 3 * fs); P.h[r][1] = ldo(iF, c + 4 * fs); P.h[r][2] = ldo(iF, c + 5 * fs);
+                P.ce[r] = ldo(ice, c);
+                psi_zero<XP, YP>(P.p[r]);
+            }
         }
         if (p > 0 && tin) {
             const int szt = slab_coord(t, nz, p);
@@ -218,13 +245,8 @@ __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
     int skq[FD_MAXSRC];
 #pragma unroll
     for (int q = 0; q < FD_MAXSRC; q++) skq[q] = (A.with_src && q < A.g.nsrc) ? A.g.sk[q] : (-2147483647 - 1);
-    // The other source arguments are read through a copy of the argument
-    // pointer that is made opaque on every plane, so they are fetched on a
-    // source plane instead of being held in scalar registers for the whole
-    // march (the argument block is the kernel's only parameter, at offset 0
-    // of the kernel-argument segment).
-    typedef const __attribute__((address_space(4))) TbArgs KArgs;
-    KArgs *Kp = (KArgs *)__builtin_amdgcn_kernarg_segment_ptr();
+    // The other source arguments are read through the opaque argument
+    // pointer Kp (below).
 
     // pipeline registers: Eo[s], Ho[s]/Hc[s], Po[s] = output of level s at the
     // plane level s+1 works on next; Ho[K] = last Hx, Hy of level K; cd[s] =
@@ -517,16 +539,30 @@ __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
             Ho[K][r][1] = nH[r][1];
         }
         if (kK >= z0 && kK < z1) {
-            const unsigned base = (unsigned)kK * nxy;
-            float *__restrict__ oF = A.out.c[0];
+            if constexpr (WIDE) {
+                const size_t pb = (size_t)kK * (size_t)Kp->g.nxy;
 #pragma unroll
-            for (int r = 0; r < R; r++) {
-                if (!own[r]) continue;
-                const unsigned c = (base + off[r]) * 4u;
+                for (int r = 0; r < R; r++) {
+                    if (!own[r]) continue;
+                    const unsigned c = off[r] * 4u;
 #pragma unroll
-                for (int q = 0; q < 3; q++) {
-                    sto(oF, c + q * fs, nE[r][q]);
-                    sto(oF, c + (3 + q) * fs, nH[r][q]);
+                    for (int q = 0; q < 3; q++) {
+                        sto(Kp->out.c[q] + pb, c, nE[r][q]);
+                        sto(Kp->out.c[3 + q] + pb, c, nH[r][q]);
+                    }
+                }
+            } else {
+                const unsigned base = (unsigned)kK * nxy;
+                float *__restrict__ oF = A.out.c[0];
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    if (!own[r]) continue;
+                    const unsigned c = (base + off[r]) * 4u;
+#pragma unroll
+                    for (int q = 0; q < 3; q++) {
+                        sto(oF, c + q * fs, nE[r][q]);
+                        sto(oF, c + (3 + q) * fs, nH[r][q]);
+                    }
                 }
             }
             if (p > 0) {
@@ -588,16 +624,16 @@ __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
     }
 }
 
-template <int K, int W, int R, int PD, int TX>
+template <int K, int W, int R, int PD, int TX, bool WIDE = false>
 hipError_t launch_kwrp(const TbArgs &a, int cls, hipStream_t s)
 {
     constexpr int threads = 64 * W;
     if (a.ntiles <= 0) return hipSuccess;
     switch (cls) {
-    case 0: hipLaunchKernelGGL((k_tb_forward<K, false, false, PD, W, R, TX>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
-    case 1: hipLaunchKernelGGL((k_tb_forward<K, true, false, PD, W, R, TX>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_tb_forward<K, false, true, PD, W, R, TX>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_tb_forward<K, true, true, PD, W, R, TX>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
+    case 0: hipLaunchKernelGGL((k_tb_forward<K, false, false, PD, W, R, TX, WIDE>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_tb_forward<K, true, false, PD, W, R, TX, WIDE>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_tb_forward<K, false, true, PD, W, R, TX, WIDE>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_tb_forward<K, true, true, PD, W, R, TX, WIDE>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
     }
     return hipGetLastError();
 }
@@ -616,11 +652,15 @@ constexpr int NSHAPE = 4;
 constexpr int SHAPE_W[NSHAPE] = {16, 8, 16, 8};
 constexpr int SHAPE_R[NSHAPE] = {1, 1, 1, 1};
 constexpr int ALIGN_X = 32;   // floats per 128-byte line
+constexpr int TB_WIDE_SHAPE = 3;
 __host__ __device__ constexpr int shape_tx(int sh, int K) { return sh == 0 ? 64 : sh == 1 ? 32 : ALIGN_X + 2 * K; }
 
 template <int K>
-hipError_t launch_k(const TbArgs &a, int cls, int shape, hipStream_t s)
+hipError_t launch_k(const TbArgs &a, int cls, int shape, bool wide, hipStream_t s)
 {
+    // the 64-bit-base instance exists for the default shape only
+    if (wide) return shape == TB_WIDE_SHAPE ? launch_kwrp<K, 8, 1, 1, ALIGN_X + 2 * K, true>(a, cls, s)
+                                            : hipErrorInvalidValue;
     switch (shape) {
     case 0: return launch_kwrp<K, 16, 1, 1, 64>(a, cls, s);
     case 2: return launch_kwrp<K, 16, 1, 1, ALIGN_X + 2 * K>(a, cls, s);
@@ -641,16 +681,17 @@ int tb_tile_y(int K, int shape)
     return (64 * SHAPE_W[sh] / shape_tx(sh, K)) * SHAPE_R[sh] - 2 * K;
 }
 bool tb_tile_aligned(int shape) { return shape_index(shape) >= 2; }
+bool tb_wide_shape(int shape) { return shape_index(shape) == TB_WIDE_SHAPE; }
 
 // Tiles of class cls: bit 0 = x CPML slab in the extended footprint, bit 1 = y.
-hipError_t launch_tb_forward_class(const TbArgs &a, int K, int cls, int shape, hipStream_t s)
+hipError_t launch_tb_forward_class(const TbArgs &a, int K, int cls, int shape, bool wide, hipStream_t s)
 {
     shape = shape_index(shape);
     switch (K) {
-    case 1: return launch_k<1>(a, cls, shape, s);
-    case 2: return launch_k<2>(a, cls, shape, s);
-    case 3: return launch_k<3>(a, cls, shape, s);
-    case 4: return launch_k<4>(a, cls, shape, s);
+    case 1: return launch_k<1>(a, cls, shape, wide, s);
+    case 2: return launch_k<2>(a, cls, shape, wide, s);
+    case 3: return launch_k<3>(a, cls, shape, wide, s);
+    case 4: return launch_k<4>(a, cls, shape, wide, s);
     default: return hipErrorInvalidValue;
     }
 }

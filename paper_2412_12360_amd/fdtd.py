@@ -53,7 +53,7 @@ ENTRY_POINTS = [
     "fdtd_footprint", "fdtd_create", "fdtd_forward", "fdtd_inverse", "fdtd_grad", "fdtd_set_inv_eps",
     "fdtd_reset", "fdtd_destroy", "fdtd_time", "fdtd_last_error", "fdtd_field_ptr", "fdtd_state_arrays",
     "fdtd_linear_steps", "fdtd_record_ptr", "fdtd_time_block", "fdtd_checkpoint_bytes",
-    "fdtd_grad_checkpointed",
+    "fdtd_grad_checkpointed", "fdtd_kernel_path",
 ]
 
 _lib = None
@@ -93,6 +93,7 @@ def lib():
     L.fdtd_linear_steps.argtypes = [H, C.c_int32, C.c_int32]
     L.fdtd_record_ptr.argtypes = [H, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_size_t)]
     L.fdtd_time_block.argtypes = [H, C.POINTER(C.c_int32)]
+    L.fdtd_kernel_path.argtypes = [H, C.POINTER(C.c_int32)]
     for name in ENTRY_POINTS:
         if name != "fdtd_last_error":
             getattr(L, name).restype = C.c_int
@@ -295,6 +296,15 @@ class Solver:
         v = C.c_int32(0)
         check(lib().fdtd_time_block(self.handle, C.byref(v)), self.handle)
         return int(v.value)
+
+    @property
+    def kernel_path(self) -> str:
+        """Kernels the forward step runs on: "per-cell", "z-march" (32-bit
+        offsets from one base per field set) or "z-march-wide" (a 64-bit base
+        per component and plane, for field sets of 4 GiB or more)."""
+        v = C.c_int32(0)
+        check(lib().fdtd_kernel_path(self.handle, C.byref(v)), self.handle)
+        return ("per-cell", "z-march", "z-march-wide")[v.value]
 
     def field(self, comp: int, which: int = 0):
         """Device view [nz, ny, nx] of field component comp (0..5) of the

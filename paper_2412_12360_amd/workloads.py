@@ -140,10 +140,11 @@ def eps_from_rho(rho: np.ndarray) -> np.ndarray:
 
 # ------------------------------------------------------------------- configs
 
-def _sheet_problem(name, nx, ny, nz, p, T, eps, eps_bg, design_lo, design_hi, rho=None):
+def _sheet_problem(name, nx, ny, nz, p, T, eps, eps_bg, design_lo, design_hi, rho=None, inv=None):
     S = courant()
     m, sig, kap, alp = pml_grading(S, eps_bg)
-    inv = (1.0 / eps).astype(np.float32)
+    if inv is None:
+        inv = (1.0 / eps).astype(np.float32)
     src = Source(kind=1, comp=0, i=0, j=0, k=p + 2, amp=ramped_sine(T, S))
     det = Detector(k=nz - p - 3, i0=p, i1=nx - p, j0=p, j1=ny - p, weight=1.0)
     return Problem(name=name, nx=nx, ny=ny, nz=nz, S=S, p=p, pml_m=m, pml_sigma_max=sig,
@@ -223,6 +224,24 @@ def config4(T: int = 4000, nx: int = 640, ny: int = 640, nz: int = 400, p: int =
     eps = np.full((nz, ny, nx), 2.25, np.float32)
     eps[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] = eps_from_rho(rho)
     return _sheet_problem(f"c4_large{nx}x{ny}x{nz}", nx, ny, nz, p, T, eps, 2.25, lo, hi, rho=rho)
+
+
+def shard_slab(T: int = 100, nx: int = 2400, ny: int = 1600, nz: int = 150, p: int = 12) -> Problem:
+    """One GPU's share of a 2400x1600x600 grid (about 2.3e9 cells, the size
+    the paper's largest runs reach) cut into four z-slabs: 2400x1600x150 with a
+    12-cell CPML on all six faces (a slab of a decomposed grid has it on the x
+    and y faces only, and exchanges one plane with each z neighbour instead),
+    background eps_r 2.25 with a centred half-edge block of per-cell
+    eps_r ~ U[2.25, 12.25] (seed 9); Ex sheet source and flux detector as in
+    the other configurations.  1/eps_r is built directly in FP32 (the field
+    set alone is 13.8 GB)."""
+    rng = np.random.Generator(np.random.PCG64(9))
+    lo = (nx // 4, ny // 4, nz // 4)
+    hi = (lo[0] + nx // 2, lo[1] + ny // 2, lo[2] + nz // 2)
+    inv = np.full((nz, ny, nx), 1.0 / 2.25, np.float32)
+    block = rng.uniform(2.25, 12.25, size=(hi[2] - lo[2], hi[1] - lo[1], hi[0] - lo[0]))
+    inv[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] = 1.0 / block
+    return _sheet_problem(f"shard{nx}x{ny}x{nz}", nx, ny, nz, p, T, None, 2.25, lo, hi, inv=inv)
 
 
 def small_cpml(nx=40, ny=36, nz=44, p=6, T=160, d=8, seed=11, name="small_cpml") -> Problem:

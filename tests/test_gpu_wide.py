@@ -1,0 +1,110 @@
+"""Forward z-march with a 64-bit base per component and plane, the instance a
+non-recording handle runs when one field set spans 4 GiB or more (above
+about 179M cells), through the C ABI:
+  - forced onto small ragged grids (FDTD_TB_WIDE), it gives the bits of the
+    32-bit-offset instance at every time-block size, with the one-sided
+    plane wave, an H point source, a plain and an interpolated flux detector;
+  - on a PEC box its fdtd_inverse (per-cell reverse kernels) gives the bits
+    of the fused reverse march;
+  - at full size, one GPU's z-slab of a 2400x1600x600 grid (2400x1600x150,
+    576M cells, 12-cell CPML), it is chosen by itself and gives the bits of
+    the per-cell kernels.
+All comparisons are bitwise: the instances differ only in addressing.
+"""
+import dataclasses
+
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2412_12360_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(*a, **k):
+    from paper_2412_12360_amd.fdtd import Solver
+    return Solver(*a, **k)
+
+
+def announce(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+def problem(shape, p, T):
+    pr = W.with_tfsf(W.small_cpml(nx=shape[0], ny=shape[1], nz=shape[2], p=p, T=T, d=8, seed=21))
+    q = W.Source(kind=0, comp=4, i=pr.nx // 3, j=pr.ny // 2 + 1, k=pr.nz // 2 + 3,
+                 amp=W.gaussian_pulse(pr.T, 16, 5))
+    d0 = pr.detectors[0]
+    d1 = dataclasses.replace(d0, k=d0.k - 2, i0=d0.i0 + 1, j0=d0.j0 + 2, weight=0.5, interpolate=True)
+    return dataclasses.replace(pr, sources=list(pr.sources) + [q], detectors=[d0, d1])
+
+
+def run(pr, K, wide, monkeypatch, naive=False):
+    monkeypatch.setenv("FDTD_TB_WIDE", "1" if wide else "0")
+    monkeypatch.setenv("FDTD_NAIVE", "1" if naive else "0")
+    s = _solver(pr, record=False, time_block=K)
+    want = "per-cell" if naive else ("z-march-wide" if wide else "z-march")
+    assert s.kernel_path == want
+    tr, J = s.forward()
+    torch.cuda.synchronize()
+    return s, {
+        "fields": torch.stack([f.clone() for f in s.fields()]),
+        "psi": [a.clone() for a in s.state_arrays(0)[6:]],
+        "trace": tr.clone(),
+        "J": J.clone(),
+    }
+
+
+@pytest.mark.parametrize("shape,p,T", [((70, 45, 38), 5, 37), ((33, 61, 70), 6, 30), ((40, 36, 44), 0, 25)])
+def test_wide_instance_bitwise_all_K(shape, p, T, monkeypatch):
+    pr = problem(shape, p, T) if p > 0 else W.config1(T=T, n=shape[0])
+    for K in (1, 2, 3, 4):
+        announce(f"wide vs narrow z-march {shape} p={p} T={T} K={K}")
+        _, ref = run(pr, K, False, monkeypatch)
+        _, out = run(pr, K, True, monkeypatch)
+        assert torch.equal(out["fields"], ref["fields"])
+        for x, y in zip(out["psi"], ref["psi"]):
+            assert torch.equal(x, y)
+        assert torch.equal(out["trace"], ref["trace"])
+        assert torch.equal(out["J"], ref["J"])
+
+
+def test_wide_inverse_on_pec_box(monkeypatch):
+    pr = W.config1(T=60)
+    announce("wide forward + per-cell inverse on the 32^3 PEC box")
+    outs = []
+    for wide in (False, True):
+        s, _ = run(pr, 2, wide, monkeypatch)
+        s.inverse(pr.T // 2)
+        torch.cuda.synchronize()
+        outs.append(torch.stack([f.clone() for f in s.fields()]))
+    assert torch.equal(outs[0], outs[1])
+
+
+def test_wide_chosen_and_bitwise_at_shard_size(monkeypatch):
+    """2400x1600x150 (the field set is 13.8 GB): four steps of the wide
+    z-march against four steps of the per-cell kernels."""
+    pr = W.shard_slab(T=4)
+    announce("wide z-march at 2400x1600x150, 4 steps")
+    monkeypatch.delenv("FDTD_TB_WIDE", raising=False)
+    monkeypatch.setenv("FDTD_NAIVE", "0")
+    s = _solver(pr, record=False, time_block=2)
+    assert s.kernel_path == "z-march-wide"
+    tr, J = s.forward()
+    torch.cuda.synchronize()
+    wide = [f.clone() for f in s.fields()]
+    tw, Jw = tr.clone(), J.clone()
+    del s, tr, J
+    torch.cuda.empty_cache()
+    announce("per-cell kernels at 2400x1600x150, 4 steps")
+    monkeypatch.setenv("FDTD_NAIVE", "1")
+    s = _solver(pr, record=False, time_block=2)
+    assert s.kernel_path == "per-cell"
+    tr, J = s.forward()
+    torch.cuda.synchronize()
+    assert float(wide[0].abs().max().item()) > 0.0
+    for a, b in zip(wide, s.fields()):
+        assert torch.equal(a, b)
+    assert torch.equal(tw, tr)
+    assert torch.equal(Jw, J)
