@@ -234,13 +234,12 @@ fdtd_status fdtd_record_ptr(fdtd_handle h, int32_t n, float **dev, size_t *float
 /* Time-block size K actually used (host). */
 fdtd_status fdtd_time_block(fdtd_handle h, int32_t *K);
 
-/* Kernels the forward step runs on (host): 0 = per-cell kernels (a CPML
- * thicker than the z-march stages, a recording handle whose field set spans
- * 4 GiB or more, or FDTD_NAIVE); 1 = the z-march with 32-bit offsets from one
- * base per field set; 2 = the z-march with a 64-bit base per component and
- * plane (a non-recording handle whose field set spans 4 GiB or more; its
- * fdtd_inverse runs the per-cell reverse kernels).  All three give the same
- * bits. */
+/* Kernels the forward and reverse steps run on (host): 0 = per-cell kernels
+ * (a CPML thicker than the z-march stages, or FDTD_NAIVE); 1 = the forward
+ * and reverse z-marches with 32-bit offsets from one base per field set;
+ * 2 = the same marches with a 64-bit base per component and plane (a field
+ * set of 4 GiB or more; fdtd_grad_checkpointed then returns
+ * FDTD_E_UNSUPPORTED).  All three give the same bits. */
 fdtd_status fdtd_kernel_path(fdtd_handle h, int32_t *path);
 
 #ifdef __cplusplus

@@ -706,7 +706,7 @@ fdtd_status reverse_fused(fdtd_ctx *h, int n, int do_inv, int do_adj, int with_d
         if (a.ntiles == 0) continue;
         hipStream_t st = (par && c > 0) ? h->side[c - 1] : h->stream;
         if (st != h->stream) HIPCHK(h, hipStreamWaitEvent(st, h->fork, 0));
-        HIPCHK(h, launch_tb_reverse_class(a, c, st));
+        HIPCHK(h, launch_tb_reverse_class(a, c, h->wide, st));
         if (st != h->stream) {
             HIPCHK(h, hipEventRecord(h->join[c - 1], st));
             HIPCHK(h, hipStreamWaitEvent(h->stream, h->join[c - 1], 0));
@@ -842,11 +842,10 @@ fdtd_status fdtd_create(const fdtd_desc *desc, const fdtd_source *src, int32_t n
             }
         }
         // A field set of 4 GiB or more (above about 179M cells) runs the
-        // forward march with a 64-bit base per component and plane, offsets
-        // within one plane still 32-bit; the fused reverse march has no such
-        // instance, so a recording handle of that size, like any other
-        // addressing misfit, takes the per-cell kernels.
-        const bool wide_ok = !desc->record && tb_wide_shape(h->shape) &&
+        // forward and the fused reverse march with a 64-bit base per
+        // component and plane, offsets within one plane still 32-bit; any
+        // other addressing misfit takes the per-cell kernels.
+        const bool wide_ok = tb_wide_shape(h->shape) &&
                              (unsigned long long)h->geo.nx * (unsigned long long)h->geo.ny * 4ull < (1ull << 32);
         const char *ew = getenv("FDTD_TB_WIDE");   // tests: the wide instance on any size
         const bool force_wide = ew && atoi(ew) != 0 && wide_ok;
@@ -1015,8 +1014,7 @@ fdtd_status fdtd_inverse(fdtd_handle h, int32_t n_steps)
     if (n_steps < 0 || n_steps > h->t) return fail(h, FDTD_E_STATE, "cannot undo %d steps at t = %d", n_steps, h->t);
     if (h->geo.p > 0 && !h->desc.record) return fail(h, FDTD_E_STATE, "inverse with a PML needs record = 1");
     for (int s = 0; s < n_steps; s++) {
-        fdtd_status st = (h->naive || h->wide) ? reverse_step(h, h->t - 1, 0)
-                                               : reverse_fused(h, h->t - 1, 1, 0, 0, nullptr);
+        fdtd_status st = h->naive ? reverse_step(h, h->t - 1, 0) : reverse_fused(h, h->t - 1, 1, 0, 0, nullptr);
         if (st != FDTD_OK) return st;
         h->t -= 1;
     }
@@ -1139,6 +1137,7 @@ fdtd_status fdtd_grad_checkpointed(fdtd_handle h, int32_t segment, void *store, 
     if (energy_in_design(h))
         return fail(h, FDTD_E_UNSUPPORTED, "a weighted energy detector must lie outside the design box in z");
     if (h->naive) return fail(h, FDTD_E_UNSUPPORTED, "the checkpointed gradient runs on the z-march path only");
+    if (h->wide) return fail(h, FDTD_E_UNSUPPORTED, "the checkpointed gradient needs field sets under 4 GiB");
     if (segment < 1 || segment > h->T) return fail(h, FDTD_E_INVALID, "segment %d not in [1, T]", segment);
     if (!store || !dJ_deps) return fail(h, FDTD_E_INVALID, "store or dJ_deps is NULL");
     if (((uintptr_t)store & 255) != 0) return fail(h, FDTD_E_INVALID, "store not 256-byte aligned");

@@ -229,7 +229,8 @@ struct RevArgs {
     unsigned fstride;        // bytes from component q to q+1 of a field or adjoint set
     unsigned pstride[3];     // bytes from auxiliary q to q+1 of axis a (pin and pout alike)
 };
-hipError_t launch_tb_reverse_class(const RevArgs &a, int cls, hipStream_t s);
+// (wide: 64-bit component bases per plane, for sets of 4 GiB or more)
+hipError_t launch_tb_reverse_class(const RevArgs &a, int cls, bool wide, hipStream_t s);
 int rev_halo();
 int rev_tile_x();
 int rev_tile_y();

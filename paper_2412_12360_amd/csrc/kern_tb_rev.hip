@@ -60,7 +60,10 @@ template <bool XP, bool YP> struct RPlane {
     PsiB<XP, YP> pb;
 };
 
-template <bool XP, bool YP>
+// WIDE: field and adjoint sets of 4 GiB or more, addressed per plane from a
+// 64-bit base per component (read through Kp) plus the 32-bit offset of the
+// column within the plane; otherwise one base per set with 32-bit offsets.
+template <bool XP, bool YP, bool WIDE>
 __global__ __launch_bounds__(NT, 4) void k_tb_reverse(RevArgs A)
 {
     __shared__ float sH[3][EY + 1][EX];
@@ -138,20 +141,36 @@ __global__ __launch_bounds__(NT, 4) void k_tb_reverse(RevArgs A)
     // grid, replays the record and adds the detector adjoint source.
     auto load_raw = [&](int t, RPlane<XP, YP> &P) __attribute__((always_inline)) {
         const bool tin = t >= 0 && t < nz;
-        const unsigned c = ((unsigned)(tin ? t : 0) * nxy + off) * 4u;
         auto ld = [&](const float *base, unsigned o) { return *(const GLOBAL float *)((const GLOBAL char *)base + o); };
+        if constexpr (WIDE) {
+            const size_t pb = (size_t)(tin ? t : 0) * (size_t)Kp->g.nxy;
+            const unsigned c = off * 4u;
 #pragma unroll
-        for (int q = 0; q < 3; q++) {
-            P.e[q] = ld(A.fin.c[0], c + q * fs);
-            P.h[q] = ld(A.fin.c[0], c + (3 + q) * fs);
-        }
-        P.ce = ld(g.ce, c);
-        // (issued on every path, so the compiler's wait counts stay exact;
-        // without an adjoint, ain points at a readable set and finish drops it)
+            for (int q = 0; q < 3; q++) {
+                P.e[q] = ld(Kp->fin.c[q] + pb, c);
+                P.h[q] = ld(Kp->fin.c[3 + q] + pb, c);
+            }
+            P.ce = ld(Kp->g.ce + pb, c);
 #pragma unroll
-        for (int q = 0; q < 3; q++) {
-            P.ae[q] = ld(A.ain.c[0], c + q * fs);
-            P.ah[q] = ld(A.ain.c[0], c + (3 + q) * fs);
+            for (int q = 0; q < 3; q++) {
+                P.ae[q] = ld(Kp->ain.c[q] + pb, c);
+                P.ah[q] = ld(Kp->ain.c[3 + q] + pb, c);
+            }
+        } else {
+            const unsigned c = ((unsigned)(tin ? t : 0) * nxy + off) * 4u;
+#pragma unroll
+            for (int q = 0; q < 3; q++) {
+                P.e[q] = ld(A.fin.c[0], c + q * fs);
+                P.h[q] = ld(A.fin.c[0], c + (3 + q) * fs);
+            }
+            P.ce = ld(g.ce, c);
+            // (issued on every path, so the compiler's wait counts stay exact;
+            // without an adjoint, ain points at a readable set and finish drops it)
+#pragma unroll
+            for (int q = 0; q < 3; q++) {
+                P.ae[q] = ld(A.ain.c[0], c + q * fs);
+                P.ah[q] = ld(A.ain.c[0], c + (3 + q) * fs);
+            }
         }
 #pragma unroll
         for (int q = 0; q < 4; q++) P.pb.z[q] = 0.f;
@@ -440,15 +459,24 @@ __global__ __launch_bounds__(NT, 4) void k_tb_reverse(RevArgs A)
             const bool hex = y == 0 || bpl == 0, hey = x == 0 || bpl == 0, hez = x == 0 || y == 0;
             const bool store = own && bpl >= z0 && bpl < z1;
             if (store) {
-                const unsigned c = ((unsigned)bpl * nxy + off) * 4u;
+                const unsigned c = WIDE ? off * 4u : ((unsigned)bpl * nxy + off) * 4u;
                 auto st = [&](float *base, unsigned o, float v) { *(GLOBAL float *)((GLOBAL char *)base + o) = v; };
+                // component q of the forward (stf) and adjoint (sta) output sets at plane bpl
+                auto stf = [&](int q, float v) {
+                    if constexpr (WIDE) st(Kp->fout.c[q] + (size_t)bpl * (size_t)Kp->g.nxy, c, v);
+                    else st(A.fout.c[0], c + q * fs, v);
+                };
+                auto sta = [&](int q, float v) {
+                    if constexpr (WIDE) st(Kp->aout.c[q] + (size_t)bpl * (size_t)Kp->g.nxy, c, v);
+                    else st(A.aout.c[0], c + q * fs, v);
+                };
                 if (A.do_inv && interior) {
                     const float ex = bEn[0], ey = bEn[1], ez = bEn[2];
                     const float ey_x = sEn[1][row][lr], ez_x = sEn[2][row][lr];
                     const float ex_y = sEn[0][ru][lane], ez_y = sEn[2][ru][lane];
                     const float ex_z = aEn[0], ey_z = aEn[1];
 #pragma unroll
-                    for (int q = 0; q < 3; q++) st(A.fout.c[0], c + q * fs, bEn[q]);
+                    for (int q = 0; q < 3; q++) stf(q, bEn[q]);
                     // H sources of step n, in order, before the un-update
                     float hx = bH[0], hy = bH[1], hz = bH[2];
 #pragma unroll
@@ -462,9 +490,9 @@ __global__ __launch_bounds__(NT, 4) void k_tb_reverse(RevArgs A)
                             hz = (hit && comp == 5) ? hz - Am : hz;
                         }
                     }
-                    st(A.fout.c[0], c + 3 * fs, h_unupdate(hx, S, ez_y - ez, ey_z - ey));
-                    st(A.fout.c[0], c + 4 * fs, h_unupdate(hy, S, ex_z - ex, ez_x - ez));
-                    st(A.fout.c[0], c + 5 * fs, h_unupdate(hz, S, ey_x - ey, ex_y - ex));
+                    stf(3, h_unupdate(hx, S, ez_y - ez, ey_z - ey));
+                    stf(4, h_unupdate(hy, S, ex_z - ex, ez_x - ez));
+                    stf(5, h_unupdate(hz, S, ey_x - ey, ex_y - ex));
                 }
                 if (A.do_adj) {
                     // adjoint E with the transposed H pairs
@@ -484,9 +512,9 @@ __global__ __launch_bounds__(NT, 4) void k_tb_reverse(RevArgs A)
                         const float rb = sR[3][row][ll] - bR[5];
                         ez = ez + (ra + rb);
                     }
-                    st(A.aout.c[0], c, ex); st(A.aout.c[0], c + fs, ey); st(A.aout.c[0], c + 2 * fs, ez);
+                    sta(0, ex); sta(1, ey); sta(2, ez);
 #pragma unroll
-                    for (int q = 0; q < 3; q++) st(A.aout.c[0], c + (3 + q) * fs, bAh[q]);
+                    for (int q = 0; q < 3; q++) sta(3 + q, bAh[q]);
                     // psibar updates of the slab cells
                     if (p > 0) {
                         const float ce = bCe;
@@ -587,15 +615,23 @@ int rev_halo() { return HALO; }
 int rev_tile_x() { return EX - 2 * HALO; }
 int rev_tile_y() { return EY - 2 * HALO; }
 
-hipError_t launch_tb_reverse_class(const RevArgs &a, int cls, hipStream_t s)
+namespace {
+template <bool WIDE>
+hipError_t launch_rev(const RevArgs &a, int cls, hipStream_t s)
 {
-    if (a.ntiles <= 0) return hipSuccess;
     constexpr int threads = NT;
     switch (cls) {
-    case 0: hipLaunchKernelGGL((k_tb_reverse<false, false>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
-    case 1: hipLaunchKernelGGL((k_tb_reverse<true, false>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_tb_reverse<false, true>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_tb_reverse<true, true>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
+    case 0: hipLaunchKernelGGL((k_tb_reverse<false, false, WIDE>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_tb_reverse<true, false, WIDE>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_tb_reverse<false, true, WIDE>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_tb_reverse<true, true, WIDE>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
     }
     return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_tb_reverse_class(const RevArgs &a, int cls, bool wide, hipStream_t s)
+{
+    if (a.ntiles <= 0) return hipSuccess;
+    return wide ? launch_rev<true>(a, cls, s) : launch_rev<false>(a, cls, s);
 }
