@@ -211,6 +211,7 @@ def fwd_grad_run(pg, Solver, torch, time_block: int, workload: str, checkpoint: 
         "fwd_ms": round(tf, 2), "bwd_ms": round(tb, 2),
         "recon_err": float(recon.item()),
         "hbm_footprint_gb": round(g.footprint / 1e9, 2),
+        "kernel_path": g.kernel_path,
     }
     if checkpoint:
         # the baseline the time reversal replaces: checkpoints every sqrt(T)
@@ -355,7 +356,8 @@ def main():
     ap.add_argument("--solve-steps", type=int, default=0,
                     help="profiling runs only: time steps per solve instead of the workload's (0 = workload)")
     ap.add_argument("--large", action="store_true",
-                    help="also run the 640x640x400 forward+gradient problem (CPML 12, 4000 steps)")
+                    help="also run the 640x640x400 forward+gradient problem (CPML 12, 4000 steps) and "
+                         "forward+gradient on the 2400x1600x150 z-slab (100 steps)")
     ap.add_argument("--serving-max-active", type=int, default=6,
                     help="requests on the GPU at once in the batched runs (6 measured best on a "
                          "200-request mix: more sharing lengthens the largest requests)")
@@ -460,6 +462,11 @@ def main():
                                              Solver, torch, args.time_block,
                                              "640x640x400 grid, CPML 12, 256x256x128 design box (blurred binary rho, "
                                              "seed 5), eps_r = 2.25 + 10 rho, 4000 steps, interface record in HBM")
+        T = args.solve_steps if args.solve_steps else 100
+        out["shard_fwd_grad"] = fwd_grad_run(W.shard_slab(T=T), Solver, torch, args.time_block,
+                                             f"2400x1600x150 z-slab, CPML 12, 1200x800x75 design block, {T} steps "
+                                             "with the interface record, then the gradient (a sample: the wave has "
+                                             "not reached the detector yet; the kernels do the same work either way)")
 
     if args.serving > 0:
         out["serving"] = serving_bench(args.serving, torch, budget_gb=args.serving_budget_gb,
