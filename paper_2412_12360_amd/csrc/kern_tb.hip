@@ -40,9 +40,11 @@ __device__ __forceinline__ float ldo(const float *__restrict__ base, unsigned by
 {
     return *(const float *)((const char *)base + byteoff);
 }
+// (non-temporal: the march never reads back what it writes in this sweep;
+// 0.3-0.8% faster than plain stores)
 __device__ __forceinline__ void sto(float *__restrict__ base, unsigned byteoff, float v)
 {
-    *(float *)((char *)base + byteoff) = v;
+    __builtin_nontemporal_store(v, (float *)((char *)base + byteoff));
 }
 
 __device__ __forceinline__ int remap_xcd(int b, int nb)
