@@ -399,6 +399,11 @@ def main():
         copy_calibration(torch)
         return
     rank = int(os.environ.get("RANK", "0"))
+    t_bench = time.perf_counter()
+
+    def progress(leg):   # one stderr line per finished leg (a --large run takes minutes)
+        print(f"[bench] {leg} done ({time.perf_counter() - t_bench:.0f} s)", file=sys.stderr, flush=True)
+
     pr = W.config2(T=args.solve_steps) if args.solve_steps else W.config2()
     s = Solver(pr, record=False, time_block=args.time_block)
     K = s.time_block
@@ -461,13 +466,16 @@ def main():
         },
     }
 
+    progress("headline forward")
     if not args.no_variants:
         out["tfsf"] = tfsf_run(pr, Solver, torch, args.time_block, args.steps, W)
         out["interpolated_detector"] = interp_detector_run(pr, Solver, torch, args.time_block, args.steps)
+        progress("forward variants")
 
     if not args.no_shard:
         out["shard"] = shard_run(Solver, torch, args.time_block, args.steps, W,
                                  T=args.solve_steps if args.solve_steps else 100)
+        progress("z-slab forward")
 
     if not args.no_grad:
         pg = W.config3(T=args.solve_steps) if args.solve_steps else W.config3()
@@ -475,17 +483,20 @@ def main():
                                        "200^3 grid, CPML 10, 64^3 design cube rho~U[0,1] (seed 3), eps_r = 2.25 + 10 rho, "
                                        "1500 steps, objective = time-integrated flux; forward with interface record, "
                                        "then inverse-step + adjoint backward", checkpoint=True)
+        progress("forward + gradient")
 
     if args.large and not args.no_grad:
         out["fwd_grad_large"] = fwd_grad_run(W.config4(T=args.solve_steps) if args.solve_steps else W.config4(),
                                              Solver, torch, args.time_block,
                                              "640x640x400 grid, CPML 12, 256x256x128 design box (blurred binary rho, "
                                              "seed 5), eps_r = 2.25 + 10 rho, 4000 steps, interface record in HBM")
+        progress("large forward + gradient")
         T = args.solve_steps if args.solve_steps else 100
         out["shard_fwd_grad"] = fwd_grad_run(W.shard_slab(T=T), Solver, torch, args.time_block,
                                              f"2400x1600x150 z-slab, CPML 12, 1200x800x75 design block, {T} steps "
                                              "with the interface record, then the gradient (a sample: the wave has "
                                              "not reached the detector yet; the kernels do the same work either way)")
+        progress("z-slab forward + gradient")
 
     if args.serving > 0:
         out["serving"] = serving_bench(args.serving, torch, budget_gb=args.serving_budget_gb,

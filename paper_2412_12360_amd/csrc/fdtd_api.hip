@@ -323,28 +323,40 @@ std::vector<std::pair<int, int>> split_uniform(int n, int w)
 }
 
 // z extent of one workgroup's march: enough workgroups to fill the chip
-// (about 1024) without letting the 2K-plane z halo dominate.
+// (about 1024) without letting the 2K-plane z halo dominate.  Marches are
+// split evenly: nz planes in ceil(nz / zc) chunks of equal length (up to one
+// plane), never longer than zc.
+int even_chunk(int nz, int zc)
+{
+    const int nc = (nz + zc - 1) / zc;
+    return (nz + nc - 1) / nc;
+}
+
 int zchunk(const Geometry &G, int K, bool reverse)
 {
     const char *e = getenv(reverse ? "FDTD_REV_ZC" : "FDTD_TB_ZC");
     if (e && atoi(e) > 0) return std::min(atoi(e), G.nz);
     if (reverse) {
         // the reverse march does about twice the work per plane: 32 or 24
-        // planes only with at least eight workgroups per slot (measured: 32
-        // best on 640x640x400, 16 on 200^3)
+        // planes only with at least eight workgroups per slot, else 20
+        // (measured: 32 best on 640x640x400; 20 on 200^3, 0.439 against
+        // 0.451 ms per step at 16)
         const long long tx = (long long)split_uniform(G.nx, rev_tile_x()).size();
         const long long ty = (long long)split_axis(G.ny, rev_tile_y()).size();
         for (int zc : {32, 24}) {
             const long long nwg = tx * ty * ((G.nz + zc - 1) / zc);
-            if (nwg >= 8 * 2LL * 256) return std::min(zc, G.nz);
+            if (nwg >= 8 * 2LL * 256) return even_chunk(G.nz, std::min(zc, G.nz));
         }
-        return std::min(16, G.nz);
+        return even_chunk(G.nz, std::min(20, G.nz));
     }
     // A longer march fetches its 2K-plane z halo less often, but leaves fewer
     // workgroups to balance over the chip (the work of one is serial).  Take
-    // the longest of 16..64 planes that still gives at least four workgroups
-    // per slot (two per CU): measured best on 200^3 (16-20 planes), 256^3 (24)
-    // and 640x640x400 (32 and up).
+    // the longest of 20..64 planes that still gives at least four workgroups
+    // per slot (two per CU), else 16: measured best on 200^3 (16-20 planes)
+    // and 256^3 (24).  Where 64 planes leave that many, marches of up to 80
+    // planes, still with four workgroups per slot: 80 x 5 on 640x640x400
+    // (104.0 against 101.7 Gcell/s for 64 x 6 + 16), 75 x 2 on
+    // 2400x1600x150 (97.7 against 80.0 for 64 x 2 + 22).
     const int shape = tb_shape();
     const long long tx = (long long)(tb_tile_aligned(shape) ? split_uniform(G.nx, tb_tile_x(K, shape))
                                                              : split_axis(G.nx, tb_tile_x(K, shape))).size();
@@ -352,9 +364,15 @@ int zchunk(const Geometry &G, int K, bool reverse)
     const long long slots = 2LL * 256;
     for (int zc : {64, 48, 32, 24, 20}) {
         const long long nwg = tx * ty * ((G.nz + zc - 1) / zc);
-        if (nwg >= 4 * slots) return std::min(zc, G.nz);
+        if (nwg < 4 * slots) continue;
+        if (zc == 64)
+            for (long long nc = (G.nz + 79) / 80;; nc++) {
+                const int z = (int)((G.nz + nc - 1) / nc);
+                if (tx * ty * nc >= 4 * slots || z <= 64) return std::min(z, G.nz);
+            }
+        return even_chunk(G.nz, std::min(zc, G.nz));
     }
-    return std::min(16, G.nz);
+    return even_chunk(G.nz, std::min(16, G.nz));
 }
 
 // Tile tables of the z-march kernels, four classes each (bit 0 = an x CPML
