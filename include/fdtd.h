@@ -180,7 +180,8 @@ fdtd_status fdtd_grad(fdtd_handle h, float *dJ_deps, float *recon_err);
  * Needs a handle created with record = 1 (for the adjoint state; the record
  * itself is not used) on the z-march path.  Any t on entry; t = 0 on return
  * with zeroed fields.  Errors: E_STATE without record, E_UNSUPPORTED on the
- * per-cell fallback, E_INVALID for a segment outside [1, T] or NULL/unaligned
+ * per-cell fallback or on field sets of 4 GiB or more (the 64-bit-base path),
+ * E_INVALID for a segment outside [1, T] or NULL/unaligned
  * pointers, E_NOMEM when store_bytes is too small. */
 fdtd_status fdtd_checkpoint_bytes(fdtd_handle h, int32_t segment, size_t *bytes);
 fdtd_status fdtd_grad_checkpointed(fdtd_handle h, int32_t segment, void *store, size_t store_bytes,

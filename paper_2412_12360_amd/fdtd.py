@@ -299,7 +299,7 @@ class Solver:
 
     @property
     def kernel_path(self) -> str:
-        """Kernels the forward step runs on: "per-cell", "z-march" (32-bit
+        """Kernels the forward and reverse steps run on: "per-cell", "z-march" (32-bit
         offsets from one base per field set) or "z-march-wide" (a 64-bit base
         per component and plane, for field sets of 4 GiB or more)."""
         v = C.c_int32(0)
