@@ -296,7 +296,8 @@ def serving_bench(count: int, torch, seed_rate: float = 0.8, budget_gb: float = 
         sch = serve.Scheduler(serve.GpuExecutor(n_streams=streams), budget_bytes=budget,
                               max_active=max_active, chunk=64)
         t0 = time.perf_counter()
-        res = sch.run(reqs, open_loop=arrivals is not None)
+        res = sch.run(reqs, open_loop=arrivals is not None,
+                      progress=lambda d, n: log(f"  {d} of {n} requests served"))
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         out = serve.summarize(res, wall)

@@ -241,12 +241,18 @@ class Scheduler:
 
     # -------------------------------------------------------------- driver
     def run(self, requests: List[Request], open_loop: bool = True, poll_s: float = 2e-4,
-            sleep: Callable[[float], None] = time.sleep) -> Dict[int, Result]:
+            sleep: Callable[[float], None] = time.sleep,
+            progress: Optional[Callable[[int, int], None]] = None, progress_every: int = 50) -> Dict[int, Result]:
         """Feed `requests` by their arrival times (or all at once) and serve
-        until every one has a result."""
+        until every one has a result.  `progress(done, total)` is called each
+        time another `progress_every` results are in."""
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        total, reported = len(requests), 0
         self.now()
         while pending or not self.idle():
+            if progress is not None and len(self.results) // progress_every > reported:
+                reported = len(self.results) // progress_every
+                progress(len(self.results), total)
             t = self.now()
             while pending and (not open_loop or pending[0].arrival <= t):
                 r = pending.popleft()
