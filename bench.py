@@ -274,13 +274,15 @@ def copy_calibration(torch, nbytes: int = 1 << 30, reps: int = 4):
 
 
 def serving_bench(count: int, torch, seed_rate: float = 0.8, budget_gb: float = 0.0, max_active: int = 6,
-                  streams: int = 6, extra_rates=()):
+                  streams: int = 6, extra_rates=(), open_loops: bool = True, open_rate: float = 0.0):
     """Serving mix: `count` requests of the Poisson mix recipe (edges U{64..256},
     50% forward / 50% gradient, T = 8 x max edge, CPML 8).  Measures saturation
     throughput one-at-a-time and with continuous batching (all queued at t=0),
     then open-loop Poisson arrivals at 0.8 x the one-at-a-time request rate for
     both systems, reporting p50/p99 latency; `extra_rates` repeats the open
-    loop at further multiples of that rate (same arrival seed)."""
+    loop at further multiples of that rate (same arrival seed).  A long mix can
+    be split over two runs: `open_rate` > 0 skips the closed loops and runs the
+    open loops at that rate (req/s); `open_loops` = False skips the open loops."""
     from paper_2412_12360_amd import serve
     from paper_2412_12360_amd import workloads as W
     descs = W.serving_mix(count=count, rate_hz=None)
@@ -311,23 +313,38 @@ def serving_bench(count: int, torch, seed_rate: float = 0.8, budget_gb: float = 
 
     run(1, 1, limit=8)                          # warm-up (code objects, allocator)
     log("warm-up done")
-    seq = run(1, 1)
-    log(f"one at a time: {seq['req_per_s']:.3f} req/s")
-    bat = run(max_active, streams)
-    log(f"batched: {bat['req_per_s']:.3f} req/s")
+    r = lambda v: None if v is None else round(v, 4)
+    res = {"workload": f"{count} requests of the serving mix (edges U{{64..256}} per axis, 50% gradient, "
+                       f"T = 8 x max edge, CPML 8, eps_r U[1,12.25]; seeds 6/7/1000+rid)",
+           "hbm_budget_gb": round(budget / 1e9, 1), "max_active": max_active, "streams": streams}
+    if open_rate <= 0:
+        seq = run(1, 1)
+        log(f"one at a time: {seq['req_per_s']:.3f} req/s")
+        bat = run(max_active, streams)
+        log(f"batched: {bat['req_per_s']:.3f} req/s")
+        res["one_at_a_time"] = {"throughput_mcell_steps_s": r(seq["throughput_mcell_steps_s"]),
+                                "req_per_s": r(seq["req_per_s"]), "wall_s": r(seq["wall_s"])}
+        res["batched"] = {"throughput_mcell_steps_s": r(bat["throughput_mcell_steps_s"]),
+                          "req_per_s": r(bat["req_per_s"]), "wall_s": r(bat["wall_s"]),
+                          "peak_hbm_gb": bat["peak_hbm_gb"]}
+        res["speedup_throughput"] = r(bat["throughput_mcell_steps_s"] / seq["throughput_mcell_steps_s"])
+        seq_rate = seq["req_per_s"]
+    else:
+        seq_rate = open_rate / seed_rate
+    if not open_loops:
+        return res
     import numpy as np
 
     def arrivals(factor):
         rng = np.random.Generator(np.random.PCG64(8))
-        return list(np.cumsum(rng.exponential(1.0 / (factor * seq["req_per_s"]), size=count)))
+        return list(np.cumsum(rng.exponential(1.0 / (factor * seq_rate), size=count)))
 
-    rate = seed_rate * seq["req_per_s"]
+    rate = seed_rate * seq_rate
     arr = arrivals(seed_rate)
     seq_open = run(1, 1, arr)
     log(f"open loop, one at a time: p99 {seq_open['p99_latency_s']:.3f} s")
     bat_open = run(max_active, streams, arr)
     log(f"open loop, batched: p99 {bat_open['p99_latency_s']:.3f} s")
-    r = lambda v: None if v is None else round(v, 4)
     more = []
     for f in extra_rates:
         a = arrivals(f)
@@ -335,25 +352,15 @@ def serving_bench(count: int, torch, seed_rate: float = 0.8, budget_gb: float = 
         log(f"open loop at {f} x, one at a time: p99 {so['p99_latency_s']:.3f} s")
         bo = run(max_active, streams, a)
         log(f"open loop at {f} x, batched: p99 {bo['p99_latency_s']:.3f} s")
-        more.append({"rate_factor": f, "rate_req_s": r(f * seq["req_per_s"]),
+        more.append({"rate_factor": f, "rate_req_s": r(f * seq_rate),
                      "one_at_a_time_open": {"p50_s": r(so["p50_latency_s"]), "p99_s": r(so["p99_latency_s"])},
                      "batched_open": {"p50_s": r(bo["p50_latency_s"]), "p99_s": r(bo["p99_latency_s"])}})
-    return {
-        "workload": f"{count} requests of the serving mix (edges U{{64..256}} per axis, 50% gradient, "
-                    f"T = 8 x max edge, CPML 8, eps_r U[1,12.25]; seeds 6/7/1000+rid)",
-        "one_at_a_time": {"throughput_mcell_steps_s": r(seq["throughput_mcell_steps_s"]),
-                          "req_per_s": r(seq["req_per_s"]), "wall_s": r(seq["wall_s"])},
-        "batched": {"throughput_mcell_steps_s": r(bat["throughput_mcell_steps_s"]),
-                    "req_per_s": r(bat["req_per_s"]), "wall_s": r(bat["wall_s"]),
-                    "peak_hbm_gb": bat["peak_hbm_gb"]},
-        "open_loop_rate_req_s": r(rate),
-        "one_at_a_time_open": {"p50_s": r(seq_open["p50_latency_s"]), "p99_s": r(seq_open["p99_latency_s"])},
-        "batched_open": {"p50_s": r(bat_open["p50_latency_s"]), "p99_s": r(bat_open["p99_latency_s"])},
-        "speedup_throughput": r(bat["throughput_mcell_steps_s"] / seq["throughput_mcell_steps_s"]),
-        "hbm_budget_gb": round(budget / 1e9, 1),
-        "max_active": max_active, "streams": streams,
-        **({"open_loop_other_rates": more} if more else {}),
-    }
+    res["open_loop_rate_req_s"] = r(rate)
+    res["one_at_a_time_open"] = {"p50_s": r(seq_open["p50_latency_s"]), "p99_s": r(seq_open["p99_latency_s"])}
+    res["batched_open"] = {"p50_s": r(bat_open["p50_latency_s"]), "p99_s": r(bat_open["p99_latency_s"])}
+    if more:
+        res["open_loop_other_rates"] = more
+    return res
 
 
 def main():
@@ -379,6 +386,10 @@ def main():
                     help="requests on the GPU at once in the batched runs (6 measured best on a "
                          "200-request mix: more sharing lengthens the largest requests)")
     ap.add_argument("--serving-streams", type=int, default=6)
+    ap.add_argument("--serving-closed-only", action="store_true",
+                    help="serving: the two closed loops only (a long mix split over two runs)")
+    ap.add_argument("--serving-open-rate", type=float, default=0.0,
+                    help="serving: skip the closed loops and run the open loops at this rate (req/s)")
     ap.add_argument("--serving-extra-rates", default="",
                     help="comma-separated multiples of the one-at-a-time rate for further open-loop runs "
                          "(e.g. 0.5,1.2)")
@@ -502,7 +513,8 @@ def main():
     if args.serving > 0:
         out["serving"] = serving_bench(args.serving, torch, budget_gb=args.serving_budget_gb,
                                        max_active=args.serving_max_active, streams=args.serving_streams,
-                                       extra_rates=[float(v) for v in args.serving_extra_rates.split(",") if v])
+                                       extra_rates=[float(v) for v in args.serving_extra_rates.split(",") if v],
+                                       open_loops=not args.serving_closed_only, open_rate=args.serving_open_rate)
 
     if rank == 0 and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pr)
