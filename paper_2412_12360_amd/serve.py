@@ -264,6 +264,8 @@ class Scheduler:
                     sleep(max(0.0, min(pending[0].arrival - self.now(), 0.01)))
                 else:
                     sleep(poll_s)
+        if progress is not None and len(self.results) // progress_every > reported:
+            progress(len(self.results), total)
         return self.results
 
 

@@ -63,6 +63,18 @@ def test_all_requests_complete_with_correct_results():
     assert ex.live == 0 and sch.in_use == 0
 
 
+def test_progress_reported_once_per_block_of_results():
+    reqs = [mk(i, edge=32, T=64) for i in range(23)]
+    clk = VClock()
+    sch = serve.Scheduler(serve.MockExecutor(clk), 10**12, max_active=4, chunk=32, clock=clk)
+    seen = []
+    res = sch.run(reqs, open_loop=False, sleep=clk.sleep, progress=lambda d, n: seen.append((d, n)),
+                  progress_every=5)
+    assert len(res) == 23
+    assert [d // 5 for d, _ in seen] == [1, 2, 3, 4]
+    assert all(n == 23 for _, n in seen)
+
+
 def test_admission_never_exceeds_budget_and_is_fifo():
     reqs = [mk(i, edge=40 + 10 * (i % 5)) for i in range(20)]
     fps = [r.problem.N * 100 for r in reqs]
