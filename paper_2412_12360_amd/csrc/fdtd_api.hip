@@ -339,10 +339,15 @@ int zchunk(const Geometry &G, int K, bool reverse)
     if (reverse) {
         // the reverse march does about twice the work per plane: 32 or 24
         // planes only with at least eight workgroups per slot, else 20
-        // (measured: 32 best on 640x640x400; 20 on 200^3, 0.439 against
-        // 0.451 ms per step at 16)
+        // (measured: 32 best on 640x640x400 among 16..32; 20 on 200^3, 0.439
+        // against 0.451 ms per step at 16).  Where even marches of up to 60
+        // planes still leave eight per slot, those: 58 x 7 on 640x640x400
+        // (6.03 against 6.08 ms per step at 32), 50 x 3 on 2400x1600x150
+        // (20.8 against 22.5 ms; 75 x 2: 21.2).
         const long long tx = (long long)split_uniform(G.nx, rev_tile_x()).size();
         const long long ty = (long long)split_axis(G.ny, rev_tile_y()).size();
+        const long long nc60 = (G.nz + 59) / 60;
+        if (tx * ty * nc60 >= 8 * 2LL * 256) return even_chunk(G.nz, std::min(60, G.nz));
         for (int zc : {32, 24}) {
             const long long nwg = tx * ty * ((G.nz + zc - 1) / zc);
             if (nwg >= 8 * 2LL * 256) return even_chunk(G.nz, std::min(zc, G.nz));
