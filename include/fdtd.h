@@ -243,6 +243,14 @@ fdtd_status fdtd_time_block(fdtd_handle h, int32_t *K);
  * FDTD_E_UNSUPPORTED).  All three give the same bits. */
 fdtd_status fdtd_kernel_path(fdtd_handle h, int32_t *path);
 
+/* Tiles of each z-march class (host): counts[c] for class c = bit 0 (an x
+ * CPML slab within the tile's halo-extended footprint) | bit 1 (a y slab);
+ * class 0 tiles run the instance without x/y auxiliaries.  march = 0: the
+ * fused reverse march; march = K' in 1..K: a forward sweep of K' steps.
+ * All zero on the per-cell path.  Lets tests confirm which kernel instances
+ * a problem exercises. */
+fdtd_status fdtd_tile_classes(fdtd_handle h, int32_t march, int32_t counts[4]);
+
 #ifdef __cplusplus
 }
 #endif

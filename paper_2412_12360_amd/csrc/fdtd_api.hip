@@ -1358,4 +1358,12 @@ fdtd_status fdtd_kernel_path(fdtd_handle h, int32_t *path)
     return FDTD_OK;
 }
 
+fdtd_status fdtd_tile_classes(fdtd_handle h, int32_t march, int32_t counts[4])
+{
+    if (!h || !counts) return fail(h, FDTD_E_INVALID, "NULL argument");
+    if (march < 0 || march > h->K) return fail(h, FDTD_E_INVALID, "march %d outside [0, K = %d]", march, h->K);
+    for (int c = 0; c < 4; c++) counts[c] = h->naive ? 0 : h->tb_cnt[march][c];
+    return FDTD_OK;
+}
+
 }  // extern "C"

@@ -53,7 +53,7 @@ ENTRY_POINTS = [
     "fdtd_footprint", "fdtd_create", "fdtd_forward", "fdtd_inverse", "fdtd_grad", "fdtd_set_inv_eps",
     "fdtd_reset", "fdtd_destroy", "fdtd_time", "fdtd_last_error", "fdtd_field_ptr", "fdtd_state_arrays",
     "fdtd_linear_steps", "fdtd_record_ptr", "fdtd_time_block", "fdtd_checkpoint_bytes",
-    "fdtd_grad_checkpointed", "fdtd_kernel_path",
+    "fdtd_grad_checkpointed", "fdtd_kernel_path", "fdtd_tile_classes",
 ]
 
 _lib = None
@@ -94,6 +94,7 @@ def lib():
     L.fdtd_record_ptr.argtypes = [H, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_size_t)]
     L.fdtd_time_block.argtypes = [H, C.POINTER(C.c_int32)]
     L.fdtd_kernel_path.argtypes = [H, C.POINTER(C.c_int32)]
+    L.fdtd_tile_classes.argtypes = [H, C.c_int32, C.POINTER(C.c_int32)]
     for name in ENTRY_POINTS:
         if name != "fdtd_last_error":
             getattr(L, name).restype = C.c_int
@@ -197,8 +198,15 @@ class Solver:
         self.ws_off = (-base) % 256
         self.ws_ptr = base + self.ws_off
         self.handle = C.c_void_p(0)
+        # The inputs were written on the current stream; fdtd_create enqueues
+        # its uploads on self.stream.  Order the two streams (no host wait, so
+        # other streams' queued work keeps running), and tell the caching
+        # allocator that the workspace is used on self.stream.
+        cur = torch.cuda.current_stream(dev)
+        if self.stream != cur:
+            self.stream.wait_stream(cur)
+            workspace.record_stream(self.stream)
         with torch.cuda.stream(self.stream):
-            torch.cuda.synchronize(dev)
             check(lib().fdtd_create(C.byref(self.desc), self.srcs, len(prob.sources), self.dets, self.ndet,
                                     C.c_void_p(self.ws_ptr), C.c_size_t(workspace.numel() - self.ws_off),
                                     C.c_void_p(self.stream.cuda_stream), C.byref(self.handle)))
@@ -305,6 +313,13 @@ class Solver:
         v = C.c_int32(0)
         check(lib().fdtd_kernel_path(self.handle, C.byref(v)), self.handle)
         return ("per-cell", "z-march", "z-march-wide")[v.value]
+
+    def tile_classes(self, march: int = 0):
+        """Tiles per z-march class [interior, x slab, y slab, both] of the fused
+        reverse march (march = 0) or of a forward sweep of `march` steps."""
+        v = (C.c_int32 * 4)()
+        check(lib().fdtd_tile_classes(self.handle, int(march), v), self.handle)
+        return [int(x) for x in v]
 
     def field(self, comp: int, which: int = 0):
         """Device view [nz, ny, nx] of field component comp (0..5) of the
