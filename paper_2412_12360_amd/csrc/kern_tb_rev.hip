@@ -13,8 +13,14 @@
 //            Ebar -= S C^T Hbar with the transposed CPML (coefficients R);
 //            psibar_H <- b (psibar_H + w)
 // Phase A at a cell reads H at -1 and Q at +1; phase B reads E^n at +1 and R
-// at -1, so a workgroup computes a tile with a 2-cell halo and marches up in
-// z with phase A one plane behind the fetch and phase B two planes behind.
+// at -1, so a workgroup marches up in z with phase A one plane behind the
+// fetch and phase B two planes behind.  An owned cell's outputs need E^n of
+// the cell above it in x and y (phase A there reads only owned H) and R of
+// the cell below it (from Hbar of that cell, whose phase A reads Q of the
+// owned cell): raw inputs one cell beyond the tile on each side suffice, so
+// the halo is one cell in x and y.  In z the march starts at the tile's
+// first plane (with the plane below it preloaded) and ends two planes past
+// the last.
 // The four x/y exchanges of a plane (H, Q, E^n, R) share one LDS round.
 // Record values replace the fields on the PML-side layers (H on the low
 // faces from step n, E^n on the high faces from step n-1) as they are read.
@@ -26,11 +32,11 @@ namespace {
 // Workgroup: W waves as rows of EX = 32 + 2*HALO lanes; the owned part of
 // a row is one whole 128-byte line, line aligned (x tiles are cut into whole
 // lines), so no two workgroups write parts of the same line.  The threads
-// beyond the last full row (512 - 14*36 = 8) work on a spare LDS row and
+// beyond the last full row (512 - 15*34 = 2) work on a spare LDS row and
 // write nothing.  8 waves and at most 128 registers, so that two workgroups
-// share a CU (measured 2% faster than one 16-wave workgroup per CU, despite
-// the taller halo share: 10 of 14 rows owned instead of 24 of 28).
-constexpr int HALO = 2;
+// share a CU (measured 2% faster than one 16-wave workgroup per CU at a
+// two-cell halo).  With the one-cell halo 13 of 15 rows are owned.
+constexpr int HALO = 1;
 constexpr int EX = 32 + 2 * HALO;
 constexpr int W = 8;
 constexpr int NT = 64 * W;
@@ -336,7 +342,8 @@ __global__ __launch_bounds__(NT, 4) void k_tb_reverse(RevArgs A)
     float Rz0 = 0.f, Rz3 = 0.f;     // R of plane b-1: Hy along z, Hx along z
     float Hm0 = 0.f, Hm1 = 0.f;     // Hx, Hy of plane a-1
 
-    const int zs = z0 - HALO;
+    // body(t) runs phase A at t-1 and phase B at t-2: t = z0 .. z1+1
+    const int zs = z0, ze = z1 + 2;
     {
         RPlane<XP, YP> R;
         load_raw(zs - 1, R);        // plane a = zs - 1 (zero unless in the grid)
@@ -580,7 +587,7 @@ __global__ __launch_bounds__(NT, 4) void k_tb_reverse(RevArgs A)
         // which stores nothing: its planes lie beyond the owned range.
         RPlane<XP, YP> R0, R1;
         load_raw(zs, R0);
-        for (int t = zs; t < z1 + HALO; t += 2) {
+        for (int t = zs; t < ze; t += 2) {
             {
                 asm volatile("" : "+s"(Kp));
                 load_raw(t + 1, R1);
@@ -599,7 +606,7 @@ __global__ __launch_bounds__(NT, 4) void k_tb_reverse(RevArgs A)
     } else {
         // slab tiles carry the auxiliaries too and have no registers for a
         // second plane in flight: fetch and use
-        for (int t = zs; t < z1 + HALO; t++) {
+        for (int t = zs; t < ze; t++) {
             asm volatile("" : "+s"(Kp));
             RPlane<XP, YP> R, L;
             load_raw(t, R);
