@@ -187,6 +187,20 @@ fdtd_status fdtd_checkpoint_bytes(fdtd_handle h, int32_t segment, size_t *bytes)
 fdtd_status fdtd_grad_checkpointed(fdtd_handle h, int32_t segment, void *store, size_t store_bytes,
                                    float *dJ_deps, float *J);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc): the same
+ * computation as fdtd_grad_checkpointed, with the checkpoint store taken from
+ * a fixed device array inside the library instead of caller memory.  The
+ * array holds fdtd_noalloc_store_bytes() bytes (256 MiB) on every GPU the
+ * library runs this call on, from the first call on that GPU until the
+ * process ends; the call allocates nothing.  Every call on one GPU uses the
+ * same array (each call writes every store byte it later reads), so calls
+ * that overlap on one GPU -- from two handles, threads or streams -- race and
+ * must be serialised by the caller.  Errors: as fdtd_grad_checkpointed, and
+ * FDTD_E_NOMEM when fdtd_checkpoint_bytes(h, segment) exceeds the array. */
+fdtd_status fdtd_grad_checkpointed_noalloc(fdtd_handle h, int32_t segment, float *dJ_deps, float *J);
+size_t fdtd_noalloc_store_bytes(void);
+
 /* Replace 1/eps_r (device, N values) and the per-cell update coefficients;
  * allowed when t = 0. */
 fdtd_status fdtd_set_inv_eps(fdtd_handle h, const float *inv_eps);

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -58,6 +59,7 @@ struct fdtd_ctx {
     fdtd_flux_detector det[FDTD_MAX_DETECTORS];
     int nsrc = 0, ndet = 0;
     hipStream_t stream = nullptr;
+    int device = 0;                        // HIP device current at create
     char err[512] = "";
     int t = 0;
     int T = 0;
@@ -817,6 +819,7 @@ fdtd_status fdtd_create(const fdtd_desc *desc, const fdtd_source *src, int32_t n
     }
     for (int m = 0; m < ndet; m++) h->det[m] = det[m];
     h->stream = (hipStream_t)stream;
+    if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;
     h->T = desc->n_steps;
     h->K = choose_K(desc);
     h->naive = false;
@@ -1152,7 +1155,8 @@ fdtd_status fdtd_checkpoint_bytes(fdtd_handle h, int32_t segment, size_t *bytes)
     return FDTD_OK;
 }
 
-fdtd_status fdtd_grad_checkpointed(fdtd_handle h, int32_t segment, void *store, size_t store_bytes,
+namespace {
+fdtd_status grad_checkpointed_impl(fdtd_handle h, int32_t segment, void *store, size_t store_bytes,
                                    float *dJ_deps, float *J)
 {
     if (!h) return fail(nullptr, FDTD_E_INVALID, "handle is NULL");
@@ -1233,6 +1237,70 @@ fdtd_status fdtd_grad_checkpointed(fdtd_handle h, int32_t segment, void *store, 
     h->t = 0;
     return FDTD_OK;
 }
+}  // namespace
+
+fdtd_status fdtd_grad_checkpointed(fdtd_handle h, int32_t segment, void *store, size_t store_bytes,
+                                   float *dJ_deps, float *J)
+{
+    return grad_checkpointed_impl(h, segment, store, store_bytes, dJ_deps, J);
+}
+
+// ----------------------------------------------------------------------
+// Allocation-free variant: the checkpoint store is a fixed device array of
+// the library instead of caller memory.  Each GPU holds its own copy until
+// the process ends; host code must use its address from hipGetSymbolAddress
+// (the array's name on the host is only a stand-in), taken once per device
+// with that device current.
+namespace {
+
+constexpr size_t NOALLOC_STORE_BYTES = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_STORE_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// device address of this device's store (taken once per device, with that
+// device current, and kept)
+fdtd_status scratch_address(fdtd_ctx *h, void **out)
+{
+    *out = nullptr;
+    if (h->device < 0 || h->device >= NOALLOC_MAX_DEVICES)
+        return fail(h, FDTD_E_UNSUPPORTED, "device %d beyond the %d the store table holds", h->device,
+                    NOALLOC_MAX_DEVICES);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[h->device]) {
+        int prev = 0;
+        HIPCHK(h, hipGetDevice(&prev));
+        if (prev != h->device) HIPCHK(h, hipSetDevice(h->device));
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (prev != h->device) HIPCHK(h, hipSetDevice(prev));
+        if (e != hipSuccess || !ptr)
+            return fail(h, FDTD_E_DEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_scratch_ptr[h->device] = ptr;
+    }
+    *out = g_scratch_ptr[h->device];
+    return FDTD_OK;
+}
+
+}  // namespace
+
+fdtd_status fdtd_grad_checkpointed_noalloc(fdtd_handle h, int32_t segment, float *dJ_deps, float *J)
+{
+    if (!h) return fail(nullptr, FDTD_E_INVALID, "handle is NULL");
+    if (segment < 1 || segment > h->T) return fail(h, FDTD_E_INVALID, "segment %d not in [1, T]", segment);
+    const size_t need = ckpt_plan(h, segment).total;
+    if (need > NOALLOC_STORE_BYTES)
+        return fail(h, FDTD_E_NOMEM, "checkpoint store of %zu bytes exceeds the library's fixed %zu-byte store",
+                    need, NOALLOC_STORE_BYTES);
+    void *store = nullptr;
+    const fdtd_status st = scratch_address(h, &store);
+    if (st != FDTD_OK) return st;
+    return grad_checkpointed_impl(h, segment, store, NOALLOC_STORE_BYTES, dJ_deps, J);
+}
+
+size_t fdtd_noalloc_store_bytes(void) { return NOALLOC_STORE_BYTES; }
 
 fdtd_status fdtd_set_inv_eps(fdtd_handle h, const float *inv_eps)
 {

@@ -53,7 +53,8 @@ ENTRY_POINTS = [
     "fdtd_footprint", "fdtd_create", "fdtd_forward", "fdtd_inverse", "fdtd_grad", "fdtd_set_inv_eps",
     "fdtd_reset", "fdtd_destroy", "fdtd_time", "fdtd_last_error", "fdtd_field_ptr", "fdtd_state_arrays",
     "fdtd_linear_steps", "fdtd_record_ptr", "fdtd_time_block", "fdtd_checkpoint_bytes",
-    "fdtd_grad_checkpointed", "fdtd_kernel_path", "fdtd_tile_classes",
+    "fdtd_grad_checkpointed", "fdtd_kernel_path", "fdtd_tile_classes", "fdtd_grad_checkpointed_noalloc",
+    "fdtd_noalloc_store_bytes",
 ]
 
 _lib = None
@@ -81,6 +82,8 @@ def lib():
     L.fdtd_grad.argtypes = [H, fp, fp]
     L.fdtd_checkpoint_bytes.argtypes = [H, C.c_int32, C.POINTER(C.c_size_t)]
     L.fdtd_grad_checkpointed.argtypes = [H, C.c_int32, C.c_void_p, C.c_size_t, fp, fp]
+    L.fdtd_grad_checkpointed_noalloc.argtypes = [H, C.c_int32, fp, fp]
+    L.fdtd_noalloc_store_bytes.argtypes = []
     L.fdtd_set_inv_eps.argtypes = [H, fp]
     L.fdtd_reset.argtypes = [H]
     L.fdtd_destroy.argtypes = [H]
@@ -96,8 +99,9 @@ def lib():
     L.fdtd_kernel_path.argtypes = [H, C.POINTER(C.c_int32)]
     L.fdtd_tile_classes.argtypes = [H, C.c_int32, C.POINTER(C.c_int32)]
     for name in ENTRY_POINTS:
-        if name != "fdtd_last_error":
+        if name not in ("fdtd_last_error", "fdtd_noalloc_store_bytes"):
             getattr(L, name).restype = C.c_int
+    L.fdtd_noalloc_store_bytes.restype = C.c_size_t
     _lib = L
     return L
 
@@ -280,6 +284,15 @@ class Solver:
                                            C.c_size_t(store.numel() * store.element_size()),
                                            C.c_void_p(g.data_ptr()), C.c_void_p(J.data_ptr())), self.handle)
         self._keep_store = store
+        return g, J
+
+    def grad_checkpointed_noalloc(self, segment: int):
+        """grad_checkpointed with the library's fixed device store (no
+        allocation by the library or for the store); outputs as there."""
+        g = self.torch.empty(self.prob.design_shape(), dtype=self.torch.float32, device=self.device)
+        J = self.torch.zeros(1, dtype=self.torch.float32, device=self.device)
+        check(lib().fdtd_grad_checkpointed_noalloc(self.handle, int(segment), C.c_void_p(g.data_ptr()),
+                                                   C.c_void_p(J.data_ptr())), self.handle)
         return g, J
 
     def fdtd_set_inv_eps(self, inv_eps):

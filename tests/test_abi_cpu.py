@@ -18,7 +18,7 @@ def _F():
 
 def declared_functions():
     txt = open(os.path.join(ROOT, "include", "fdtd.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:fdtd_status|const char \*)\s*(fdtd_\w+)\s*\(", txt, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:fdtd_status|const char \*|size_t)\s*(fdtd_\w+)\s*\(", txt, re.M)))
 
 
 def test_library_exports_every_declared_symbol():
