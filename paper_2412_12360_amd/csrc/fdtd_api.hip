@@ -88,14 +88,17 @@ struct fdtd_ctx {
     float *trace = nullptr, *planes = nullptr, *wdev = nullptr, *rec = nullptr, *gacc = nullptr;
     float *parts[2] = {nullptr, nullptr};
     int nparts_cap = 0;
-    int4 *tiles = nullptr;                 // tile tables of every K' <= K, two classes each
-    int tb_off[5][4], tb_cnt[5][4];
+    int4 *tiles = nullptr;                 // tile tables: the reverse march, then every K' <= K
+    int tb_off[5], tb_n[5];                // per table: first tile, tiles (all classes, spatial order)
+    int tb_cnt[5][4];                      // per table and class: tiles
+    TbArgs *targs = nullptr;               // the z-marches' fixed arguments, in the workspace
+    RevArgs *rargs = nullptr;
+    TbArgs host_targs;                     // (host copies, kept for the uploads)
+    RevArgs host_rargs;
     unsigned fstride, pstride[3];   // z-march addressing: bytes between arrays of one set
     float4 *profv[3];
     bool naive = false;                    // per-cell kernels instead of the z-march
     bool wide = false;                     // forward z-march with 64-bit component bases
-    hipStream_t side[3] = {nullptr, nullptr, nullptr};   // concurrent tile classes (default priority)
-    hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
     int shape = 0;                         // z-march workgroup shape
     float wS[FDTD_MAX_DETECTORS];
     float wS_plain[FDTD_MAX_DETECTORS];   // wS with the interpolated detectors' entries zero
@@ -382,14 +385,19 @@ int zchunk(const Geometry &G, int K, bool reverse)
     return even_chunk(G.nz, std::min(16, G.nz));
 }
 
-// Tile tables of the z-march kernels, four classes each (bit 0 = an x CPML
-// slab inside the halo-extended footprint, bit 1 = a y slab): slot 0 for the
-// fused reverse march, slot K' for a forward sweep of K' = 1..K steps.
-void build_tiles(const Geometry &G, int K, std::vector<int4> &out, int off[5][4], int cnt[5][4])
+// Tile tables of the z-march kernels: slot 0 for the fused reverse march,
+// slot K' for a forward sweep of K' = 1..K steps.  Each table lists every
+// tile in spatial order (x fastest, then y, then z chunks) with its class
+// (bit 0 = an x CPML slab inside the halo-extended footprint, bit 1 = a y
+// slab), so that consecutive tiles -- one XCD's share after the remap --
+// are neighbours with the grid's mix of classes.
+void build_tiles(const Geometry &G, int K, std::vector<int4> &out, int off[5], int n[5], int cnt[5][4])
 {
     out.clear();
-    for (int kk = 0; kk < 5; kk++)
-        for (int c = 0; c < 4; c++) off[kk][c] = cnt[kk][c] = 0;
+    for (int kk = 0; kk < 5; kk++) {
+        off[kk] = n[kk] = 0;
+        for (int c = 0; c < 4; c++) cnt[kk][c] = 0;
+    }
     // slot 0: the reverse march (halo rev_halo()); slots 1..K: forward, halo kk
     for (int kk = 0; kk <= K; kk++) {
         const int halo = kk == 0 ? rev_halo() : kk;
@@ -400,7 +408,7 @@ void build_tiles(const Geometry &G, int K, std::vector<int4> &out, int off[5][4]
         // from x = 0
         const auto xs = (kk == 0 || tb_tile_aligned(tb_shape())) ? split_uniform(G.nx, tx) : split_axis(G.nx, tx);
         const auto ys = split_axis(G.ny, ty);
-        std::vector<int4> cls[4];
+        off[kk] = (int)out.size() / 2;
         for (int z0 = 0; z0 < G.nz; z0 += ZC)
             for (const auto &yt : ys)
                 for (const auto &xt : xs) {
@@ -410,14 +418,11 @@ void build_tiles(const Geometry &G, int K, std::vector<int4> &out, int off[5][4]
                         if (xt.first - halo < G.p || xt.second + halo > G.nx - G.p) c |= 1;
                         if (yt.first - halo < G.p || yt.second + halo > G.ny - G.p) c |= 2;
                     }
-                    cls[c].push_back(make_int4(xt.first, xt.second, yt.first, yt.second));
-                    cls[c].push_back(make_int4(z0, z1, c, 0));
+                    out.push_back(make_int4(xt.first, xt.second, yt.first, yt.second));
+                    out.push_back(make_int4(z0, z1, c, 0));
+                    cnt[kk][c]++;
                 }
-        for (int c = 0; c < 4; c++) {
-            off[kk][c] = (int)out.size() / 2;
-            cnt[kk][c] = (int)cls[c].size() / 2;
-            out.insert(out.end(), cls[c].begin(), cls[c].end());
-        }
+        n[kk] = (int)out.size() / 2 - off[kk];
     }
 }
 
@@ -464,8 +469,10 @@ size_t plan(fdtd_ctx *h, const fdtd_desc *d, const Geometry &G, int K, void *bas
                                                     std::max(1, K)));
         h->red = B.take(rs);
     }
-    build_tiles(G, K, h->host_tiles, h->tb_off, h->tb_cnt);
+    build_tiles(G, K, h->host_tiles, h->tb_off, h->tb_n, h->tb_cnt);
     h->tiles = B.take_as<int4>(std::max<size_t>(1, h->host_tiles.size()));
+    h->targs = B.take_as<TbArgs>(1);
+    h->rargs = B.take_as<RevArgs>(1);
     for (int ax = 0; ax < 3; ax++) h->profv[ax] = B.take_as<float4>(2 * (size_t)n[ax]);
     const long long nparts = (interior_cells(G) + 255) / 256;
     h->nparts_cap = (int)nparts;
@@ -596,58 +603,67 @@ fdtd_status step_naive(fdtd_ctx *h, int n, int with_src, int with_rec, int with_
     return FDTD_OK;
 }
 
-// K' steps from n0 with the z-march kernel (buffer cur -> cur^1)
-fdtd_status steps_tb(fdtd_ctx *h, int n0, int kk, int with_src, int with_rec, int with_det)
+// The launch entry of handle h for a forward sweep of kk steps from n0
+// (buffer cur -> cur^1); first = its first block in the launch.
+TbReq tb_request(fdtd_ctx *h, int n0, int kk, int with_src, int with_rec, int with_det, int first)
 {
     const Geometry &G = h->geo;
-    TbArgs a;
-    a.g = h->g;
-    a.in = fields_of(h, h->cur);
-    a.out = fields_of(h, h->cur ^ 1);
-    a.pin = psi_of(h, h->cur);
-    a.pout = psi_of(h, h->cur ^ 1);
-    a.n0 = n0;
-    a.with_src = with_src;
-    a.rec = (with_rec && h->rec && G.R.per_step > 0) ? h->rec + (size_t)n0 * G.R.per_step : nullptr;
-    a.R = G.R;
-    a.planes = (with_det && G.D.ndet > 0) ? h->planes : nullptr;
-    a.raw = h->drec ? h->drec + (size_t)n0 * G.D.raw_per_step : h->raw;
-    a.D = G.D;
-    // E^n of the interpolated detectors' planes (the sweep reads buffer cur
-    // and writes the other one, so this gather may run beside it)
-    if (a.planes && h->raw) HIPCHK(h, launch_det_eprev(h->g, a.in, G.D, h->eprev, h->stream));
-    if (a.planes && h->drec && n0 == 0) HIPCHK(h, launch_det_eprev(h->g, a.in, G.D, h->drec_e0, h->stream));
-    a.xcd_remap = 1;
-    for (int ax = 0; ax < 3; ax++) a.profv[ax] = h->profv[ax];
-    a.fstride = h->fstride;
-    for (int ax = 0; ax < 3; ax++) a.pstride[ax] = h->pstride[ax];
-    // The four tile classes are independent (all read buffer cur, write
-    // disjoint cells of buffer cur^1): classes 1..3 run on side streams that
-    // fork from and join back into the handle's stream, so a small class
-    // does not serialise a whole march behind the large ones.
-    const bool par = h->side[0] != nullptr;
-    if (par) HIPCHK(h, hipEventRecord(h->fork, h->stream));
-    for (int c = 0; c < 4; c++) {
-        a.tiles = h->tiles + 2 * (size_t)h->tb_off[kk][c];
-        a.ntiles = h->tb_cnt[kk][c];
-        if (a.ntiles == 0) continue;
-        hipStream_t st = (par && c > 0) ? h->side[c - 1] : h->stream;
-        if (st != h->stream) HIPCHK(h, hipStreamWaitEvent(st, h->fork, 0));
-        HIPCHK(h, launch_tb_forward_class(a, kk, c, h->shape, h->wide, st));
-        if (st != h->stream) {
-            HIPCHK(h, hipEventRecord(h->join[c - 1], st));
-            HIPCHK(h, hipStreamWaitEvent(h->stream, h->join[c - 1], 0));
-        }
-    }
-    h->cur ^= 1;
-    if (a.planes && h->raw) HIPCHK(h, launch_det_interp(h->g, G.D, a.raw, h->eprev, kk, h->planes, h->stream));
-    if (a.planes)
-        for (int m = 0; m < G.D.ndet; m++) {
-            const long long L = (long long)(G.D.i1[m] - G.D.i0[m]) * (G.D.j1[m] - G.D.j0[m]);
-            HIPCHK(h, launch_reduce_rows2(h->planes + G.D.off[m], L, kk, G.D.per_step,
-                                          h->trace + (size_t)n0 * G.D.ndet + m, G.D.ndet, h->red, h->stream));
-        }
+    TbReq q;
+    q.args = (unsigned long long)(uintptr_t)h->targs;
+    q.tiles = h->tiles + 2 * (size_t)h->tb_off[kk];
+    q.rec = (with_rec && h->rec && G.R.per_step > 0) ? h->rec + (size_t)n0 * G.R.per_step : nullptr;
+    q.planes = (with_det && G.D.ndet > 0) ? h->planes : nullptr;
+    q.raw = h->drec ? h->drec + (size_t)n0 * G.D.raw_per_step : h->raw;
+    q.n0 = n0;
+    q.first = first;
+    q.flags = (h->cur ? TB_CUR : 0u) | (with_src ? TB_SRC : 0u);
+    q.pad = 0;
+    return q;
+}
+
+// what a forward sweep launches before its march (interpolated detectors'
+// E^n gather, which reads buffer cur while the march writes the other one)
+fdtd_status tb_prologue(fdtd_ctx *h, int n0, int with_det)
+{
+    const Geometry &G = h->geo;
+    const bool planes = with_det && G.D.ndet > 0;
+    if (planes && h->raw) HIPCHK(h, launch_det_eprev(h->g, fields_of(h, h->cur), G.D, h->eprev, h->stream));
+    if (planes && h->drec && n0 == 0)
+        HIPCHK(h, launch_det_eprev(h->g, fields_of(h, h->cur), G.D, h->drec_e0, h->stream));
     return FDTD_OK;
+}
+
+// what follows a forward sweep of kk steps from n0: swap the buffers, the
+// detectors' densities and fixed-order sums into the trace
+fdtd_status tb_epilogue(fdtd_ctx *h, int n0, int kk, int with_det)
+{
+    const Geometry &G = h->geo;
+    h->cur ^= 1;
+    if (!(with_det && G.D.ndet > 0)) return FDTD_OK;
+    float *raw = h->drec ? h->drec + (size_t)n0 * G.D.raw_per_step : h->raw;
+    if (h->raw) HIPCHK(h, launch_det_interp(h->g, G.D, raw, h->eprev, kk, h->planes, h->stream));
+    for (int m = 0; m < G.D.ndet; m++) {
+        const long long L = (long long)(G.D.i1[m] - G.D.i0[m]) * (G.D.j1[m] - G.D.j0[m]);
+        HIPCHK(h, launch_reduce_rows2(h->planes + G.D.off[m], L, kk, G.D.per_step,
+                                      h->trace + (size_t)n0 * G.D.ndet + m, G.D.ndet, h->red, h->stream));
+    }
+    return FDTD_OK;
+}
+
+// K' steps from n0 with the z-march kernel (buffer cur -> cur^1): one launch
+// over the tiles of every class
+fdtd_status steps_tb(fdtd_ctx *h, int n0, int kk, int with_src, int with_rec, int with_det)
+{
+    fdtd_status st = tb_prologue(h, n0, with_det);
+    if (st != FDTD_OK) return st;
+    TbLaunch L;
+    L.nreq = 1;
+    L.nblocks = h->tb_n[kk];
+    L.xcd_remap = 1;
+    L.pad = 0;
+    L.r[0] = tb_request(h, n0, kk, with_src, with_rec, with_det, 0);
+    HIPCHK(h, launch_tb_forward(L, kk, h->shape, h->wide, h->stream));
+    return tb_epilogue(h, n0, kk, with_det);
 }
 
 fdtd_status advance(fdtd_ctx *h, int t0, int n, int with_src, int with_rec, int with_det)
@@ -690,59 +706,87 @@ fdtd_status reverse_step(fdtd_ctx *h, int n, int do_adj)
     return FDTD_OK;
 }
 
-// one reverse step n with the fused z-march kernel (all state ping-pong);
-// do_inv = 0 applies only the adjoint of the source-free step map
-fdtd_status reverse_fused(fdtd_ctx *h, int n, int do_inv, int do_adj, int with_det, float *gacc,
-                          const Fields *fin = nullptr)
+// The launch entry of handle h for reverse step n with the fused z-march
+// (all state ping-pong); do_inv = 0 applies only the adjoint of the
+// source-free step map; fin: the forward state s_{n+1} read instead of the
+// current buffer (adjoint-only mode), or nullptr.
+RevReq rev_request(fdtd_ctx *h, int n, int do_inv, int do_adj, int with_det, float *gacc, const float *fin,
+                   int first)
 {
     const Geometry &G = h->geo;
-    RevArgs a;
-    a.g = h->g;
-    a.fin = fin ? *fin : fields_of(h, h->cur);
-    a.fout = fields_of(h, h->cur ^ 1);
-    // without an adjoint the march still issues its adjoint loads (from the
-    // forward input set, a readable buffer of the same size) and drops them
-    a.ain = do_adj ? adj_of(h, h->acur) : fields_of(h, h->cur);
-    a.aout = do_adj ? adj_of(h, h->acur ^ 1) : Fields{};
-    a.pin = psibar_of(h, h->apar);
-    a.pout = psibar_of(h, h->apar ^ 1);
-    a.n = n;
-    a.do_inv = do_inv;
-    a.do_adj = do_adj;
-    a.with_det = with_det && G.D.ndet > 0;
-    a.rec_h = (do_inv && G.p > 0) ? h->rec + (size_t)n * G.R.per_step : nullptr;
-    a.rec_e = (do_inv && G.p > 0 && n > 0) ? h->rec + (size_t)(n - 1) * G.R.per_step : nullptr;
-    a.R = G.R;
-    a.D = G.D;
-    for (int m = 0; m < FD_MAXDET; m++) a.wS[m] = h->wS_plain[m];
-    a.gacc = gacc;
-    a.dlo = make_int3(h->desc.design_lo[0], h->desc.design_lo[1], h->desc.design_lo[2]);
-    a.dhi = make_int3(h->desc.design_hi[0], h->desc.design_hi[1], h->desc.design_hi[2]);
-    for (int ax = 0; ax < 3; ax++) a.profv[ax] = h->profv[ax];
-    a.xcd_remap = 1;
-    a.fstride = h->fstride;
-    for (int ax = 0; ax < 3; ax++) a.pstride[ax] = h->pstride[ax];
-    const int kt = 0;   // tile table slot of the reverse march
-    const bool par = h->side[0] != nullptr;
-    if (par) HIPCHK(h, hipEventRecord(h->fork, h->stream));
-    for (int c = 0; c < 4; c++) {
-        a.tiles = h->tiles + 2 * (size_t)h->tb_off[kt][c];
-        a.ntiles = h->tb_cnt[kt][c];
-        if (a.ntiles == 0) continue;
-        hipStream_t st = (par && c > 0) ? h->side[c - 1] : h->stream;
-        if (st != h->stream) HIPCHK(h, hipStreamWaitEvent(st, h->fork, 0));
-        HIPCHK(h, launch_tb_reverse_class(a, c, h->wide, st));
-        if (st != h->stream) {
-            HIPCHK(h, hipEventRecord(h->join[c - 1], st));
-            HIPCHK(h, hipStreamWaitEvent(h->stream, h->join[c - 1], 0));
-        }
-    }
+    RevReq q;
+    q.args = (unsigned long long)(uintptr_t)h->rargs;
+    q.tiles = h->tiles + 2 * (size_t)h->tb_off[0];
+    q.rec_h = (do_inv && G.p > 0) ? h->rec + (size_t)n * G.R.per_step : nullptr;
+    q.rec_e = (do_inv && G.p > 0 && n > 0) ? h->rec + (size_t)(n - 1) * G.R.per_step : nullptr;
+    q.gacc = gacc;
+    q.fin = fin;
+    q.n = n;
+    q.first = first;
+    q.flags = (h->cur ? RV_CUR : 0u) | (h->acur ? RV_ACUR : 0u) | (h->apar ? RV_APAR : 0u) |
+              (do_inv ? RV_INV : 0u) | (do_adj ? RV_ADJ : 0u) | ((with_det && G.D.ndet > 0) ? RV_DET : 0u);
+    q.pad = 0;
+    return q;
+}
+
+// the buffer swaps after a reverse step
+void rev_epilogue(fdtd_ctx *h, int do_inv, int do_adj)
+{
     if (do_inv) h->cur ^= 1;
     if (do_adj) {
         h->acur ^= 1;
         h->apar ^= 1;
     }
+}
+
+fdtd_status reverse_fused(fdtd_ctx *h, int n, int do_inv, int do_adj, int with_det, float *gacc,
+                          const Fields *fin = nullptr)
+{
+    RevLaunch L;
+    L.nreq = 1;
+    L.nblocks = h->tb_n[0];
+    L.xcd_remap = 1;
+    L.pad = 0;
+    L.r[0] = rev_request(h, n, do_inv, do_adj, with_det, gacc, fin ? fin->c[0] : nullptr, 0);
+    HIPCHK(h, launch_tb_reverse(L, h->wide, h->stream));
+    rev_epilogue(h, do_inv, do_adj);
     return FDTD_OK;
+}
+
+// the z-marches' fixed arguments of handle h (host copies)
+void fill_static_args(fdtd_ctx *h)
+{
+    const Geometry &G = h->geo;
+    TbArgs &t = h->host_targs;
+    memset(&t, 0, sizeof t);
+    t.g = h->g;
+    for (int b = 0; b < 2; b++) {
+        for (int q = 0; q < 6; q++) t.fld[b][q] = h->fld[b][q];
+        for (int a = 0; a < 3; a++) t.psi[b][a] = h->psi[b][a][0];
+    }
+    t.R = G.R;
+    t.D = G.D;
+    for (int a = 0; a < 3; a++) t.profv[a] = h->profv[a];
+    t.fstride = h->fstride;
+    for (int a = 0; a < 3; a++) t.pstride[a] = h->pstride[a];
+    RevArgs &r = h->host_rargs;
+    memset(&r, 0, sizeof r);
+    r.g = h->g;
+    for (int b = 0; b < 2; b++) {
+        for (int q = 0; q < 6; q++) {
+            r.fld[b][q] = h->fld[b][q];
+            r.adj[b][q] = h->adj[b][q];
+        }
+        for (int a = 0; a < 3; a++) r.pb[b][a] = h->pb[b][a][0];
+    }
+    r.R = G.R;
+    r.D = G.D;
+    for (int m = 0; m < FD_MAXDET; m++) r.wS[m] = h->wS_plain[m];
+    r.dlo = make_int3(h->desc.design_lo[0], h->desc.design_lo[1], h->desc.design_lo[2]);
+    r.dhi = make_int3(h->desc.design_hi[0], h->desc.design_hi[1], h->desc.design_hi[2]);
+    for (int a = 0; a < 3; a++) r.profv[a] = h->profv[a];
+    r.fstride = h->fstride;
+    for (int a = 0; a < 3; a++) r.pstride[a] = h->pstride[a];
 }
 
 fdtd_status upload_materials(fdtd_ctx *h, const float *inv_eps)
@@ -962,6 +1006,14 @@ fdtd_status fdtd_create(const fdtd_desc *desc, const fdtd_source *src, int32_t n
                                       hipMemcpyHostToDevice, h->stream);
         if (e != hipSuccess) { fdtd_status r = fail(nullptr, FDTD_E_DEVICE, "tiles: %s", hipGetErrorString(e)); delete h; return r; }
     }
+    // the z-marches' fixed arguments
+    fill_static_args(h);
+    {
+        hipError_t e = hipMemcpyAsync(h->targs, &h->host_targs, sizeof(TbArgs), hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h->rargs, &h->host_rargs, sizeof(RevArgs), hipMemcpyHostToDevice, h->stream);
+        if (e != hipSuccess) { fdtd_status r = fail(nullptr, FDTD_E_DEVICE, "args: %s", hipGetErrorString(e)); delete h; return r; }
+    }
     // the caller's amplitudes: plain sources into their slots, TFSF waveforms
     // into the workspace (upload_materials runs their incident lines)
     for (int q = 0; q < nint; q++) {
@@ -992,20 +1044,6 @@ fdtd_status fdtd_create(const fdtd_desc *desc, const fdtd_source *src, int32_t n
         fail(nullptr, FDTD_E_DEVICE, "create sync: %s", hipGetErrorString(e));
         delete h;
         return FDTD_E_DEVICE;
-    }
-    // side streams for concurrent tile classes (large grids only: on small
-    // grids the fork/join costs more than it saves)
-    if (!h->naive && G.N >= (1LL << 22) && getenv("FDTD_TB_SERIAL") == nullptr) {
-        bool ok = hipEventCreateWithFlags(&h->fork, hipEventDisableTiming) == hipSuccess;
-        for (int i = 0; i < 3 && ok; i++) {
-            ok = hipStreamCreateWithFlags(&h->side[i], hipStreamNonBlocking) == hipSuccess &&
-                 hipEventCreateWithFlags(&h->join[i], hipEventDisableTiming) == hipSuccess;
-        }
-        if (!ok) {
-            fail(nullptr, FDTD_E_DEVICE, "side stream creation failed");
-            fdtd_destroy(h);
-            return FDTD_E_DEVICE;
-        }
     }
     h->t = 0;
     *out = h;
@@ -1324,16 +1362,8 @@ fdtd_status fdtd_reset(fdtd_handle h)
 fdtd_status fdtd_destroy(fdtd_handle h)
 {
     if (!h) return FDTD_OK;
-    // release everything, then report the first failure
-    hipError_t first = hipSuccess;
-    auto keep = [&](hipError_t e) { if (first == hipSuccess) first = e; };
-    for (int i = 0; i < 3; i++) {
-        if (h->side[i]) keep(hipStreamDestroy(h->side[i]));
-        if (h->join[i]) keep(hipEventDestroy(h->join[i]));
-    }
-    if (h->fork) keep(hipEventDestroy(h->fork));
+    // the handle owns host state only
     delete h;
-    if (first != hipSuccess) return fail(nullptr, FDTD_E_DEVICE, "destroy: %s", hipGetErrorString(first));
     return FDTD_OK;
 }
 

@@ -177,30 +177,48 @@ hipError_t launch_scale_ce(const float *inv_eps, float S, float *ce, long long n
 hipError_t launch_gather_box(const float *src, const Grid &g, const int *lo, const int *hi,
                              float *dst, hipStream_t s);
 
-// temporally blocked forward pass over K steps (fields and psi ping-pong)
+// ---------------------------------------------------------------- z-marches
+// A z-march launch covers the tiles of every class of one or more handles
+// (a batch of requests): block b finds its request r by the prefix counts
+// first[], its tile in that request's table, and the tile's class picks the
+// kernel body (bit 0: an x CPML slab in the halo-extended footprint, bit 1:
+// a y slab).  What stays fixed over a handle's life (grid, both buffer sets,
+// geometry of records and detectors) lives in device memory, one struct per
+// handle, written at create; what changes per launch (step index, which
+// buffer is current, per-step pointers) travels in the launch arguments.
+constexpr int ZM_MAXREQ = 32;
+
+// forward pass over K steps (fields and psi ping-pong)
 struct TbArgs {
     Grid g;
-    Fields in, out;
-    Psi pin, pout;
-    int n0;                 // first step index of this block of K steps
-    int with_src;
-    float *rec;             // record of step n0 (or nullptr); step n0+s at rec + s*per_step
+    float *fld[2][6];       // the two field sets: component q of set b
+    float *psi[2][3];       // the two CPML auxiliary sets: auxiliary 0 of slab axis a
     RecGeom R;
+    Detectors D;
+    const float4 *profv[3]; // per axis, per index: (b, a, 1/kappa) at E then H positions
+    unsigned fstride;       // bytes from component q to q+1 of a field set (both sets alike)
+    unsigned pstride[3];    // bytes from CPML auxiliary q to q+1 of axis a (both sets alike)
+};
+enum { TB_CUR = 1, TB_SRC = 2 };
+struct TbReq {
+    unsigned long long args;   // device address of the handle's TbArgs
+    const int4 *tiles;      // per tile two int4: (x0, x1, y0, y1), (z0, z1, class, 0) owned box
+    float *rec;             // record of step n0 (or nullptr); step n0+s at rec + s*per_step
     float *planes;          // detector flux planes of step n0 (or nullptr); + s*D.per_step
     float *raw;             // raw planes of the interpolated detectors, step n0; + s*D.raw_per_step
-    Detectors D;
-    const int4 *tiles;      // per tile two int4: (x0, x1, y0, y1), (z0, z1, class, 0) owned box
-    int ntiles;
-    const float4 *profv[3]; // per axis, per index: (b, a, 1/kappa) at E then H positions
-    int xcd_remap;          // 1: map consecutive tiles to one XCD
-    unsigned fstride;       // bytes from component q to q+1 of a field set (in and out alike)
-    unsigned pstride[3];    // bytes from CPML auxiliary q to q+1 of axis a (pin and pout alike)
+    int n0;                 // first step index of this block of K steps
+    int first;              // first block of this request in the launch
+    unsigned flags;         // TB_CUR: set 1 is the input; TB_SRC: apply sources
+    int pad;
 };
-// one sweep of K steps over the tiles of class cls (bit 0: an x CPML slab in
-// the halo-extended footprint, bit 1: a y slab)
-// (wide: the instance with a 64-bit base per component and plane, for field
-// sets of 4 GiB or more; fstride is unused there)
-hipError_t launch_tb_forward_class(const TbArgs &a, int K, int cls, int shape, bool wide, hipStream_t s);
+struct TbLaunch {
+    int nreq, nblocks, xcd_remap, pad;
+    TbReq r[ZM_MAXREQ];
+};
+// one sweep of K steps over every tile of the launch (wide: the instance
+// with a 64-bit base per component and plane, for field sets of 4 GiB or
+// more; fstride is unused there)
+hipError_t launch_tb_forward(const TbLaunch &L, int K, int shape, bool wide, hipStream_t s);
 int tb_tile_x(int K, int shape);
 int tb_tile_y(int K, int shape);
 bool tb_tile_aligned(int shape);   // x tiles start on 128-byte lines (uniform split)
@@ -210,27 +228,37 @@ int tb_max_pml();
 // fused reverse step (inverse + adjoint) as a z-march, tile halo rev_halo()
 struct RevArgs {
     Grid g;
-    Fields fin, fout;        // forward state s_{n+1} -> s_n (interior cells written)
-    Fields ain, aout;        // adjoint fields
-    Psi pin, pout;           // CPML auxiliaries of the adjoint (all four per slab axis)
-    int n;                   // forward step being reversed
-    int do_inv, do_adj, with_det;
-    const float *rec_h;      // record of step n (H on the low faces) or nullptr
-    const float *rec_e;      // record of step n-1 (E on the high faces) or nullptr (E^0 = 0)
+    float *fld[2][6];        // the two forward field sets
+    float *adj[2][6];        // the two adjoint field sets
+    float *pb[2][3];         // the two psi-bar sets: auxiliary 0 of slab axis a
     RecGeom R;
     Detectors D;
-    float wS[FD_MAXDET];     // S * detector weight
-    float *gacc;             // dJ/dd accumulator over the design box (or nullptr)
-    int3 dlo, dhi;
-    const int4 *tiles;
-    int ntiles;
+    float wS[FD_MAXDET];     // S * detector weight (interpolated detectors 0)
+    int3 dlo, dhi;           // design box
     const float4 *profv[3];
-    int xcd_remap;
     unsigned fstride;        // bytes from component q to q+1 of a field or adjoint set
-    unsigned pstride[3];     // bytes from auxiliary q to q+1 of axis a (pin and pout alike)
+    unsigned pstride[3];     // bytes from auxiliary q to q+1 of axis a (both sets alike)
 };
-// (wide: 64-bit component bases per plane, for sets of 4 GiB or more)
-hipError_t launch_tb_reverse_class(const RevArgs &a, int cls, bool wide, hipStream_t s);
+// RV_CUR: forward set 1 is s_{n+1}; RV_ACUR: adjoint set 1 is the input;
+// RV_APAR: psi-bar set 1 is the input
+enum { RV_CUR = 1, RV_ACUR = 2, RV_APAR = 4, RV_INV = 8, RV_ADJ = 16, RV_DET = 32 };
+struct RevReq {
+    unsigned long long args;  // device address of the handle's RevArgs
+    const int4 *tiles;
+    const float *rec_h;      // record of step n (H on the low faces) or nullptr
+    const float *rec_e;      // record of step n-1 (E on the high faces) or nullptr (E^0 = 0)
+    float *gacc;             // dJ/dd accumulator over the design box (or nullptr)
+    const float *fin;        // forward state read instead of set RV_CUR (or nullptr)
+    int n;                   // forward step being reversed
+    int first;
+    unsigned flags;
+    int pad;
+};
+struct RevLaunch {
+    int nreq, nblocks, xcd_remap, pad;
+    RevReq r[ZM_MAXREQ];
+};
+hipError_t launch_tb_reverse(const RevLaunch &L, bool wide, hipStream_t s);
 int rev_halo();
 int rev_tile_x();
 int rev_tile_y();

@@ -89,22 +89,28 @@ __device__ __forceinline__ float cpml_term_h(float d, float &psi, float b, float
     return fmaf(d, kinv, psi);
 }
 
-// TX lanes of a wave row span x; W waves; R rows per thread.  The register
-// budget allows 4 waves per SIMD (two workgroups per CU at 512 threads).
+// The handle's fixed arguments and the launch's per-request arguments, read
+// with scalar loads from constant memory.
+typedef const __attribute__((address_space(4))) TbArgs KArgs;
+typedef const __attribute__((address_space(4))) TbReq KReq;
+typedef const __attribute__((address_space(4))) TbLaunch KLaunch;
+
+// One tile's march.  TX lanes of a wave row span x; W waves; R rows per
+// thread.  The LDS arrays belong to the kernel (one set whatever the class).
 template <int K, bool XP, bool YP, int PD, int W, int R, int TX, bool WIDE>
-__global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
+__device__ __forceinline__ void tb_march(KArgs &A, KArgs *Kp, KReq *Rq, const int4 tl, const int4 tz,
+                                         float (*sE)[(64 * W / TX) * R + 1][TX],
+                                         float (*sH)[(64 * W / TX) * R + 1][TX], float (*sGz)[6],
+                                         float (*sAmp)[K])
 {
     constexpr int EX = TX;
     constexpr int EY = (64 * W / TX) * R;
-    // (one spare row for the threads beyond the last full row when TX does
-    // not divide the workgroup: they compute on it and write nothing)
-    __shared__ float sE[3][EY + 1][EX];
-    __shared__ float sH[3][EY + 1][EX];
-    // z grading of the 2p slab planes (E b, a, 1/k, H b, a, 1/k) and the
-    // source amplitudes of the K steps of this sweep, staged once so the
-    // march never waits on a vector load other than its own plane fetches
-    __shared__ float sGz[2 * TB_MAXP][6];
-    __shared__ float sAmp[FD_MAXSRC][K];
+    const int n0 = Rq->n0;
+    const unsigned ic = Rq->flags & TB_CUR;   // input buffer set
+    const bool with_src = (Rq->flags & TB_SRC) != 0;
+    float *const rec_n0 = Rq->rec;
+    float *const planes = Rq->planes;
+    float *const raw_n0 = Rq->raw;
 
     const int nx = A.g.nx, ny = A.g.ny, nz = A.g.nz, p = A.g.p;
     for (int e = threadIdx.x; e < 2 * p; e += blockDim.x) {
@@ -115,14 +121,11 @@ __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
     }
     if ((int)threadIdx.x < FD_MAXSRC * K) {
         const int q = threadIdx.x / K, s = threadIdx.x % K;
-        sAmp[q][s] = (A.with_src && q < A.g.nsrc) ? A.g.samp[q][A.n0 + s] : 0.f;
+        sAmp[q][s] = (with_src && q < A.g.nsrc) ? A.g.samp[q][n0 + s] : 0.f;
     }
     __syncthreads();
     const unsigned nxy = (unsigned)A.g.nxy;
     const float S = A.g.S;
-    int b = blockIdx.x;
-    if (A.xcd_remap) b = remap_xcd(b, gridDim.x);
-    const int4 tl = A.tiles[2 * b], tz = A.tiles[2 * b + 1];
     const int x0 = tl.x, x1 = tl.y, y0 = tl.z, y1 = tl.w, z0 = tz.x, z1 = tz.y;
     const bool active = (int)threadIdx.x < EX * (EY / R);
     const int lane = active ? (int)threadIdx.x % EX : 0;
@@ -166,7 +169,7 @@ __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
 
     // one base per buffer set: component q of a field set at q * fs bytes,
     // CPML auxiliary q of axis a at q * A.pstride[a] bytes (32-bit offsets)
-    const float *__restrict__ iF = A.in.c[0];
+    const float *__restrict__ iF = A.fld[ic][0];
     const float *__restrict__ ice = A.g.ce;
     const unsigned fs = A.fstride;
 
@@ -176,8 +179,6 @@ __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
     // whole march (the argument block is the kernel's only parameter, at
     // offset 0 of the kernel-argument segment): the source arguments, and the
     // component bases of the WIDE instance.
-    typedef const __attribute__((address_space(4))) TbArgs KArgs;
-    KArgs *Kp = (KArgs *)__builtin_amdgcn_kernarg_segment_ptr();
 
     auto load_plane = [&](int t, Plane<R, XP, YP> &P) {
         const bool tin = t >= 0 && t < nz;
@@ -188,8 +189,8 @@ __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
                 const unsigned c = off[r] * 4u;
 #pragma unroll
                 for (int q = 0; q < 3; q++) {
-                    P.e[r][q] = ldo(Kp->in.c[q] + pb, c);
-                    P.h[r][q] = ldo(Kp->in.c[3 + q] + pb, c);
+                    P.e[r][q] = ldo(Kp->fld[ic][q] + pb, c);
+                    P.h[r][q] = ldo(Kp->fld[ic][3 + q] + pb, c);
                 }
                 P.ce[r] = ldo(Kp->g.ce + pb, c);
                 psi_zero<XP, YP>(P.p[r]);
@@ -216,7 +217,7 @@ __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
                 for (int r = 0; r < R; r++) {
                     const unsigned o = (zb + off[r]) * 4u;
 #pragma unroll
-                    for (int q = 0; q < 4; q++) P.p[r].z[q] = ldo(A.pin.a[2][0], o + q * ps);
+                    for (int q = 0; q < 4; q++) P.p[r].z[q] = ldo(A.psi[ic][2], o + q * ps);
                 }
             }
             if constexpr (XP) {
@@ -226,7 +227,7 @@ __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
                 for (int r = 0; r < R; r++) {
                     const unsigned o = (xb + soff_x[r]) * 4u;
 #pragma unroll
-                    for (int q = 0; q < 4; q++) P.p[r].x[q] = ldo(A.pin.a[0][0], o + q * ps);
+                    for (int q = 0; q < 4; q++) P.p[r].x[q] = ldo(A.psi[ic][0], o + q * ps);
                 }
             }
             if constexpr (YP) {
@@ -236,7 +237,7 @@ __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
                 for (int r = 0; r < R; r++) {
                     const unsigned o = (yb + soff_y[r]) * 4u;
 #pragma unroll
-                    for (int q = 0; q < 4; q++) P.p[r].y[q] = ldo(A.pin.a[1][0], o + q * ps);
+                    for (int q = 0; q < 4; q++) P.p[r].y[q] = ldo(A.psi[ic][1], o + q * ps);
                 }
             }
         }
@@ -246,7 +247,7 @@ __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
     // per-level test issues no scalar memory load
     int skq[FD_MAXSRC];
 #pragma unroll
-    for (int q = 0; q < FD_MAXSRC; q++) skq[q] = (A.with_src && q < A.g.nsrc) ? A.g.sk[q] : (-2147483647 - 1);
+    for (int q = 0; q < FD_MAXSRC; q++) skq[q] = (with_src && q < A.g.nsrc) ? A.g.sk[q] : (-2147483647 - 1);
     // The other source arguments are read through the opaque argument
     // pointer Kp (below).
 
@@ -426,7 +427,7 @@ __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
                     }
                 }
                 // ---- detector flux planes (uniform plane test)
-                if (A.planes && k >= z0 && k < z1 && k >= A.D.kmin && k <= A.D.kmax) {
+                if (planes && k >= z0 && k < z1 && k >= A.D.kmin && k <= A.D.kmax) {
                     for (int m = 0; m < A.D.ndet; m++) {
                         // an energy detector also takes Ez of the layer below its plane
                         const bool at = k == A.D.k[m], below = A.D.energy[m] && k == A.D.k[m] - 1;
@@ -442,7 +443,7 @@ __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
                             for (int r = 0; r < R; r++) {
                                 const int yy = ys[r];
                                 if (own[r] && x >= A.D.i0[m] && x <= A.D.i1[m] && yy >= A.D.j0[m] && yy <= A.D.j1[m]) {
-                                    float *rw = A.raw + (long long)(s - 1) * A.D.raw_per_step + A.D.roff[m] +
+                                    float *rw = raw_n0 + (long long)(s - 1) * A.D.raw_per_step + A.D.roff[m] +
                                                 (long long)(yy - A.D.j0[m]) * wx + (x - A.D.i0[m]);
                                     if (at) {
                                         rw[0] = mE[r][0];
@@ -469,15 +470,15 @@ __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
                             if (own[r] && x >= A.D.i0[m] && x < A.D.i1[m] && yy >= A.D.j0[m] && yy < A.D.j1[m]) {
                                 const long long e = A.D.off[m] + (long long)(yy - A.D.j0[m]) * (A.D.i1[m] - A.D.i0[m]) +
                                                     (x - A.D.i0[m]);
-                                A.planes[(long long)(s - 1) * A.D.per_step + e] =
+                                planes[(long long)(s - 1) * A.D.per_step + e] =
                                     flux_density(mE[r][0], mE[r][1], mH[r][0], mH[r][1]);
                             }
                         }
                     }
                 }
                 // ---- interface record (section 2.2)
-                if (A.rec && k >= z0 && k < z1 && k >= p - 1 && k <= nz - p) {
-                    float *rs = A.rec + (long long)(s - 1) * A.R.per_step;
+                if (rec_n0 && k >= z0 && k < z1 && k >= p - 1 && k <= nz - p) {
+                    float *rs = rec_n0 + (long long)(s - 1) * A.R.per_step;
                     const bool wz = k >= p && k < nz - p;
 #pragma unroll
                     for (int r = 0; r < R; r++) {
@@ -549,13 +550,13 @@ __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
                     const unsigned c = off[r] * 4u;
 #pragma unroll
                     for (int q = 0; q < 3; q++) {
-                        sto(Kp->out.c[q] + pb, c, nE[r][q]);
-                        sto(Kp->out.c[3 + q] + pb, c, nH[r][q]);
+                        sto(Kp->fld[ic ^ 1][q] + pb, c, nE[r][q]);
+                        sto(Kp->fld[ic ^ 1][3 + q] + pb, c, nH[r][q]);
                     }
                 }
             } else {
                 const unsigned base = (unsigned)kK * nxy;
-                float *__restrict__ oF = A.out.c[0];
+                float *__restrict__ oF = A.fld[ic ^ 1][0];
 #pragma unroll
                 for (int r = 0; r < R; r++) {
                     if (!own[r]) continue;
@@ -577,7 +578,7 @@ __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
                         if (own[r]) {
                             const unsigned o = (zb + off[r]) * 4u;
 #pragma unroll
-                            for (int q = 0; q < 4; q++) sto(A.pout.a[2][0], o + q * ps, nP[r].z[q]);
+                            for (int q = 0; q < 4; q++) sto(A.psi[ic ^ 1][2], o + q * ps, nP[r].z[q]);
                         }
                 }
                 if constexpr (XP) {
@@ -589,7 +590,7 @@ __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
                             if (own[r]) {
                                 const unsigned o = (xb + soff_x[r]) * 4u;
 #pragma unroll
-                                for (int q = 0; q < 4; q++) sto(A.pout.a[0][0], o + q * ps, nP[r].x[q]);
+                                for (int q = 0; q < 4; q++) sto(A.psi[ic ^ 1][0], o + q * ps, nP[r].x[q]);
                             }
                     }
                 }
@@ -601,7 +602,7 @@ __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
                         if (own[r] && sy[r] >= 0) {
                             const unsigned o = (yb + soff_y[r]) * 4u;
 #pragma unroll
-                            for (int q = 0; q < 4; q++) sto(A.pout.a[1][0], o + q * ps, nP[r].y[q]);
+                            for (int q = 0; q < 4; q++) sto(A.psi[ic ^ 1][1], o + q * ps, nP[r].y[q]);
                         }
                 }
             }
@@ -626,17 +627,51 @@ __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbArgs A)
     }
 }
 
+// The kernel: block b (XCD-remapped) finds its request and tile; the tile's
+// class picks the march instance.
+template <int K, int PD, int W, int R, int TX, bool WIDE>
+__global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbLaunch)
+{
+    constexpr int EY = (64 * W / TX) * R;
+    // (one spare row for the threads beyond the last full row when TX does
+    // not divide the workgroup: they compute on it and write nothing)
+    __shared__ float sE[3][EY + 1][TX];
+    __shared__ float sH[3][EY + 1][TX];
+    // z grading of the 2p slab planes (E b, a, 1/k, H b, a, 1/k) and the
+    // source amplitudes of the K steps of this sweep, staged once so the
+    // march never waits on a vector load other than its own plane fetches
+    __shared__ float sGz[2 * TB_MAXP][6];
+    __shared__ float sAmp[FD_MAXSRC][K];
+    // (the launch block is the kernel's only parameter, at offset 0 of the
+    // kernel-argument segment)
+    KLaunch *Lp = (KLaunch *)__builtin_amdgcn_kernarg_segment_ptr();
+    int b = blockIdx.x;
+    if (Lp->xcd_remap) b = remap_xcd(b, gridDim.x);
+    int r = 0;
+    while (r + 1 < Lp->nreq && b >= Lp->r[r + 1].first) r++;
+    KReq *Rq = &Lp->r[r];
+    // Arguments used only now and then are read through a copy of this
+    // pointer that is made opaque on every plane, so they are fetched where
+    // they are used instead of being held in scalar registers for the whole
+    // march: the source arguments, and the component bases of the WIDE
+    // instance.
+    KArgs *Ap = (KArgs *)Rq->args;
+    const int4 *tt = Rq->tiles + 2 * (b - Rq->first);
+    const int4 tl = tt[0], tz = tt[1];
+    switch (tz.z) {
+    case 0: tb_march<K, false, false, PD, W, R, TX, WIDE>(*Ap, Ap, Rq, tl, tz, sE, sH, sGz, sAmp); break;
+    case 1: tb_march<K, true, false, PD, W, R, TX, WIDE>(*Ap, Ap, Rq, tl, tz, sE, sH, sGz, sAmp); break;
+    case 2: tb_march<K, false, true, PD, W, R, TX, WIDE>(*Ap, Ap, Rq, tl, tz, sE, sH, sGz, sAmp); break;
+    default: tb_march<K, true, true, PD, W, R, TX, WIDE>(*Ap, Ap, Rq, tl, tz, sE, sH, sGz, sAmp); break;
+    }
+}
+
 template <int K, int W, int R, int PD, int TX, bool WIDE = false>
-hipError_t launch_kwrp(const TbArgs &a, int cls, hipStream_t s)
+hipError_t launch_kwrp(const TbLaunch &L, hipStream_t s)
 {
     constexpr int threads = 64 * W;
-    if (a.ntiles <= 0) return hipSuccess;
-    switch (cls) {
-    case 0: hipLaunchKernelGGL((k_tb_forward<K, false, false, PD, W, R, TX, WIDE>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
-    case 1: hipLaunchKernelGGL((k_tb_forward<K, true, false, PD, W, R, TX, WIDE>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_tb_forward<K, false, true, PD, W, R, TX, WIDE>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_tb_forward<K, true, true, PD, W, R, TX, WIDE>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
-    }
+    if (L.nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_tb_forward<K, PD, W, R, TX, WIDE>), dim3(L.nblocks), dim3(threads), 0, s, L);
     return hipGetLastError();
 }
 
@@ -658,16 +693,16 @@ constexpr int TB_WIDE_SHAPE = 3;
 __host__ __device__ constexpr int shape_tx(int sh, int K) { return sh == 0 ? 64 : sh == 1 ? 32 : ALIGN_X + 2 * K; }
 
 template <int K>
-hipError_t launch_k(const TbArgs &a, int cls, int shape, bool wide, hipStream_t s)
+hipError_t launch_k(const TbLaunch &L, int shape, bool wide, hipStream_t s)
 {
     // the 64-bit-base instance exists for the default shape only
-    if (wide) return shape == TB_WIDE_SHAPE ? launch_kwrp<K, 8, 1, 1, ALIGN_X + 2 * K, true>(a, cls, s)
+    if (wide) return shape == TB_WIDE_SHAPE ? launch_kwrp<K, 8, 1, 1, ALIGN_X + 2 * K, true>(L, s)
                                             : hipErrorInvalidValue;
     switch (shape) {
-    case 0: return launch_kwrp<K, 16, 1, 1, 64>(a, cls, s);
-    case 2: return launch_kwrp<K, 16, 1, 1, ALIGN_X + 2 * K>(a, cls, s);
-    case 3: return launch_kwrp<K, 8, 1, 1, ALIGN_X + 2 * K>(a, cls, s);
-    default: return launch_kwrp<K, 8, 1, 1, 32>(a, cls, s);
+    case 0: return launch_kwrp<K, 16, 1, 1, 64>(L, s);
+    case 2: return launch_kwrp<K, 16, 1, 1, ALIGN_X + 2 * K>(L, s);
+    case 3: return launch_kwrp<K, 8, 1, 1, ALIGN_X + 2 * K>(L, s);
+    default: return launch_kwrp<K, 8, 1, 1, 32>(L, s);
     }
 }
 
@@ -685,15 +720,14 @@ int tb_tile_y(int K, int shape)
 bool tb_tile_aligned(int shape) { return shape_index(shape) >= 2; }
 bool tb_wide_shape(int shape) { return shape_index(shape) == TB_WIDE_SHAPE; }
 
-// Tiles of class cls: bit 0 = x CPML slab in the extended footprint, bit 1 = y.
-hipError_t launch_tb_forward_class(const TbArgs &a, int K, int cls, int shape, bool wide, hipStream_t s)
+hipError_t launch_tb_forward(const TbLaunch &L, int K, int shape, bool wide, hipStream_t s)
 {
     shape = shape_index(shape);
     switch (K) {
-    case 1: return launch_k<1>(a, cls, shape, wide, s);
-    case 2: return launch_k<2>(a, cls, shape, wide, s);
-    case 3: return launch_k<3>(a, cls, shape, wide, s);
-    case 4: return launch_k<4>(a, cls, shape, wide, s);
+    case 1: return launch_k<1>(L, shape, wide, s);
+    case 2: return launch_k<2>(L, shape, wide, s);
+    case 3: return launch_k<3>(L, shape, wide, s);
+    case 4: return launch_k<4>(L, shape, wide, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -69,17 +69,48 @@ template <bool XP, bool YP> struct RPlane {
 // WIDE: field and adjoint sets of 4 GiB or more, addressed per plane from a
 // 64-bit base per component (read through Kp) plus the 32-bit offset of the
 // column within the plane; otherwise one base per set with 32-bit offsets.
-template <bool XP, bool YP, bool WIDE>
-__global__ __launch_bounds__(NT, 4) void k_tb_reverse(RevArgs A)
-{
-    __shared__ float sH[3][EY + 1][EX];
-    __shared__ float sQ[4][EY + 1][EX];
-    __shared__ float sEn[3][EY + 1][EX];
-    __shared__ float sR[4][EY + 1][EX];
-    __shared__ float sGz[2 * 64][6];
-    __shared__ float sAmp[FD_MAXSRC];   // source amplitudes of step n
+// The handle's fixed arguments and the launch's per-request arguments, read
+// with scalar loads from constant memory.
+typedef const __attribute__((address_space(4))) RevArgs KArgs;
+typedef const __attribute__((address_space(4))) RevReq KReq;
+typedef const __attribute__((address_space(4))) RevLaunch KLaunch;
+typedef const __attribute__((address_space(4))) Grid KGrid;
 
-    const Grid &g = A.g;
+// LDS of the kernel, one set whatever the tile class
+struct RevLds {
+    float sH[3][EY + 1][EX];
+    float sQ[4][EY + 1][EX];
+    float sEn[3][EY + 1][EX];
+    float sR[4][EY + 1][EX];
+    float sGz[2 * 64][6];
+    float sAmp[FD_MAXSRC];   // source amplitudes of step n
+};
+
+// One tile's reverse march.
+template <bool XP, bool YP, bool WIDE>
+__device__ __forceinline__ void rev_march(KArgs &A, KArgs *Kp, KReq *Rq, const int4 tl, const int4 tz, RevLds &L_)
+{
+    auto &sH = L_.sH;
+    auto &sQ = L_.sQ;
+    auto &sEn = L_.sEn;
+    auto &sR = L_.sR;
+    auto &sGz = L_.sGz;
+    auto &sAmp = L_.sAmp;
+    const int n = Rq->n;
+    const unsigned fl = Rq->flags;
+    const bool do_inv = (fl & RV_INV) != 0, do_adj = (fl & RV_ADJ) != 0, with_det = (fl & RV_DET) != 0;
+    const int ic = (fl & RV_CUR) ? 1 : 0, ia = (fl & RV_ACUR) ? 1 : 0, ip = (fl & RV_APAR) ? 1 : 0;
+    // forward state s_{n+1} in and s_n out, adjoint in and out (without the
+    // adjoint the march still issues its adjoint loads, from the forward
+    // input set, and drops them), psi-bar in and out
+    const float *const fin0 = Rq->fin ? Rq->fin : A.fld[ic][0];
+    float *const fout0 = A.fld[ic ^ 1][0];
+    const float *const ain0 = do_adj ? A.adj[ia][0] : A.fld[ic][0];
+    float *const aout0 = A.adj[ia ^ 1][0];
+    const bool has_rec_h = Rq->rec_h != nullptr, has_rec_e = Rq->rec_e != nullptr;
+    const bool has_gacc = Rq->gacc != nullptr;
+
+    KGrid &g = A.g;
     const int nx = g.nx, ny = g.ny, nz = g.nz, p = g.p;
     const unsigned nxy = (unsigned)g.nxy;
     const float S = g.S;
@@ -89,7 +120,7 @@ __global__ __launch_bounds__(NT, 4) void k_tb_reverse(RevArgs A)
         sGz[e][0] = gE.x; sGz[e][1] = gE.y; sGz[e][2] = gE.z;
         sGz[e][3] = gH.x; sGz[e][4] = gH.y; sGz[e][5] = gH.z;
     }
-    if ((int)threadIdx.x < FD_MAXSRC) sAmp[threadIdx.x] = (int)threadIdx.x < g.nsrc ? g.samp[threadIdx.x][A.n] : 0.f;
+    if ((int)threadIdx.x < FD_MAXSRC) sAmp[threadIdx.x] = (int)threadIdx.x < g.nsrc ? g.samp[threadIdx.x][n] : 0.f;
     __syncthreads();
     // source and detector planes (uniform; -2^31 when absent), hoisted so the
     // per-plane tests issue no scalar memory load
@@ -98,19 +129,15 @@ __global__ __launch_bounds__(NT, 4) void k_tb_reverse(RevArgs A)
 #pragma unroll
     for (int q = 0; q < FD_MAXSRC; q++) skq[q] = q < g.nsrc ? g.sk[q] : NONE;
 #pragma unroll
-    for (int m = 0; m < FD_MAXDET; m++) dkq[m] = (A.do_adj && A.with_det && m < A.D.ndet) ? A.D.k[m] : NONE;
+    for (int m = 0; m < FD_MAXDET; m++) dkq[m] = (do_adj && with_det && m < A.D.ndet) ? A.D.k[m] : NONE;
     // Arguments used only on rare planes (record layers, detector, source)
     // are read through a copy of the argument pointer that is made opaque on
     // every plane, so they are fetched where used instead of being held in
     // scalar registers for the whole march.
     // (the argument block is the kernel's only parameter, at offset 0 of the
     // kernel-argument segment)
-    typedef const __attribute__((address_space(4))) RevArgs KArgs;
-    KArgs *Kp = (KArgs *)__builtin_amdgcn_kernarg_segment_ptr();
-
-    int b = blockIdx.x;
-    if (A.xcd_remap) b = remap_xcd_r(b, gridDim.x);
-    const int4 tl = A.tiles[2 * b], tz = A.tiles[2 * b + 1];
+    // The same holds for the per-request record and accumulator pointers.
+    KReq *Rk = Rq;
     const int x0 = tl.x, x1 = tl.y, y0 = tl.z, y1 = tl.w, z0 = tz.x, z1 = tz.y;
     const bool active = (int)threadIdx.x < EX * EY;
     const int lane = active ? (int)threadIdx.x % EX : 0;
@@ -153,29 +180,29 @@ __global__ __launch_bounds__(NT, 4) void k_tb_reverse(RevArgs A)
             const unsigned c = off * 4u;
 #pragma unroll
             for (int q = 0; q < 3; q++) {
-                P.e[q] = ld(Kp->fin.c[q] + pb, c);
-                P.h[q] = ld(Kp->fin.c[3 + q] + pb, c);
+                P.e[q] = ld(Kp->fld[ic][q] + pb, c);
+                P.h[q] = ld(Kp->fld[ic][3 + q] + pb, c);
             }
             P.ce = ld(Kp->g.ce + pb, c);
 #pragma unroll
             for (int q = 0; q < 3; q++) {
-                P.ae[q] = ld(Kp->ain.c[q] + pb, c);
-                P.ah[q] = ld(Kp->ain.c[3 + q] + pb, c);
+                P.ae[q] = ld((do_adj ? Kp->adj[ia][q] : Kp->fld[ic][q]) + pb, c);
+                P.ah[q] = ld((do_adj ? Kp->adj[ia][3 + q] : Kp->fld[ic][3 + q]) + pb, c);
             }
         } else {
             const unsigned c = ((unsigned)(tin ? t : 0) * nxy + off) * 4u;
 #pragma unroll
             for (int q = 0; q < 3; q++) {
-                P.e[q] = ld(A.fin.c[0], c + q * fs);
-                P.h[q] = ld(A.fin.c[0], c + (3 + q) * fs);
+                P.e[q] = ld(fin0, c + q * fs);
+                P.h[q] = ld(fin0, c + (3 + q) * fs);
             }
             P.ce = ld(g.ce, c);
             // (issued on every path, so the compiler's wait counts stay exact;
             // without an adjoint, ain points at a readable set and finish drops it)
 #pragma unroll
             for (int q = 0; q < 3; q++) {
-                P.ae[q] = ld(A.ain.c[0], c + q * fs);
-                P.ah[q] = ld(A.ain.c[0], c + (3 + q) * fs);
+                P.ae[q] = ld(ain0, c + q * fs);
+                P.ah[q] = ld(ain0, c + (3 + q) * fs);
             }
         }
 #pragma unroll
@@ -188,29 +215,29 @@ __global__ __launch_bounds__(NT, 4) void k_tb_reverse(RevArgs A)
 #pragma unroll
             for (int q = 0; q < 4; q++) P.pb.y[q] = 0.f;
         }
-        if (A.do_adj && p > 0 && tin) {
+        if (do_adj && p > 0 && tin) {
             const int szt = slab_coord(t, nz, p);
             if (szt >= 0) {
                 const unsigned zi = (unsigned)szt * nxy + off;
 #pragma unroll
-                for (int q = 0; q < 4; q++) P.pb.z[q] = ld(A.pin.a[2][0], zi * 4u + q * A.pstride[2]);
+                for (int q = 0; q < 4; q++) P.pb.z[q] = ld(A.pb[ip][2], zi * 4u + q * A.pstride[2]);
             }
             if constexpr (XP) {
                 const unsigned xi = (unsigned)t * (unsigned)ny * (unsigned)(2 * p) + soff_x;
 #pragma unroll
-                for (int q = 0; q < 4; q++) P.pb.x[q] = ld(A.pin.a[0][0], xi * 4u + q * A.pstride[0]);
+                for (int q = 0; q < 4; q++) P.pb.x[q] = ld(A.pb[ip][0], xi * 4u + q * A.pstride[0]);
             }
             if constexpr (YP) {
                 const unsigned yi = (unsigned)t * (unsigned)(2 * p) * (unsigned)nx + soff_y;
 #pragma unroll
-                for (int q = 0; q < 4; q++) P.pb.y[q] = ld(A.pin.a[1][0], yi * 4u + q * A.pstride[1]);
+                for (int q = 0; q < 4; q++) P.pb.y[q] = ld(A.pb[ip][1], yi * 4u + q * A.pstride[1]);
             }
         }
     };
     auto finish = [&](int t, const RPlane<XP, YP> &R, RPlane<XP, YP> &P) __attribute__((always_inline)) {
         const bool tin = t >= 0 && t < nz;
         const bool v = tin && incol;
-        const bool va = v && A.do_adj;
+        const bool va = v && do_adj;
 #pragma unroll
         for (int q = 0; q < 3; q++) {
             P.e[q] = v ? R.e[q] : 0.f;
@@ -221,25 +248,25 @@ __global__ __launch_bounds__(NT, 4) void k_tb_reverse(RevArgs A)
         P.ce = v ? R.ce : 0.f;
         P.pb = R.pb;
         // H^{n+1/2} on the low-face layers comes from the record of step n
-        if (A.rec_h && v && t >= p - 1 && t < nz - p) {
+        if (has_rec_h && v && t >= p - 1 && t < nz - p) {
             const bool wz = t >= p;
             if (t == p - 1 && wx && wy) {
                 const long long e = Kp->R.off[4] + (long long)(y - p) * Kp->R.Lu[2] + (x - p);
                 const long long fsr = (long long)Kp->R.Lu[2] * Kp->R.Lv[2];
-                P.h[0] = gld(Kp->rec_h + e);
-                P.h[1] = gld(Kp->rec_h + e + fsr);
+                P.h[0] = gld(Rk->rec_h + e);
+                P.h[1] = gld(Rk->rec_h + e + fsr);
             }
             if (wz && x == p - 1 && wy) {
                 const long long e = Kp->R.off[0] + (long long)(t - p) * Kp->R.Lu[0] + (y - p);
                 const long long fsr = (long long)Kp->R.Lu[0] * Kp->R.Lv[0];
-                P.h[1] = gld(Kp->rec_h + e);
-                P.h[2] = gld(Kp->rec_h + e + fsr);
+                P.h[1] = gld(Rk->rec_h + e);
+                P.h[2] = gld(Rk->rec_h + e + fsr);
             }
             if (wz && y == p - 1 && wx) {
                 const long long e = Kp->R.off[2] + (long long)(t - p) * Kp->R.Lu[1] + (x - p);
                 const long long fsr = (long long)Kp->R.Lu[1] * Kp->R.Lv[1];
-                P.h[2] = gld(Kp->rec_h + e);
-                P.h[0] = gld(Kp->rec_h + e + fsr);
+                P.h[2] = gld(Rk->rec_h + e);
+                P.h[0] = gld(Rk->rec_h + e + fsr);
             }
         }
         // detector adjoint source: dJ/dE^{n+1}, dJ/dH^{n+1/2} (uniform plane
@@ -387,16 +414,16 @@ __global__ __launch_bounds__(NT, 4) void k_tb_reverse(RevArgs A)
             const bool hex = y == 0 || a == 0, hey = x == 0 || a == 0, hez = x == 0 || y == 0;
             // dJ/dd += Ebar' . curl H^{n+1/2} (also in the adjoint-only mode,
             // where the forward state comes from storage instead of the inverse)
-            if (interior && A.do_adj && A.gacc && own && a >= z0 && a < z1 && in_design_xy && a >= A.dlo.z &&
+            if (interior && do_adj && has_gacc && own && a >= z0 && a < z1 && in_design_xy && a >= A.dlo.z &&
                 a < A.dhi.z) {
                 const long long dc = (long long)(a - A.dlo.z) * dplane + dxy;
-                float acc = gld(Kp->gacc + dc);
+                float acc = gld(Rk->gacc + dc);
                 if (!hex) acc = fmaf(Pa.ae[0], dy_hz - dz_hy, acc);
                 if (!hey) acc = fmaf(Pa.ae[1], dz_hx - dx_hz, acc);
                 if (!hez) acc = fmaf(Pa.ae[2], dx_hy - dy_hx, acc);
-                *(GLOBAL float *)(Kp->gacc + dc) = acc;
+                *(GLOBAL float *)(Rk->gacc + dc) = acc;
             }
-            if (A.do_inv && interior) {
+            if (do_inv && interior) {
                 float ex = Pa.e[0], ey = Pa.e[1], ez = Pa.e[2];
                 // sources, in order (uniform plane test against the hoisted
                 // source planes; one select per component)
@@ -418,31 +445,31 @@ __global__ __launch_bounds__(NT, 4) void k_tb_reverse(RevArgs A)
                 aEn[0] = ex; aEn[1] = ey; aEn[2] = ez;
             } else {
                 aEn[0] = Pa.e[0]; aEn[1] = Pa.e[1]; aEn[2] = Pa.e[2];
-                if (A.do_inv && p > 0 && incol && kin) {
+                if (do_inv && p > 0 && incol && kin) {
                     // E^n on the high-face layers from the record of step n-1 (E^0 = 0)
                     const bool wz = a >= p && a < nz - p;
                     if (a == nz - p && wx && wy) {
                         const long long e = Kp->R.off[5] + (long long)(y - p) * Kp->R.Lu[2] + (x - p);
                         const long long fsr = (long long)Kp->R.Lu[2] * Kp->R.Lv[2];
-                        aEn[0] = A.rec_e ? gld(Kp->rec_e + e) : 0.f;
-                        aEn[1] = A.rec_e ? gld(Kp->rec_e + e + fsr) : 0.f;
+                        aEn[0] = has_rec_e ? gld(Rk->rec_e + e) : 0.f;
+                        aEn[1] = has_rec_e ? gld(Rk->rec_e + e + fsr) : 0.f;
                     }
                     if (wz && x == nx - p && wy) {
                         const long long e = Kp->R.off[1] + (long long)(a - p) * Kp->R.Lu[0] + (y - p);
                         const long long fsr = (long long)Kp->R.Lu[0] * Kp->R.Lv[0];
-                        aEn[1] = A.rec_e ? gld(Kp->rec_e + e) : 0.f;
-                        aEn[2] = A.rec_e ? gld(Kp->rec_e + e + fsr) : 0.f;
+                        aEn[1] = has_rec_e ? gld(Rk->rec_e + e) : 0.f;
+                        aEn[2] = has_rec_e ? gld(Rk->rec_e + e + fsr) : 0.f;
                     }
                     if (wz && y == ny - p && wx) {
                         const long long e = Kp->R.off[3] + (long long)(a - p) * Kp->R.Lu[1] + (x - p);
                         const long long fsr = (long long)Kp->R.Lu[1] * Kp->R.Lv[1];
-                        aEn[2] = A.rec_e ? gld(Kp->rec_e + e) : 0.f;
-                        aEn[0] = A.rec_e ? gld(Kp->rec_e + e + fsr) : 0.f;
+                        aEn[2] = has_rec_e ? gld(Rk->rec_e + e) : 0.f;
+                        aEn[0] = has_rec_e ? gld(Rk->rec_e + e + fsr) : 0.f;
                     }
                 }
             }
             if (!(incol && kin)) { aEn[0] = aEn[1] = aEn[2] = 0.f; }
-            if (A.do_adj) {
+            if (do_adj) {
                 float Qt[6];
                 qcoef(L, t, Qt);
                 const float qa = Qa[0] - Qt[0];
@@ -470,14 +497,14 @@ __global__ __launch_bounds__(NT, 4) void k_tb_reverse(RevArgs A)
                 auto st = [&](float *base, unsigned o, float v) { *(GLOBAL float *)((GLOBAL char *)base + o) = v; };
                 // component q of the forward (stf) and adjoint (sta) output sets at plane bpl
                 auto stf = [&](int q, float v) {
-                    if constexpr (WIDE) st(Kp->fout.c[q] + (size_t)bpl * (size_t)Kp->g.nxy, c, v);
-                    else st(A.fout.c[0], c + q * fs, v);
+                    if constexpr (WIDE) st(Kp->fld[ic ^ 1][q] + (size_t)bpl * (size_t)Kp->g.nxy, c, v);
+                    else st(fout0, c + q * fs, v);
                 };
                 auto sta = [&](int q, float v) {
-                    if constexpr (WIDE) st(Kp->aout.c[q] + (size_t)bpl * (size_t)Kp->g.nxy, c, v);
-                    else st(A.aout.c[0], c + q * fs, v);
+                    if constexpr (WIDE) st(Kp->adj[ia ^ 1][q] + (size_t)bpl * (size_t)Kp->g.nxy, c, v);
+                    else st(aout0, c + q * fs, v);
                 };
-                if (A.do_inv && interior) {
+                if (do_inv && interior) {
                     const float ex = bEn[0], ey = bEn[1], ez = bEn[2];
                     const float ey_x = sEn[1][row][lr], ez_x = sEn[2][row][lr];
                     const float ex_y = sEn[0][ru][lane], ez_y = sEn[2][ru][lane];
@@ -501,7 +528,7 @@ __global__ __launch_bounds__(NT, 4) void k_tb_reverse(RevArgs A)
                     stf(4, h_unupdate(hy, S, ex_z - ex, ez_x - ez));
                     stf(5, h_unupdate(hz, S, ey_x - ey, ex_y - ex));
                 }
-                if (A.do_adj) {
+                if (do_adj) {
                     // adjoint E with the transposed H pairs
                     float ex = bAe[0], ey = bAe[1], ez = bAe[2];
                     if (!hex) {
@@ -531,20 +558,20 @@ __global__ __launch_bounds__(NT, 4) void k_tb_reverse(RevArgs A)
                             const float bE = sGz[szb][0], bHh = sGz[szb][3];
                             // z idx 0: Ex (-), idx 1: Ey (+); idx 2: Hx (+S), idx 3: Hy (-S)
                             const float w0 = -1.f * (ce * bAe[0]), w1 = 1.f * (ce * bAe[1]);
-                            st(A.pout.a[2][0], zi * 4u + 0 * A.pstride[2], hex ? bPb.z[0] : bE * (bPb.z[0] + w0));
-                            st(A.pout.a[2][0], zi * 4u + 1 * A.pstride[2], hey ? bPb.z[1] : bE * (bPb.z[1] + w1));
-                            st(A.pout.a[2][0], zi * 4u + 2 * A.pstride[2], bHh * (bPb.z[2] + 1.f * (S * bAh[0])));
-                            st(A.pout.a[2][0], zi * 4u + 3 * A.pstride[2], bHh * (bPb.z[3] + -1.f * (S * bAh[1])));
+                            st(A.pb[ip ^ 1][2], zi * 4u + 0 * A.pstride[2], hex ? bPb.z[0] : bE * (bPb.z[0] + w0));
+                            st(A.pb[ip ^ 1][2], zi * 4u + 1 * A.pstride[2], hey ? bPb.z[1] : bE * (bPb.z[1] + w1));
+                            st(A.pb[ip ^ 1][2], zi * 4u + 2 * A.pstride[2], bHh * (bPb.z[2] + 1.f * (S * bAh[0])));
+                            st(A.pb[ip ^ 1][2], zi * 4u + 3 * A.pstride[2], bHh * (bPb.z[3] + -1.f * (S * bAh[1])));
                         }
                         if constexpr (XP) {
                             if (sx >= 0) {
                                 const unsigned xi = (unsigned)bpl * (unsigned)ny * (unsigned)(2 * p) + soff_x;
                                 // x idx 0: Ey (-), idx 1: Ez (+); idx 2: Hy (+S), idx 3: Hz (-S)
                                 const float w0 = -1.f * (ce * bAe[1]), w1 = 1.f * (ce * bAe[2]);
-                                st(A.pout.a[0][0], xi * 4u + 0 * A.pstride[0], hey ? bPb.x[0] : gxE.x * (bPb.x[0] + w0));
-                                st(A.pout.a[0][0], xi * 4u + 1 * A.pstride[0], hez ? bPb.x[1] : gxE.x * (bPb.x[1] + w1));
-                                st(A.pout.a[0][0], xi * 4u + 2 * A.pstride[0], gxH.x * (bPb.x[2] + 1.f * (S * bAh[1])));
-                                st(A.pout.a[0][0], xi * 4u + 3 * A.pstride[0], gxH.x * (bPb.x[3] + -1.f * (S * bAh[2])));
+                                st(A.pb[ip ^ 1][0], xi * 4u + 0 * A.pstride[0], hey ? bPb.x[0] : gxE.x * (bPb.x[0] + w0));
+                                st(A.pb[ip ^ 1][0], xi * 4u + 1 * A.pstride[0], hez ? bPb.x[1] : gxE.x * (bPb.x[1] + w1));
+                                st(A.pb[ip ^ 1][0], xi * 4u + 2 * A.pstride[0], gxH.x * (bPb.x[2] + 1.f * (S * bAh[1])));
+                                st(A.pb[ip ^ 1][0], xi * 4u + 3 * A.pstride[0], gxH.x * (bPb.x[3] + -1.f * (S * bAh[2])));
                             }
                         }
                         if constexpr (YP) {
@@ -552,10 +579,10 @@ __global__ __launch_bounds__(NT, 4) void k_tb_reverse(RevArgs A)
                                 const unsigned yi = (unsigned)bpl * (unsigned)(2 * p) * (unsigned)nx + soff_y;
                                 // y idx 0: Ez (-), idx 1: Ex (+); idx 2: Hz (+S), idx 3: Hx (-S)
                                 const float w0 = -1.f * (ce * bAe[2]), w1 = 1.f * (ce * bAe[0]);
-                                st(A.pout.a[1][0], yi * 4u + 0 * A.pstride[1], hez ? bPb.y[0] : gyE.x * (bPb.y[0] + w0));
-                                st(A.pout.a[1][0], yi * 4u + 1 * A.pstride[1], hex ? bPb.y[1] : gyE.x * (bPb.y[1] + w1));
-                                st(A.pout.a[1][0], yi * 4u + 2 * A.pstride[1], gyH.x * (bPb.y[2] + 1.f * (S * bAh[2])));
-                                st(A.pout.a[1][0], yi * 4u + 3 * A.pstride[1], gyH.x * (bPb.y[3] + -1.f * (S * bAh[0])));
+                                st(A.pb[ip ^ 1][1], yi * 4u + 0 * A.pstride[1], hez ? bPb.y[0] : gyE.x * (bPb.y[0] + w0));
+                                st(A.pb[ip ^ 1][1], yi * 4u + 1 * A.pstride[1], hex ? bPb.y[1] : gyE.x * (bPb.y[1] + w1));
+                                st(A.pb[ip ^ 1][1], yi * 4u + 2 * A.pstride[1], gyH.x * (bPb.y[2] + 1.f * (S * bAh[2])));
+                                st(A.pb[ip ^ 1][1], yi * 4u + 3 * A.pstride[1], gyH.x * (bPb.y[3] + -1.f * (S * bAh[0])));
                             }
                         }
                     }
@@ -589,14 +616,14 @@ __global__ __launch_bounds__(NT, 4) void k_tb_reverse(RevArgs A)
         load_raw(zs, R0);
         for (int t = zs; t < ze; t += 2) {
             {
-                asm volatile("" : "+s"(Kp));
+                asm volatile("" : "+s"(Kp), "+s"(Rk));
                 load_raw(t + 1, R1);
                 RPlane<XP, YP> L;
                 finish(t, R0, L);
                 body(t, L);
             }
             {
-                asm volatile("" : "+s"(Kp));
+                asm volatile("" : "+s"(Kp), "+s"(Rk));
                 load_raw(t + 2, R0);
                 RPlane<XP, YP> L;
                 finish(t + 1, R1, L);
@@ -607,12 +634,41 @@ __global__ __launch_bounds__(NT, 4) void k_tb_reverse(RevArgs A)
         // slab tiles carry the auxiliaries too and have no registers for a
         // second plane in flight: fetch and use
         for (int t = zs; t < ze; t++) {
-            asm volatile("" : "+s"(Kp));
+            asm volatile("" : "+s"(Kp), "+s"(Rk));
             RPlane<XP, YP> R, L;
             load_raw(t, R);
             finish(t, R, L);
             body(t, L);
         }
+    }
+}
+
+// The kernel: block b (XCD-remapped) finds its request and tile; the tile's
+// class picks the march instance.
+template <bool WIDE>
+__global__ __launch_bounds__(NT, 4) void k_tb_reverse(RevLaunch)
+{
+    __shared__ RevLds lds;
+    // (the launch block is the kernel's only parameter, at offset 0 of the
+    // kernel-argument segment)
+    KLaunch *Lp = (KLaunch *)__builtin_amdgcn_kernarg_segment_ptr();
+    int b = blockIdx.x;
+    if (Lp->xcd_remap) b = remap_xcd_r(b, gridDim.x);
+    int r = 0;
+    while (r + 1 < Lp->nreq && b >= Lp->r[r + 1].first) r++;
+    KReq *Rq = &Lp->r[r];
+    // Arguments used only on rare planes (record layers, detector, source)
+    // are read through a copy of this pointer that is made opaque on every
+    // plane, so they are fetched where used instead of being held in scalar
+    // registers for the whole march.
+    KArgs *Ap = (KArgs *)Rq->args;
+    const int4 *tt = Rq->tiles + 2 * (b - Rq->first);
+    const int4 tl = tt[0], tz = tt[1];
+    switch (tz.z) {
+    case 0: rev_march<false, false, WIDE>(*Ap, Ap, Rq, tl, tz, lds); break;
+    case 1: rev_march<true, false, WIDE>(*Ap, Ap, Rq, tl, tz, lds); break;
+    case 2: rev_march<false, true, WIDE>(*Ap, Ap, Rq, tl, tz, lds); break;
+    default: rev_march<true, true, WIDE>(*Ap, Ap, Rq, tl, tz, lds); break;
     }
 }
 
@@ -622,23 +678,10 @@ int rev_halo() { return HALO; }
 int rev_tile_x() { return EX - 2 * HALO; }
 int rev_tile_y() { return EY - 2 * HALO; }
 
-namespace {
-template <bool WIDE>
-hipError_t launch_rev(const RevArgs &a, int cls, hipStream_t s)
+hipError_t launch_tb_reverse(const RevLaunch &L, bool wide, hipStream_t s)
 {
-    constexpr int threads = NT;
-    switch (cls) {
-    case 0: hipLaunchKernelGGL((k_tb_reverse<false, false, WIDE>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
-    case 1: hipLaunchKernelGGL((k_tb_reverse<true, false, WIDE>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_tb_reverse<false, true, WIDE>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_tb_reverse<true, true, WIDE>), dim3(a.ntiles), dim3(threads), 0, s, a); break;
-    }
+    if (L.nblocks <= 0) return hipSuccess;
+    if (wide) hipLaunchKernelGGL((k_tb_reverse<true>), dim3(L.nblocks), dim3(NT), 0, s, L);
+    else hipLaunchKernelGGL((k_tb_reverse<false>), dim3(L.nblocks), dim3(NT), 0, s, L);
     return hipGetLastError();
-}
-}  // namespace
-
-hipError_t launch_tb_reverse_class(const RevArgs &a, int cls, bool wide, hipStream_t s)
-{
-    if (a.ntiles <= 0) return hipSuccess;
-    return wide ? launch_rev<true>(a, cls, s) : launch_rev<false>(a, cls, s);
 }
