@@ -274,7 +274,7 @@ def copy_calibration(torch, nbytes: int = 1 << 30, reps: int = 4):
 
 
 def serving_bench(count: int, torch, seed_rate: float = 0.8, budget_gb: float = 0.0, max_active: int = 6,
-                  streams: int = 6, extra_rates=(), open_loops: bool = True, open_rate: float = 0.0):
+                  chunk: int = 64, extra_rates=(), open_loops: bool = True, open_rate: float = 0.0):
     """Serving mix: `count` requests of the Poisson mix recipe (edges U{64..256},
     50% forward / 50% gradient, T = 8 x max edge, CPML 8).  Measures saturation
     throughput one-at-a-time and with continuous batching (all queued at t=0),
@@ -290,13 +290,12 @@ def serving_bench(count: int, torch, seed_rate: float = 0.8, budget_gb: float = 
     kinds = {rid: k for (rid, _, k, _) in descs}
     budget = int(budget_gb * 1e9) if budget_gb > 0 else int(torch.cuda.mem_get_info()[0] * 0.8)
 
-    def run(max_active, streams, arrivals=None, limit=None):
+    def run(max_active, arrivals=None, limit=None):
         rids = sorted(probs)[:limit]
         reqs = [serve.Request(rid=rid, kind=kinds[rid], problem=probs[rid],
                               arrival=0.0 if arrivals is None else arrivals[i])
                 for i, rid in enumerate(rids)]
-        sch = serve.Scheduler(serve.GpuExecutor(n_streams=streams), budget_bytes=budget,
-                              max_active=max_active, chunk=64)
+        sch = serve.Scheduler(serve.GpuExecutor(), budget_bytes=budget, max_active=max_active, chunk=chunk)
         t0 = time.perf_counter()
         res = sch.run(reqs, open_loop=arrivals is not None,
                       progress=lambda d, n: log(f"  {d} of {n} requests served"))
@@ -311,16 +310,17 @@ def serving_bench(count: int, torch, seed_rate: float = 0.8, budget_gb: float = 
     def log(msg):   # one line per phase (a long mix runs for minutes)
         print(f"[serving] {msg} ({time.perf_counter() - t_start:.0f} s)", file=sys.stderr, flush=True)
 
-    run(1, 1, limit=8)                          # warm-up (code objects, allocator)
+    run(1, limit=8)                          # warm-up (code objects, allocator)
     log("warm-up done")
     r = lambda v: None if v is None else round(v, 4)
     res = {"workload": f"{count} requests of the serving mix (edges U{{64..256}} per axis, 50% gradient, "
                        f"T = 8 x max edge, CPML 8, eps_r U[1,12.25]; seeds 6/7/1000+rid)",
-           "hbm_budget_gb": round(budget / 1e9, 1), "max_active": max_active, "streams": streams}
+           "hbm_budget_gb": round(budget / 1e9, 1), "max_active": max_active, "chunk_steps": chunk,
+           "batched_launches": "one z-march launch per forward sweep and per reverse step spans all active requests"}
     if open_rate <= 0:
-        seq = run(1, 1)
+        seq = run(1)
         log(f"one at a time: {seq['req_per_s']:.3f} req/s")
-        bat = run(max_active, streams)
+        bat = run(max_active)
         log(f"batched: {bat['req_per_s']:.3f} req/s")
         res["one_at_a_time"] = {"throughput_mcell_steps_s": r(seq["throughput_mcell_steps_s"]),
                                 "req_per_s": r(seq["req_per_s"]), "wall_s": r(seq["wall_s"])}
@@ -341,16 +341,16 @@ def serving_bench(count: int, torch, seed_rate: float = 0.8, budget_gb: float = 
 
     rate = seed_rate * seq_rate
     arr = arrivals(seed_rate)
-    seq_open = run(1, 1, arr)
+    seq_open = run(1, arr)
     log(f"open loop, one at a time: p99 {seq_open['p99_latency_s']:.3f} s")
-    bat_open = run(max_active, streams, arr)
+    bat_open = run(max_active, arr)
     log(f"open loop, batched: p99 {bat_open['p99_latency_s']:.3f} s")
     more = []
     for f in extra_rates:
         a = arrivals(f)
-        so = run(1, 1, a)
+        so = run(1, a)
         log(f"open loop at {f} x, one at a time: p99 {so['p99_latency_s']:.3f} s")
-        bo = run(max_active, streams, a)
+        bo = run(max_active, a)
         log(f"open loop at {f} x, batched: p99 {bo['p99_latency_s']:.3f} s")
         more.append({"rate_factor": f, "rate_req_s": r(f * seq_rate),
                      "one_at_a_time_open": {"p50_s": r(so["p50_latency_s"]), "p99_s": r(so["p99_latency_s"])},
@@ -385,7 +385,7 @@ def main():
     ap.add_argument("--serving-max-active", type=int, default=6,
                     help="requests on the GPU at once in the batched runs (6 measured best on a "
                          "200-request mix: more sharing lengthens the largest requests)")
-    ap.add_argument("--serving-streams", type=int, default=6)
+    ap.add_argument("--serving-chunk", type=int, default=64, help="serving: forward steps per scheduler iteration")
     ap.add_argument("--serving-closed-only", action="store_true",
                     help="serving: the two closed loops only (a long mix split over two runs)")
     ap.add_argument("--serving-open-rate", type=float, default=0.0,
@@ -512,7 +512,7 @@ def main():
 
     if args.serving > 0:
         out["serving"] = serving_bench(args.serving, torch, budget_gb=args.serving_budget_gb,
-                                       max_active=args.serving_max_active, streams=args.serving_streams,
+                                       max_active=args.serving_max_active, chunk=args.serving_chunk,
                                        extra_rates=[float(v) for v in args.serving_extra_rates.split(",") if v],
                                        open_loops=not args.serving_closed_only, open_rate=args.serving_open_rate)
 

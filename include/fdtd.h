@@ -165,6 +165,41 @@ fdtd_status fdtd_inverse(fdtd_handle h, int32_t n_steps);
  * arithmetic) over the RMS of the interior fields at t = T. */
 fdtd_status fdtd_grad(fdtd_handle h, float *dJ_deps, float *recon_err);
 
+/* The same gradient in chunks (section 2.2), so that a caller can interleave
+ * the reverse steps of several solves:
+ *   fdtd_grad_begin  requires what fdtd_grad requires (record = 1, t = T from
+ *                    a reset); zeroes the adjoint state and the accumulator.
+ *   fdtd_grad_steps  runs n_steps reverse steps (n_steps <= t); t decreases.
+ *   fdtd_grad_end    at t = 0: writes dJ_deps (and recon_err), as fdtd_grad.
+ * begin, steps of any sizes summing to T, then end give the bits of
+ * fdtd_grad.  Between begin and end, fdtd_forward, fdtd_inverse and the
+ * checkpointed gradient return FDTD_E_STATE; fdtd_reset abandons the
+ * gradient. */
+fdtd_status fdtd_grad_begin(fdtd_handle h);
+fdtd_status fdtd_grad_steps(fdtd_handle h, int32_t n_steps);
+fdtd_status fdtd_grad_end(fdtd_handle h, float *dJ_deps, float *recon_err);
+
+/* Batches of handles, for a serving loop that advances many solves at once
+ * (continuous batching; the forward step of section 2.1 and the reverse
+ * step of section 2.2 on several grids).  hs[0..nh) are distinct handles
+ * created on one stream (the batch's); each keeps its own grid, state and
+ * outputs.  Every sweep of the forward z-march, and every reverse step, is
+ * one kernel launch whose tiles span all handles that take a sweep of that
+ * length (handles on the per-cell kernels advance on their own).  The bits
+ * of every handle's results are those of the single-handle calls.
+ *   fdtd_forward_batch:    hs[i] as fdtd_forward(hs[i], n_steps[i],
+ *                          traces ? traces[i] : NULL, Js ? Js[i] : NULL).
+ *   fdtd_grad_steps_batch: hs[i] as fdtd_grad_steps(hs[i], n_steps[i]).
+ * Host arrays: hs, n_steps, traces, Js (traces[i], Js[i]: device or NULL).
+ * Errors: FDTD_E_INVALID for NULL or repeated handles, handles on different
+ * streams or negative counts (fdtd_last_error(NULL)); FDTD_E_STATE as the
+ * single-handle calls (that handle's message); nothing is enqueued on a
+ * validation error.  A launch error is reported on every handle of the
+ * launch and on fdtd_last_error(NULL). */
+fdtd_status fdtd_forward_batch(const fdtd_handle *hs, int32_t nh, const int32_t *n_steps, float *const *traces,
+                               float *const *Js);
+fdtd_status fdtd_grad_steps_batch(const fdtd_handle *hs, int32_t nh, const int32_t *n_steps);
+
 /* Gradient by checkpointing, the baseline the time-reversal gradient is
  * measured against (section 2.2 compares the two): runs the forward pass from
  * zero fields, keeping the complete state (fields and CPML auxiliaries) at

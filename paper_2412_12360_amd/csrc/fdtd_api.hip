@@ -70,6 +70,8 @@ struct fdtd_ctx {
     float *fld[2][6];
     float *psi[2][3][4];
     int cur = 0;
+    bool in_grad = false;                  // between fdtd_grad_begin and fdtd_grad_end
+    int grad_np = 0;                       // partial sums of the interior norm at t = T
     // adjoint state: fields, psi-bar E-type (in place), psi-bar H-type (ping-pong)
     float *adj[2][6];
     float *pb[2][3][4];
@@ -1054,6 +1056,7 @@ fdtd_status fdtd_forward(fdtd_handle h, int32_t n_steps, float *trace, float *J)
 {
     if (!h) return fail(nullptr, FDTD_E_INVALID, "handle is NULL");
     if (n_steps < 0) return fail(h, FDTD_E_INVALID, "n_steps < 0");
+    if (h->in_grad) return fail(h, FDTD_E_STATE, "a gradient is running on this handle");
     if (h->t + n_steps > h->T)
         return fail(h, FDTD_E_STATE, "t + n_steps = %d exceeds n_steps of the descriptor (%d)", h->t + n_steps, h->T);
     const int t0 = h->t;
@@ -1075,6 +1078,7 @@ fdtd_status fdtd_forward(fdtd_handle h, int32_t n_steps, float *trace, float *J)
 fdtd_status fdtd_inverse(fdtd_handle h, int32_t n_steps)
 {
     if (!h) return fail(nullptr, FDTD_E_INVALID, "handle is NULL");
+    if (h->in_grad) return fail(h, FDTD_E_STATE, "a gradient is running on this handle");
     if (n_steps < 0 || n_steps > h->t) return fail(h, FDTD_E_STATE, "cannot undo %d steps at t = %d", n_steps, h->t);
     if (h->geo.p > 0 && !h->desc.record) return fail(h, FDTD_E_STATE, "inverse with a PML needs record = 1");
     for (int s = 0; s < n_steps; s++) {
@@ -1096,34 +1100,277 @@ static bool energy_in_design(const fdtd_ctx *h)
     return false;
 }
 
-fdtd_status fdtd_grad(fdtd_handle h, float *dJ_deps, float *recon_err)
+namespace {
+
+fdtd_status grad_begin_check(fdtd_ctx *h)
 {
-    if (!h) return fail(nullptr, FDTD_E_INVALID, "handle is NULL");
-    if (!h->desc.record) return fail(h, FDTD_E_STATE, "fdtd_grad needs record = 1");
+    if (!h->desc.record) return fail(h, FDTD_E_STATE, "the gradient needs record = 1");
     if (energy_in_design(h))
         return fail(h, FDTD_E_UNSUPPORTED, "a weighted energy detector must lie outside the design box in z");
-    if (h->t != h->T) return fail(h, FDTD_E_STATE, "fdtd_grad needs t = T (t = %d, T = %d)", h->t, h->T);
-    if (!dJ_deps) return fail(h, FDTD_E_INVALID, "dJ_deps is NULL");
+    if (h->in_grad) return fail(h, FDTD_E_STATE, "a gradient is already running on this handle");
+    if (h->t != h->T) return fail(h, FDTD_E_STATE, "the gradient needs t = T (t = %d, T = %d)", h->t, h->T);
+    return FDTD_OK;
+}
+
+fdtd_status grad_begin_impl(fdtd_ctx *h)
+{
+    fdtd_status st0 = grad_begin_check(h);
+    if (st0 != FDTD_OK) return st0;
     const Geometry &G = h->geo;
-    int np = 0;
-    HIPCHK(h, launch_interior_sumsq(h->g, fields_of(h, h->cur), h->parts[0], &np, h->stream));
+    HIPCHK(h, launch_interior_sumsq(h->g, fields_of(h, h->cur), h->parts[0], &h->grad_np, h->stream));
     fdtd_status st = zero_adjoint(h);
     if (st != FDTD_OK) return st;
     HIPCHK(h, launch_fill(h->gacc, G.design_cells, 0.f, h->stream));
-    for (int n = h->T - 1; n >= 0; n--) {
-        if (h->drec)
-            HIPCHK(h, launch_det_interp_adjoint(h->g, G.D, h->drec, h->drec_e0, n, h->T, h->wS, adj_of(h, h->acur),
-                                                h->stream));
-        st = h->naive ? reverse_step(h, n, 1) : reverse_fused(h, n, 1, 1, 1, h->gacc);
-        if (st != FDTD_OK) return st;
-    }
+    h->in_grad = true;
+    return FDTD_OK;
+}
+
+// what precedes reverse step n: the interpolated detectors' adjoint source
+fdtd_status grad_pre_step(fdtd_ctx *h, int n)
+{
+    if (h->drec)
+        HIPCHK(h, launch_det_interp_adjoint(h->g, h->geo.D, h->drec, h->drec_e0, n, h->T, h->wS, adj_of(h, h->acur),
+                                            h->stream));
+    return FDTD_OK;
+}
+
+// one reverse step of a running gradient, on its own
+fdtd_status grad_step_single(fdtd_ctx *h)
+{
+    const int n = h->t - 1;
+    fdtd_status st = grad_pre_step(h, n);
+    if (st == FDTD_OK) st = h->naive ? reverse_step(h, n, 1) : reverse_fused(h, n, 1, 1, 1, h->gacc);
+    if (st == FDTD_OK) h->t = n;
+    return st;
+}
+
+fdtd_status grad_end_impl(fdtd_ctx *h, float *dJ_deps, float *recon_err)
+{
+    const Geometry &G = h->geo;
+    int np = 0;
     HIPCHK(h, launch_interior_sumsq(h->g, fields_of(h, h->cur), h->parts[1], &np, h->stream));
     if (recon_err) HIPCHK(h, launch_recon(h->parts[0], h->parts[1], np, recon_err, h->stream));
     HIPCHK(h, launch_deps(h->gacc, h->d_design, G.design_cells, h->desc.courant, dJ_deps, h->stream));
-    st = zero_forward(h);
+    fdtd_status st = zero_forward(h);
     if (st != FDTD_OK) return st;
     HIPCHK(h, launch_fill(h->trace, (long long)h->T * std::max(1, G.D.ndet), 0.f, h->stream));
     h->t = 0;
+    h->in_grad = false;
+    return FDTD_OK;
+}
+
+}  // namespace
+
+fdtd_status fdtd_grad(fdtd_handle h, float *dJ_deps, float *recon_err)
+{
+    if (!h) return fail(nullptr, FDTD_E_INVALID, "handle is NULL");
+    fdtd_status st = grad_begin_check(h);
+    if (st != FDTD_OK) return st;
+    if (!dJ_deps) return fail(h, FDTD_E_INVALID, "dJ_deps is NULL");
+    st = grad_begin_impl(h);
+    while (st == FDTD_OK && h->t > 0) st = grad_step_single(h);
+    if (st == FDTD_OK) st = grad_end_impl(h, dJ_deps, recon_err);
+    if (st != FDTD_OK) h->in_grad = false;
+    return st;
+}
+
+fdtd_status fdtd_grad_begin(fdtd_handle h)
+{
+    if (!h) return fail(nullptr, FDTD_E_INVALID, "handle is NULL");
+    return grad_begin_impl(h);
+}
+
+fdtd_status fdtd_grad_steps(fdtd_handle h, int32_t n_steps)
+{
+    if (!h) return fail(nullptr, FDTD_E_INVALID, "handle is NULL");
+    if (!h->in_grad) return fail(h, FDTD_E_STATE, "fdtd_grad_steps needs fdtd_grad_begin first");
+    if (n_steps < 0 || n_steps > h->t) return fail(h, FDTD_E_STATE, "cannot reverse %d steps at t = %d", n_steps, h->t);
+    for (int s = 0; s < n_steps; s++) {
+        fdtd_status st = grad_step_single(h);
+        if (st != FDTD_OK) return st;
+    }
+    return FDTD_OK;
+}
+
+fdtd_status fdtd_grad_end(fdtd_handle h, float *dJ_deps, float *recon_err)
+{
+    if (!h) return fail(nullptr, FDTD_E_INVALID, "handle is NULL");
+    if (!h->in_grad) return fail(h, FDTD_E_STATE, "fdtd_grad_end needs fdtd_grad_begin first");
+    if (h->t != 0) return fail(h, FDTD_E_STATE, "fdtd_grad_end needs t = 0 (t = %d)", h->t);
+    if (!dJ_deps) return fail(h, FDTD_E_INVALID, "dJ_deps is NULL");
+    return grad_end_impl(h, dJ_deps, recon_err);
+}
+
+// ----------------------------------------------------------------------
+// Batches of handles (serving): one z-march launch per sweep spans the tiles
+// of every handle in the batch.
+namespace {
+
+// common checks of a batch; the stream of the first handle is the batch's
+fdtd_status batch_check(const fdtd_handle *hs, int32_t nh, const int32_t *n_steps)
+{
+    if (nh < 0 || (nh > 0 && (!hs || !n_steps))) return fail(nullptr, FDTD_E_INVALID, "bad batch arguments");
+    for (int i = 0; i < nh; i++) {
+        if (!hs[i]) return fail(nullptr, FDTD_E_INVALID, "batch handle %d is NULL", i);
+        if (hs[i]->stream != hs[0]->stream)
+            return fail(nullptr, FDTD_E_INVALID, "batch handle %d was created on another stream", i);
+        if (n_steps[i] < 0) return fail(nullptr, FDTD_E_INVALID, "n_steps[%d] < 0", i);
+        for (int j = 0; j < i; j++)
+            if (hs[j] == hs[i]) return fail(nullptr, FDTD_E_INVALID, "handle %d appears twice in the batch", i);
+    }
+    return FDTD_OK;
+}
+
+// a batch launch failed: the message goes to every handle of the launch
+fdtd_status batch_fail(fdtd_ctx *const *g, int n, hipError_t e)
+{
+    for (int i = 0; i < n; i++) fail(g[i], FDTD_E_DEVICE, "batched z-march launch: %s", hipGetErrorString(e));
+    return fail(nullptr, FDTD_E_DEVICE, "batched z-march launch: %s", hipGetErrorString(e));
+}
+
+}  // namespace
+
+fdtd_status fdtd_forward_batch(const fdtd_handle *hs, int32_t nh, const int32_t *n_steps, float *const *traces,
+                               float *const *Js)
+{
+    fdtd_status st = batch_check(hs, nh, n_steps);
+    if (st != FDTD_OK) return st;
+    for (int i = 0; i < nh; i++) {
+        if (hs[i]->in_grad) return fail(hs[i], FDTD_E_STATE, "a gradient is running on batch handle %d", i);
+        if (hs[i]->t + n_steps[i] > hs[i]->T)
+            return fail(hs[i], FDTD_E_STATE, "t + n_steps = %d exceeds n_steps of the descriptor (%d)",
+                        hs[i]->t + n_steps[i], hs[i]->T);
+    }
+    std::vector<int> t0(nh), pos(nh);
+    for (int i = 0; i < nh; i++) t0[i] = pos[i] = hs[i]->t;
+    // handles on the per-cell kernels advance on their own
+    for (int i = 0; i < nh; i++)
+        if (hs[i]->naive) {
+            st = advance(hs[i], pos[i], n_steps[i], 1, 1, 1);
+            if (st != FDTD_OK) return st;
+            pos[i] += n_steps[i];
+        }
+    // every round: one launch per (sweep length, instance) group of handles
+    for (;;) {
+        bool any = false;
+        for (int kk = 1; kk <= 4; kk++)
+            for (int wide = 0; wide < 2; wide++)
+                for (int shape = 0; shape < 4; shape++) {
+                    std::vector<fdtd_ctx *> grp;
+                    std::vector<int> idx;
+                    for (int i = 0; i < nh; i++) {
+                        fdtd_ctx *h = hs[i];
+                        const int rem = t0[i] + n_steps[i] - pos[i];
+                        if (h->naive || rem <= 0 || std::min(h->K, rem) != kk || (int)h->wide != wide ||
+                            h->shape != shape)
+                            continue;
+                        grp.push_back(h);
+                        idx.push_back(i);
+                    }
+                    for (size_t a = 0; a < grp.size(); a += ZM_MAXREQ) {
+                        const int cnt = (int)std::min<size_t>(ZM_MAXREQ, grp.size() - a);
+                        TbLaunch L;
+                        L.nreq = cnt;
+                        L.nblocks = 0;
+                        L.xcd_remap = 1;
+                        L.pad = 0;
+                        for (int j = 0; j < cnt; j++) {
+                            fdtd_ctx *h = grp[a + j];
+                            const int i = idx[a + j];
+                            st = tb_prologue(h, pos[i], 1);
+                            if (st != FDTD_OK) return st;
+                            L.r[j] = tb_request(h, pos[i], kk, 1, 1, 1, L.nblocks);
+                            L.nblocks += h->tb_n[kk];
+                        }
+                        const hipError_t e = launch_tb_forward(L, kk, shape, wide != 0, grp[a]->stream);
+                        if (e != hipSuccess) return batch_fail(grp.data() + a, cnt, e);
+                        for (int j = 0; j < cnt; j++) {
+                            fdtd_ctx *h = grp[a + j];
+                            const int i = idx[a + j];
+                            st = tb_epilogue(h, pos[i], kk, 1);
+                            if (st != FDTD_OK) return st;
+                            pos[i] += kk;
+                        }
+                        any = true;
+                    }
+                }
+        if (!any) break;
+    }
+    // outputs, as fdtd_forward gives them
+    for (int i = 0; i < nh; i++) {
+        fdtd_ctx *h = hs[i];
+        const Geometry &G = h->geo;
+        h->t = t0[i] + n_steps[i];
+        float *trace = traces ? traces[i] : nullptr;
+        float *J = Js ? Js[i] : nullptr;
+        if (trace && G.D.ndet > 0 && n_steps[i] > 0)
+            HIPCHK(h, launch_copy(trace, h->trace + (size_t)t0[i] * G.D.ndet, (long long)n_steps[i] * G.D.ndet,
+                                  h->stream));
+        if (J) {
+            if (G.D.ndet > 0)
+                HIPCHK(h, launch_objective(h->trace, h->t, G.D.ndet, h->wdev, h->desc.courant, J, h->stream));
+            else
+                HIPCHK(h, launch_fill(J, 1, 0.f, h->stream));
+        }
+    }
+    return FDTD_OK;
+}
+
+fdtd_status fdtd_grad_steps_batch(const fdtd_handle *hs, int32_t nh, const int32_t *n_steps)
+{
+    fdtd_status st = batch_check(hs, nh, n_steps);
+    if (st != FDTD_OK) return st;
+    for (int i = 0; i < nh; i++) {
+        if (!hs[i]->in_grad) return fail(hs[i], FDTD_E_STATE, "batch handle %d has no running gradient", i);
+        if (n_steps[i] > hs[i]->t)
+            return fail(hs[i], FDTD_E_STATE, "cannot reverse %d steps at t = %d", n_steps[i], hs[i]->t);
+    }
+    std::vector<int> left(n_steps, n_steps + nh);
+    for (int i = 0; i < nh; i++)
+        if (hs[i]->naive)
+            for (; left[i] > 0; left[i]--) {
+                st = grad_step_single(hs[i]);
+                if (st != FDTD_OK) return st;
+            }
+    // every round: one reverse step of every handle that has steps left, one
+    // launch per instance
+    for (;;) {
+        bool any = false;
+        for (int wide = 0; wide < 2; wide++) {
+            std::vector<fdtd_ctx *> grp;
+            std::vector<int> idx;
+            for (int i = 0; i < nh; i++)
+                if (!hs[i]->naive && left[i] > 0 && (int)hs[i]->wide == wide) {
+                    grp.push_back(hs[i]);
+                    idx.push_back(i);
+                }
+            for (size_t a = 0; a < grp.size(); a += ZM_MAXREQ) {
+                const int cnt = (int)std::min<size_t>(ZM_MAXREQ, grp.size() - a);
+                RevLaunch L;
+                L.nreq = cnt;
+                L.nblocks = 0;
+                L.xcd_remap = 1;
+                L.pad = 0;
+                for (int j = 0; j < cnt; j++) {
+                    fdtd_ctx *h = grp[a + j];
+                    st = grad_pre_step(h, h->t - 1);
+                    if (st != FDTD_OK) return st;
+                    L.r[j] = rev_request(h, h->t - 1, 1, 1, 1, h->gacc, nullptr, L.nblocks);
+                    L.nblocks += h->tb_n[0];
+                }
+                const hipError_t e = launch_tb_reverse(L, wide != 0, grp[a]->stream);
+                if (e != hipSuccess) return batch_fail(grp.data() + a, cnt, e);
+                for (int j = 0; j < cnt; j++) {
+                    fdtd_ctx *h = grp[a + j];
+                    rev_epilogue(h, 1, 1);
+                    h->t -= 1;
+                    left[idx[a + j]]--;
+                }
+                any = true;
+            }
+        }
+        if (!any) break;
+    }
     return FDTD_OK;
 }
 
@@ -1202,6 +1449,7 @@ fdtd_status grad_checkpointed_impl(fdtd_handle h, int32_t segment, void *store, 
     if (energy_in_design(h))
         return fail(h, FDTD_E_UNSUPPORTED, "a weighted energy detector must lie outside the design box in z");
     if (h->naive) return fail(h, FDTD_E_UNSUPPORTED, "the checkpointed gradient runs on the z-march path only");
+    if (h->in_grad) return fail(h, FDTD_E_STATE, "a gradient is running on this handle");
     if (h->wide) return fail(h, FDTD_E_UNSUPPORTED, "the checkpointed gradient needs field sets under 4 GiB");
     if (segment < 1 || segment > h->T) return fail(h, FDTD_E_INVALID, "segment %d not in [1, T]", segment);
     if (!store || !dJ_deps) return fail(h, FDTD_E_INVALID, "store or dJ_deps is NULL");
@@ -1356,6 +1604,7 @@ fdtd_status fdtd_reset(fdtd_handle h)
     if (st != FDTD_OK) return st;
     HIPCHK(h, launch_fill(h->trace, (long long)h->T * std::max(1, h->geo.D.ndet), 0.f, h->stream));
     h->t = 0;
+    h->in_grad = false;
     return FDTD_OK;
 }
 

@@ -54,7 +54,8 @@ ENTRY_POINTS = [
     "fdtd_reset", "fdtd_destroy", "fdtd_time", "fdtd_last_error", "fdtd_field_ptr", "fdtd_state_arrays",
     "fdtd_linear_steps", "fdtd_record_ptr", "fdtd_time_block", "fdtd_checkpoint_bytes",
     "fdtd_grad_checkpointed", "fdtd_kernel_path", "fdtd_tile_classes", "fdtd_grad_checkpointed_noalloc",
-    "fdtd_noalloc_store_bytes",
+    "fdtd_noalloc_store_bytes", "fdtd_grad_begin", "fdtd_grad_steps", "fdtd_grad_end", "fdtd_forward_batch",
+    "fdtd_grad_steps_batch",
 ]
 
 _lib = None
@@ -80,6 +81,12 @@ def lib():
     L.fdtd_forward.argtypes = [H, C.c_int32, fp, fp]
     L.fdtd_inverse.argtypes = [H, C.c_int32]
     L.fdtd_grad.argtypes = [H, fp, fp]
+    L.fdtd_grad_begin.argtypes = [H]
+    L.fdtd_grad_steps.argtypes = [H, C.c_int32]
+    L.fdtd_grad_end.argtypes = [H, fp, fp]
+    L.fdtd_forward_batch.argtypes = [C.POINTER(H), C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_void_p),
+                                     C.POINTER(C.c_void_p)]
+    L.fdtd_grad_steps_batch.argtypes = [C.POINTER(H), C.c_int32, C.POINTER(C.c_int32)]
     L.fdtd_checkpoint_bytes.argtypes = [H, C.c_int32, C.POINTER(C.c_size_t)]
     L.fdtd_grad_checkpointed.argtypes = [H, C.c_int32, C.c_void_p, C.c_size_t, fp, fp]
     L.fdtd_grad_checkpointed_noalloc.argtypes = [H, C.c_int32, fp, fp]
@@ -164,6 +171,55 @@ def footprint(prob, record: bool = False, time_block: int = 0, T: Optional[int] 
     out = C.c_size_t(0)
     check(lib().fdtd_footprint(C.byref(d), srcs, len(prob.sources), dets, len(prob.detectors), C.byref(out)))
     return int(out.value)
+
+
+def _handles(solvers):
+    return (C.c_void_p * max(1, len(solvers)))(*[s.handle.value for s in solvers])
+
+
+def _batch_check(status: int, solvers):
+    """A failed batch call: the batch-level message and every handle's last
+    message (a handle's message may predate this call)."""
+    if status == FDTD_OK:
+        return
+    parts = []
+    m = lib().fdtd_last_error(None)
+    if m:
+        parts.append(m.decode())
+    for i, s in enumerate(solvers):
+        m = lib().fdtd_last_error(s.handle)
+        if m:
+            parts.append(f"handle {i}: {m.decode()}")
+    raise FdtdError(status, "; ".join(parts))
+
+
+def forward_batch(solvers, n_steps):
+    """fdtd_forward_batch: advance solvers[i] by n_steps[i] (all created on one
+    stream) with one z-march launch per sweep spanning all of them; returns
+    per solver (trace [n, ndet], J) device tensors, as Solver.forward."""
+    import torch
+    nh = len(solvers)
+    if nh == 0:
+        return []
+    counts = (C.c_int32 * nh)(*[int(n) for n in n_steps])
+    outs, tptr, jptr = [], (C.c_void_p * nh)(), (C.c_void_p * nh)()
+    for i, (s, n) in enumerate(zip(solvers, n_steps)):
+        tr = torch.zeros((max(int(n), 1), max(s.ndet, 1)), dtype=torch.float32, device=s.device)
+        outs.append((tr, s.J))
+        tptr[i] = tr.data_ptr()
+        jptr[i] = s.J.data_ptr()
+    _batch_check(lib().fdtd_forward_batch(_handles(solvers), nh, counts, tptr, jptr), solvers)
+    return [(tr[:int(n), :s.ndet], J) for (tr, J), s, n in zip(outs, solvers, n_steps)]
+
+
+def grad_steps_batch(solvers, n_steps):
+    """fdtd_grad_steps_batch: n_steps[i] reverse steps of solvers[i]'s running
+    gradient, one launch per reverse step spanning all of them."""
+    nh = len(solvers)
+    if nh == 0:
+        return
+    counts = (C.c_int32 * nh)(*[int(n) for n in n_steps])
+    _batch_check(lib().fdtd_grad_steps_batch(_handles(solvers), nh, counts), solvers)
 
 
 class Solver:
@@ -262,6 +318,20 @@ class Solver:
         g = self.torch.empty(self.prob.design_shape(), dtype=self.torch.float32, device=self.device)
         r = self.torch.zeros(1, dtype=self.torch.float32, device=self.device)
         self.fdtd_grad(g, r)
+        return g, r
+
+    # the gradient in chunks (fdtd_grad_begin / _steps / _end)
+    def grad_begin(self):
+        check(lib().fdtd_grad_begin(self.handle), self.handle)
+
+    def grad_steps(self, n: int):
+        check(lib().fdtd_grad_steps(self.handle, int(n)), self.handle)
+
+    def grad_end(self):
+        """dJ/deps_r and the reconstruction error once the chunks reached t = 0."""
+        g = self.torch.empty(self.prob.design_shape(), dtype=self.torch.float32, device=self.device)
+        r = self.torch.zeros(1, dtype=self.torch.float32, device=self.device)
+        check(lib().fdtd_grad_end(self.handle, C.c_void_p(g.data_ptr()), C.c_void_p(r.data_ptr())), self.handle)
         return g, r
 
     def checkpoint_bytes(self, segment: int) -> int:

@@ -4,19 +4,24 @@ Requests of uneven grid sizes arrive at arbitrary times.  Each scheduler
 iteration
   1. admits queued requests (FIFO) while the sum of the admitted requests'
      exact workspace footprints (fdtd_footprint) stays within the HBM budget
-     and a slot is free; an admitted request gets its own handle, workspace
-     and one of several device streams, so its fields and interface record
-     stay resident until it finishes;
+     and a slot is free; an admitted request gets its own handle and
+     workspace, so its fields and interface record stay resident until it
+     finishes;
   2. gives every active request whose previous chunk has finished its next
      chunk of work: `chunk` more forward time steps, or, once a gradient
-     request's forward is complete, its time-reversed backward pass;
-  3. retires finished requests: copies their results out, releases the slot
+     request's forward is complete, `bchunk` more time-reversed steps of its
+     backward pass;
+  3. hands the iteration's chunks to the executor at once (flush): the GPU
+     executor advances all of them with batched launches -- every forward
+     sweep and every reverse step is one kernel launch whose tile table
+     spans all requests of the batch (fdtd_forward_batch,
+     fdtd_grad_steps_batch);
+  4. retires finished requests: copies their results out, releases the slot
      and its memory, records the latency.
-Work of different requests runs on different streams and overlaps on the
-device; a request that arrives while others run is admitted as soon as memory
-and a slot are free.  A request that cannot be served (invalid problem,
-footprint above the whole budget, a device error) fails alone with an error
-result and frees its slot.
+A request that arrives while others run is admitted as soon as memory and a
+slot are free and joins the next batch.  A request that cannot be served
+(invalid problem, footprint above the whole budget, a device error) fails
+alone with an error result and frees its slot.
 
 The scheduler only talks to an executor object, so its policy is testable on
 the CPU with a mock executor that simulates durations.
@@ -29,6 +34,15 @@ import math
 import threading
 import time
 from typing import Callable, Deque, Dict, List, Optional
+
+
+class BatchError(RuntimeError):
+    """A batched call failed; rids: the requests whose work it held."""
+
+    def __init__(self, rids, cause):
+        super().__init__(str(cause))
+        self.rids = list(rids)
+        self.cause = cause
 
 
 @dataclasses.dataclass
@@ -74,9 +88,14 @@ class Executor:
         """Enqueue nsteps forward steps (non-blocking)."""
         raise NotImplementedError
 
-    def backward(self, slot) -> None:
-        """Enqueue the gradient pass (non-blocking)."""
+    def backward(self, slot, nsteps: int) -> None:
+        """Enqueue nsteps more reverse steps of the gradient pass (non-blocking);
+        the first call starts the pass, the one that reaches step 0 ends it."""
         raise NotImplementedError
+
+    def flush(self) -> None:
+        """Issue the work enqueued since the last flush (called once per
+        scheduler iteration)."""
 
     def ready(self, slot) -> bool:
         """True when everything enqueued for the slot has finished."""
@@ -96,6 +115,7 @@ class _Active:
     slot: object
     footprint: int
     t: int = 0
+    rt: int = 0                   # reverse steps left in the backward pass
     phase: str = "forward"        # forward -> backward -> done
     t_admit: float = 0.0
     cancel: bool = False
@@ -103,13 +123,15 @@ class _Active:
 
 class Scheduler:
     def __init__(self, executor: Executor, budget_bytes: int, max_active: int = 32, chunk: int = 64,
-                 clock: Callable[[], float] = time.perf_counter):
-        if budget_bytes <= 0 or max_active <= 0 or chunk <= 0:
-            raise ValueError("budget, max_active and chunk must be positive")
+                 clock: Callable[[], float] = time.perf_counter, bchunk: Optional[int] = None):
+        bchunk = max(1, chunk // 2) if bchunk is None else bchunk
+        if budget_bytes <= 0 or max_active <= 0 or chunk <= 0 or bchunk <= 0:
+            raise ValueError("budget, max_active, chunk and bchunk must be positive")
         self.ex = executor
         self.budget = int(budget_bytes)
         self.max_active = int(max_active)
         self.chunk = int(chunk)
+        self.bchunk = int(bchunk)
         self.clock = clock
         self.queue: Deque[Request] = collections.deque()
         self.active: Dict[int, _Active] = {}
@@ -224,11 +246,18 @@ class Scheduler:
                     a.t += n
                 elif a.phase == "forward":
                     if a.req.kind == "gradient":
-                        self.ex.backward(a.slot)
                         a.phase = "backward"
+                        a.rt = T
+                        n = min(self.bchunk, a.rt)
+                        self.ex.backward(a.slot, n)
+                        a.rt -= n
                     else:
                         a.phase = "done"
                         self._retire(a, True)
+                elif a.phase == "backward" and a.rt > 0:
+                    n = min(self.bchunk, a.rt)
+                    self.ex.backward(a.slot, n)
+                    a.rt -= n
                 elif a.phase == "backward":
                     a.phase = "done"
                     self._retire(a, True)
@@ -237,7 +266,18 @@ class Scheduler:
                 if rid in self.active:
                     self._retire(a, False, f"{type(e).__name__}: {e}")
                 acted += 1
+        self._flush()
         return acted
+
+    def _flush(self):
+        """Hand the iteration's chunks to the executor; a failure there fails
+        the requests whose work it held (the executor names them)."""
+        try:
+            self.ex.flush()
+        except BatchError as e:
+            for rid in e.rids:
+                if rid in self.active:
+                    self._retire(self.active[rid], False, f"{type(e.cause).__name__}: {e.cause}")
 
     # -------------------------------------------------------------- driver
     def run(self, requests: List[Request], open_loop: bool = True, poll_s: float = 2e-4,
@@ -291,55 +331,79 @@ def summarize(results: Dict[int, Result], wall_s: float) -> dict:
 # ------------------------------------------------------------ GPU executor
 
 class GpuExecutor(Executor):
-    """Slots are libfdtd handles (fdtd.Solver) on a pool of device streams.
-    Completion is tested with a device event recorded after each chunk."""
+    """Slots are libfdtd handles (fdtd.Solver), all on one device stream.
+    forward() and backward() only queue a chunk; flush() issues the queued
+    chunks of all slots as batch calls (one z-march launch per sweep and per
+    reverse step spanning every queued request) and records one event that
+    tells each of those slots when its chunk has finished."""
 
-    def __init__(self, n_streams: int = 8, time_block: int = 0, device: str = "cuda"):
+    def __init__(self, time_block: int = 0, device: str = "cuda"):
         import torch
         from . import fdtd
         self.torch = torch
         self.fdtd = fdtd
         self.device = torch.device(device)
-        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
-        self._next = 0
+        self.stream = torch.cuda.Stream(device=self.device)
         self.time_block = time_block
+        self._fwd = []
+        self._bwd = []
 
     def footprint(self, req: Request) -> int:
         return self.fdtd.footprint(req.problem, record=req.kind == "gradient", time_block=self.time_block) + 256
 
     def start(self, req: Request):
-        st = self.streams[self._next % len(self.streams)]
-        self._next += 1
-        with self.torch.cuda.stream(st):
+        with self.torch.cuda.stream(self.stream):
             s = self.fdtd.Solver(req.problem, record=req.kind == "gradient", time_block=self.time_block,
-                                 device=str(self.device), stream=st)
-            slot = {"s": s, "ev": self.torch.cuda.Event(), "stream": st, "kind": req.kind,
-                    "trace": [], "grad": None, "recon": None}
-            slot["ev"].record(st)
+                                 device=str(self.device), stream=self.stream)
+            slot = {"s": s, "ev": self.torch.cuda.Event(), "kind": req.kind, "rid": req.rid,
+                    "trace": [], "grad": None, "recon": None, "rleft": None}
+            slot["ev"].record(self.stream)
         return slot
 
     def forward(self, slot, nsteps: int) -> None:
-        st = slot["stream"]
-        with self.torch.cuda.stream(st):
-            tr, J = slot["s"].forward(nsteps)
-            slot["trace"].append(tr)
-            slot["J"] = J
-            slot["ev"].record(st)
+        self._fwd.append((slot, int(nsteps)))
 
-    def backward(self, slot) -> None:
-        st = slot["stream"]
-        with self.torch.cuda.stream(st):
-            J = slot["J"].clone()
-            g, r = slot["s"].grad()
-            slot["J"] = J
-            slot["grad"], slot["recon"] = g, r
-            slot["ev"].record(st)
+    def backward(self, slot, nsteps: int) -> None:
+        self._bwd.append((slot, int(nsteps)))
+
+    def flush(self) -> None:
+        fwd, bwd = self._fwd, self._bwd
+        self._fwd, self._bwd = [], []
+        if not fwd and not bwd:
+            return
+        with self.torch.cuda.stream(self.stream):
+            if fwd:
+                try:
+                    outs = self.fdtd.forward_batch([sl["s"] for sl, _ in fwd], [n for _, n in fwd])
+                except Exception as e:
+                    raise BatchError([sl["rid"] for sl, _ in fwd] + [sl["rid"] for sl, _ in bwd], e)
+                for (sl, _), (tr, J) in zip(fwd, outs):
+                    sl["trace"].append(tr)
+                    sl["J"] = J
+            if bwd:
+                try:
+                    for sl, _ in bwd:
+                        if sl["rleft"] is None:          # the pass starts
+                            sl["J"] = sl["J"].clone()
+                            sl["s"].grad_begin()
+                            sl["rleft"] = sl["s"].t
+                    self.fdtd.grad_steps_batch([sl["s"] for sl, _ in bwd], [n for _, n in bwd])
+                    for sl, n in bwd:
+                        sl["rleft"] -= n
+                        if sl["rleft"] == 0:             # the pass ends
+                            sl["grad"], sl["recon"] = sl["s"].grad_end()
+                except Exception as e:
+                    raise BatchError([sl["rid"] for sl, _ in bwd], e)
+            ev = self.torch.cuda.Event()
+            ev.record(self.stream)
+        for sl, _ in fwd + bwd:
+            sl["ev"] = ev
 
     def ready(self, slot) -> bool:
         return slot["ev"].query()
 
     def result(self, slot) -> dict:
-        slot["stream"].synchronize()
+        self.stream.synchronize()
         out = {"J": float(slot["J"].item())}
         if slot["trace"]:
             out["trace"] = self.torch.cat(slot["trace"]).cpu().numpy()
@@ -349,7 +413,7 @@ class GpuExecutor(Executor):
         return out
 
     def release(self, slot) -> None:
-        slot["stream"].synchronize()
+        self.stream.synchronize()
         slot["s"].close()
         slot.clear()
 
@@ -391,9 +455,10 @@ class MockExecutor(Executor):
         slot["steps"] += nsteps
         self._work(slot, slot["req"].problem.N * nsteps)
 
-    def backward(self, slot) -> None:
-        slot["grad"] = True
-        self._work(slot, 2 * slot["req"].problem.N * slot["req"].problem.T)
+    def backward(self, slot, nsteps: int) -> None:
+        slot["rsteps"] = slot.get("rsteps", 0) + nsteps
+        slot["grad"] = slot["rsteps"] == slot["req"].problem.T
+        self._work(slot, 2 * slot["req"].problem.N * nsteps)
 
     def ready(self, slot) -> bool:
         return self.clock.t >= slot["busy_until"]

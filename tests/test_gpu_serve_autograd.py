@@ -56,10 +56,10 @@ def test_serving_result_same_alone_and_in_mix():
     announce("serving alone")
     alone = {}
     for r in reqs:
-        sch = serve.Scheduler(serve.GpuExecutor(n_streams=1), budget_bytes=8 << 30, max_active=1, chunk=32)
+        sch = serve.Scheduler(serve.GpuExecutor(), budget_bytes=8 << 30, max_active=1, chunk=32)
         alone.update(sch.run([r], open_loop=False))
     announce("serving mix")
-    sch = serve.Scheduler(serve.GpuExecutor(n_streams=3), budget_bytes=8 << 30, max_active=6, chunk=16)
+    sch = serve.Scheduler(serve.GpuExecutor(), budget_bytes=8 << 30, max_active=6, chunk=16)
     mix = sch.run(reqs, open_loop=False)
     for r in reqs:
         a, b = alone[r.rid], mix[r.rid]
@@ -77,7 +77,7 @@ def test_serving_admission_respects_budget_on_gpu():
     fps = [fdtd.footprint(r.problem, record=r.kind == "gradient") + 256 for r in reqs]
     budget = max(fps) * 2
     announce("serving budget")
-    sch = serve.Scheduler(serve.GpuExecutor(n_streams=2), budget_bytes=budget, max_active=8, chunk=32)
+    sch = serve.Scheduler(serve.GpuExecutor(), budget_bytes=budget, max_active=8, chunk=32)
     res = sch.run(reqs, open_loop=False)
     assert all(r.ok for r in res.values())
     assert sch.peak_in_use <= budget
