@@ -329,10 +329,9 @@ std::vector<std::pair<int, int>> split_uniform(int n, int w)
     return v;
 }
 
-// z extent of one workgroup's march: enough workgroups to fill the chip
-// (about 1024) without letting the 2K-plane z halo dominate.  Marches are
-// split evenly: nz planes in ceil(nz / zc) chunks of equal length (up to one
-// plane), never longer than zc.
+// z extent of one workgroup's march.  Marches are split evenly: nz planes in
+// ceil(nz / zc) chunks of equal length (up to one plane), never longer than
+// zc.
 int even_chunk(int nz, int zc)
 {
     const int nc = (nz + zc - 1) / zc;
@@ -343,48 +342,47 @@ int zchunk(const Geometry &G, int K, bool reverse)
 {
     const char *e = getenv(reverse ? "FDTD_REV_ZC" : "FDTD_TB_ZC");
     if (e && atoi(e) > 0) return std::min(atoi(e), G.nz);
+    const long long slots = 2LL * 256;   // two workgroups per CU
     if (reverse) {
-        // the reverse march does about twice the work per plane: 32 or 24
-        // planes only with at least eight workgroups per slot, else 20
-        // (measured: 32 best on 640x640x400 among 16..32; 20 on 200^3, 0.439
-        // against 0.451 ms per step at 16).  Where even marches of up to 60
-        // planes still leave eight per slot, those: 58 x 7 on 640x640x400
-        // (6.03 against 6.08 ms per step at 32), 50 x 3 on 2400x1600x150
-        // (20.8 against 22.5 ms; 75 x 2: 21.2).
+        // The reverse march is kept short: the longest of at most 20 planes
+        // that still gives four workgroups per slot, else 8.  One launch holds
+        // every tile class, so many short marches balance the slab classes'
+        // longer ones.  Measured: 10-11 planes on 200^3 (0.351 against 0.376
+        // ms per step at 20, 0.391 at 5), 20 on 640x640x400 (5.26 against 5.38
+        // ms per step at 58).  Planes of 2M cells or more take even marches of
+        // up to 60 planes while those leave eight workgroups per slot: 50 x 3
+        // on 2400x1600x150 (18.0 against 20.0-21.0 ms per step at 19).
         const long long tx = (long long)split_uniform(G.nx, rev_tile_x()).size();
         const long long ty = (long long)split_axis(G.ny, rev_tile_y()).size();
-        const long long nc60 = (G.nz + 59) / 60;
-        if (tx * ty * nc60 >= 8 * 2LL * 256) return even_chunk(G.nz, std::min(60, G.nz));
-        for (int zc : {32, 24}) {
-            const long long nwg = tx * ty * ((G.nz + zc - 1) / zc);
-            if (nwg >= 8 * 2LL * 256) return even_chunk(G.nz, std::min(zc, G.nz));
-        }
-        return even_chunk(G.nz, std::min(20, G.nz));
+        if ((long long)G.nx * G.ny >= (2LL << 20) && tx * ty * ((G.nz + 59) / 60) >= 8 * slots)
+            return even_chunk(G.nz, std::min(60, G.nz));
+        for (int zc = std::min(20, G.nz); zc > 8; zc--)
+            if (tx * ty * ((G.nz + zc - 1) / zc) >= 4 * slots) return even_chunk(G.nz, zc);
+        return even_chunk(G.nz, std::min(8, G.nz));
     }
-    // A longer march fetches its 2K-plane z halo less often, but leaves fewer
-    // workgroups to balance over the chip (the work of one is serial).  Take
-    // the longest of 20..64 planes that still gives at least four workgroups
-    // per slot (two per CU), else 16: measured best on 200^3 (16-20 planes)
-    // and 256^3 (24).  Where 64 planes leave that many, marches of up to 80
-    // planes, still with four workgroups per slot: 80 x 5 on 640x640x400
-    // (104.0 against 101.7 Gcell/s for 64 x 6 + 16), 75 x 2 on
-    // 2400x1600x150 (97.7 against 80.0 for 64 x 2 + 22).
+    // The forward march: a longer one fetches its 2K-plane z halo less often
+    // but leaves fewer workgroups, and the last round of workgroups may fill
+    // the chip only in part.  Over even splits into 16..80-plane marches that
+    // leave at least two workgroups per slot, take the least
+    // rounds x (planes + 2K).  Measured on 256^3: 37 planes 86.3 Gcell/s
+    // (against 81.4 at 24, 82.2 at 20, 81.9 at 43, 72.5 at 64); 640x640x400:
+    // 67-80 planes 104-105 (100.5 at 134); 2400x1600x150: 75.
     const int shape = tb_shape();
     const long long tx = (long long)(tb_tile_aligned(shape) ? split_uniform(G.nx, tb_tile_x(K, shape))
                                                              : split_axis(G.nx, tb_tile_x(K, shape))).size();
     const long long ty = (long long)split_axis(G.ny, tb_tile_y(K, shape)).size();
-    const long long slots = 2LL * 256;
-    for (int zc : {64, 48, 32, 24, 20}) {
-        const long long nwg = tx * ty * ((G.nz + zc - 1) / zc);
-        if (nwg < 4 * slots) continue;
-        if (zc == 64)
-            for (long long nc = (G.nz + 79) / 80;; nc++) {
-                const int z = (int)((G.nz + nc - 1) / nc);
-                if (tx * ty * nc >= 4 * slots || z <= 64) return std::min(z, G.nz);
-            }
-        return even_chunk(G.nz, std::min(zc, G.nz));
+    long long best = -1;
+    int bz = 0;
+    for (int nc = 1; nc <= G.nz; nc++) {
+        const int z = (G.nz + nc - 1) / nc;
+        if (z > 80) continue;
+        if (z < 16) break;
+        const long long nwg = tx * ty * nc;
+        if (nwg < 2 * slots) continue;
+        const long long cost = (nwg + slots - 1) / slots * (z + 2 * K);
+        if (best < 0 || cost < best) { best = cost; bz = z; }
     }
-    return even_chunk(G.nz, std::min(16, G.nz));
+    return bz > 0 ? bz : even_chunk(G.nz, std::min(16, G.nz));
 }
 
 // Tile tables of the z-march kernels: slot 0 for the fused reverse march,

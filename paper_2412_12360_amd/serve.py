@@ -98,8 +98,13 @@ class Executor:
         scheduler iteration)."""
 
     def ready(self, slot) -> bool:
-        """True when everything enqueued for the slot has finished."""
+        """True when the slot can take another chunk (an executor may keep
+        a chunk queued behind the running one)."""
         raise NotImplementedError
+
+    def idle(self, slot) -> bool:
+        """True when everything enqueued for the slot has finished."""
+        return self.ready(slot)
 
     def result(self, slot) -> dict:
         """Host copies of the outputs (only after ready())."""
@@ -236,6 +241,8 @@ class Scheduler:
                 if not self.ex.ready(a.slot):
                     continue
                 if a.cancel:
+                    if not self.ex.idle(a.slot):
+                        continue
                     self._retire(a, False, "cancelled")
                     acted += 1
                     continue
@@ -252,6 +259,8 @@ class Scheduler:
                         self.ex.backward(a.slot, n)
                         a.rt -= n
                     else:
+                        if not self.ex.idle(a.slot):
+                            continue
                         a.phase = "done"
                         self._retire(a, True)
                 elif a.phase == "backward" and a.rt > 0:
@@ -259,6 +268,8 @@ class Scheduler:
                     self.ex.backward(a.slot, n)
                     a.rt -= n
                 elif a.phase == "backward":
+                    if not self.ex.idle(a.slot):
+                        continue
                     a.phase = "done"
                     self._retire(a, True)
                 acted += 1
@@ -335,7 +346,10 @@ class GpuExecutor(Executor):
     forward() and backward() only queue a chunk; flush() issues the queued
     chunks of all slots as batch calls (one z-march launch per sweep and per
     reverse step spanning every queued request) and records one event that
-    tells each of those slots when its chunk has finished."""
+    tells each of those slots when its chunk has finished.  A slot takes its
+    next chunk while one is still running (ready), so the next batch is
+    queued on the stream before the running one ends and the device does not
+    wait for the host between iterations."""
 
     def __init__(self, time_block: int = 0, device: str = "cuda"):
         import torch
@@ -355,9 +369,10 @@ class GpuExecutor(Executor):
         with self.torch.cuda.stream(self.stream):
             s = self.fdtd.Solver(req.problem, record=req.kind == "gradient", time_block=self.time_block,
                                  device=str(self.device), stream=self.stream)
-            slot = {"s": s, "ev": self.torch.cuda.Event(), "kind": req.kind, "rid": req.rid,
+            ev = self.torch.cuda.Event()
+            ev.record(self.stream)
+            slot = {"s": s, "evs": [ev], "kind": req.kind, "rid": req.rid,
                     "trace": [], "grad": None, "recon": None, "rleft": None}
-            slot["ev"].record(self.stream)
         return slot
 
     def forward(self, slot, nsteps: int) -> None:
@@ -397,13 +412,23 @@ class GpuExecutor(Executor):
             ev = self.torch.cuda.Event()
             ev.record(self.stream)
         for sl, _ in fwd + bwd:
-            sl["ev"] = ev
+            sl["evs"].append(ev)
+
+    def _pending(self, slot) -> int:
+        evs = slot["evs"]
+        while evs and evs[0].query():
+            evs.pop(0)
+        return len(evs)
 
     def ready(self, slot) -> bool:
-        return slot["ev"].query()
+        return self._pending(slot) <= 1
+
+    def idle(self, slot) -> bool:
+        return self._pending(slot) == 0
 
     def result(self, slot) -> dict:
-        self.stream.synchronize()
+        # (the slot is idle: its work has finished, the copies need no wait
+        # on the stream, where other slots' work may be queued)
         out = {"J": float(slot["J"].item())}
         if slot["trace"]:
             out["trace"] = self.torch.cat(slot["trace"]).cpu().numpy()
@@ -413,7 +438,8 @@ class GpuExecutor(Executor):
         return out
 
     def release(self, slot) -> None:
-        self.stream.synchronize()
+        # the workspace was allocated on self.stream, so the allocator orders
+        # its reuse after the slot's last (finished) work there
         slot["s"].close()
         slot.clear()
 
