@@ -235,6 +235,28 @@ def fwd_grad_run(pg, Solver, torch, time_block: int, workload: str, checkpoint: 
             "grad_rel_diff_vs_time_reversal": float(((dck - dg).norm() / dg.norm()).item()),
         }
         del store
+        # the schedules section 2.2 names: recursive halving, and treeverse
+        # with a fixed number of kept states (each a complete forward state)
+        from paper_2412_12360_amd.fdtd import revolve_plan
+        sched = {}
+        for name, k in (("halving", 0), ("treeverse", 4)):
+            fsteps, peak, _ = revolve_plan(pg.T, name, k)
+            store = torch.empty(g.revolve_bytes(name, k), dtype=torch.uint8, device=g.device)
+            c0 = torch.cuda.Event(enable_timing=True)
+            c1 = torch.cuda.Event(enable_timing=True)
+            c0.record(g.stream)
+            dr, _ = g.grad_revolve(name, k, store=store)
+            c1.record(g.stream)
+            torch.cuda.synchronize()
+            tc = c0.elapsed_time(c1)
+            sched[name if name == "halving" else f"treeverse_{k}"] = {
+                "value": round(pg.N * pg.T / (tc / 1e3) / 1e6, 1), "unit": "Mcell-steps/s", "ms": round(tc, 2),
+                "forward_steps": fsteps, "kept_states": peak, "extra_hbm_gb": round(store.numel() / 1e9, 2),
+                "time_reversal_speedup": round(tc / (tf + tb), 3),
+                "grad_bitwise_equal_to_segments": bool(torch.equal(dr, dck)),
+            }
+            del store
+        res["checkpoint_schedules"] = sched
     del g
     torch.cuda.empty_cache()
     return res

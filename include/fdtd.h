@@ -222,6 +222,39 @@ fdtd_status fdtd_checkpoint_bytes(fdtd_handle h, int32_t segment, size_t *bytes)
 fdtd_status fdtd_grad_checkpointed(fdtd_handle h, int32_t segment, void *store, size_t store_bytes,
                                    float *dJ_deps, float *J);
 
+/* Gradient by the checkpoint schedules section 2.2 contrasts with time
+ * reversal, for measuring memory against time:
+ *   schedule 0, recursive halving: the state at the middle of the span still
+ *     to be reversed is kept, recursively, so ceil(log2 T) states at most are
+ *     held; for T a power of two it costs T/2 log2 T forward steps beyond the
+ *     T a stored history needs (the count the paper gives).
+ *   schedule 1, treeverse: at most `snapshots` kept states, placed where the
+ *     fewest forward steps result (dynamic programming over span length and
+ *     free slots); 0 recomputes every step from s_0.
+ * Each kept state is a complete forward state (fields and CPML auxiliaries).
+ * The adjoint steps are those of fdtd_grad_checkpointed, applied in order
+ * T-1 .. 0 to recomputed states, so dJ_deps and J equal its results bit for
+ * bit.
+ *   fdtd_revolve_plan (host only, no handle): for T steps, the forward steps
+ *     the schedule runs, the most states it keeps at once, and (when actions
+ *     is not NULL, capacity cap triples) its actions as (op, a, b) triples:
+ *     op 0 restore kept state a (a = -1: the zero state s_0), op 1 advance b
+ *     steps from step a, op 2 keep the current state as state a, op 3 the
+ *     adjoint of step a on the current state (which is then s_{a+1}).
+ *     n_actions receives the count.  E_INVALID for T < 1, a schedule other
+ *     than 0 or 1, snapshots outside [0, 64], or cap too small;
+ *     E_UNSUPPORTED when T x (snapshots + 1) exceeds 2^26.
+ *   fdtd_revolve_bytes: device bytes of the store for handle h.
+ *   fdtd_grad_revolve: runs the forward pass itself from zero fields and the
+ *     whole gradient; store: caller-owned device memory, 256-byte aligned, of
+ *     at least fdtd_revolve_bytes bytes.  Requirements and errors as
+ *     fdtd_grad_checkpointed; t = 0 on return. */
+fdtd_status fdtd_revolve_plan(int32_t T, int32_t schedule, int32_t snapshots, int64_t *forward_steps,
+                              int32_t *peak_snapshots, int32_t *actions, int32_t cap, int32_t *n_actions);
+fdtd_status fdtd_revolve_bytes(fdtd_handle h, int32_t schedule, int32_t snapshots, size_t *bytes);
+fdtd_status fdtd_grad_revolve(fdtd_handle h, int32_t schedule, int32_t snapshots, void *store, size_t store_bytes,
+                              float *dJ_deps, float *J);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, serving loops and harnesses that forbid hipMalloc): the same
  * computation as fdtd_grad_checkpointed, with the checkpoint store taken from

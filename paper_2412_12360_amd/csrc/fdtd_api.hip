@@ -1586,6 +1586,237 @@ fdtd_status fdtd_grad_checkpointed_noalloc(fdtd_handle h, int32_t segment, float
 
 size_t fdtd_noalloc_store_bytes(void) { return NOALLOC_STORE_BYTES; }
 
+// ----------------------------------------------------------------------
+// Checkpoint schedules of section 2.2 for the gradient without time
+// reversal: recursive halving (the states at the midpoints of ever smaller
+// halves are kept) and treeverse (with a fixed number k of kept states, the
+// split points that need the fewest forward steps, by dynamic programming).
+// A schedule is a list of actions on one forward state (the handle's
+// current buffer) and k snapshot slots:
+//   restore slot a (a = -1: the zero state s_0), advance b steps from step
+//   a, save to slot a, adjoint of step a (on the current state s_{a+1}).
+namespace {
+
+enum { RV_RESTORE = 0, RV_ADVANCE = 1, RV_SAVE = 2, RV_ADJOINT = 3 };
+struct RevAct {
+    int op, a, b;
+};
+
+struct RevPlanner {
+    int T = 0, sched = 0, k = 0;
+    // treeverse: best[l][j] = fewest forward steps to reverse l steps with j
+    // free slots (the first state already kept), split[l][j] = its first split
+    std::vector<long long> best;
+    std::vector<int> split;
+    std::vector<RevAct> acts;
+    long long fwd = 0;
+    int peak = 0;
+
+    long long &B(int l, int j) { return best[(size_t)l * (k + 1) + j]; }
+    int &P(int l, int j) { return split[(size_t)l * (k + 1) + j]; }
+
+    void table()
+    {
+        best.assign((size_t)(T + 1) * (k + 1), 0);
+        split.assign((size_t)(T + 1) * (k + 1), 0);
+        for (int j = 0; j <= k; j++) B(1, j) = 1;
+        for (int l = 2; l <= T; l++) {
+            B(l, 0) = (long long)l * (l + 1) / 2;
+            for (int j = 1; j <= k; j++) {
+                long long bv = -1;
+                int bm = 1;
+                // advance m steps, keep that state, reverse the right part
+                // with one slot fewer, then the left part with all of them
+                for (int m = 1; m < l; m++) {
+                    const long long c = m + B(l - m, j - 1) + B(m, j);
+                    if (bv < 0 || c < bv) { bv = c; bm = m; }
+                }
+                B(l, j) = bv;
+                P(l, j) = bm;
+            }
+        }
+    }
+
+    // reverse steps [s, e) with state s in slot `slot` (-1: s_0), j free slots
+    void rec(int s, int e, int slot, int j, int used)
+    {
+        peak = std::max(peak, used);
+        const int l = e - s;
+        if (l <= 0) return;
+        if (l == 1) {
+            acts.push_back({RV_RESTORE, slot, 0});
+            acts.push_back({RV_ADVANCE, s, 1});
+            acts.push_back({RV_ADJOINT, s, 0});
+            fwd += 1;
+            return;
+        }
+        if (j == 0) {
+            for (int n = e - 1; n >= s; n--) {
+                acts.push_back({RV_RESTORE, slot, 0});
+                acts.push_back({RV_ADVANCE, s, n + 1 - s});
+                acts.push_back({RV_ADJOINT, n, 0});
+                fwd += n + 1 - s;
+            }
+            return;
+        }
+        const int m = sched == 0 ? l / 2 : P(l, j);
+        acts.push_back({RV_RESTORE, slot, 0});
+        acts.push_back({RV_ADVANCE, s, m});
+        acts.push_back({RV_SAVE, used, 0});
+        fwd += m;
+        rec(s + m, e, used, j - 1, used + 1);
+        rec(s, s + m, slot, j, used);
+    }
+
+    // sched 0: recursive halving (k is set to the depth it needs);
+    // sched 1: treeverse with k slots
+    void build(int T_, int sched_, int k_)
+    {
+        T = T_;
+        sched = sched_;
+        k = k_;
+        if (sched == 0) {
+            k = 0;
+            while ((1LL << k) < T) k++;
+        } else {
+            table();
+        }
+        acts.clear();
+        fwd = 0;
+        peak = 0;
+        rec(0, T, -1, k, 0);
+    }
+};
+
+fdtd_status revolve_check(int T, int schedule, int snapshots)
+{
+    if (T < 1) return fail(nullptr, FDTD_E_INVALID, "T = %d < 1", T);
+    if (schedule != 0 && schedule != 1) return fail(nullptr, FDTD_E_INVALID, "schedule %d not 0 or 1", schedule);
+    if (schedule == 1 && (snapshots < 0 || snapshots > 64))
+        return fail(nullptr, FDTD_E_INVALID, "snapshots %d not in [0, 64]", snapshots);
+    if (schedule == 1 && (long long)T * (snapshots + 1) > (1LL << 26))
+        return fail(nullptr, FDTD_E_UNSUPPORTED, "treeverse table of %d x %d too large", T, snapshots + 1);
+    return FDTD_OK;
+}
+
+}  // namespace
+
+fdtd_status fdtd_revolve_plan(int32_t T, int32_t schedule, int32_t snapshots, int64_t *forward_steps,
+                              int32_t *peak_snapshots, int32_t *actions, int32_t cap, int32_t *n_actions)
+{
+    fdtd_status st = revolve_check(T, schedule, snapshots);
+    if (st != FDTD_OK) return st;
+    RevPlanner P;
+    P.build(T, schedule, snapshots);
+    if (forward_steps) *forward_steps = P.fwd;
+    if (peak_snapshots) *peak_snapshots = P.peak;
+    if (n_actions) *n_actions = (int32_t)P.acts.size();
+    if (actions) {
+        if (cap < (int32_t)P.acts.size()) return fail(nullptr, FDTD_E_INVALID, "cap %d < %zu actions", cap, P.acts.size());
+        for (size_t i = 0; i < P.acts.size(); i++) {
+            actions[3 * i] = P.acts[i].op;
+            actions[3 * i + 1] = P.acts[i].a;
+            actions[3 * i + 2] = P.acts[i].b;
+        }
+    }
+    return FDTD_OK;
+}
+
+fdtd_status fdtd_revolve_bytes(fdtd_handle h, int32_t schedule, int32_t snapshots, size_t *bytes)
+{
+    if (!h || !bytes) return fail(h, FDTD_E_INVALID, "NULL argument");
+    fdtd_status st = revolve_check(h->T, schedule, snapshots);
+    if (st != FDTD_OK) return fail(h, st, "%s", g_err);
+    RevPlanner P;
+    P.build(h->T, schedule, snapshots);
+    *bytes = (size_t)std::max(1, P.peak) * ckpt_plan(h, 1).snap_bytes;
+    return FDTD_OK;
+}
+
+fdtd_status fdtd_grad_revolve(fdtd_handle h, int32_t schedule, int32_t snapshots, void *store, size_t store_bytes,
+                              float *dJ_deps, float *J)
+{
+    if (!h) return fail(nullptr, FDTD_E_INVALID, "handle is NULL");
+    if (!h->desc.record) return fail(h, FDTD_E_STATE, "the checkpointed gradient needs the adjoint state (record = 1)");
+    if (energy_in_design(h))
+        return fail(h, FDTD_E_UNSUPPORTED, "a weighted energy detector must lie outside the design box in z");
+    if (h->naive) return fail(h, FDTD_E_UNSUPPORTED, "the checkpointed gradient runs on the z-march path only");
+    if (h->in_grad) return fail(h, FDTD_E_STATE, "a gradient is running on this handle");
+    fdtd_status st = revolve_check(h->T, schedule, snapshots);
+    if (st != FDTD_OK) return fail(h, st, "%s", g_err);
+    if (!store || !dJ_deps) return fail(h, FDTD_E_INVALID, "store or dJ_deps is NULL");
+    if (((uintptr_t)store & 255) != 0) return fail(h, FDTD_E_INVALID, "store not 256-byte aligned");
+    RevPlanner P;
+    P.build(h->T, schedule, snapshots);
+    const size_t snap = ckpt_plan(h, 1).snap_bytes;
+    if (store_bytes < (size_t)std::max(1, P.peak) * snap)
+        return fail(h, FDTD_E_NOMEM, "store %zu bytes < %zu", store_bytes, (size_t)std::max(1, P.peak) * snap);
+    const Geometry &G = h->geo;
+    char *base = (char *)store;
+    st = zero_forward(h);
+    if (st == FDTD_OK) st = zero_adjoint(h);
+    if (st != FDTD_OK) return st;
+    HIPCHK(h, launch_fill(h->trace, (long long)h->T * std::max(1, G.D.ndet), 0.f, h->stream));
+    HIPCHK(h, launch_fill(h->gacc, G.design_cells, 0.f, h->stream));
+    int at = 0;      // step of the state in the current buffer
+    int high = 0;    // steps below this one have run once (their detector output is in the trace)
+    std::vector<int> slot_step(std::max(1, P.peak), -1);
+    for (const RevAct &a : P.acts) {
+        if (a.op == RV_RESTORE) {
+            // the forward step is deterministic: a buffer at step s holds the
+            // bits of any kept state of step s, so a restore to the current
+            // step is skipped
+            const int want = a.a < 0 ? 0 : slot_step[a.a];
+            if (want != at) {
+                if (a.a < 0) {
+                    st = zero_forward(h);
+                } else {
+                    float *sf[6], *sp[3][4];
+                    ckpt_arrays(h, base + (size_t)a.a * snap, sf, sp);
+                    st = copy_state(h, h->fld[h->cur], h->psi[h->cur], sf, sp);
+                }
+                if (st != FDTD_OK) return st;
+                at = want;
+            }
+        } else if (a.op == RV_ADVANCE) {
+            const int s0 = a.a, s1 = a.a + a.b;
+            const int old_end = std::min(s1, std::max(s0, high));
+            if (old_end > s0) {
+                st = advance(h, s0, old_end - s0, 1, 0, 0);
+                if (st != FDTD_OK) return st;
+            }
+            if (s1 > old_end) {
+                st = advance(h, old_end, s1 - old_end, 1, 0, 1);
+                if (st != FDTD_OK) return st;
+                high = s1;
+            }
+            at = s1;
+        } else if (a.op == RV_SAVE) {
+            float *sf[6], *sp[3][4];
+            ckpt_arrays(h, base + (size_t)a.a * snap, sf, sp);
+            st = copy_state(h, sf, sp, h->fld[h->cur], h->psi[h->cur]);
+            if (st != FDTD_OK) return st;
+            slot_step[a.a] = at;
+        } else {
+            st = grad_pre_step(h, a.a);
+            if (st == FDTD_OK) st = reverse_fused(h, a.a, 0, 1, 1, h->gacc);
+            if (st != FDTD_OK) return st;
+        }
+    }
+    if (J) {
+        if (G.D.ndet > 0)
+            HIPCHK(h, launch_objective(h->trace, h->T, G.D.ndet, h->wdev, h->desc.courant, J, h->stream));
+        else
+            HIPCHK(h, launch_fill(J, 1, 0.f, h->stream));
+    }
+    HIPCHK(h, launch_deps(h->gacc, h->d_design, G.design_cells, h->desc.courant, dJ_deps, h->stream));
+    st = zero_forward(h);
+    if (st != FDTD_OK) return st;
+    HIPCHK(h, launch_fill(h->trace, (long long)h->T * std::max(1, G.D.ndet), 0.f, h->stream));
+    h->t = 0;
+    return FDTD_OK;
+}
+
 fdtd_status fdtd_set_inv_eps(fdtd_handle h, const float *inv_eps)
 {
     if (!h) return fail(nullptr, FDTD_E_INVALID, "handle is NULL");

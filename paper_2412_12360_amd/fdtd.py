@@ -55,7 +55,7 @@ ENTRY_POINTS = [
     "fdtd_linear_steps", "fdtd_record_ptr", "fdtd_time_block", "fdtd_checkpoint_bytes",
     "fdtd_grad_checkpointed", "fdtd_kernel_path", "fdtd_tile_classes", "fdtd_grad_checkpointed_noalloc",
     "fdtd_noalloc_store_bytes", "fdtd_grad_begin", "fdtd_grad_steps", "fdtd_grad_end", "fdtd_forward_batch",
-    "fdtd_grad_steps_batch",
+    "fdtd_grad_steps_batch", "fdtd_revolve_plan", "fdtd_revolve_bytes", "fdtd_grad_revolve",
 ]
 
 _lib = None
@@ -87,6 +87,10 @@ def lib():
     L.fdtd_forward_batch.argtypes = [C.POINTER(H), C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_void_p),
                                      C.POINTER(C.c_void_p)]
     L.fdtd_grad_steps_batch.argtypes = [C.POINTER(H), C.c_int32, C.POINTER(C.c_int32)]
+    L.fdtd_revolve_plan.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32)]
+    L.fdtd_revolve_bytes.argtypes = [H, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]
+    L.fdtd_grad_revolve.argtypes = [H, C.c_int32, C.c_int32, C.c_void_p, C.c_size_t, fp, fp]
     L.fdtd_checkpoint_bytes.argtypes = [H, C.c_int32, C.POINTER(C.c_size_t)]
     L.fdtd_grad_checkpointed.argtypes = [H, C.c_int32, C.c_void_p, C.c_size_t, fp, fp]
     L.fdtd_grad_checkpointed_noalloc.argtypes = [H, C.c_int32, fp, fp]
@@ -175,6 +179,26 @@ def footprint(prob, record: bool = False, time_block: int = 0, T: Optional[int] 
 
 def _handles(solvers):
     return (C.c_void_p * max(1, len(solvers)))(*[s.handle.value for s in solvers])
+
+
+SCHEDULES = {"halving": 0, "treeverse": 1}
+
+
+def revolve_plan(T: int, schedule: str, snapshots: int = 0, actions: bool = False):
+    """fdtd_revolve_plan: (forward steps, most kept states, [(op, a, b), ...]
+    or None) of a checkpoint schedule for T steps (host only)."""
+    f = C.c_int64(0)
+    pk = C.c_int32(0)
+    n = C.c_int32(0)
+    check(lib().fdtd_revolve_plan(int(T), SCHEDULES[schedule], int(snapshots), C.byref(f), C.byref(pk), None, 0,
+                                  C.byref(n)))
+    acts = None
+    if actions:
+        buf = (C.c_int32 * (3 * max(1, n.value)))()
+        check(lib().fdtd_revolve_plan(int(T), SCHEDULES[schedule], int(snapshots), None, None, buf, n.value,
+                                      C.byref(n)))
+        acts = [(buf[3 * i], buf[3 * i + 1], buf[3 * i + 2]) for i in range(n.value)]
+    return int(f.value), int(pk.value), acts
 
 
 def _batch_check(status: int, solvers):
@@ -353,6 +377,26 @@ class Solver:
         check(lib().fdtd_grad_checkpointed(self.handle, int(segment), C.c_void_p(store.data_ptr()),
                                            C.c_size_t(store.numel() * store.element_size()),
                                            C.c_void_p(g.data_ptr()), C.c_void_p(J.data_ptr())), self.handle)
+        self._keep_store = store
+        return g, J
+
+    def revolve_bytes(self, schedule: str, snapshots: int = 0) -> int:
+        v = C.c_size_t(0)
+        check(lib().fdtd_revolve_bytes(self.handle, SCHEDULES[schedule], int(snapshots), C.byref(v)), self.handle)
+        return int(v.value)
+
+    def grad_revolve(self, schedule: str, snapshots: int = 0, store=None):
+        """The gradient by recursive halving ("halving") or treeverse with
+        `snapshots` kept states ("treeverse"): runs the forward pass itself;
+        returns dJ/deps_r over the design box and J."""
+        nbytes = self.revolve_bytes(schedule, snapshots)
+        if store is None:
+            store = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.device)
+        g = self.torch.empty(self.prob.design_shape(), dtype=self.torch.float32, device=self.device)
+        J = self.torch.zeros(1, dtype=self.torch.float32, device=self.device)
+        check(lib().fdtd_grad_revolve(self.handle, SCHEDULES[schedule], int(snapshots), C.c_void_p(store.data_ptr()),
+                                      C.c_size_t(store.numel() * store.element_size()), C.c_void_p(g.data_ptr()),
+                                      C.c_void_p(J.data_ptr())), self.handle)
         self._keep_store = store
         return g, J
 

@@ -68,3 +68,43 @@ def test_checkpoint_store_too_small_is_rejected():
         s.grad_checkpointed(4, store=small)
     with pytest.raises(FdtdError):
         s.checkpoint_bytes(0)
+
+
+@pytest.mark.parametrize("schedule,k", [("halving", 0), ("treeverse", 0), ("treeverse", 2), ("treeverse", 5)])
+def test_revolve_schedules_equal_uniform_checkpointing(schedule, k):
+    """Recursive halving and treeverse recompute the same forward states
+    (the forward step is deterministic) and apply the same adjoint steps in
+    the same order: the bits of the uniform-segment gradient and objective;
+    the oracle's stored-history gradient within the gradient tolerance."""
+    from paper_2412_12360_amd.fdtd import Solver
+    T = 60 if k == 0 and schedule == "treeverse" else 90
+    pr = W.small_cpml(nx=70, ny=45, nz=38, p=5, T=T, d=8, seed=23)
+    announce(f"revolve {schedule} k={k} T={T}")
+    o = Oracle(pr)
+    g_ref, _, _ = o.grad_history()
+    ref = o.deps_design(g_ref)
+    s = Solver(pr, record=True)
+    g_u, J_u = s.grad_checkpointed(9)
+    torch.cuda.synchronize()
+    g_u, J_u = g_u.cpu().numpy(), float(J_u.item())
+    g, J = s.grad_revolve(schedule, k)
+    torch.cuda.synchronize()
+    assert s.t == 0
+    assert float(J.item()) == J_u
+    assert np.array_equal(g.cpu().numpy(), g_u)
+    assert rel_l2(g.cpu().numpy(), ref) <= GRAD_TOL
+    # the store holds the schedule's largest number of kept states
+    from paper_2412_12360_amd.fdtd import revolve_plan
+    _, peak, _ = revolve_plan(T, schedule, k)
+    assert s.revolve_bytes(schedule, k) == max(1, peak) * s.revolve_bytes("treeverse", 1)
+
+
+def test_revolve_store_too_small_is_rejected():
+    from paper_2412_12360_amd.fdtd import Solver, FdtdError
+    pr = W.small_cpml(nx=40, ny=36, nz=30, p=4, T=16, d=6, seed=24)
+    announce("revolve store too small")
+    s = Solver(pr, record=True)
+    need = s.revolve_bytes("halving")
+    small = torch.empty(need - 256, dtype=torch.uint8, device=s.device)
+    with pytest.raises(FdtdError):
+        s.grad_revolve("halving", store=small)
