@@ -5,20 +5,23 @@ A step is one complete solve of the benchmark workload: zero the fields, then
 T leapfrog steps of the Yee/CPML update with the plane-wave source and the
 flux detector.  The default workload is a 256^3 grid with a 10-cell CPML on
 every face and T = 2000 (forward only).  The line also carries:
-  - fwd_grad: the 200^3 gradient problem (CPML 10, 64^3 design cube,
-    T = 1500): forward with the interface record, then the time-reversed
-    adjoint pass, rated as N*T / (t_fwd + t_bwd); beside it the same
-    gradient by checkpointing (the method time reversal replaces);
-  - roofline: the forward sweep (the tile-class kernels of one K-step
-    sweep, timed on the same grid without the detector so no reduction
-    kernel is inside the events) against the 8 TB/s HBM peak, with
+  - roofline: the forward sweep (one launch of the z-march over every tile
+    class for K steps, timed on the same grid without the detector so no
+    reduction kernel is inside the events) against the 8 TB/s HBM peak, with
     algorithmic bytes 52 B per cell plus 32 B per CPML slab cell and slab
     axis, per time step; traffic from the committed counter summary;
-  - serving: the first requests of the serving mix (12 by default), one at
+  - fwd_grad: the 200^3 gradient problem (CPML 10, 64^3 design cube,
+    T = 1500): forward with the interface record, then the time-reversed
+    adjoint pass, rated as N*T / (t_fwd + t_bwd), the fused reverse step
+    against the roofline; beside it the same gradient by uniform
+    checkpointing, recursive halving and treeverse (the methods time
+    reversal replaces);
+  - fwd_grad_large: the same on 640x640x400 (CPML 12, 4000 steps, 71.8 GB);
+  - serving: the first requests of the serving mix (100 by default), one at
     a time and with continuous batching: throughput, and p50/p99 latency
     under Poisson arrivals at 0.8x the one-at-a-time rate;
-  - cpu_baseline: the FP64 oracle on the host cores, timed on a bounded
-    sample (the same 256^3 grid, a few time steps).
+  - cpu_baseline: the FP64 oracle on the host cores and on one core, timed
+    on a bounded sample (the same 256^3 grid, a few time steps).
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -79,6 +82,36 @@ def measured_traffic(K: int):
     return int(b.group(1))
 
 
+REV_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "fdtd_reverse_zmarch_200cube_hbm_traffic.md")
+
+
+def rev_source_hash() -> str:
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2412_12360_amd/csrc/kern_tb_rev.hip"), "rb") as f:
+        h.update(f.read())
+    with open(os.path.join(ROOT, "paper_2412_12360_amd/csrc/fdtd_api.hip"), "rb") as f:
+        api = f.read()
+    i, j = api.index(PLANNER_BEGIN), api.index(PLANNER_END)
+    h.update(api[i:j])
+    return h.hexdigest()
+
+
+def measured_rev_traffic(pr):
+    """HBM bytes per fused reverse step of this grid from the committed
+    counter summary, or None when there is none for the grid or the reverse
+    kernel or tile planner has changed since it was taken."""
+    try:
+        with open(REV_TRAFFIC_PROFILE) as f:
+            text = f.read()
+    except OSError:
+        return None
+    h = re.search(r"sources_sha256:\s*([0-9a-f]{64})", text)
+    b = re.search(r"traffic_bytes_per_step_%dx%dx%d:\s*(\d+)" % (pr.nx, pr.ny, pr.nz), text)
+    if not (h and b) or h.group(1) != rev_source_hash():
+        return None
+    return int(b.group(1))
+
+
 def slab_cell_axes(pr) -> int:
     if pr.p == 0:
         return 0
@@ -92,6 +125,21 @@ def alg_bytes_fwd_step(pr, record: bool = False) -> int:
         Lx, Ly, Lz = pr.nx - 2 * pr.p, pr.ny - 2 * pr.p, pr.nz - 2 * pr.p
         b += 4 * 2 * 2 * (Ly * Lz + Lx * Lz + Lx * Ly)
     return b
+
+
+def alg_bytes_rev_step(pr) -> int:
+    """Algorithmic bytes of one fused reverse step: 100 B per interior cell
+    (forward E, H read and written, adjoint E, H read and written, S/eps
+    read), 52 B per CPML cell (adjoint only), 32 B per slab cell and slab
+    axis (four psi-bar read and written), 8 B per design cell (dJ/deps
+    accumulator read and written) and the record of one step read."""
+    Lx, Ly, Lz = pr.nx - 2 * pr.p, pr.ny - 2 * pr.p, pr.nz - 2 * pr.p
+    interior = Lx * Ly * Lz
+    d = 1
+    for a in range(3):
+        d *= pr.design_hi[a] - pr.design_lo[a]
+    rec = 4 * 2 * 2 * (Ly * Lz + Lx * Lz + Lx * Ly) if pr.p > 0 else 0
+    return 100 * interior + 52 * (pr.N - interior) + 32 * slab_cell_axes(pr) + 8 * d + rec
 
 
 def time_solves(solver, count: int, torch):
@@ -186,13 +234,17 @@ def shard_run(Solver, torch, time_block: int, steps: int, W, T: int = 100):
     }
 
 
-def fwd_grad_run(pg, Solver, torch, time_block: int, workload: str, checkpoint: bool = False):
-    """One warm-up solve, then a timed forward (with the interface record)
-    and gradient on the solver's stream: N*T / (t_fwd + t_bwd)."""
+def fwd_grad_run(pg, Solver, torch, time_block: int, workload: str, checkpoint: bool = False,
+                 warmup: bool = True):
+    """A warm-up solve (unless the kernels ran already), then a timed forward
+    (with the interface record) and gradient on the solver's stream:
+    N*T / (t_fwd + t_bwd).  The fused reverse step is rated against the HBM
+    roofline by its algorithmic bytes."""
     g = Solver(pg, record=True, time_block=time_block)
-    g.reset()
-    g.forward()
-    g.grad()
+    if warmup:
+        g.reset()
+        g.forward()
+        g.grad()
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -212,6 +264,15 @@ def fwd_grad_run(pg, Solver, torch, time_block: int, workload: str, checkpoint: 
         "recon_err": float(recon.item()),
         "hbm_footprint_gb": round(g.footprint / 1e9, 2),
         "kernel_path": g.kernel_path,
+    }
+    rev_alg = alg_bytes_rev_step(pg)
+    rev_ms = tb / pg.T
+    res["roofline_reverse"] = {
+        "bound": "hbm", "kernel": "fused reverse z-march step (inverse + adjoint, one launch per step)",
+        "achieved": round(rev_alg / (rev_ms / 1e3) / 1e9, 1), "peak": PEAK_GBS, "unit": "GB/s",
+        "frac": round(rev_alg / (rev_ms / 1e3) / 1e9 / PEAK_GBS, 4), "alg_bytes_per_launch": rev_alg,
+        "avg_launch_ms": round(rev_ms, 5), "launches_timed": pg.T,
+        "traffic": measured_rev_traffic(pg),
     }
     if checkpoint:
         # the baseline the time reversal replaces: checkpoints every sqrt(T)
@@ -262,10 +323,37 @@ def fwd_grad_run(pg, Solver, torch, time_block: int, workload: str, checkpoint: 
     return res
 
 
-def cpu_baseline(pr, target_s: float = 12.0):
-    """The FP64 oracle on the host: the benchmark grid for a few steps."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_oracle_rate(threads: int, target_s: float):
+    """The FP64 oracle on the benchmark grid in a child process (its own
+    OpenMP thread count; the child never touches the GPU): (Mcell-updates/s,
+    steps timed)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS=str(threads), OMP_PROC_BIND="false")
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-oracle-child", str(target_s)],
+                       env=env, capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        raise RuntimeError(f"oracle child failed: {r.stderr[-400:]}")
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    return d["rate"], d["steps"]
+
+
+def cpu_oracle_child(target_s: float):
+    """Child of cpu_oracle_rate: times oracle steps of the benchmark grid."""
     from oracle.oracle import Oracle, build as build_oracle
+    from paper_2412_12360_amd import workloads as W
     build_oracle(force=False)
+    pr = W.config2()
     o = Oracle(pr)
     st = o.new_state()
     t0 = time.perf_counter()
@@ -275,10 +363,23 @@ def cpu_baseline(pr, target_s: float = 12.0):
     t0 = time.perf_counter()
     o.forward(st, n, 1)
     dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(pr.N * n / dt / 1e6, 3), "unit": "Mcell-updates/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"{pr.nx}x{pr.ny}x{pr.nz} grid, {n} FP64 time steps (steps 1..{n}) of the same problem"}
+    print(json.dumps({"rate": pr.N * n / dt / 1e6, "steps": n}), flush=True)
+
+
+def cpu_baseline(pr, target_s: float = 10.0):
+    """The FP64 oracle on the host cores available to this process (their
+    count from the CPU affinity, capped by OMP_NUM_THREADS when set) and on
+    one core: the benchmark grid for a bounded number of steps."""
+    cores = len(os.sched_getaffinity(0))
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit():
+        cores = max(1, min(cores, int(os.environ["OMP_NUM_THREADS"])))
+    rate, n = cpu_oracle_rate(cores, target_s)
+    rate1, n1 = cpu_oracle_rate(1, target_s)
+    return {"value": round(rate, 3), "unit": "Mcell-updates/s", "cores": cores,
+            "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": f"{pr.nx}x{pr.ny}x{pr.nz} grid, {n} FP64 time steps (steps 1..{n}) of the same problem "
+                      f"with {cores} threads; {n1} steps with 1 thread",
+            "value_1_thread": round(rate1, 3)}
 
 
 def copy_calibration(torch, nbytes: int = 1 << 30, reps: int = 4):
@@ -296,7 +397,8 @@ def copy_calibration(torch, nbytes: int = 1 << 30, reps: int = 4):
 
 
 def serving_bench(count: int, torch, seed_rate: float = 0.8, budget_gb: float = 0.0, max_active: int = 6,
-                  chunk: int = 64, extra_rates=(), open_loops: bool = True, open_rate: float = 0.0):
+                  chunk: int = 64, extra_rates=(), open_loops: bool = True, open_rate: float = 0.0,
+                  share: int = 0):
     """Serving mix: `count` requests of the Poisson mix recipe (edges U{64..256},
     50% forward / 50% gradient, T = 8 x max edge, CPML 8).  Measures saturation
     throughput one-at-a-time and with continuous batching (all queued at t=0),
@@ -317,7 +419,8 @@ def serving_bench(count: int, torch, seed_rate: float = 0.8, budget_gb: float = 
         reqs = [serve.Request(rid=rid, kind=kinds[rid], problem=probs[rid],
                               arrival=0.0 if arrivals is None else arrivals[i])
                 for i, rid in enumerate(rids)]
-        sch = serve.Scheduler(serve.GpuExecutor(), budget_bytes=budget, max_active=max_active, chunk=chunk)
+        sch = serve.Scheduler(serve.GpuExecutor(), budget_bytes=budget, max_active=max_active, chunk=chunk,
+                              share=share if share > 0 else None)
         t0 = time.perf_counter()
         res = sch.run(reqs, open_loop=arrivals is not None,
                       progress=lambda d, n: log(f"  {d} of {n} requests served"))
@@ -338,6 +441,7 @@ def serving_bench(count: int, torch, seed_rate: float = 0.8, budget_gb: float = 
     res = {"workload": f"{count} requests of the serving mix (edges U{{64..256}} per axis, 50% gradient, "
                        f"T = 8 x max edge, CPML 8, eps_r U[1,12.25]; seeds 6/7/1000+rid)",
            "hbm_budget_gb": round(budget / 1e9, 1), "max_active": max_active, "chunk_steps": chunk,
+           "share": share if share > 0 else None,
            "batched_launches": "one z-march launch per forward sweep and per reverse step spans all active requests"}
     if open_rate <= 0:
         seq = run(1)
@@ -397,7 +501,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-shard", action="store_true",
                     help="skip the forward step on one z-slab of a 2400x1600x600 grid (2400x1600x150)")
-    ap.add_argument("--serving", type=int, default=12,
+    ap.add_argument("--serving", type=int, default=100,
                     help="requests of the serving mix to run (0 = skip; the first requests of the 500-request mix)")
     ap.add_argument("--solve-steps", type=int, default=0,
                     help="profiling runs only: time steps per solve instead of the workload's (0 = workload)")
@@ -408,6 +512,8 @@ def main():
                     help="requests on the GPU at once in the batched runs (6 measured best on a "
                          "200-request mix: more sharing lengthens the largest requests)")
     ap.add_argument("--serving-chunk", type=int, default=64, help="serving: forward steps per scheduler iteration")
+    ap.add_argument("--serving-share", type=int, default=0,
+                    help="serving: younger requests take 1/share of a chunk (0 = equal chunks)")
     ap.add_argument("--serving-closed-only", action="store_true",
                     help="serving: the two closed loops only (a long mix split over two runs)")
     ap.add_argument("--serving-open-rate", type=float, default=0.0,
@@ -417,9 +523,17 @@ def main():
                          "(e.g. 0.5,1.2)")
     ap.add_argument("--serving-budget-gb", type=float, default=0.0,
                     help="HBM budget for the serving mix (0 = 80%% of free memory)")
+    ap.add_argument("--cpu-oracle-child", type=float, default=0.0, help=argparse.SUPPRESS)
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 640x640x400 forward + gradient leg")
+    ap.add_argument("--no-checkpoint", action="store_true",
+                    help="skip the checkpointing comparators of the 200^3 gradient leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="profiling runs only: run a plain 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
+    if args.cpu_oracle_child > 0:
+        cpu_oracle_child(args.cpu_oracle_child)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU z-slab decomposition is a design, not built)", file=sys.stderr)
@@ -516,15 +630,19 @@ def main():
         out["fwd_grad"] = fwd_grad_run(pg, Solver, torch, args.time_block,
                                        "200^3 grid, CPML 10, 64^3 design cube rho~U[0,1] (seed 3), eps_r = 2.25 + 10 rho, "
                                        "1500 steps, objective = time-integrated flux; forward with interface record, "
-                                       "then inverse-step + adjoint backward", checkpoint=True)
+                                       "then inverse-step + adjoint backward", checkpoint=not args.no_checkpoint)
         progress("forward + gradient")
 
-    if args.large and not args.no_grad:
+    if not args.no_grad and not args.no_large:
+        # (the kernels ran in the 200^3 leg: no warm-up solve)
         out["fwd_grad_large"] = fwd_grad_run(W.config4(T=args.solve_steps) if args.solve_steps else W.config4(),
                                              Solver, torch, args.time_block,
                                              "640x640x400 grid, CPML 12, 256x256x128 design box (blurred binary rho, "
-                                             "seed 5), eps_r = 2.25 + 10 rho, 4000 steps, interface record in HBM")
+                                             "seed 5), eps_r = 2.25 + 10 rho, 4000 steps, interface record in HBM",
+                                             warmup=False)
         progress("large forward + gradient")
+
+    if args.large and not args.no_grad:
         T = args.solve_steps if args.solve_steps else 100
         out["shard_fwd_grad"] = fwd_grad_run(W.shard_slab(T=T), Solver, torch, args.time_block,
                                              f"2400x1600x150 z-slab, CPML 12, 1200x800x75 design block, {T} steps "
@@ -534,7 +652,7 @@ def main():
 
     if args.serving > 0:
         out["serving"] = serving_bench(args.serving, torch, budget_gb=args.serving_budget_gb,
-                                       max_active=args.serving_max_active, chunk=args.serving_chunk,
+                                       max_active=args.serving_max_active, chunk=args.serving_chunk, share=args.serving_share,
                                        extra_rates=[float(v) for v in args.serving_extra_rates.split(",") if v],
                                        open_loops=not args.serving_closed_only, open_rate=args.serving_open_rate)
 

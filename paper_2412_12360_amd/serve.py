@@ -10,7 +10,10 @@ iteration
   2. gives every active request whose previous chunk has finished its next
      chunk of work: `chunk` more forward time steps, or, once a gradient
      request's forward is complete, `bchunk` more time-reversed steps of its
-     backward pass;
+     backward pass (with `share` = s, only the oldest active request takes
+     whole chunks and the others 1/s of them: they fill what the oldest
+     leaves of the device, in the same launches, without holding it back
+     much -- first-come first-served with backfill);
   3. hands the iteration's chunks to the executor at once (flush): the GPU
      executor advances all of them with batched launches -- every forward
      sweep and every reverse step is one kernel launch whose tile table
@@ -128,10 +131,14 @@ class _Active:
 
 class Scheduler:
     def __init__(self, executor: Executor, budget_bytes: int, max_active: int = 32, chunk: int = 64,
-                 clock: Callable[[], float] = time.perf_counter, bchunk: Optional[int] = None):
+                 clock: Callable[[], float] = time.perf_counter, bchunk: Optional[int] = None,
+                 share: Optional[int] = None):
         bchunk = max(1, chunk // 2) if bchunk is None else bchunk
         if budget_bytes <= 0 or max_active <= 0 or chunk <= 0 or bchunk <= 0:
             raise ValueError("budget, max_active, chunk and bchunk must be positive")
+        if share is not None and share <= 0:
+            raise ValueError("share must be positive")
+        self.share = share
         self.ex = executor
         self.budget = int(budget_bytes)
         self.max_active = int(max_active)
@@ -233,8 +240,10 @@ class Scheduler:
     def step(self) -> int:
         """One scheduler iteration; returns how many actions it took."""
         acted = self._admit()
-        for rid in list(self.active.keys()):
+        for rank, rid in enumerate(list(self.active.keys())):
             a = self.active[rid]
+            div = self.share if (self.share and rank > 0) else 1
+            fchunk, rchunk = max(2, self.chunk // div), max(1, self.bchunk // div)
             if rid in self._cancelled:
                 a.cancel = True
             try:
@@ -248,14 +257,14 @@ class Scheduler:
                     continue
                 T = a.req.problem.T
                 if a.phase == "forward" and a.t < T:
-                    n = min(self.chunk, T - a.t)
+                    n = min(fchunk, T - a.t)
                     self.ex.forward(a.slot, n)
                     a.t += n
                 elif a.phase == "forward":
                     if a.req.kind == "gradient":
                         a.phase = "backward"
                         a.rt = T
-                        n = min(self.bchunk, a.rt)
+                        n = min(rchunk, a.rt)
                         self.ex.backward(a.slot, n)
                         a.rt -= n
                     else:
@@ -264,7 +273,7 @@ class Scheduler:
                         a.phase = "done"
                         self._retire(a, True)
                 elif a.phase == "backward" and a.rt > 0:
-                    n = min(self.bchunk, a.rt)
+                    n = min(rchunk, a.rt)
                     self.ex.backward(a.slot, n)
                     a.rt -= n
                 elif a.phase == "backward":

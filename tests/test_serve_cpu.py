@@ -155,3 +155,28 @@ def test_serving_mix_descriptor_recipe():
 def test_scheduler_rejects_bad_configuration():
     with pytest.raises(ValueError):
         serve.Scheduler(serve.MockExecutor(VClock()), budget_bytes=0)
+
+
+def test_share_gives_whole_chunks_to_the_oldest_only():
+    """With share = s the oldest active request takes whole chunks and the
+    younger ones 1/s of a chunk per iteration (first come, first served with
+    backfill); every request still completes with its full work."""
+    clk = VClock()
+    ex = serve.MockExecutor(clk)
+    seen = []
+    orig = ex.forward
+
+    def fwd(slot, n):
+        seen.append((slot["rid"], n))
+        orig(slot, n)
+    ex.forward = fwd
+    sch = serve.Scheduler(ex, 10**12, max_active=4, chunk=64, clock=clk, share=4)
+    reqs = [mk(i, edge=32, T=256) for i in range(3)]
+    res = sch.run(reqs, open_loop=False, sleep=clk.sleep)
+    assert all(r.ok and r.J == r.cell_steps for r in res.values())
+    first = {}
+    for rid, n in seen:
+        first.setdefault(rid, n)
+    assert first[0] == 64 and first[1] == 16 and first[2] == 16
+    with pytest.raises(ValueError):
+        serve.Scheduler(ex, 10**12, share=0)
