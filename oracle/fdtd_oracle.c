@@ -54,6 +54,9 @@
 #define OR_MAXSRC 4
 #define OR_MAXDET 4
 #define OR_NSLOT 18
+/* grids smaller than this run their sweeps on one thread: thread start-up
+ * would cost more than the sweep */
+#define OR_PAR_MIN 65536
 
 typedef struct {
     int nx, ny, nz;
@@ -172,7 +175,7 @@ static void h_sweep(const or_problem *P, double *st, const or_prof *PH)
 {
     const double S = P->S;
     double *E[3] = {slot(st, P, 0), slot(st, P, 1), slot(st, P, 2)};
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (ncell(P) >= OR_PAR_MIN)
     for (int k = 0; k < P->nz; k++)
         for (int j = 0; j < P->ny; j++)
             for (int i = 0; i < P->nx; i++) {
@@ -196,7 +199,7 @@ static void e_sweep(const or_problem *P, double *st, const or_prof *PE)
 {
     const double S = P->S;
     double *H[3] = {slot(st, P, 3), slot(st, P, 4), slot(st, P, 5)};
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (ncell(P) >= OR_PAR_MIN)
     for (int k = 0; k < P->nz; k++)
         for (int j = 0; j < P->ny; j++)
             for (int i = 0; i < P->nx; i++) {
@@ -613,7 +616,7 @@ static void inverse_step(const or_problem *P, double *st, int n, const double *r
     sub_sources_interior(P, st, n, 0);
     double *H[3] = {slot(st, P, 3), slot(st, P, 4), slot(st, P, 5)};
     double *E[3] = {slot(st, P, 0), slot(st, P, 1), slot(st, P, 2)};
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (ncell(P) >= OR_PAR_MIN)
     for (int k = p; k < P->nz - p; k++)
         for (int j = p; j < P->ny - p; j++)
             for (int i = p; i < P->nx - p; i++) {
@@ -635,7 +638,7 @@ static void inverse_step(const or_problem *P, double *st, int n, const double *r
         }
     }
     sub_sources_interior(P, st, n, 1);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (ncell(P) >= OR_PAR_MIN)
     for (int k = p; k < P->nz - p; k++)
         for (int j = p; j < P->ny - p; j++)
             for (int i = p; i < P->nx - p; i++) {
@@ -703,7 +706,7 @@ static void adjoint_step(const or_problem *P, double *adj, const double *fwd, do
     /* reverse of the E half: per E pair (q, s) along axis ax with sign +/-S*d,
      * psibar_tot = psibar + w; Q = w*kinv + a*psibar_tot multiplies
      * H(x) - H(x - e_ax); psibar <- b*psibar_tot.  tmp[6][N] holds Q. */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (ncell(P) >= OR_PAR_MIN)
     for (int k = 0; k < P->nz; k++)
         for (int j = 0; j < P->ny; j++)
             for (int i = 0; i < P->nx; i++) {
@@ -723,7 +726,7 @@ static void adjoint_step(const or_problem *P, double *adj, const double *fwd, do
                     }
             }
     /* H_F is differenced by pair (q = F+1, s = 0, axis F+2) and (q = F+2, s = 1, axis F+1) */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (ncell(P) >= OR_PAR_MIN)
     for (int k = 0; k < P->nz; k++)
         for (int j = 0; j < P->ny; j++)
             for (int i = 0; i < P->nx; i++) {
@@ -740,7 +743,7 @@ static void adjoint_step(const or_problem *P, double *adj, const double *fwd, do
             }
     /* reverse of the H half: H_q -= S*(T_r - T_t), so pair s = 0 has weight -S,
      * s = 1 weight +S; R multiplies E(x + e_ax) - E(x). */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (ncell(P) >= OR_PAR_MIN)
     for (int k = 0; k < P->nz; k++)
         for (int j = 0; j < P->ny; j++)
             for (int i = 0; i < P->nx; i++) {
@@ -756,7 +759,7 @@ static void adjoint_step(const or_problem *P, double *adj, const double *fwd, do
                     }
             }
     /* E_F is differenced by pair (q = F+1, s = 0, axis F+2) and (q = F+2, s = 1, axis F+1) */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (ncell(P) >= OR_PAR_MIN)
     for (int k = 0; k < P->nz; k++)
         for (int j = 0; j < P->ny; j++)
             for (int i = 0; i < P->nx; i++) {
