@@ -42,6 +42,14 @@
  *   - gradients by stored history (checkpointed segments, recomputation with
  *     the forward step only) and by time reversal (inverse steps plus the
  *     interface record).
+ *   - conducting cells in a box inside the interior: eps dE/dt = curl H - sigma E
+ *     with E averaged over the two time levels, E^{n+1} = ca E^n + cb curl H,
+ *     u = sigma S d / 2, ca = (1-u)/(1+u), cb = S d/(1+u).  The update divides
+ *     by nothing but damps, so it is not inverted: section 2.2 bases the time
+ *     reversal on lossless media, and, as for the PML, the record keeps what
+ *     the inverse cannot rebuild -- E^n of every cell of the lossy box, per
+ *     step, after the interface layers.  The VJP carries ca, cb and their
+ *     derivatives in d.
  *
  * Layout: every 3D array is [nz][ny][nx], x fastest.  A state buffer holds 18
  * arrays of N doubles: slots 0..5 = Ex,Ey,Ez,Hx,Hy,Hz; slot 6+2c+s = psi of
@@ -76,6 +84,10 @@ typedef struct {
     int det_interp[OR_MAXDET];      /* 1: co-located (interpolated) flux */
     int det_energy[OR_MAXDET];      /* 1: co-located energy density instead of flux */
     int dlo[3], dhi[3];             /* half-open design box */
+    const double *sig;              /* N values of the conductivity sigma (NULL: lossless);
+                                       zero outside the lossy box */
+    int llo[3], lhi[3];             /* half-open lossy box inside the interior; E^n of
+                                       its cells is part of the record of step n */
 } or_problem;
 
 /* ---------------------------------------------------------------- helpers */
@@ -215,7 +227,16 @@ static void e_sweep(const or_problem *P, double *st, const or_prof *PE)
                     *pt = PE->b[t][it] * *pt + PE->a[t][it] * dt;
                     double Tr = dr * PE->kinv[r][ir] + *pr;
                     double Tt = dt * PE->kinv[t][it] + *pt;
-                    slot(st, P, q)[c] += S * P->d[c] * (Tr - Tt);
+                    double sg = P->sig ? P->sig[c] : 0.0;
+                    if (sg == 0.0) {
+                        slot(st, P, q)[c] += S * P->d[c] * (Tr - Tt);
+                    } else {
+                        /* conducting cell: eps dE/dt = curl H - sigma E with E
+                         * averaged over the two time levels */
+                        double u = 0.5 * sg * S * P->d[c];
+                        double *Eq = slot(st, P, q) + c;
+                        *Eq = (1.0 - u) / (1.0 + u) * *Eq + S * P->d[c] / (1.0 + u) * (Tr - Tt);
+                    }
                 }
             }
 }
@@ -345,14 +366,53 @@ static double det_energy_interp(const or_problem *P, const double *st, const dou
  * the two other axes u < v, each restricted to [p, n-p), stored [comp][v][u]. */
 static void face_axes(int a, int *u, int *v) { *u = a == 0 ? 1 : 0; *v = a == 2 ? 1 : 2; }
 
-size_t or_record_floats(const or_problem *P)
+static size_t iface_floats(const or_problem *P)
 {
     size_t tot = 0;
+    if (P->p == 0) return 0;
     for (int a = 0; a < 3; a++) {
         int u, v; face_axes(a, &u, &v);
         tot += 2 * 2 * (size_t)(dim(P, u) - 2 * P->p) * (dim(P, v) - 2 * P->p);
     }
     return tot;
+}
+
+/* cells of the lossy box (0 without conductivity) */
+static size_t lossy_cells(const or_problem *P)
+{
+    if (!P->sig) return 0;
+    size_t c = 1;
+    for (int a = 0; a < 3; a++) c *= (size_t)(P->lhi[a] > P->llo[a] ? P->lhi[a] - P->llo[a] : 0);
+    return c;
+}
+
+/* the record of one step: the interface layers, then E^n of the lossy box */
+size_t or_record_floats(const or_problem *P)
+{
+    return iface_floats(P) + 3 * lossy_cells(P);
+}
+
+/* position of component q of cell (i,j,k) in a lossy-box array */
+static size_t lossy_index(const or_problem *P, int q, int i, int j, int k)
+{
+    size_t lx = P->lhi[0] - P->llo[0], ly = P->lhi[1] - P->llo[1], lz = P->lhi[2] - P->llo[2];
+    return (((size_t)q * lz + (k - P->llo[2])) * ly + (j - P->llo[1])) * lx + (i - P->llo[0]);
+}
+
+/* E of the lossy box, [comp][z][y][x] over the box: dir = 0 state -> buf,
+ * dir = 1 buf -> state */
+static void lossy_io(const or_problem *P, double *st, double *buf, int dir)
+{
+    size_t r = 0;
+    for (int q = 0; q < 3; q++) {
+        double *F = slot(st, P, q);
+        for (int k = P->llo[2]; k < P->lhi[2]; k++)
+            for (int j = P->llo[1]; j < P->lhi[1]; j++)
+                for (int i = P->llo[0]; i < P->lhi[0]; i++, r++) {
+                    size_t c = idx(P, i, j, k);
+                    if (dir == 0) buf[r] = F[c]; else F[c] = buf[r];
+                }
+    }
 }
 
 /* dir = 0: state -> record; dir = 1: record -> state.  which = 0 low (H) faces, 1 high (E) faces */
@@ -404,12 +464,13 @@ static void step_fwd(const or_problem *P, double *st, int n, const or_prof *PE, 
                 memcpy(eprev + (4 * (size_t)m + 3) * A, slot(st, P, 2) + (size_t)(P->det_k[m] - 1) * A,
                        sizeof(double) * A);
             }
+    if (rec && lossy_cells(P)) lossy_io(P, st, rec + iface_floats(P), 0);
     h_sweep(P, st, PH);
     if (with_src) add_sources(P, st, n, 1.0, 1);
-    if (rec) record_io(P, st, rec, 0, 0);
+    if (rec && P->p > 0) record_io(P, st, rec, 0, 0);
     e_sweep(P, st, PE);
     if (with_src) add_sources(P, st, n, 1.0, 0);
-    if (rec) record_io(P, st, rec, 1, 0);
+    if (rec && P->p > 0) record_io(P, st, rec, 1, 0);
     if (trow)
         for (int m = 0; m < P->ndet; m++)
             trow[m] = !P->det_interp[m] ? det_flux(P, st, m)
@@ -637,6 +698,9 @@ static void inverse_step(const or_problem *P, double *st, int n, const double *r
             free(zero);
         }
     }
+    /* conducting cells are not inverted (their update divides by a factor
+     * below one): E^n of the lossy box comes from the record of step n */
+    if (lossy_cells(P)) lossy_io(P, st, (double *)(rec + (size_t)n * rf + iface_floats(P)), 1);
     sub_sources_interior(P, st, n, 1);
 #pragma omp parallel for schedule(static) if (ncell(P) >= OR_PAR_MIN)
     for (int k = p; k < P->nz - p; k++)
@@ -664,7 +728,8 @@ void or_inverse(const or_problem *P, double *st, int n0, int T, const double *re
  * the design box.  g (N values, may be NULL) accumulates dJ/dd.  With
  * with_det = 0 and g == NULL this is exactly the transpose of the linear map. */
 static void adjoint_step(const or_problem *P, double *adj, const double *fwd, double *g,
-                         int with_det, const or_prof *PE, const or_prof *PH, double *tmp)
+                         int with_det, const or_prof *PE, const or_prof *PH, double *tmp,
+                         const double *lE)
 {
     const double S = P->S;
     size_t N = ncell(P);
@@ -686,7 +751,10 @@ static void adjoint_step(const or_problem *P, double *adj, const double *fwd, do
                 }
         }
     }
-    /* dJ/dd: E^{n+1} = E^n + S*d*(curl_kappa^T H + psi_E) */
+    /* dJ/dd: E^{n+1} = E^n + S*d*(curl_kappa^T H + psi_E); in a conducting
+     * cell E^{n+1} = ca(d) E^n + cb(d) (curl H) with u = sigma*S*d/2,
+     * ca = (1-u)/(1+u), cb = S*d/(1+u), so dca/dd = -sigma*S/(1+u)^2 and
+     * dcb/dd = S/(1+u)^2 (E^n of the lossy box in lE) */
     if (g) {
         const double *fH[3] = {fwd + 3 * N, fwd + 4 * N, fwd + 5 * N};
         for (int k = P->dlo[2]; k < P->dhi[2]; k++)
@@ -699,7 +767,14 @@ static void adjoint_step(const or_problem *P, double *adj, const double *fwd, do
                         int ir = coord(r, i, j, k), it = coord(t, i, j, k);
                         double Tr = dbwd(fH[t], P, r, i, j, k) * PE->kinv[r][ir] + fwd[(size_t)(6 + 2 * q) * N + c];
                         double Tt = dbwd(fH[r], P, t, i, j, k) * PE->kinv[t][it] + fwd[(size_t)(7 + 2 * q) * N + c];
-                        g[c] += S * adj[(size_t)q * N + c] * (Tr - Tt);
+                        double sg = P->sig ? P->sig[c] : 0.0;
+                        if (sg == 0.0) {
+                            g[c] += S * adj[(size_t)q * N + c] * (Tr - Tt);
+                        } else {
+                            double u = 0.5 * sg * S * P->d[c];
+                            double En = lE[lossy_index(P, q, i, j, k)];
+                            g[c] += S / ((1.0 + u) * (1.0 + u)) * adj[(size_t)q * N + c] * ((Tr - Tt) - sg * En);
+                        }
                     }
                 }
     }
@@ -711,19 +786,25 @@ static void adjoint_step(const or_problem *P, double *adj, const double *fwd, do
         for (int j = 0; j < P->ny; j++)
             for (int i = 0; i < P->nx; i++) {
                 size_t c = idx(P, i, j, k);
-                for (int q = 0; q < 3; q++)
+                double sg = P->sig ? P->sig[c] : 0.0;
+                double u = 0.5 * sg * S * P->d[c];
+                for (int q = 0; q < 3; q++) {
                     for (int s = 0; s < 2; s++) {
                         int ax = (q + 1 + s) % 3, ia = coord(ax, i, j, k);
                         double *pb = adj + (size_t)(6 + 2 * q + s) * N + c;
                         double Q = 0.0;
                         if (!e_held(q, i, j, k)) {
-                            double w = (s == 0 ? 1.0 : -1.0) * S * P->d[c] * adj[(size_t)q * N + c];
+                            double cb = sg == 0.0 ? S * P->d[c] : S * P->d[c] / (1.0 + u);
+                            double w = (s == 0 ? 1.0 : -1.0) * cb * adj[(size_t)q * N + c];
                             double tot = *pb + w;
                             Q = w * PE->kinv[ax][ia] + PE->a[ax][ia] * tot;
                             *pb = PE->b[ax][ia] * tot;
                         }
                         tmp[(size_t)(2 * q + s) * N + c] = Q;
                     }
+                    /* a conducting cell passes ca Ebar' on to E^n */
+                    if (sg != 0.0 && !e_held(q, i, j, k)) adj[(size_t)q * N + c] *= (1.0 - u) / (1.0 + u);
+                }
             }
     /* H_F is differenced by pair (q = F+1, s = 0, axis F+2) and (q = F+2, s = 1, axis F+1) */
 #pragma omp parallel for schedule(static) if (ncell(P) >= OR_PAR_MIN)
@@ -783,7 +864,7 @@ void or_adjoint_linear(const or_problem *P, double *adj, int T)
     or_prof PE, PH;
     prof_make(P, &PE, &PH);
     double *tmp = malloc(sizeof(double) * 6 * ncell(P));
-    for (int n = 0; n < T; n++) adjoint_step(P, adj, NULL, NULL, 0, &PE, &PH, tmp);
+    for (int n = 0; n < T; n++) adjoint_step(P, adj, NULL, NULL, 0, &PE, &PH, tmp, NULL);
     free(tmp);
     prof_free(&PE); prof_free(&PH);
 }
@@ -823,6 +904,7 @@ double or_grad_history(const or_problem *P, int T, int seg, double *g, double *t
     if (trace) memcpy(trace, tr, sizeof(double) * (size_t)T * P->ndet);
     double *adj = calloc(SZ, sizeof(double));
     double *tmp = malloc(sizeof(double) * 6 * N);
+    double *lE = lossy_cells(P) ? malloc(sizeof(double) * 3 * lossy_cells(P)) : NULL;
     memset(g, 0, sizeof(double) * N);
     for (int s0 = ((T - 1) / seg) * seg; s0 >= 0; s0 -= seg) {
         int len = T - s0 < seg ? T - s0 : seg;
@@ -833,10 +915,12 @@ double or_grad_history(const or_problem *P, int T, int seg, double *g, double *t
         }
         for (int m = len - 1; m >= 0; m--) {
             if (store) det_interp_adjoint(P, adj, store, e0, s0 + m, T);
-            adjoint_step(P, adj, buf + (size_t)(m + 1) * SZ, g, 1, &PE, &PH, tmp);
+            /* E^n of the conducting cells, from the stored state s_n */
+            if (lE) lossy_io(P, buf + (size_t)m * SZ, lE, 0);
+            adjoint_step(P, adj, buf + (size_t)(m + 1) * SZ, g, 1, &PE, &PH, tmp, lE);
         }
     }
-    free(ck); free(buf); free(st); free(adj); free(tmp); free(tr); free(store); free(e0);
+    free(ck); free(buf); free(st); free(adj); free(tmp); free(tr); free(store); free(e0); free(lE);
     prof_free(&PE); prof_free(&PH);
     return J;
 }
@@ -850,7 +934,7 @@ double or_grad_reversed(const or_problem *P, int T, double *g, double *trace, do
 {
     size_t N = ncell(P), SZ = OR_NSLOT * N, rf = or_record_floats(P);
     double *st = calloc(SZ, sizeof(double));
-    double *rec = P->p > 0 ? malloc(sizeof(double) * (size_t)(T > 0 ? T : 1) * rf) : NULL;
+    double *rec = rf > 0 ? malloc(sizeof(double) * (size_t)(T > 0 ? T : 1) * rf) : NULL;
     size_t A = (size_t)P->nx * P->ny;
     double *store = any_interp(P) ? calloc(dstore_floats(P, T) + 1, sizeof(double)) : NULL;
     double *e0 = any_interp(P) ? calloc((size_t)P->ndet * OR_DE0 * A, sizeof(double)) : NULL;
@@ -868,7 +952,8 @@ double or_grad_reversed(const or_problem *P, int T, double *g, double *trace, do
     memset(g, 0, sizeof(double) * N);
     for (int n = T - 1; n >= 0; n--) {
         if (store) det_interp_adjoint(P, adj, store, e0, n, T);
-        adjoint_step(P, adj, st, g, 1, &PE, &PH, tmp);
+        adjoint_step(P, adj, st, g, 1, &PE, &PH, tmp,
+                     lossy_cells(P) ? rec + (size_t)n * rf + iface_floats(P) : NULL);
         inverse_step(P, st, n, rec);
     }
     if (recon) {

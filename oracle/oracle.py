@@ -51,6 +51,8 @@ class _Problem(C.Structure):
         ("det_interp", C.c_int * MAXDET),
         ("det_energy", C.c_int * MAXDET),
         ("dlo", C.c_int * 3), ("dhi", C.c_int * 3),
+        ("sig", C.POINTER(C.c_double)),
+        ("llo", C.c_int * 3), ("lhi", C.c_int * 3),
     ]
 
 
@@ -181,6 +183,19 @@ class Oracle:
                 assert det.k >= 1 and det.i1 < prob.nx and det.j1 < prob.ny
         for a in range(3):
             s.dlo[a], s.dhi[a] = prob.design_lo[a], prob.design_hi[a]
+        # conducting cells: sigma over the whole grid, zero outside the lossy box
+        self.sig = None
+        if getattr(prob, "sigma", None) is not None:
+            n = (prob.nx, prob.ny, prob.nz)
+            for a in range(3):
+                lo, hi = prob.lossy_lo[a], prob.lossy_hi[a]
+                assert prob.p <= lo < hi <= n[a] - prob.p, "the lossy box lies in the interior"
+            assert prob.sigma.shape == prob.lossy_shape()
+            self.sig = np.zeros(prob.shape, np.float64)
+            self.sig[prob.lossy_slices()] = np.asarray(prob.sigma, np.float64)
+            s.sig = _ptr(self.sig)
+            for a in range(3):
+                s.llo[a], s.lhi[a] = prob.lossy_lo[a], prob.lossy_hi[a]
         self.s = s
 
     # -------------------------------------------------------------- helpers
@@ -218,7 +233,9 @@ class Oracle:
         return st, J, trace, rec
 
     def inverse(self, state: np.ndarray, rec: np.ndarray | None, T: int, n0: int = 0):
-        """Undo steps n0+T-1 .. n0 on the interior (in place)."""
+        """Undo steps n0+T-1 .. n0 on the interior (in place).  The record is
+        needed with a CPML and with conducting cells."""
+        assert rec is not None or self.record_floats() == 0, "this problem's inverse reads the record"
         self.L.or_inverse(C.byref(self.s), _ptr(state), n0, T, _ptr(rec) if rec is not None else None)
 
     def step_linear(self, state: np.ndarray, T: int = 1):

@@ -81,6 +81,12 @@ class Problem:
     design_hi: Tuple[int, int, int]
     T: int
     rho: Optional[np.ndarray] = None  # design parameters [dz, dy, dx] when eps = 2.25 + 10 rho
+    # conducting (lossy) cells: sigma over the half-open box [lossy_lo, lossy_hi)
+    # (x, y, z), float32 [lz, ly, lx] in normalised units (eps dE/dt = curl H - sigma E);
+    # None = lossless
+    sigma: Optional[np.ndarray] = None
+    lossy_lo: Tuple[int, int, int] = (0, 0, 0)
+    lossy_hi: Tuple[int, int, int] = (0, 0, 0)
 
     @property
     def N(self) -> int:
@@ -96,6 +102,14 @@ class Problem:
 
     def design_slices(self):
         lo, hi = self.design_lo, self.design_hi
+        return (slice(lo[2], hi[2]), slice(lo[1], hi[1]), slice(lo[0], hi[0]))
+
+    def lossy_shape(self) -> Tuple[int, int, int]:
+        lo, hi = self.lossy_lo, self.lossy_hi
+        return (hi[2] - lo[2], hi[1] - lo[1], hi[0] - lo[0])
+
+    def lossy_slices(self):
+        lo, hi = self.lossy_lo, self.lossy_hi
         return (slice(lo[2], hi[2]), slice(lo[1], hi[1]), slice(lo[0], hi[0]))
 
     def with_steps(self, T: int) -> "Problem":
@@ -160,6 +174,20 @@ def with_tfsf(prob: Problem, k: Optional[int] = None, comp: int = 0) -> Problem:
     s0 = prob.sources[0]
     src = Source(kind=2, comp=comp, i=0, j=0, k=s0.k if k is None else k, amp=s0.amp)
     return dataclasses.replace(prob, name=prob.name + "_tfsf", sources=[src] + list(prob.sources[1:]))
+
+
+def with_lossy(prob: Problem, lo=None, hi=None, sigma_max: float = 1.0, seed: int = 21) -> Problem:
+    """The same problem with conducting cells: per-cell sigma ~ U[0, sigma_max]
+    (seed) over the box [lo, hi) (default: the design box, so the lossy
+    region is also the design region).  In normalised units a cell with
+    sigma and eps_r damps E by (1 - u)/(1 + u) per step, u = sigma S / (2 eps_r);
+    sigma = 1 at eps_r = 2.25 gives u = 0.13, a 1/e length of a few cells."""
+    lo = tuple(prob.design_lo) if lo is None else tuple(lo)
+    hi = tuple(prob.design_hi) if hi is None else tuple(hi)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shape = (hi[2] - lo[2], hi[1] - lo[1], hi[0] - lo[0])
+    sig = rng.uniform(0.0, sigma_max, size=shape).astype(np.float32)
+    return dataclasses.replace(prob, name=prob.name + "_lossy", sigma=sig, lossy_lo=lo, lossy_hi=hi)
 
 
 def config1(T: int = 500, n: int = 32) -> Problem:
