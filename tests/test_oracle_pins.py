@@ -764,3 +764,84 @@ def test_energy_objective_gradient_matches_central_differences():
         fd[idx] = (vals[0] - vals[1]) / (2 * h)
     assert np.max(np.abs(adj)) > 0
     assert np.linalg.norm(fd - adj) <= 1e-6 * np.linalg.norm(adj)
+
+
+# ------------------------------------ P10b: CPML along each axis, in 1D
+
+def _grading_1d(n, p, u, m, smax, kmax, amax):
+    """The CFS-CPML grading at staggered coordinate u (reading R7: depth
+    delta = max(p-u, u-(n-p), 0)/p, sigma = smax delta^m, kappa = 1 + (kmax-1)
+    delta^m, alpha = amax (1-delta), b = exp(-(sigma/kappa + alpha)),
+    a = sigma (b-1) / (sigma kappa + kappa^2 alpha))."""
+    delta = max(p - u, u - (n - p), 0.0) / p
+    if delta <= 0.0:
+        return 1.0, 0.0, 1.0
+    dm = delta ** m
+    sig, kap, alp = smax * dm, 1.0 + (kmax - 1.0) * dm, amax * (1.0 - delta)
+    b = math.exp(-(sig / kap + alp))
+    return b, sig * (b - 1.0) / (sig * kap + kap * kap * alp), 1.0 / kap
+
+
+def _line_1d(n, p, S, d, pr, E0, T):
+    """A separate 1D recursion along one axis: H at i + 1/2 from the forward
+    difference of E, E at i from the backward difference of H, each difference
+    wrapped by its own psi recursion, E held at index 0 and read as 0 at n."""
+    gE = np.array([_grading_1d(n, p, float(i), pr.pml_m, pr.pml_sigma_max, pr.pml_kappa_max, pr.pml_alpha_max)
+                   for i in range(n)])
+    gH = np.array([_grading_1d(n, p, i + 0.5, pr.pml_m, pr.pml_sigma_max, pr.pml_kappa_max, pr.pml_alpha_max)
+                   for i in range(n)])
+    E, H = E0.astype(np.float64).copy(), np.zeros(n)
+    pE, pH = np.zeros(n), np.zeros(n)
+    out = []
+    for _ in range(T):
+        dH = np.append(E[1:], 0.0) - E
+        pH = gH[:, 0] * pH + gH[:, 1] * dH
+        H = H - S * (dH * gH[:, 2] + pH)
+        dE = H - np.concatenate(([0.0], H[:-1]))
+        pE = gE[:, 0] * pE + gE[:, 1] * dE
+        E = E - S * d * (dE * gE[:, 2] + pE)
+        E[0] = 0.0
+        out.append(E.copy())
+    return np.array(out)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_cpml_along_each_axis_matches_1d_recursion(axis):
+    """A pulse uniform across the two other axes, travelling along `axis` into
+    the graded CPML (kappa_max 3, so every term of the recursion acts): the
+    oracle's central line equals a separately written 1D recursion with the
+    grading evaluated at integer (E) and half-integer (H) coordinates, until
+    the transverse conducting walls can reach the line (one cell per step)."""
+    n, p, T = 40, 8, 56
+    w = 2 * T + 6
+    shape = [w, w, w]
+    shape[axis] = n
+    nx, ny, nz = shape
+    S = W.courant()
+    m, sig, kap, alp = W.pml_grading(S, 2.25, kappa_max=3.0, alpha_max=0.05)
+    pr = W.Problem(name="cpml1d", nx=nx, ny=ny, nz=nz, S=S, p=p, pml_m=m, pml_sigma_max=sig,
+                   pml_kappa_max=kap, pml_alpha_max=alp,
+                   inv_eps=np.full((nz, ny, nx), 1.0 / 2.25, np.float32), sources=[], detectors=[],
+                   design_lo=(p, p, p), design_hi=(p + 1, p + 1, p + 1), T=T)
+    o = Oracle(pr)
+    e = (axis + 1) % 3                      # E component across the line; H is (axis + 2) % 3
+    i = np.arange(n, dtype=np.float64)
+    E0 = np.exp(-((i - n / 2) / 3.0) ** 2)
+    E0[0] = 0.0
+    st = o.new_state()
+    bshape = [1, 1, 1]
+    bshape[2 - axis] = n
+    st[e] = np.broadcast_to(E0.reshape(bshape), (nz, ny, nx))
+    st[e][held_mask(nx, ny, nz)[e]] = 0.0
+    ref = _line_1d(n, p, S, float(np.float32(1.0 / 2.25)), pr, E0, T)
+    c = [w // 2, w // 2, w // 2]
+    got = []
+    for _ in range(T):
+        o.step_linear(st, 1)
+        idx = [c[2], c[1], c[0]]
+        idx[2 - axis] = slice(None)
+        got.append(st[e][tuple(idx)].copy())
+    got = np.array(got)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+    # the pulse has entered the CPML and been damped there
+    assert np.max(np.abs(ref[-1])) < 0.5 * np.max(np.abs(E0))
