@@ -26,3 +26,34 @@ def test_oracle_under_asan_and_ubsan(tmp_path):
     assert r.returncode == 0, r.stdout + r.stderr
     assert "runtime error" not in r.stderr and "AddressSanitizer" not in r.stderr, r.stderr
     assert r.stdout.count("recon=") == 4
+
+
+def test_host_api_under_asan_and_ubsan(tmp_path):
+    """fdtd_api.hip with AddressSanitizer and UBSan on its host code, linked
+    with the library's kernel objects: the validation of every descriptor
+    field, workspace sizing with and without conducting cells, create's
+    argument checks and the checkpoint planner run clean (no GPU needed)."""
+    root = os.path.dirname(HERE)
+    build = os.path.join(root, "paper_2412_12360_amd", "_build")
+    hipcc = "/opt/rocm/bin/hipcc"
+    kern = [os.path.join(build, f + ".hip.o") for f in ("kern_aux", "kern_naive", "kern_tb", "kern_tb_rev")]
+    if not os.path.exists(hipcc) or not all(os.path.exists(k) for k in kern):
+        pytest.skip("needs hipcc and the built kernel objects")
+    inc = os.path.join(root, "include")
+    api = tmp_path / "api.o"
+    subprocess.check_call([hipcc, "--offload-arch=gfx950", "-O1", "-g", "-std=c++17", "-fPIC", "-I", inc,
+                           "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                           "-c", os.path.join(root, "paper_2412_12360_amd", "csrc", "fdtd_api.hip"), "-o", str(api)],
+                          stderr=subprocess.DEVNULL)
+    drv = tmp_path / "drv.o"
+    subprocess.check_call(["/opt/rocm/bin/amdclang++", "-O1", "-g", "-std=c++17", "-I", inc, "-D__HIP_PLATFORM_AMD__",
+                           "-fsanitize=address,undefined", "-c", os.path.join(HERE, "sanitize", "api_driver.cpp"),
+                           "-o", str(drv)])
+    exe = tmp_path / "api_asan"
+    subprocess.check_call([hipcc, "-fsanitize=address,undefined", "-fno-gpu-sanitize", str(drv), str(api), *kern,
+                           "-o", str(exe)], stderr=subprocess.DEVNULL)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0", UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+    r = subprocess.run([str(exe)], capture_output=True, text=True, env=env, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "runtime error" not in r.stderr and "AddressSanitizer" not in r.stderr, r.stderr
+    assert r.stdout.count("case ") == 12 and "lossy 0" in r.stdout
