@@ -76,6 +76,23 @@ typedef struct {
                                  /* by fdtd_grad and by fdtd_inverse with a PML)   */
     int32_t time_block;          /* K steps fused per pass over the grid (0 = auto,*/
                                  /* 1..4); results are bitwise independent of K    */
+    /* Conducting (lossy) cells.  Section 2.2 bases the time reversal on
+     * lossless media: a conducting cell damps E by a factor below one per
+     * step, so its update is not inverted.  As for the PML, the record keeps
+     * what the inverse cannot rebuild: E^n of every cell of the lossy box,
+     * each step (12 B per box cell per step).  In a box cell the E update is
+     *     E^{n+1} = ca E^n + cb curl H^{n+1/2},  u = sigma S / (2 eps_r),
+     *     ca = (1 - u) / (1 + u),  cb = S / (eps_r (1 + u))
+     * (eps dE/dt = curl H - sigma E with E averaged over the two time levels),
+     * and the gradient carries ca and cb and their derivatives in eps_r.
+     * sigma: device, one value >= 0 per cell of the half-open box
+     * [lossy_lo, lossy_hi) (x, y, z), [z][y][x] over the box, or NULL for
+     * none; copied at create.  The box lies in the interior [p, n-p) and
+     * outside the z layers of any TFSF plane.  A handle with conducting
+     * cells runs the per-cell kernels (fdtd_kernel_path reports 0).     */
+    const float *sigma;
+    int32_t lossy_lo[3];
+    int32_t lossy_hi[3];
 } fdtd_desc;
 
 /* Sources (section 2.1).
@@ -276,10 +293,18 @@ fdtd_status fdtd_set_inv_eps(fdtd_handle h, const float *inv_eps);
 /* Zero the fields, PML state and adjoint state; t = 0. */
 fdtd_status fdtd_reset(fdtd_handle h);
 
-/* Release host-side state (and the handle's side streams and events).  The
- * workspace is the caller's to free.  The handle is gone even when a HIP
- * teardown call fails; that failure is reported as FDTD_E_DEVICE with the
- * message in fdtd_last_error(NULL). */
+/* Move the handle to another stream (a hipStream_t as void*; NULL = the
+ * default stream): later calls enqueue their work there.  The caller orders
+ * the new stream after the work already enqueued on the old one (fdtd_create
+ * returns with its own work finished).  A serving loop creates each handle on
+ * a stream of its own, so that the creation does not wait for other
+ * requests' queued work, and then moves it to the stream of its batches.
+ * Not allowed while a chunked gradient runs (FDTD_E_STATE). */
+fdtd_status fdtd_set_stream(fdtd_handle h, void *stream);
+
+/* Release host-side state.  The workspace is the caller's to free.  The
+ * handle is gone even when a HIP teardown call fails; that failure is
+ * reported as FDTD_E_DEVICE with the message in fdtd_last_error(NULL). */
 fdtd_status fdtd_destroy(fdtd_handle h);
 
 /* Current time step t (host). */

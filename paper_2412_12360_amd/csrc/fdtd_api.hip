@@ -49,6 +49,7 @@ struct Geometry {
     RecGeom R;
     Detectors D;
     long long design_cells;
+    long long lossy_cells;          // cells of the lossy box (0: none)
 };
 
 }  // namespace
@@ -77,6 +78,7 @@ struct fdtd_ctx {
     float *pb[2][3][4];
     int acur = 0, apar = 0;
     float *ce = nullptr, *inv_eps = nullptr, *d_design = nullptr;
+    float *lsig = nullptr, *lca = nullptr;  // conducting cells: sigma and ca per lossy-box cell
     float *prof[2][3][3];
     float *amps[FDTD_MAX_SOURCES];         // per internal source (see expand_sources)
     // total-field/scattered-field planes: their waveforms and the incident line
@@ -228,6 +230,17 @@ fdtd_status validate(fdtd_ctx *h, const fdtd_desc *d, const fdtd_source *src, in
     for (int a = 0; a < 3; a++)
         if (!inside(d->design_lo[a], d->design_hi[a], a))
             return fail(h, FDTD_E_INVALID, "design box axis %d outside the %s or empty", a, rec ? "interior" : "grid");
+    if (d->sigma) {
+        // conducting cells: a box in the interior, off the layers of any TFSF plane
+        for (int a = 0; a < 3; a++) {
+            const int lo = d->lossy_lo[a], hi = d->lossy_hi[a];
+            if (!(lo >= p && hi <= dim_of(d, a) - p && lo < hi))
+                return fail(h, FDTD_E_INVALID, "lossy box axis %d outside the interior or empty", a);
+        }
+        for (int s = 0; s < nsrc; s++)
+            if (src[s].kind == 2 && src[s].k - 1 < d->lossy_hi[2] && d->lossy_lo[2] <= src[s].k)
+                return fail(h, FDTD_E_INVALID, "source %d: TFSF layers k-1, k meet the lossy box", s);
+    }
     return FDTD_OK;
 }
 
@@ -247,7 +260,14 @@ void geometry(const fdtd_desc *d, const fdtd_flux_detector *det, int ndet, Geome
             off += 2LL * G.R.Lu[a] * G.R.Lv[a];
         }
     }
-    G.R.per_step = off;
+    // the record of step n ends with E^n of the lossy box (three components)
+    G.lossy_cells = 0;
+    if (d->sigma) {
+        G.lossy_cells = 1;
+        for (int a = 0; a < 3; a++) G.lossy_cells *= (d->lossy_hi[a] - d->lossy_lo[a]);
+    }
+    G.R.loff = off;
+    G.R.per_step = off + 3 * G.lossy_cells;
     G.D.ndet = ndet;
     long long doff = 0, roff = 0, eoff = 0;
     for (int m = 0; m < FDTD_MAX_DETECTORS; m++) {
@@ -342,7 +362,6 @@ int zchunk(const Geometry &G, int K, bool reverse)
 {
     const char *e = getenv(reverse ? "FDTD_REV_ZC" : "FDTD_TB_ZC");
     if (e && atoi(e) > 0) return std::min(atoi(e), G.nz);
-    const long long slots = 2LL * 256;   // two workgroups per CU
     if (reverse) {
         // The reverse march is kept short: the longest of at most 20 planes
         // that still gives four workgroups per slot, else 8.  One launch holds
@@ -354,6 +373,7 @@ int zchunk(const Geometry &G, int K, bool reverse)
         // on 2400x1600x150 (18.0 against 20.0-21.0 ms per step at 19).
         const long long tx = (long long)split_uniform(G.nx, rev_tile_x()).size();
         const long long ty = (long long)split_axis(G.ny, rev_tile_y()).size();
+        const long long slots = (long long)rev_wg_per_cu() * 256;
         if ((long long)G.nx * G.ny >= (2LL << 20) && tx * ty * ((G.nz + 59) / 60) >= 8 * slots)
             return even_chunk(G.nz, std::min(60, G.nz));
         for (int zc = std::min(20, G.nz); zc > 8; zc--)
@@ -368,6 +388,7 @@ int zchunk(const Geometry &G, int K, bool reverse)
     // (against 81.4 at 24, 82.2 at 20, 81.9 at 43, 72.5 at 64); 640x640x400:
     // 67-80 planes 104-105 (100.5 at 134); 2400x1600x150: 75.
     const int shape = tb_shape();
+    const long long fslots = (long long)tb_wg_per_cu(shape) * 256;
     const long long tx = (long long)(tb_tile_aligned(shape) ? split_uniform(G.nx, tb_tile_x(K, shape))
                                                              : split_axis(G.nx, tb_tile_x(K, shape))).size();
     const long long ty = (long long)split_axis(G.ny, tb_tile_y(K, shape)).size();
@@ -378,8 +399,8 @@ int zchunk(const Geometry &G, int K, bool reverse)
         if (z > 80) continue;
         if (z < 16) break;
         const long long nwg = tx * ty * nc;
-        if (nwg < 2 * slots) continue;
-        const long long cost = (nwg + slots - 1) / slots * (z + 2 * K);
+        if (nwg < 2 * fslots) continue;
+        const long long cost = (nwg + fslots - 1) / fslots * (z + 2 * K);
         if (best < 0 || cost < best) { best = cost; bz = z; }
     }
     return bz > 0 ? bz : even_chunk(G.nz, std::min(16, G.nz));
@@ -446,6 +467,8 @@ size_t plan(fdtd_ctx *h, const fdtd_desc *d, const Geometry &G, int K, void *bas
             for (int q = 0; q < 4; q++) h->psi[b][a][q] = G.p > 0 ? B.take(G.slab_n[a]) : nullptr;
     h->ce = B.take(N);
     h->d_design = B.take(G.design_cells);
+    h->lsig = G.lossy_cells > 0 ? B.take(G.lossy_cells) : nullptr;
+    h->lca = G.lossy_cells > 0 ? B.take(G.lossy_cells) : nullptr;
     for (int t = 0; t < 2; t++)
         for (int a = 0; a < 3; a++)
             for (int f = 0; f < 3; f++) h->prof[t][a][f] = B.take(n[a]);
@@ -583,11 +606,11 @@ fdtd_status step_naive(fdtd_ctx *h, int n, int with_src, int with_rec, int with_
     if (interp) HIPCHK(h, launch_det_eprev(h->g, F, G.D, h->eprev, h->stream));
     if (interp && h->drec && n == 0) HIPCHK(h, launch_det_eprev(h->g, F, G.D, h->drec_e0, h->stream));
     HIPCHK(h, launch_h_naive(h->g, F, P, n, with_src, h->stream));
-    if (with_rec && h->rec && G.R.per_step > 0)
-        HIPCHK(h, launch_record(h->g, F, G.R, h->rec + (size_t)n * G.R.per_step, 0, 0, h->stream));
-    HIPCHK(h, launch_e_naive(h->g, F, P, n, with_src, h->stream));
-    if (with_rec && h->rec && G.R.per_step > 0)
-        HIPCHK(h, launch_record(h->g, F, G.R, h->rec + (size_t)n * G.R.per_step, 1, 0, h->stream));
+    const bool iface = with_rec && h->rec && G.p > 0;
+    if (iface) HIPCHK(h, launch_record(h->g, F, G.R, h->rec + (size_t)n * G.R.per_step, 0, 0, h->stream));
+    float *lrec = (with_rec && h->rec && G.lossy_cells > 0) ? h->rec + (size_t)n * G.R.per_step + G.R.loff : nullptr;
+    HIPCHK(h, launch_e_naive(h->g, F, P, n, with_src, lrec, h->stream));
+    if (iface) HIPCHK(h, launch_record(h->g, F, G.R, h->rec + (size_t)n * G.R.per_step, 1, 0, h->stream));
     if (with_det && G.D.ndet > 0) {
         HIPCHK(h, launch_det_planes(h->g, F, G.D, h->planes, h->stream));
         if (interp) {
@@ -699,8 +722,9 @@ fdtd_status reverse_step(fdtd_ctx *h, int n, int do_adj)
     Fields A = do_adj ? adj_of(h, h->acur) : Fields{};
     if (do_adj && G.D.ndet > 0) HIPCHK(h, launch_det_adjoint(h->g, F, A, G.D, h->wS_plain, h->stream));
     Psi Pc = psibar_of(h, h->apar), Pn = psibar_of(h, h->apar ^ 1);
+    const float *lrec = G.lossy_cells > 0 ? h->rec + (size_t)n * G.R.per_step + G.R.loff : nullptr;
     HIPCHK(h, launch_bwd_a(h->g, F, A, Pc, n, 1, do_adj, do_adj ? h->gacc : nullptr, h->desc.design_lo,
-                           h->desc.design_hi, h->stream));
+                           h->desc.design_hi, lrec, h->stream));
     HIPCHK(h, launch_bwd_b(h->g, F, A, Pc, Pn, n, 1, do_adj, h->stream));
     if (do_adj) h->apar ^= 1;
     return FDTD_OK;
@@ -793,6 +817,7 @@ fdtd_status upload_materials(fdtd_ctx *h, const float *inv_eps)
 {
     const Geometry &G = h->geo;
     HIPCHK(h, launch_scale_ce(inv_eps, h->desc.courant, h->ce, G.N, h->stream));
+    HIPCHK(h, launch_lossy_coef(h->g, inv_eps, h->ce, h->lca, h->stream));
     HIPCHK(h, launch_gather_box(inv_eps, h->g, h->desc.design_lo, h->desc.design_hi, h->d_design, h->stream));
     // incident line of each TFSF plane, with S/eps_r of the plane's centre cell
     for (int t = 0; t < h->ntfsf; t++) {
@@ -870,6 +895,8 @@ fdtd_status fdtd_create(const fdtd_desc *desc, const fdtd_source *src, int32_t n
     if (const char *e = getenv("FDTD_NAIVE")) h->naive = atoi(e) != 0;
     // the z-march stages at most tb_max_pml() CPML planes per side
     if (desc->pml_cells > tb_max_pml()) h->naive = true;
+    // conducting cells run on the per-cell kernels
+    if (desc->sigma) h->naive = true;
     h->shape = tb_shape();
     geometry(desc, det, ndet, h->geo);
     const size_t need = plan(h, desc, h->geo, h->K, nullptr);
@@ -942,6 +969,12 @@ fdtd_status fdtd_create(const fdtd_desc *desc, const fdtd_source *src, int32_t n
         g.si[s] = on ? isrc[s].i : 0; g.sj[s] = on ? isrc[s].j : 0; g.sk[s] = on ? isrc[s].k : -1;
         g.samp[s] = h->amps[s];
     }
+    for (int a = 0; a < 3; a++) {
+        g.llo[a] = G.lossy_cells > 0 ? desc->lossy_lo[a] : 0;
+        g.lhi[a] = G.lossy_cells > 0 ? desc->lossy_hi[a] : 0;
+    }
+    g.lca = h->lca;
+    g.lsig = h->lsig;
 
     // CPML grading tables (double precision on the host, stored as float)
     const double m = desc->pml_order >= 0.f ? desc->pml_order : 3.0;
@@ -1026,6 +1059,11 @@ fdtd_status fdtd_create(const fdtd_desc *desc, const fdtd_source *src, int32_t n
                                       hipMemcpyDeviceToDevice, h->stream);
         if (e != hipSuccess) { fdtd_status r = fail(nullptr, FDTD_E_DEVICE, "amp copy: %s", hipGetErrorString(e)); delete h; return r; }
     }
+    if (G.lossy_cells > 0) {
+        hipError_t e = hipMemcpyAsync(h->lsig, desc->sigma, sizeof(float) * G.lossy_cells, hipMemcpyDeviceToDevice,
+                                      h->stream);
+        if (e != hipSuccess) { fdtd_status r = fail(nullptr, FDTD_E_DEVICE, "sigma copy: %s", hipGetErrorString(e)); delete h; return r; }
+    }
     st = upload_materials(h, desc->inv_eps);
     if (st == FDTD_OK) st = zero_forward(h);
     if (st == FDTD_OK) st = zero_adjoint(h);
@@ -1079,6 +1117,8 @@ fdtd_status fdtd_inverse(fdtd_handle h, int32_t n_steps)
     if (h->in_grad) return fail(h, FDTD_E_STATE, "a gradient is running on this handle");
     if (n_steps < 0 || n_steps > h->t) return fail(h, FDTD_E_STATE, "cannot undo %d steps at t = %d", n_steps, h->t);
     if (h->geo.p > 0 && !h->desc.record) return fail(h, FDTD_E_STATE, "inverse with a PML needs record = 1");
+    if (h->geo.lossy_cells > 0 && !h->desc.record)
+        return fail(h, FDTD_E_STATE, "inverse with conducting cells needs record = 1");
     for (int s = 0; s < n_steps; s++) {
         fdtd_status st = h->naive ? reverse_step(h, h->t - 1, 0) : reverse_fused(h, h->t - 1, 1, 0, 0, nullptr);
         if (st != FDTD_OK) return st;
@@ -1149,6 +1189,7 @@ fdtd_status grad_end_impl(fdtd_ctx *h, float *dJ_deps, float *recon_err)
     HIPCHK(h, launch_interior_sumsq(h->g, fields_of(h, h->cur), h->parts[1], &np, h->stream));
     if (recon_err) HIPCHK(h, launch_recon(h->parts[0], h->parts[1], np, recon_err, h->stream));
     HIPCHK(h, launch_deps(h->gacc, h->d_design, G.design_cells, h->desc.courant, dJ_deps, h->stream));
+    HIPCHK(h, launch_deps_lossy(h->g, h->gacc, h->d_design, h->desc.design_lo, h->desc.design_hi, dJ_deps, h->stream));
     fdtd_status st = zero_forward(h);
     if (st != FDTD_OK) return st;
     HIPCHK(h, launch_fill(h->trace, (long long)h->T * std::max(1, G.D.ndet), 0.f, h->stream));
@@ -1837,6 +1878,14 @@ fdtd_status fdtd_reset(fdtd_handle h)
     return FDTD_OK;
 }
 
+fdtd_status fdtd_set_stream(fdtd_handle h, void *stream)
+{
+    if (!h) return fail(nullptr, FDTD_E_INVALID, "handle is NULL");
+    if (h->in_grad) return fail(h, FDTD_E_STATE, "a gradient is running on this handle");
+    h->stream = (hipStream_t)stream;
+    return FDTD_OK;
+}
+
 fdtd_status fdtd_destroy(fdtd_handle h)
 {
     if (!h) return FDTD_OK;
@@ -1900,7 +1949,8 @@ fdtd_status fdtd_linear_steps(fdtd_handle h, int32_t n, int32_t adjoint)
         } else {
             Fields F = fields_of(h, h->cur), A = adj_of(h, h->acur);
             Psi Pc = psibar_of(h, h->apar), Pn = psibar_of(h, h->apar ^ 1);
-            HIPCHK(h, launch_bwd_a(h->g, F, A, Pc, 0, 0, 1, nullptr, h->desc.design_lo, h->desc.design_hi, h->stream));
+            HIPCHK(h, launch_bwd_a(h->g, F, A, Pc, 0, 0, 1, nullptr, h->desc.design_lo, h->desc.design_hi, nullptr,
+                                   h->stream));
             HIPCHK(h, launch_bwd_b(h->g, F, A, Pc, Pn, 0, 0, 1, h->stream));
             h->apar ^= 1;
             st = FDTD_OK;

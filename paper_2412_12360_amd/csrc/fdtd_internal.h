@@ -38,7 +38,21 @@ struct Grid {
     int nsrc;
     int skind[FD_MAXSRC], scomp[FD_MAXSRC], si[FD_MAXSRC], sj[FD_MAXSRC], sk[FD_MAXSRC];
     const float *samp[FD_MAXSRC];
+    // conducting cells: the box [llo, lhi) and per box cell ([z][y][x] over
+    // the box) ca = (1-u)/(1+u) and sigma; ce holds cb = S/eps/(1+u) there.
+    // lca == nullptr: none.
+    int llo[3], lhi[3];
+    const float *lca, *lsig;
 };
+
+// index of cell (i,j,k) in a lossy-box array, or -1 outside the box
+__device__ __forceinline__ long long lossy_index(const Grid &g, int i, int j, int k)
+{
+    if (!g.lca || i < g.llo[0] || i >= g.lhi[0] || j < g.llo[1] || j >= g.lhi[1] || k < g.llo[2] || k >= g.lhi[2])
+        return -1;
+    return ((long long)(k - g.llo[2]) * (g.lhi[1] - g.llo[1]) + (j - g.llo[1])) * (g.lhi[0] - g.llo[0]) +
+           (i - g.llo[0]);
+}
 
 struct Fields {
     float *c[6];                   // Ex, Ey, Ez, Hx, Hy, Hz
@@ -53,6 +67,7 @@ struct Psi {
 struct RecGeom {
     int Lu[3], Lv[3];              // window sizes per face axis
     long long off[6];              // float offset of face f within one step
+    long long loff;                // float offset of the lossy box's E^n (3 x box cells) within one step
     long long per_step;            // floats per step
 };
 
@@ -122,12 +137,15 @@ __device__ __forceinline__ bool held_ez(int i, int j, int k) { (void)k; return i
 // All return hipSuccess or the launch error.
 
 hipError_t launch_h_naive(const Grid &g, const Fields &F, const Psi &P, int n, int with_src, hipStream_t s);
-hipError_t launch_e_naive(const Grid &g, const Fields &F, const Psi &P, int n, int with_src, hipStream_t s);
+// lrec: E^n of the lossy box into the record of step n (or nullptr)
+hipError_t launch_e_naive(const Grid &g, const Fields &F, const Psi &P, int n, int with_src, float *lrec,
+                          hipStream_t s);
 
-// phase A of a reverse step: inverse E (interior), dJ/dd accumulation, adjoint H
+// phase A of a reverse step: inverse E (interior), dJ/dd accumulation, adjoint H;
+// lrec: E^n of the lossy box from the record of step n (or nullptr)
 hipError_t launch_bwd_a(const Grid &g, const Fields &F, const Fields &A, const Psi &Pb, int n,
                         int do_inv, int do_adj, float *gacc, const int *dlo, const int *dhi,
-                        hipStream_t s);
+                        const float *lrec, hipStream_t s);
 // phase B: inverse H (interior), adjoint E, psi-bar updates (H-type ping-pong)
 hipError_t launch_bwd_b(const Grid &g, const Fields &F, const Fields &A, const Psi &Pb_cur,
                         const Psi &Pb_next, int n, int do_inv, int do_adj, hipStream_t s);
@@ -171,6 +189,11 @@ hipError_t launch_recon(const float *part_T, const float *part_0, int nparts, fl
                         hipStream_t s);
 hipError_t launch_deps(const float *gacc, const float *d_design, long long D, float S, float *out,
                        hipStream_t s);
+// dJ/deps of the design cells that conduct: -d^2 S/(1+u)^2 g (overwrites launch_deps' values there)
+hipError_t launch_deps_lossy(const Grid &g, const float *gacc, const float *d_design, const int *dlo, const int *dhi,
+                             float *out, hipStream_t s);
+// ca and cb = S/eps/(1+u) of the lossy box from 1/eps and sigma
+hipError_t launch_lossy_coef(const Grid &g, const float *inv_eps, float *ce, float *lca, hipStream_t s);
 hipError_t launch_fill(float *p, long long n, float v, hipStream_t s);
 hipError_t launch_copy(float *dst, const float *src, long long n, hipStream_t s);
 hipError_t launch_scale_ce(const float *inv_eps, float S, float *ce, long long n, hipStream_t s);
@@ -223,6 +246,7 @@ int tb_tile_x(int K, int shape);
 int tb_tile_y(int K, int shape);
 bool tb_tile_aligned(int shape);   // x tiles start on 128-byte lines (uniform split)
 bool tb_wide_shape(int shape);     // the wide instance exists for this shape
+int tb_wg_per_cu(int shape);       // workgroups of this shape that share a CU
 int tb_max_pml();
 
 // fused reverse step (inverse + adjoint) as a z-march, tile halo rev_halo()
@@ -262,3 +286,4 @@ hipError_t launch_tb_reverse(const RevLaunch &L, bool wide, hipStream_t s);
 int rev_halo();
 int rev_tile_x();
 int rev_tile_y();
+int rev_wg_per_cu();

@@ -464,6 +464,40 @@ __global__ __launch_bounds__(NT) void k_gather_box(const float *src, Grid g, int
     dst[t] = src[cidx(g, i, j, k)];
 }
 
+// conducting cells: u = sigma S d / 2, ca = (1-u)/(1+u), cb = S d/(1+u) into ce
+__global__ __launch_bounds__(NT) void k_lossy_coef(Grid g, const float *inv_eps, float *ce, float *lca)
+{
+    const int dx = g.lhi[0] - g.llo[0], dy = g.lhi[1] - g.llo[1], dz = g.lhi[2] - g.llo[2];
+    const long long t = (long long)blockIdx.x * NT + threadIdx.x;
+    if (t >= (long long)dx * dy * dz) return;
+    const int i = g.llo[0] + (int)(t % dx);
+    const int j = g.llo[1] + (int)((t / dx) % dy);
+    const int k = g.llo[2] + (int)(t / ((long long)dx * dy));
+    const long long c = cidx(g, i, j, k);
+    const float d = inv_eps[c];
+    const float u = 0.5f * (g.lsig[t] * (g.S * d));
+    lca[t] = (1.f - u) / (1.f + u);
+    ce[c] = (g.S * d) / (1.f + u);
+}
+
+// dJ/deps = -d^2 dJ/dd with dJ/dd = S/(1+u)^2 g in the design cells that conduct
+__global__ __launch_bounds__(NT) void k_deps_lossy(Grid g, const float *gacc, const float *dd, int3 lo, int3 hi,
+                                                   float *out)
+{
+    const int dx = hi.x - lo.x, dy = hi.y - lo.y, dz = hi.z - lo.z;
+    const long long t = (long long)blockIdx.x * NT + threadIdx.x;
+    if (t >= (long long)dx * dy * dz) return;
+    const int i = lo.x + (int)(t % dx);
+    const int j = lo.y + (int)((t / dx) % dy);
+    const int k = lo.z + (int)(t / ((long long)dx * dy));
+    const long long li = lossy_index(g, i, j, k);
+    if (li < 0) return;
+    const float d = dd[t];
+    const float u = 0.5f * (g.lsig[li] * (g.S * d));
+    const float f = 1.f / ((1.f + u) * (1.f + u));
+    out[t] = -(d * d) * ((g.S * f) * gacc[t]);
+}
+
 unsigned nblk(long long n) { return (unsigned)((n + NT - 1) / NT); }
 
 }  // namespace
@@ -635,6 +669,26 @@ hipError_t launch_copy(float *dst, const float *src, long long n, hipStream_t s)
 hipError_t launch_scale_ce(const float *inv_eps, float S, float *ce, long long n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_scale, dim3(nblk(n)), dim3(NT), 0, s, inv_eps, S, ce, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_lossy_coef(const Grid &g, const float *inv_eps, float *ce, float *lca, hipStream_t s)
+{
+    if (!g.lca) return hipSuccess;
+    const long long tot = (long long)(g.lhi[0] - g.llo[0]) * (g.lhi[1] - g.llo[1]) * (g.lhi[2] - g.llo[2]);
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lossy_coef, dim3(nblk(tot)), dim3(NT), 0, s, g, inv_eps, ce, lca);
+    return hipGetLastError();
+}
+
+hipError_t launch_deps_lossy(const Grid &g, const float *gacc, const float *d_design, const int *dlo, const int *dhi,
+                             float *out, hipStream_t s)
+{
+    if (!g.lca) return hipSuccess;
+    const long long tot = (long long)(dhi[0] - dlo[0]) * (dhi[1] - dlo[1]) * (dhi[2] - dlo[2]);
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_deps_lossy, dim3(nblk(tot)), dim3(NT), 0, s, g, gacc, d_design,
+                       make_int3(dlo[0], dlo[1], dlo[2]), make_int3(dhi[0], dhi[1], dhi[2]), out);
     return hipGetLastError();
 }
 

@@ -76,7 +76,7 @@ __global__ __launch_bounds__(256) void k_h_naive(Grid g, Fields F, Psi P, int n,
 }
 
 // ----------------------------------------------------------- forward, E half
-__global__ __launch_bounds__(256) void k_e_naive(Grid g, Fields F, Psi P, int n, int with_src)
+__global__ __launch_bounds__(256) void k_e_naive(Grid g, Fields F, Psi P, int n, int with_src, float *lrec)
 {
     const int i = blockIdx.x * BX + threadIdx.x;
     const int j = blockIdx.y * BY + threadIdx.y;
@@ -115,6 +115,16 @@ __global__ __launch_bounds__(256) void k_e_naive(Grid g, Fields F, Psi P, int n,
     }
     const float ce = g.ce[c];
     float ex = F.c[0][c], ey = F.c[1][c], ez = F.c[2][c];
+    const long long li = lossy_index(g, i, j, k);
+    if (li >= 0) {
+        // a conducting cell: E^n into the record, then ca E^n + cb curl H
+        if (lrec) {
+            const long long nb = (long long)(g.lhi[0] - g.llo[0]) * (g.lhi[1] - g.llo[1]) * (g.lhi[2] - g.llo[2]);
+            lrec[li] = ex; lrec[nb + li] = ey; lrec[2 * nb + li] = ez;
+        }
+        const float ca = g.lca[li];
+        ex = ca * ex; ey = ca * ey; ez = ca * ez;
+    }
     if (!hex) ex = e_update(ex, ce, dy_hz, dz_hy);
     if (!hey) ey = e_update(ey, ce, dz_hx, dx_hz);
     if (!hez) ez = e_update(ez, ce, dx_hy, dy_hx);
@@ -191,7 +201,7 @@ __device__ __forceinline__ bool in_interior(const Grid &g, int i, int j, int k)
 // dJ/dd: gacc += Ebar . curl H^{n+1/2} on the design box (times S later)
 // adjoint H: Hbar += S C (D Ebar), CPML-wrapped
 __global__ __launch_bounds__(256) void k_bwd_a(Grid g, Fields F, Fields A, Psi Pb, int n, int do_inv,
-                                              int do_adj, float *gacc, int3 dlo, int3 dhi)
+                                              int do_adj, float *gacc, int3 dlo, int3 dhi, const float *lrec)
 {
     const int i = blockIdx.x * BX + threadIdx.x;
     const int j = blockIdx.y * BY + threadIdx.y;
@@ -208,12 +218,27 @@ __global__ __launch_bounds__(256) void k_bwd_a(Grid g, Fields F, Fields A, Psi P
         const float dz_hx = hx - hx_z, dx_hz = hz - hz_x;
         const float dx_hy = hy - hy_x, dy_hx = hx - hx_y;
         const bool hex = held_ex(i, j, k), hey = held_ey(i, j, k), hez = held_ez(i, j, k);
+        // a conducting cell is not inverted: E^n comes from the record
+        const long long li = lrec ? lossy_index(g, i, j, k) : -1;
+        float en[3] = {0.f, 0.f, 0.f}, sg = 0.f;
+        if (li >= 0) {
+            const long long nb = (long long)(g.lhi[0] - g.llo[0]) * (g.lhi[1] - g.llo[1]) * (g.lhi[2] - g.llo[2]);
+            en[0] = lrec[li]; en[1] = lrec[nb + li]; en[2] = lrec[2 * nb + li];
+            sg = g.lsig[li];
+        }
         if (do_adj && gacc && i >= dlo.x && i < dhi.x && j >= dlo.y && j < dhi.y && k >= dlo.z && k < dhi.z) {
             const long long dc = ((long long)(k - dlo.z) * (dhi.y - dlo.y) + (j - dlo.y)) * (dhi.x - dlo.x) + (i - dlo.x);
             float acc = gacc[dc];
-            if (!hex) acc = fmaf(A.c[0][c], dy_hz - dz_hy, acc);
-            if (!hey) acc = fmaf(A.c[1][c], dz_hx - dx_hz, acc);
-            if (!hez) acc = fmaf(A.c[2][c], dx_hy - dy_hx, acc);
+            if (li < 0) {
+                if (!hex) acc = fmaf(A.c[0][c], dy_hz - dz_hy, acc);
+                if (!hey) acc = fmaf(A.c[1][c], dz_hx - dx_hz, acc);
+                if (!hez) acc = fmaf(A.c[2][c], dx_hy - dy_hx, acc);
+            } else {
+                // E^{n+1} = ca E^n + cb curl H: dJ/dd = S/(1+u)^2 Ebar'.(curl H - sigma E^n)
+                if (!hex) acc = fmaf(A.c[0][c], fmaf(-sg, en[0], dy_hz - dz_hy), acc);
+                if (!hey) acc = fmaf(A.c[1][c], fmaf(-sg, en[1], dz_hx - dx_hz), acc);
+                if (!hez) acc = fmaf(A.c[2][c], fmaf(-sg, en[2], dx_hy - dy_hx), acc);
+            }
             gacc[dc] = acc;
         }
         float ex = F.c[0][c], ey = F.c[1][c], ez = F.c[2][c];
@@ -229,6 +254,7 @@ __global__ __launch_bounds__(256) void k_bwd_a(Grid g, Fields F, Fields A, Psi P
         if (!hex) ex = e_unupdate(ex, ce, dy_hz, dz_hy);
         if (!hey) ey = e_unupdate(ey, ce, dz_hx, dx_hz);
         if (!hez) ez = e_unupdate(ez, ce, dx_hy, dy_hx);
+        if (li >= 0) { ex = en[0]; ey = en[1]; ez = en[2]; }
         F.c[0][c] = ex; F.c[1][c] = ey; F.c[2][c] = ez;
     }
     if (do_adj) {
@@ -299,6 +325,15 @@ __global__ __launch_bounds__(256) void k_bwd_b(Grid g, Fields F, Fields A, Psi P
         F.c[5][c] = h_unupdate(hz, g.S, ey_x - ey, ex_y - ex);
     }
     if (do_adj) {
+        // a conducting cell passes ca Ebar' on to E^n (its psi-bar is zero:
+        // the lossy box lies in the interior)
+        const long long li = lossy_index(g, i, j, k);
+        if (li >= 0) {
+            const float ca = g.lca[li];
+            if (!held_ex(i, j, k)) A.c[0][c] = ca * A.c[0][c];
+            if (!held_ey(i, j, k)) A.c[1][c] = ca * A.c[1][c];
+            if (!held_ez(i, j, k)) A.c[2][c] = ca * A.c[2][c];
+        }
         // Ebar_x: Hy along z (-S, z idx 3), Hz along y (+S, y idx 2)
         if (!held_ex(i, j, k)) {
             const float ra = r_hpair(g, A, Pc, 1, 2, 3, -1.f, i, j, k - 1) - r_hpair(g, A, Pc, 1, 2, 3, -1.f, i, j, k);
@@ -348,17 +383,18 @@ hipError_t launch_h_naive(const Grid &g, const Fields &F, const Psi &P, int n, i
     return hipGetLastError();
 }
 
-hipError_t launch_e_naive(const Grid &g, const Fields &F, const Psi &P, int n, int with_src, hipStream_t s)
+hipError_t launch_e_naive(const Grid &g, const Fields &F, const Psi &P, int n, int with_src, float *lrec,
+                          hipStream_t s)
 {
-    hipLaunchKernelGGL(k_e_naive, cell_grid(g), dim3(BX, BY), 0, s, g, F, P, n, with_src);
+    hipLaunchKernelGGL(k_e_naive, cell_grid(g), dim3(BX, BY), 0, s, g, F, P, n, with_src, lrec);
     return hipGetLastError();
 }
 
 hipError_t launch_bwd_a(const Grid &g, const Fields &F, const Fields &A, const Psi &Pb, int n, int do_inv,
-                        int do_adj, float *gacc, const int *dlo, const int *dhi, hipStream_t s)
+                        int do_adj, float *gacc, const int *dlo, const int *dhi, const float *lrec, hipStream_t s)
 {
     hipLaunchKernelGGL(k_bwd_a, cell_grid(g), dim3(BX, BY), 0, s, g, F, A, Pb, n, do_inv, do_adj, gacc,
-                       make_int3(dlo[0], dlo[1], dlo[2]), make_int3(dhi[0], dhi[1], dhi[2]));
+                       make_int3(dlo[0], dlo[1], dlo[2]), make_int3(dhi[0], dhi[1], dhi[2]), lrec);
     return hipGetLastError();
 }
 

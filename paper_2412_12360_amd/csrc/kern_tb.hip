@@ -685,19 +685,21 @@ hipError_t launch_kwrp(const TbLaunch &L, hipStream_t s)
 // (two rows per thread with 8 waves, 24 owned rows at K = 2, needs about 170
 // to 220 registers, so 2-3 waves per SIMD and one workgroup per CU: measured
 // 2.8 times slower than shape 3, not kept)
+// (12 waves, 21 rows with 17 owned at K = 2, three waves per SIMD with up
+// to 168 registers and no spills, one workgroup per CU: bitwise equal, but
+// 0.395 against 0.378 ms per sweep on 256^3 and 7.94 against 7.14 s for the
+// 640x640x400 forward with the record; not kept)
 constexpr int NSHAPE = 4;
 constexpr int SHAPE_W[NSHAPE] = {16, 8, 16, 8};
 constexpr int SHAPE_R[NSHAPE] = {1, 1, 1, 1};
 constexpr int ALIGN_X = 32;   // floats per 128-byte line
-constexpr int TB_WIDE_SHAPE = 3;
 __host__ __device__ constexpr int shape_tx(int sh, int K) { return sh == 0 ? 64 : sh == 1 ? 32 : ALIGN_X + 2 * K; }
 
 template <int K>
 hipError_t launch_k(const TbLaunch &L, int shape, bool wide, hipStream_t s)
 {
     // the 64-bit-base instance exists for the default shape only
-    if (wide) return shape == TB_WIDE_SHAPE ? launch_kwrp<K, 8, 1, 1, ALIGN_X + 2 * K, true>(L, s)
-                                            : hipErrorInvalidValue;
+    if (wide) return shape == 3 ? launch_kwrp<K, 8, 1, 1, ALIGN_X + 2 * K, true>(L, s) : hipErrorInvalidValue;
     switch (shape) {
     case 0: return launch_kwrp<K, 16, 1, 1, 64>(L, s);
     case 2: return launch_kwrp<K, 16, 1, 1, ALIGN_X + 2 * K>(L, s);
@@ -718,7 +720,8 @@ int tb_tile_y(int K, int shape)
     return (64 * SHAPE_W[sh] / shape_tx(sh, K)) * SHAPE_R[sh] - 2 * K;
 }
 bool tb_tile_aligned(int shape) { return shape_index(shape) >= 2; }
-bool tb_wide_shape(int shape) { return shape_index(shape) == TB_WIDE_SHAPE; }
+bool tb_wide_shape(int shape) { return shape_index(shape) == 3; }
+int tb_wg_per_cu(int shape) { return SHAPE_W[shape_index(shape)] <= 8 ? 2 : 1; }
 
 hipError_t launch_tb_forward(const TbLaunch &L, int K, int shape, bool wide, hipStream_t s)
 {

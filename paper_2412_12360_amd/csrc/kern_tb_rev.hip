@@ -38,9 +38,8 @@ namespace {
 // two-cell halo).  With the one-cell halo 13 of 15 rows are owned.
 constexpr int HALO = 1;
 constexpr int EX = 32 + 2 * HALO;
-constexpr int W = 8;
-constexpr int NT = 64 * W;
-constexpr int EY = NT / EX;
+// (rows_of(W) rows of a W-wave workgroup)
+constexpr int rows_of(int W) { return 64 * W / EX; }
 
 // every pointer here addresses device global memory; saying so keeps the
 // loads and stores on global (not flat) instructions
@@ -77,7 +76,8 @@ typedef const __attribute__((address_space(4))) RevLaunch KLaunch;
 typedef const __attribute__((address_space(4))) Grid KGrid;
 
 // LDS of the kernel, one set whatever the tile class
-struct RevLds {
+template <int W> struct RevLds {
+    static constexpr int EY = rows_of(W);
     float sH[3][EY + 1][EX];
     float sQ[4][EY + 1][EX];
     float sEn[3][EY + 1][EX];
@@ -87,9 +87,11 @@ struct RevLds {
 };
 
 // One tile's reverse march.
-template <bool XP, bool YP, bool WIDE>
-__device__ __forceinline__ void rev_march(KArgs &A, KArgs *Kp, KReq *Rq, const int4 tl, const int4 tz, RevLds &L_)
+template <bool XP, bool YP, bool WIDE, int W>
+__device__ __forceinline__ void rev_march(KArgs &A, KArgs *Kp, KReq *Rq, const int4 tl, const int4 tz,
+                                          RevLds<W> &L_)
 {
+    constexpr int EY = rows_of(W);
     auto &sH = L_.sH;
     auto &sQ = L_.sQ;
     auto &sEn = L_.sEn;
@@ -149,6 +151,19 @@ __device__ __forceinline__ void rev_march(KArgs &A, KArgs *Kp, KReq *Rq, const i
     const int xc = x < 0 ? 0 : (x >= nx ? nx - 1 : x);
     const int yc = y < 0 ? 0 : (y >= ny ? ny - 1 : y);
     const unsigned off = (unsigned)yc * (unsigned)nx + (unsigned)xc;
+    // No owned cell reads E^n of the left halo column or the bottom halo row,
+    // nor R (from the adjoint H) of the right column or the top row: those
+    // lanes load E, or the adjoint H, from the neighbouring cell inside the
+    // tile instead, whose line the tile fetches anyway, so the load costs no
+    // memory traffic of its own and the loads stay the same instructions on
+    // every lane.  (Except on detector planes, where the adjoint source of
+    // the adjoint H reads E of the same cell.)
+    // (one signed offset: > 0 moves the E loads, < 0 the adjoint-H loads; a
+    // corner lane moves only its E loads)
+    const int dsh = lane == 0 ? (xc + 1 < nx ? 1 : 0)
+                  : row == 0 ? (yc + 1 < ny ? nx : 0)
+                  : lane == EX - 1 ? (xc > 0 ? -1 : 0)
+                  : row == EY - 1 ? (yc > 0 ? -nx : 0) : 0;
     const bool icol = p == 0 ? incol : (active && x >= p && x < nx - p && y >= p && y < ny - p);
     const bool wx = x >= p && x < nx - p, wy = y >= p && y < ny - p;
     const int sx = (XP && incol) ? slab_coord(x, nx, p) : -1;
@@ -175,25 +190,31 @@ __device__ __forceinline__ void rev_march(KArgs &A, KArgs *Kp, KReq *Rq, const i
     auto load_raw = [&](int t, RPlane<XP, YP> &P) __attribute__((always_inline)) {
         const bool tin = t >= 0 && t < nz;
         auto ld = [&](const float *base, unsigned o) { return *(const GLOBAL float *)((const GLOBAL char *)base + o); };
+        bool detp = false;
+#pragma unroll
+        for (int m = 0; m < FD_MAXDET; m++) detp = detp || t == dkq[m];
+        const unsigned oe = detp ? off : off + (unsigned)max(dsh, 0);
+        const unsigned off_ah = off + (unsigned)min(dsh, 0);
         if constexpr (WIDE) {
             const size_t pb = (size_t)(tin ? t : 0) * (size_t)Kp->g.nxy;
-            const unsigned c = off * 4u;
+            const unsigned c = off * 4u, ce_ = oe * 4u, ca_ = off_ah * 4u;
 #pragma unroll
             for (int q = 0; q < 3; q++) {
-                P.e[q] = ld(Kp->fld[ic][q] + pb, c);
+                P.e[q] = ld(Kp->fld[ic][q] + pb, ce_);
                 P.h[q] = ld(Kp->fld[ic][3 + q] + pb, c);
             }
             P.ce = ld(Kp->g.ce + pb, c);
 #pragma unroll
             for (int q = 0; q < 3; q++) {
                 P.ae[q] = ld((do_adj ? Kp->adj[ia][q] : Kp->fld[ic][q]) + pb, c);
-                P.ah[q] = ld((do_adj ? Kp->adj[ia][3 + q] : Kp->fld[ic][3 + q]) + pb, c);
+                P.ah[q] = ld((do_adj ? Kp->adj[ia][3 + q] : Kp->fld[ic][3 + q]) + pb, ca_);
             }
         } else {
-            const unsigned c = ((unsigned)(tin ? t : 0) * nxy + off) * 4u;
+            const unsigned pl = (unsigned)(tin ? t : 0) * nxy;
+            const unsigned c = (pl + off) * 4u, ce_ = (pl + oe) * 4u, ca_ = (pl + off_ah) * 4u;
 #pragma unroll
             for (int q = 0; q < 3; q++) {
-                P.e[q] = ld(fin0, c + q * fs);
+                P.e[q] = ld(fin0, ce_ + q * fs);
                 P.h[q] = ld(fin0, c + (3 + q) * fs);
             }
             P.ce = ld(g.ce, c);
@@ -202,7 +223,7 @@ __device__ __forceinline__ void rev_march(KArgs &A, KArgs *Kp, KReq *Rq, const i
 #pragma unroll
             for (int q = 0; q < 3; q++) {
                 P.ae[q] = ld(ain0, c + q * fs);
-                P.ah[q] = ld(ain0, c + (3 + q) * fs);
+                P.ah[q] = ld(ain0, ca_ + (3 + q) * fs);
             }
         }
 #pragma unroll
@@ -645,10 +666,10 @@ __device__ __forceinline__ void rev_march(KArgs &A, KArgs *Kp, KReq *Rq, const i
 
 // The kernel: block b (XCD-remapped) finds its request and tile; the tile's
 // class picks the march instance.
-template <bool WIDE>
-__global__ __launch_bounds__(NT, 4) void k_tb_reverse(RevLaunch)
+template <bool WIDE, int W>
+__global__ __launch_bounds__(64 * W, W == 12 ? 3 : 4) void k_tb_reverse(RevLaunch)
 {
-    __shared__ RevLds lds;
+    __shared__ RevLds<W> lds;
     // (the launch block is the kernel's only parameter, at offset 0 of the
     // kernel-argument segment)
     KLaunch *Lp = (KLaunch *)__builtin_amdgcn_kernarg_segment_ptr();
@@ -665,10 +686,10 @@ __global__ __launch_bounds__(NT, 4) void k_tb_reverse(RevLaunch)
     const int4 *tt = Rq->tiles + 2 * (b - Rq->first);
     const int4 tl = tt[0], tz = tt[1];
     switch (tz.z) {
-    case 0: rev_march<false, false, WIDE>(*Ap, Ap, Rq, tl, tz, lds); break;
-    case 1: rev_march<true, false, WIDE>(*Ap, Ap, Rq, tl, tz, lds); break;
-    case 2: rev_march<false, true, WIDE>(*Ap, Ap, Rq, tl, tz, lds); break;
-    default: rev_march<true, true, WIDE>(*Ap, Ap, Rq, tl, tz, lds); break;
+    case 0: rev_march<false, false, WIDE, W>(*Ap, Ap, Rq, tl, tz, lds); break;
+    case 1: rev_march<true, false, WIDE, W>(*Ap, Ap, Rq, tl, tz, lds); break;
+    case 2: rev_march<false, true, WIDE, W>(*Ap, Ap, Rq, tl, tz, lds); break;
+    default: rev_march<true, true, WIDE, W>(*Ap, Ap, Rq, tl, tz, lds); break;
     }
 }
 
@@ -676,12 +697,18 @@ __global__ __launch_bounds__(NT, 4) void k_tb_reverse(RevLaunch)
 
 int rev_halo() { return HALO; }
 int rev_tile_x() { return EX - 2 * HALO; }
-int rev_tile_y() { return EY - 2 * HALO; }
+// waves per workgroup of the reverse march: 8, two workgroups per CU.
+// (12 waves, three per SIMD with up to 168 registers and no spills, 20 of 22
+// rows owned, one workgroup per CU: bitwise equal, but 0.370 against 0.361
+// ms per step on 200^3 and 21.2 against 19.8 s for the 640x640x400 reverse)
+constexpr int REV_W = 8;
+int rev_tile_y() { return rows_of(REV_W) - 2 * HALO; }
+int rev_wg_per_cu() { return 2; }
 
 hipError_t launch_tb_reverse(const RevLaunch &L, bool wide, hipStream_t s)
 {
     if (L.nblocks <= 0) return hipSuccess;
-    if (wide) hipLaunchKernelGGL((k_tb_reverse<true>), dim3(L.nblocks), dim3(NT), 0, s, L);
-    else hipLaunchKernelGGL((k_tb_reverse<false>), dim3(L.nblocks), dim3(NT), 0, s, L);
+    if (wide) hipLaunchKernelGGL((k_tb_reverse<true, REV_W>), dim3(L.nblocks), dim3(64 * REV_W), 0, s, L);
+    else hipLaunchKernelGGL((k_tb_reverse<false, REV_W>), dim3(L.nblocks), dim3(64 * REV_W), 0, s, L);
     return hipGetLastError();
 }

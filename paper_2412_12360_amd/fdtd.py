@@ -35,6 +35,8 @@ class fdtd_desc(C.Structure):
         ("n_steps", C.c_int32),
         ("record", C.c_int32),
         ("time_block", C.c_int32),
+        ("sigma", C.c_void_p),
+        ("lossy_lo", C.c_int32 * 3), ("lossy_hi", C.c_int32 * 3),
     ]
 
 
@@ -55,7 +57,7 @@ ENTRY_POINTS = [
     "fdtd_linear_steps", "fdtd_record_ptr", "fdtd_time_block", "fdtd_checkpoint_bytes",
     "fdtd_grad_checkpointed", "fdtd_kernel_path", "fdtd_tile_classes", "fdtd_grad_checkpointed_noalloc",
     "fdtd_noalloc_store_bytes", "fdtd_grad_begin", "fdtd_grad_steps", "fdtd_grad_end", "fdtd_forward_batch",
-    "fdtd_grad_steps_batch", "fdtd_revolve_plan", "fdtd_revolve_bytes", "fdtd_grad_revolve",
+    "fdtd_grad_steps_batch", "fdtd_revolve_plan", "fdtd_revolve_bytes", "fdtd_grad_revolve", "fdtd_set_stream",
 ]
 
 _lib = None
@@ -97,6 +99,7 @@ def lib():
     L.fdtd_noalloc_store_bytes.argtypes = []
     L.fdtd_set_inv_eps.argtypes = [H, fp]
     L.fdtd_reset.argtypes = [H]
+    L.fdtd_set_stream.argtypes = [H, C.c_void_p]
     L.fdtd_destroy.argtypes = [H]
     L.fdtd_time.argtypes = [H, C.POINTER(C.c_int32)]
     L.fdtd_last_error.argtypes = [H]
@@ -129,7 +132,8 @@ def check(status: int, handle=None):
         raise FdtdError(status, m.decode() if m else "")
 
 
-def make_desc(prob, inv_eps_ptr: int = 0, record: bool = False, time_block: int = 0, T: Optional[int] = None):
+def make_desc(prob, inv_eps_ptr: int = 0, record: bool = False, time_block: int = 0, T: Optional[int] = None,
+              sigma_ptr: int = 0):
     d = fdtd_desc()
     d.nx, d.ny, d.nz = prob.nx, prob.ny, prob.nz
     d.courant = prob.S
@@ -146,6 +150,12 @@ def make_desc(prob, inv_eps_ptr: int = 0, record: bool = False, time_block: int 
     d.n_steps = prob.T if T is None else T
     d.record = 1 if record else 0
     d.time_block = time_block
+    # conducting cells (sigma over the lossy box), if the problem has them
+    if getattr(prob, "sigma", None) is not None:
+        d.sigma = sigma_ptr
+        for a in range(3):
+            d.lossy_lo[a] = prob.lossy_lo[a]
+            d.lossy_hi[a] = prob.lossy_hi[a]
     return d
 
 
@@ -169,7 +179,7 @@ def make_detectors(prob):
 
 def footprint(prob, record: bool = False, time_block: int = 0, T: Optional[int] = None) -> int:
     """Workspace bytes of a problem (no device work)."""
-    d = make_desc(prob, 1, record, time_block, T)
+    d = make_desc(prob, 1, record, time_block, T, sigma_ptr=1)
     srcs = make_sources(prob, [1] * len(prob.sources))
     dets = make_detectors(prob)
     out = C.c_size_t(0)
@@ -267,7 +277,13 @@ class Solver:
             m = min(self.T, len(s.amp))
             a[:m] = s.amp[:m]
             self.amps.append(torch.from_numpy(a).to(dev))
-        self.desc = make_desc(prob, self.inv_eps.data_ptr(), record, time_block, self.T)
+        self.sigma = None
+        if getattr(prob, "sigma", None) is not None:
+            if tuple(np.shape(prob.sigma)) != tuple(prob.lossy_shape()):
+                raise ValueError(f"sigma has shape {np.shape(prob.sigma)}, the lossy box {prob.lossy_shape()}")
+            self.sigma = torch.from_numpy(np.ascontiguousarray(prob.sigma, np.float32)).to(dev)
+        self.desc = make_desc(prob, self.inv_eps.data_ptr(), record, time_block, self.T,
+                              sigma_ptr=self.sigma.data_ptr() if self.sigma is not None else 0)
         self.srcs = make_sources(prob, [a.data_ptr() for a in self.amps])
         self.dets = make_detectors(prob)
         self.ndet = len(prob.detectors)
@@ -414,6 +430,17 @@ class Solver:
         check(lib().fdtd_set_inv_eps(self.handle, C.c_void_p(inv_eps.data_ptr())), self.handle)
 
     set_inv_eps = fdtd_set_inv_eps
+
+    def fdtd_set_stream(self, stream):
+        """Move the handle to `stream` (a torch stream), ordered after the
+        work of its current stream; the workspace is marked as used there."""
+        stream.wait_stream(self.stream)
+        self.ws_tensor.record_stream(stream)
+        self.J.record_stream(stream)
+        check(lib().fdtd_set_stream(self.handle, C.c_void_p(stream.cuda_stream)), self.handle)
+        self.stream = stream
+
+    set_stream = fdtd_set_stream
 
     def fdtd_reset(self):
         check(lib().fdtd_reset(self.handle), self.handle)

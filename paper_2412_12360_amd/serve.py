@@ -4,9 +4,11 @@ Requests of uneven grid sizes arrive at arbitrary times.  Each scheduler
 iteration
   1. admits queued requests (FIFO) while the sum of the admitted requests'
      exact workspace footprints (fdtd_footprint) stays within the HBM budget
-     and a slot is free; an admitted request gets its own handle and
-     workspace, so its fields and interface record stay resident until it
-     finishes;
+     and a slot is free (with `cell_cap`, a request joins running ones only
+     while their grid cells together stay within it: grids that fill the
+     device run alone, small launch-bound ones share the launches); an
+     admitted request gets its own handle and workspace, so its fields and
+     interface record stay resident until it finishes;
   2. gives every active request whose previous chunk has finished its next
      chunk of work: `chunk` more forward time steps, or, once a gradient
      request's forward is complete, `bchunk` more time-reversed steps of its
@@ -132,13 +134,21 @@ class _Active:
 class Scheduler:
     def __init__(self, executor: Executor, budget_bytes: int, max_active: int = 32, chunk: int = 64,
                  clock: Callable[[], float] = time.perf_counter, bchunk: Optional[int] = None,
-                 share: Optional[int] = None):
+                 share: Optional[int] = None, cell_cap: Optional[int] = None):
         bchunk = max(1, chunk // 2) if bchunk is None else bchunk
         if budget_bytes <= 0 or max_active <= 0 or chunk <= 0 or bchunk <= 0:
             raise ValueError("budget, max_active, chunk and bchunk must be positive")
         if share is not None and share <= 0:
             raise ValueError("share must be positive")
+        if cell_cap is not None and cell_cap <= 0:
+            raise ValueError("cell_cap must be positive")
         self.share = share
+        # admission by size: a request joins running ones only while their
+        # grid cells together stay within cell_cap (None: no limit), so that
+        # grids that fill the device run alone at full speed and only small,
+        # launch-bound ones share the launches
+        self.cell_cap = cell_cap
+        self.cells_active = 0
         self.ex = executor
         self.budget = int(budget_bytes)
         self.max_active = int(max_active)
@@ -201,6 +211,9 @@ class Scheduler:
                 continue
             if self.in_use + fp > self.budget:
                 return n                  # FIFO: wait for memory to free up
+            cells = int(req.problem.N)
+            if self.cell_cap is not None and self.active and self.cells_active + cells > self.cell_cap:
+                return n                  # FIFO: wait until the running grids leave room
             with self._lock:
                 self.queue.popleft()
             t_admit = self.now()
@@ -211,6 +224,7 @@ class Scheduler:
                 continue
             self.active[req.rid] = _Active(req=req, slot=slot, footprint=fp, t_admit=t_admit)
             self.in_use += fp
+            self.cells_active += cells
             self.peak_in_use = max(self.peak_in_use, self.in_use)
             n += 1
 
@@ -234,6 +248,7 @@ class Scheduler:
             self.ex.release(a.slot)
         finally:
             self.in_use -= a.footprint
+            self.cells_active -= int(a.req.problem.N)
             del self.active[a.req.rid]
             self.results[a.req.rid] = res
 
@@ -367,6 +382,10 @@ class GpuExecutor(Executor):
         self.fdtd = fdtd
         self.device = torch.device(device)
         self.stream = torch.cuda.Stream(device=self.device)
+        # requests are created on a stream of their own: the uploads of a
+        # creation then wait only for themselves, not for the batches queued
+        # on self.stream; the handle then moves to self.stream
+        self.setup = torch.cuda.Stream(device=self.device)
         self.time_block = time_block
         self._fwd = []
         self._bwd = []
@@ -375,9 +394,11 @@ class GpuExecutor(Executor):
         return self.fdtd.footprint(req.problem, record=req.kind == "gradient", time_block=self.time_block) + 256
 
     def start(self, req: Request):
-        with self.torch.cuda.stream(self.stream):
+        with self.torch.cuda.stream(self.setup):
             s = self.fdtd.Solver(req.problem, record=req.kind == "gradient", time_block=self.time_block,
-                                 device=str(self.device), stream=self.stream)
+                                 device=str(self.device), stream=self.setup)
+        s.set_stream(self.stream)
+        with self.torch.cuda.stream(self.stream):
             ev = self.torch.cuda.Event()
             ev.record(self.stream)
             slot = {"s": s, "evs": [ev], "kind": req.kind, "rid": req.rid,

@@ -169,3 +169,36 @@ def test_energy_detector_validated(change, ok):
     det = W.dataclasses.replace(W.Detector(k=10, i0=0, i1=39, j0=0, j1=35, interpolate=True), **change)
     st, _ = _status(W.dataclasses.replace(pr, detectors=[det]))
     assert st == (F.FDTD_OK if ok else F.FDTD_E_INVALID)
+
+
+def test_lossy_box_record_and_validation():
+    """Conducting cells add E^n of the lossy box to each step's record (three
+    floats per box cell) plus sigma and ca per box cell; the box must lie in
+    the interior and off the layers of a TFSF plane."""
+    F = _F()
+    pr = W.small_cpml(nx=40, ny=36, nz=44, p=6, T=100, d=8)
+    lp = W.with_lossy(pr)
+    nb = 8 * 8 * 8
+    a = _fp(pr, record=True)
+    b = _fp(lp, record=True)
+    assert 4 * (3 * nb * 100 + 2 * nb) <= b - a <= 4 * (3 * nb * 100 + 2 * nb) + 3 * 256
+    # forward only: no record, just the coefficients
+    assert 0 < _fp(lp) - _fp(pr) <= 4 * 2 * nb + 2 * 256
+
+    def status(prob):
+        d = F.make_desc(prob, 1, record=True, sigma_ptr=1)
+        out = C.c_size_t(0)
+        return F.lib().fdtd_footprint(C.byref(d), F.make_sources(prob, [1] * len(prob.sources)),
+                                      len(prob.sources), F.make_detectors(prob), len(prob.detectors), C.byref(out))
+    import dataclasses
+    for lo, hi in [((5, 14, 14), (13, 22, 22)),      # x below the interior
+                   ((14, 14, 14), (14, 22, 22)),     # empty along x
+                   ((14, 14, 30), (22, 22, 39))]:    # z beyond nz - p
+        bad = dataclasses.replace(lp, lossy_lo=lo, lossy_hi=hi)
+        assert status(bad) == F.FDTD_E_INVALID
+        assert "lossy box" in F.lib().fdtd_last_error(None).decode()
+    # a TFSF plane whose layers meet the lossy box's z range
+    t = W.with_tfsf(dataclasses.replace(lp, lossy_lo=(14, 14, 8), lossy_hi=(22, 22, 16)), k=10)
+    assert status(t) == F.FDTD_E_INVALID
+    assert "lossy box" in F.lib().fdtd_last_error(None).decode()
+    assert status(lp) == F.FDTD_OK

@@ -180,3 +180,35 @@ def test_share_gives_whole_chunks_to_the_oldest_only():
     assert first[0] == 64 and first[1] == 16 and first[2] == 16
     with pytest.raises(ValueError):
         serve.Scheduler(ex, 10**12, share=0)
+
+
+def test_cell_cap_runs_large_grids_alone_and_batches_small_ones():
+    """With cell_cap, a grid at or above the cap never shares the device, and
+    small grids run together up to the cap; FIFO order holds."""
+    big = [mk(i, edge=100, T=64) for i in range(3)]            # 1e6 cells each
+    small = [mk(10 + i, edge=40, T=64) for i in range(6)]      # 64000 cells each
+    reqs = [big[0], small[0], small[1], big[1], small[2], small[3], small[4], big[2], small[5]]
+    clk = VClock()
+    ex = serve.MockExecutor(clk)
+    sch = serve.Scheduler(ex, 10**12, max_active=8, chunk=32, clock=clk, cell_cap=400_000)
+    peak = []
+    orig = sch.step
+
+    def step():
+        n = orig()
+        live = [a.req for a in sch.active.values()]
+        peak.append((len(live), sum(r.problem.N for r in live), [r.rid for r in live]))
+        return n
+    sch.step = step
+    res = sch.run(reqs, open_loop=False, sleep=clk.sleep)
+    assert all(r.ok for r in res.values()) and len(res) == len(reqs)
+    for n, cells, rids in peak:
+        if any(r in (0, 1, 2) for r in rids):
+            assert n == 1, rids               # a large grid runs alone
+        else:
+            assert cells <= 400_000
+    assert max(n for n, _, _ in peak) >= 3    # small grids did share
+    starts = [rid for (ev, rid, _) in ex.log if ev == "start"]
+    assert starts == [r.rid for r in reqs]    # FIFO admission
+    with pytest.raises(ValueError):
+        serve.Scheduler(ex, 10**9, cell_cap=0)
