@@ -234,6 +234,42 @@ def shard_run(Solver, torch, time_block: int, steps: int, W, T: int = 100):
     }
 
 
+def lossy_run(pg, Solver, torch, W):
+    """The gradient problem with its design cube conducting (sigma ~ U[0, 1]
+    per cell, seed 21): the record keeps E^n of the lossy cells every step and
+    the inverse replays it; these handles run the per-cell kernels.  A warm-up
+    solve, then forward + gradient timed on the solver's stream."""
+    pl = W.with_lossy(pg)
+    g = Solver(pl, record=True)
+    g.reset()
+    g.forward()
+    g.grad()
+    torch.cuda.synchronize()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record(g.stream)
+    g.reset()
+    g.forward()
+    e1.record(g.stream)
+    _, recon = g.grad()
+    e2.record(g.stream)
+    torch.cuda.synchronize()
+    tf, tb = e0.elapsed_time(e1), e1.elapsed_time(e2)
+    nb = 1
+    for a in range(3):
+        nb *= pl.lossy_hi[a] - pl.lossy_lo[a]
+    res = {
+        "workload": "the same problem with the design cube conducting (sigma ~ U[0,1] per cell, seed 21); "
+                    "E^n of the lossy cells recorded every step and replayed by the inverse",
+        "value": round(pl.N * pl.T / ((tf + tb) / 1e3) / 1e6, 1), "unit": "Mcell-steps/s",
+        "fwd_ms": round(tf, 2), "bwd_ms": round(tb, 2), "recon_err": float(recon.item()),
+        "lossy_record_gb": round(12 * nb * pl.T / 1e9, 3), "hbm_footprint_gb": round(g.footprint / 1e9, 2),
+        "kernel_path": g.kernel_path,
+    }
+    del g
+    torch.cuda.empty_cache()
+    return res
+
+
 def fwd_grad_run(pg, Solver, torch, time_block: int, workload: str, checkpoint: bool = False,
                  warmup: bool = True):
     """A warm-up solve (unless the kernels ran already), then a timed forward
@@ -398,7 +434,7 @@ def copy_calibration(torch, nbytes: int = 1 << 30, reps: int = 4):
 
 def serving_bench(count: int, torch, seed_rate: float = 0.8, budget_gb: float = 0.0, max_active: int = 6,
                   chunk: int = 64, extra_rates=(), open_loops: bool = True, open_rate: float = 0.0,
-                  share: int = 0):
+                  share: int = 0, cell_cap: int = 0):
     """Serving mix: `count` requests of the Poisson mix recipe (edges U{64..256},
     50% forward / 50% gradient, T = 8 x max edge, CPML 8).  Measures saturation
     throughput one-at-a-time and with continuous batching (all queued at t=0),
@@ -420,7 +456,8 @@ def serving_bench(count: int, torch, seed_rate: float = 0.8, budget_gb: float = 
                               arrival=0.0 if arrivals is None else arrivals[i])
                 for i, rid in enumerate(rids)]
         sch = serve.Scheduler(serve.GpuExecutor(), budget_bytes=budget, max_active=max_active, chunk=chunk,
-                              share=share if share > 0 else None)
+                              share=share if share > 0 else None,
+                              cell_cap=cell_cap if (cell_cap > 0 and max_active > 1) else None)
         t0 = time.perf_counter()
         res = sch.run(reqs, open_loop=arrivals is not None,
                       progress=lambda d, n: log(f"  {d} of {n} requests served"))
@@ -441,7 +478,7 @@ def serving_bench(count: int, torch, seed_rate: float = 0.8, budget_gb: float = 
     res = {"workload": f"{count} requests of the serving mix (edges U{{64..256}} per axis, 50% gradient, "
                        f"T = 8 x max edge, CPML 8, eps_r U[1,12.25]; seeds 6/7/1000+rid)",
            "hbm_budget_gb": round(budget / 1e9, 1), "max_active": max_active, "chunk_steps": chunk,
-           "share": share if share > 0 else None,
+           "share": share if share > 0 else None, "cell_cap": cell_cap if cell_cap > 0 else None,
            "batched_launches": "one z-march launch per forward sweep and per reverse step spans all active requests"}
     if open_rate <= 0:
         seq = run(1)
@@ -514,6 +551,10 @@ def main():
     ap.add_argument("--serving-chunk", type=int, default=64, help="serving: forward steps per scheduler iteration")
     ap.add_argument("--serving-share", type=int, default=0,
                     help="serving: younger requests take 1/share of a chunk (0 = equal chunks)")
+    ap.add_argument("--serving-cell-cap", type=int, default=8_000_000,
+                    help="serving: a request joins running ones only while their grid cells together stay "
+                         "within this many (0 = no limit; 8M measured best on the 100-request mix: grids that "
+                         "fill the device run alone, small ones share the launches)")
     ap.add_argument("--serving-closed-only", action="store_true",
                     help="serving: the two closed loops only (a long mix split over two runs)")
     ap.add_argument("--serving-open-rate", type=float, default=0.0,
@@ -631,6 +672,7 @@ def main():
                                        "200^3 grid, CPML 10, 64^3 design cube rho~U[0,1] (seed 3), eps_r = 2.25 + 10 rho, "
                                        "1500 steps, objective = time-integrated flux; forward with interface record, "
                                        "then inverse-step + adjoint backward", checkpoint=not args.no_checkpoint)
+        out["fwd_grad"]["lossy"] = lossy_run(pg, Solver, torch, W)
         progress("forward + gradient")
 
     if not args.no_grad and not args.no_large:
@@ -653,6 +695,7 @@ def main():
     if args.serving > 0:
         out["serving"] = serving_bench(args.serving, torch, budget_gb=args.serving_budget_gb,
                                        max_active=args.serving_max_active, chunk=args.serving_chunk, share=args.serving_share,
+                                       cell_cap=args.serving_cell_cap,
                                        extra_rates=[float(v) for v in args.serving_extra_rates.split(",") if v],
                                        open_loops=not args.serving_closed_only, open_rate=args.serving_open_rate)
 
