@@ -649,7 +649,7 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_GBS, 4), "traffic": measured_traffic(K),
-            "kernel": f"forward z-march sweep (K={K} steps, the concurrent tile-class kernels)",
+            "kernel": f"forward z-march sweep (K={K} steps, one launch over the tiles of every class)",
             "alg_bytes_per_launch": alg, "avg_launch_ms": round(pass_ms, 5),
             "launches_timed": passes,
         },

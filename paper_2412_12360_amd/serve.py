@@ -12,7 +12,9 @@ iteration
   2. gives every active request whose previous chunk has finished its next
      chunk of work: `chunk` more forward time steps, or, once a gradient
      request's forward is complete, `bchunk` more time-reversed steps of its
-     backward pass (with `share` = s, only the oldest active request takes
+     backward pass (with `chunk_cells`, both scaled by whole multiples so
+     that a chunk holds about chunk_cells cell-steps: a small grid takes
+     more steps per iteration) (with `share` = s, only the oldest active request takes
      whole chunks and the others 1/s of them: they fill what the oldest
      leaves of the device, in the same launches, without holding it back
      much -- first-come first-served with backfill);
@@ -134,7 +136,8 @@ class _Active:
 class Scheduler:
     def __init__(self, executor: Executor, budget_bytes: int, max_active: int = 32, chunk: int = 64,
                  clock: Callable[[], float] = time.perf_counter, bchunk: Optional[int] = None,
-                 share: Optional[int] = None, cell_cap: Optional[int] = None):
+                 share: Optional[int] = None, cell_cap: Optional[int] = None,
+                 chunk_cells: Optional[int] = None):
         bchunk = max(1, chunk // 2) if bchunk is None else bchunk
         if budget_bytes <= 0 or max_active <= 0 or chunk <= 0 or bchunk <= 0:
             raise ValueError("budget, max_active, chunk and bchunk must be positive")
@@ -149,6 +152,13 @@ class Scheduler:
         # launch-bound ones share the launches
         self.cell_cap = cell_cap
         self.cells_active = 0
+        # chunks by work instead of steps: a request of N cells takes
+        # chunk_cells / N forward steps per iteration (at least `chunk`), so
+        # that every chunk is about the same device time and small grids are
+        # not held to one scheduler iteration per `chunk` steps
+        if chunk_cells is not None and chunk_cells <= 0:
+            raise ValueError("chunk_cells must be positive")
+        self.chunk_cells = chunk_cells
         self.ex = executor
         self.budget = int(budget_bytes)
         self.max_active = int(max_active)
@@ -258,7 +268,11 @@ class Scheduler:
         for rank, rid in enumerate(list(self.active.keys())):
             a = self.active[rid]
             div = self.share if (self.share and rank > 0) else 1
-            fchunk, rchunk = max(2, self.chunk // div), max(1, self.bchunk // div)
+            fc, bc = self.chunk, self.bchunk
+            if self.chunk_cells is not None:
+                scale = max(1, int(self.chunk_cells // max(1, int(a.req.problem.N))) // self.chunk)
+                fc, bc = fc * scale, bc * scale
+            fchunk, rchunk = max(2, fc // div), max(1, bc // div)
             if rid in self._cancelled:
                 a.cancel = True
             try:

@@ -212,3 +212,27 @@ def test_cell_cap_runs_large_grids_alone_and_batches_small_ones():
     assert starts == [r.rid for r in reqs]    # FIFO admission
     with pytest.raises(ValueError):
         serve.Scheduler(ex, 10**9, cell_cap=0)
+
+
+def test_chunk_cells_scales_chunks_by_grid_size():
+    """With chunk_cells, a small grid takes whole multiples of `chunk` steps
+    per iteration (about chunk_cells cell-steps), a large one `chunk`."""
+    clk = VClock()
+    ex = serve.MockExecutor(clk)
+    calls = []
+    orig = ex.forward
+
+    def fwd(slot, n):
+        calls.append((slot["rid"], n))
+        return orig(slot, n)
+    ex.forward = fwd
+    sch = serve.Scheduler(ex, 10**12, max_active=4, chunk=16, clock=clk, chunk_cells=16 * 100**3)
+    reqs = [mk(0, edge=100, T=64), mk(1, edge=25, T=4096)]
+    res = sch.run(reqs, open_loop=False, sleep=clk.sleep)
+    assert all(r.ok for r in res.values())
+    big = {n for rid, n in calls if rid == 0}
+    small = [n for rid, n in calls if rid == 1]
+    assert big == {16}
+    assert small[0] == 16 * 64 and sum(small) == 4096
+    with pytest.raises(ValueError):
+        serve.Scheduler(ex, 10**9, chunk_cells=0)
