@@ -141,3 +141,32 @@ def test_batch_validation():
     g, _ = s1.grad_end()
     torch.cuda.synchronize()
     assert torch.isfinite(g).all()
+
+
+def test_set_stream_moves_a_handle_between_streams():
+    """A handle created on one stream and moved with fdtd_set_stream to
+    another (the serving loop's creation stream, then its batch stream) gives
+    the bits of a handle that stays on one stream, forward and gradient; a
+    move during a chunked gradient is refused."""
+    from paper_2412_12360_amd.fdtd import FdtdError, Solver
+    pr = W.small_cpml(nx=70, ny=45, nz=38, p=5, T=60, d=8, seed=45, name="mv")
+    announce("set_stream: forward + gradient on a moved handle")
+    ref = Solver(pr, record=True)
+    ref.forward()
+    g0, _ = ref.grad()
+    a, b = torch.cuda.Stream(), torch.cuda.Stream()
+    with torch.cuda.stream(a):
+        s = Solver(pr, record=True, stream=a)
+    s.set_stream(b)
+    with torch.cuda.stream(b):
+        s.forward(25)
+        s.forward(35)
+        g1, _ = s.grad()
+        s.forward()
+        s.grad_begin()
+        with pytest.raises(FdtdError, match="E_STATE"):
+            s.set_stream(a)
+        s.grad_steps(60)
+        s.grad_end()
+    torch.cuda.synchronize()
+    assert torch.equal(g0, g1)
