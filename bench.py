@@ -237,8 +237,8 @@ def shard_run(Solver, torch, time_block: int, steps: int, W, T: int = 100):
 def lossy_run(pg, Solver, torch, W):
     """The gradient problem with its design cube conducting (sigma ~ U[0, 1]
     per cell, seed 21): the record keeps E^n of the lossy cells every step and
-    the inverse replays it; these handles run the per-cell kernels.  A warm-up
-    solve, then forward + gradient timed on the solver's stream."""
+    the inverse replays it (the z-marches' lossy instances).  A warm-up solve,
+    then forward + gradient timed on the solver's stream."""
     pl = W.with_lossy(pg)
     g = Solver(pl, record=True)
     g.reset()

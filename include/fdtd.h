@@ -89,7 +89,10 @@ typedef struct {
      * [lossy_lo, lossy_hi) (x, y, z), [z][y][x] over the box, or NULL for
      * none; copied at create.  The box lies in the interior [p, n-p) and
      * outside the z layers of any TFSF plane.  A handle with conducting
-     * cells runs the per-cell kernels (fdtd_kernel_path reports 0).     */
+     * cells runs lossy instances of the z-marches (time_block 0, 1 or 2 and
+     * 32-bit offsets; bitwise equal to the per-cell kernels), else the
+     * per-cell kernels; the checkpointed gradients refuse it
+     * (FDTD_E_UNSUPPORTED).                                               */
     const float *sigma;
     int32_t lossy_lo[3];
     int32_t lossy_hi[3];

@@ -685,7 +685,7 @@ fdtd_status steps_tb(fdtd_ctx *h, int n0, int kk, int with_src, int with_rec, in
     L.xcd_remap = 1;
     L.pad = 0;
     L.r[0] = tb_request(h, n0, kk, with_src, with_rec, with_det, 0);
-    HIPCHK(h, launch_tb_forward(L, kk, h->shape, h->wide, h->stream));
+    HIPCHK(h, launch_tb_forward(L, kk, h->shape, h->wide, h->g.lca != nullptr, h->stream));
     return tb_epilogue(h, n0, kk, with_det);
 }
 
@@ -741,7 +741,8 @@ RevReq rev_request(fdtd_ctx *h, int n, int do_inv, int do_adj, int with_det, flo
     RevReq q;
     q.args = (unsigned long long)(uintptr_t)h->rargs;
     q.tiles = h->tiles + 2 * (size_t)h->tb_off[0];
-    q.rec_h = (do_inv && G.p > 0) ? h->rec + (size_t)n * G.R.per_step : nullptr;
+    // (the record of step n: its interface layers, and E^n of the lossy box)
+    q.rec_h = (do_inv && (G.p > 0 || G.lossy_cells > 0)) ? h->rec + (size_t)n * G.R.per_step : nullptr;
     q.rec_e = (do_inv && G.p > 0 && n > 0) ? h->rec + (size_t)(n - 1) * G.R.per_step : nullptr;
     q.gacc = gacc;
     q.fin = fin;
@@ -772,7 +773,7 @@ fdtd_status reverse_fused(fdtd_ctx *h, int n, int do_inv, int do_adj, int with_d
     L.xcd_remap = 1;
     L.pad = 0;
     L.r[0] = rev_request(h, n, do_inv, do_adj, with_det, gacc, fin ? fin->c[0] : nullptr, 0);
-    HIPCHK(h, launch_tb_reverse(L, h->wide, h->stream));
+    HIPCHK(h, launch_tb_reverse(L, h->wide, h->g.lca != nullptr, h->stream));
     rev_epilogue(h, do_inv, do_adj);
     return FDTD_OK;
 }
@@ -895,8 +896,6 @@ fdtd_status fdtd_create(const fdtd_desc *desc, const fdtd_source *src, int32_t n
     if (const char *e = getenv("FDTD_NAIVE")) h->naive = atoi(e) != 0;
     // the z-march stages at most tb_max_pml() CPML planes per side
     if (desc->pml_cells > tb_max_pml()) h->naive = true;
-    // conducting cells run on the per-cell kernels
-    if (desc->sigma) h->naive = true;
     h->shape = tb_shape();
     geometry(desc, det, ndet, h->geo);
     const size_t need = plan(h, desc, h->geo, h->K, nullptr);
@@ -948,6 +947,9 @@ fdtd_status fdtd_create(const fdtd_desc *desc, const fdtd_source *src, int32_t n
         const bool force_wide = ew && atoi(ew) != 0 && wide_ok;
         if (!ok || (!fok && !wide_ok)) h->naive = true;
         else if (!fok || force_wide) h->wide = true;
+        // conducting cells: the z-march's lossy instances (default shape,
+        // 32-bit offsets, K = 1 or 2), else the per-cell kernels
+        if (desc->sigma && !tb_lossy_ok(h->K, h->shape, h->wide)) h->naive = true;
         if (h->naive) h->wide = false;
     }
 
@@ -1294,14 +1296,15 @@ fdtd_status fdtd_forward_batch(const fdtd_handle *hs, int32_t nh, const int32_t 
         bool any = false;
         for (int kk = 1; kk <= 4; kk++)
             for (int wide = 0; wide < 2; wide++)
-                for (int shape = 0; shape < 4; shape++) {
+                for (int shape = 0; shape < 4; shape++)
+                for (int lossy = 0; lossy < 2; lossy++) {
                     std::vector<fdtd_ctx *> grp;
                     std::vector<int> idx;
                     for (int i = 0; i < nh; i++) {
                         fdtd_ctx *h = hs[i];
                         const int rem = t0[i] + n_steps[i] - pos[i];
                         if (h->naive || rem <= 0 || std::min(h->K, rem) != kk || (int)h->wide != wide ||
-                            h->shape != shape)
+                            h->shape != shape || (int)(h->g.lca != nullptr) != lossy)
                             continue;
                         grp.push_back(h);
                         idx.push_back(i);
@@ -1321,7 +1324,7 @@ fdtd_status fdtd_forward_batch(const fdtd_handle *hs, int32_t nh, const int32_t 
                             L.r[j] = tb_request(h, pos[i], kk, 1, 1, 1, L.nblocks);
                             L.nblocks += h->tb_n[kk];
                         }
-                        const hipError_t e = launch_tb_forward(L, kk, shape, wide != 0, grp[a]->stream);
+                        const hipError_t e = launch_tb_forward(L, kk, shape, wide != 0, lossy != 0, grp[a]->stream);
                         if (e != hipSuccess) return batch_fail(grp.data() + a, cnt, e);
                         for (int j = 0; j < cnt; j++) {
                             fdtd_ctx *h = grp[a + j];
@@ -1375,11 +1378,13 @@ fdtd_status fdtd_grad_steps_batch(const fdtd_handle *hs, int32_t nh, const int32
     // launch per instance
     for (;;) {
         bool any = false;
-        for (int wide = 0; wide < 2; wide++) {
+        for (int wide = 0; wide < 2; wide++)
+        for (int lossy = 0; lossy < 2; lossy++) {
             std::vector<fdtd_ctx *> grp;
             std::vector<int> idx;
             for (int i = 0; i < nh; i++)
-                if (!hs[i]->naive && left[i] > 0 && (int)hs[i]->wide == wide) {
+                if (!hs[i]->naive && left[i] > 0 && (int)hs[i]->wide == wide &&
+                    (int)(hs[i]->g.lca != nullptr) == lossy) {
                     grp.push_back(hs[i]);
                     idx.push_back(i);
                 }
@@ -1397,7 +1402,7 @@ fdtd_status fdtd_grad_steps_batch(const fdtd_handle *hs, int32_t nh, const int32
                     L.r[j] = rev_request(h, h->t - 1, 1, 1, 1, h->gacc, nullptr, L.nblocks);
                     L.nblocks += h->tb_n[0];
                 }
-                const hipError_t e = launch_tb_reverse(L, wide != 0, grp[a]->stream);
+                const hipError_t e = launch_tb_reverse(L, wide != 0, lossy != 0, grp[a]->stream);
                 if (e != hipSuccess) return batch_fail(grp.data() + a, cnt, e);
                 for (int j = 0; j < cnt; j++) {
                     fdtd_ctx *h = grp[a + j];
@@ -1487,6 +1492,7 @@ fdtd_status grad_checkpointed_impl(fdtd_handle h, int32_t segment, void *store, 
     if (!h->desc.record) return fail(h, FDTD_E_STATE, "the checkpointed gradient needs the adjoint state (record = 1)");
     if (energy_in_design(h))
         return fail(h, FDTD_E_UNSUPPORTED, "a weighted energy detector must lie outside the design box in z");
+    if (h->geo.lossy_cells > 0) return fail(h, FDTD_E_UNSUPPORTED, "the checkpointed gradients take no conducting cells");
     if (h->naive) return fail(h, FDTD_E_UNSUPPORTED, "the checkpointed gradient runs on the z-march path only");
     if (h->in_grad) return fail(h, FDTD_E_STATE, "a gradient is running on this handle");
     if (h->wide) return fail(h, FDTD_E_UNSUPPORTED, "the checkpointed gradient needs field sets under 4 GiB");
@@ -1781,6 +1787,7 @@ fdtd_status fdtd_grad_revolve(fdtd_handle h, int32_t schedule, int32_t snapshots
     if (!h->desc.record) return fail(h, FDTD_E_STATE, "the checkpointed gradient needs the adjoint state (record = 1)");
     if (energy_in_design(h))
         return fail(h, FDTD_E_UNSUPPORTED, "a weighted energy detector must lie outside the design box in z");
+    if (h->geo.lossy_cells > 0) return fail(h, FDTD_E_UNSUPPORTED, "the checkpointed gradients take no conducting cells");
     if (h->naive) return fail(h, FDTD_E_UNSUPPORTED, "the checkpointed gradient runs on the z-march path only");
     if (h->in_grad) return fail(h, FDTD_E_STATE, "a gradient is running on this handle");
     fdtd_status st = revolve_check(h->T, schedule, snapshots);

@@ -241,7 +241,10 @@ struct TbLaunch {
 // one sweep of K steps over every tile of the launch (wide: the instance
 // with a 64-bit base per component and plane, for field sets of 4 GiB or
 // more; fstride is unused there)
-hipError_t launch_tb_forward(const TbLaunch &L, int K, int shape, bool wide, hipStream_t s);
+// lossy: the instance for handles with conducting cells (default shape,
+// 32-bit offsets, K = 1 or 2: tb_lossy_ok)
+hipError_t launch_tb_forward(const TbLaunch &L, int K, int shape, bool wide, bool lossy, hipStream_t s);
+bool tb_lossy_ok(int K, int shape, bool wide);
 int tb_tile_x(int K, int shape);
 int tb_tile_y(int K, int shape);
 bool tb_tile_aligned(int shape);   // x tiles start on 128-byte lines (uniform split)
@@ -282,7 +285,8 @@ struct RevLaunch {
     int nreq, nblocks, xcd_remap, pad;
     RevReq r[ZM_MAXREQ];
 };
-hipError_t launch_tb_reverse(const RevLaunch &L, bool wide, hipStream_t s);
+// lossy: the instance for handles with conducting cells (32-bit offsets only)
+hipError_t launch_tb_reverse(const RevLaunch &L, bool wide, bool lossy, hipStream_t s);
 int rev_halo();
 int rev_tile_x();
 int rev_tile_y();

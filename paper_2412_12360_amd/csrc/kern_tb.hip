@@ -97,7 +97,10 @@ typedef const __attribute__((address_space(4))) TbLaunch KLaunch;
 
 // One tile's march.  TX lanes of a wave row span x; W waves; R rows per
 // thread.  The LDS arrays belong to the kernel (one set whatever the class).
-template <int K, bool XP, bool YP, int PD, int W, int R, int TX, bool WIDE>
+// LOSSY: the instance for handles with conducting cells: in the lossy box E
+// is damped, E' = ca E + cb curl H (cb in place of S/eps in the coefficient
+// array), and E^n of the box goes into the record before the update.
+template <int K, bool XP, bool YP, int PD, int W, int R, int TX, bool WIDE, bool LOSSY>
 __device__ __forceinline__ void tb_march(KArgs &A, KArgs *Kp, KReq *Rq, const int4 tl, const int4 tz,
                                          float (*sE)[(64 * W / TX) * R + 1][TX],
                                          float (*sH)[(64 * W / TX) * R + 1][TX], float (*sGz)[6],
@@ -399,9 +402,26 @@ __device__ __forceinline__ void tb_march(KArgs &A, KArgs *Kp, KReq *Rq, const in
                     }
                     const float ce = cd[s][r];
                     const bool live = incol[r] && kin;
-                    const float ex = e_update(Eo[s - 1][r][0], ce * ax, dy_hz, dz_hy);
-                    const float ey = e_update(Eo[s - 1][r][1], ce * ay, dz_hx, dx_hz);
-                    const float ez = e_update(Eo[s - 1][r][2], ce * az, dx_hy, dy_hx);
+                    float e0 = Eo[s - 1][r][0], e1 = Eo[s - 1][r][1], e2 = Eo[s - 1][r][2];
+                    if constexpr (LOSSY) {
+                        // a conducting cell: E^n into the record (owned cells), then ca E^n
+                        if (live && k >= A.g.llo[2] && k < A.g.lhi[2] && x >= A.g.llo[0] && x < A.g.lhi[0] &&
+                            ys[r] >= A.g.llo[1] && ys[r] < A.g.lhi[1]) {
+                            const int bx = A.g.lhi[0] - A.g.llo[0], by = A.g.lhi[1] - A.g.llo[1];
+                            const long long li = ((long long)(k - A.g.llo[2]) * by + (ys[r] - A.g.llo[1])) * bx +
+                                                 (x - A.g.llo[0]);
+                            if (own[r] && rec_n0 && k >= z0 && k < z1) {
+                                const long long nb = (long long)bx * by * (A.g.lhi[2] - A.g.llo[2]);
+                                float *lr = rec_n0 + (long long)(s - 1) * A.R.per_step + A.R.loff + li;
+                                lr[0] = e0; lr[nb] = e1; lr[2 * nb] = e2;
+                            }
+                            const float ca = ldo(A.g.lca, (unsigned)li * 4u);
+                            e0 = ca * e0; e1 = ca * e1; e2 = ca * e2;
+                        }
+                    }
+                    const float ex = e_update(e0, ce * ax, dy_hz, dz_hy);
+                    const float ey = e_update(e1, ce * ay, dz_hx, dx_hz);
+                    const float ez = e_update(e2, ce * az, dx_hy, dy_hx);
                     mE[r][0] = live ? ex : 0.f;
                     mE[r][1] = live ? ey : 0.f;
                     mE[r][2] = live ? ez : 0.f;
@@ -629,7 +649,7 @@ __device__ __forceinline__ void tb_march(KArgs &A, KArgs *Kp, KReq *Rq, const in
 
 // The kernel: block b (XCD-remapped) finds its request and tile; the tile's
 // class picks the march instance.
-template <int K, int PD, int W, int R, int TX, bool WIDE>
+template <int K, int PD, int W, int R, int TX, bool WIDE, bool LOSSY>
 __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbLaunch)
 {
     constexpr int EY = (64 * W / TX) * R;
@@ -659,19 +679,19 @@ __global__ __launch_bounds__(64 * W, 4) void k_tb_forward(TbLaunch)
     const int4 *tt = Rq->tiles + 2 * (b - Rq->first);
     const int4 tl = tt[0], tz = tt[1];
     switch (tz.z) {
-    case 0: tb_march<K, false, false, PD, W, R, TX, WIDE>(*Ap, Ap, Rq, tl, tz, sE, sH, sGz, sAmp); break;
-    case 1: tb_march<K, true, false, PD, W, R, TX, WIDE>(*Ap, Ap, Rq, tl, tz, sE, sH, sGz, sAmp); break;
-    case 2: tb_march<K, false, true, PD, W, R, TX, WIDE>(*Ap, Ap, Rq, tl, tz, sE, sH, sGz, sAmp); break;
-    default: tb_march<K, true, true, PD, W, R, TX, WIDE>(*Ap, Ap, Rq, tl, tz, sE, sH, sGz, sAmp); break;
+    case 0: tb_march<K, false, false, PD, W, R, TX, WIDE, LOSSY>(*Ap, Ap, Rq, tl, tz, sE, sH, sGz, sAmp); break;
+    case 1: tb_march<K, true, false, PD, W, R, TX, WIDE, LOSSY>(*Ap, Ap, Rq, tl, tz, sE, sH, sGz, sAmp); break;
+    case 2: tb_march<K, false, true, PD, W, R, TX, WIDE, LOSSY>(*Ap, Ap, Rq, tl, tz, sE, sH, sGz, sAmp); break;
+    default: tb_march<K, true, true, PD, W, R, TX, WIDE, LOSSY>(*Ap, Ap, Rq, tl, tz, sE, sH, sGz, sAmp); break;
     }
 }
 
-template <int K, int W, int R, int PD, int TX, bool WIDE = false>
+template <int K, int W, int R, int PD, int TX, bool WIDE = false, bool LOSSY = false>
 hipError_t launch_kwrp(const TbLaunch &L, hipStream_t s)
 {
     constexpr int threads = 64 * W;
     if (L.nblocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_tb_forward<K, PD, W, R, TX, WIDE>), dim3(L.nblocks), dim3(threads), 0, s, L);
+    hipLaunchKernelGGL((k_tb_forward<K, PD, W, R, TX, WIDE, LOSSY>), dim3(L.nblocks), dim3(threads), 0, s, L);
     return hipGetLastError();
 }
 
@@ -723,9 +743,17 @@ bool tb_tile_aligned(int shape) { return shape_index(shape) >= 2; }
 bool tb_wide_shape(int shape) { return shape_index(shape) == 3; }
 int tb_wg_per_cu(int shape) { return SHAPE_W[shape_index(shape)] <= 8 ? 2 : 1; }
 
-hipError_t launch_tb_forward(const TbLaunch &L, int K, int shape, bool wide, hipStream_t s)
+bool tb_lossy_ok(int K, int shape, bool wide) { return !wide && shape_index(shape) == 3 && (K == 1 || K == 2); }
+
+hipError_t launch_tb_forward(const TbLaunch &L, int K, int shape, bool wide, bool lossy, hipStream_t s)
 {
     shape = shape_index(shape);
+    if (lossy) {
+        // conducting cells: the default shape, 32-bit offsets, K = 1 or 2
+        if (!tb_lossy_ok(K, shape, wide)) return hipErrorInvalidValue;
+        return K == 1 ? launch_kwrp<1, 8, 1, 1, ALIGN_X + 2, false, true>(L, s)
+                      : launch_kwrp<2, 8, 1, 1, ALIGN_X + 4, false, true>(L, s);
+    }
     switch (K) {
     case 1: return launch_k<1>(L, shape, wide, s);
     case 2: return launch_k<2>(L, shape, wide, s);

@@ -87,7 +87,10 @@ template <int W> struct RevLds {
 };
 
 // One tile's reverse march.
-template <bool XP, bool YP, bool WIDE, int W>
+// LOSSY: the instance for handles with conducting cells (a lossy box):
+// there E^n is not un-updated but read from the record of step n, dJ/dd
+// takes -sigma E^n beside curl H, and the adjoint E passes ca Ebar' on.
+template <bool XP, bool YP, bool WIDE, int W, bool LOSSY>
 __device__ __forceinline__ void rev_march(KArgs &A, KArgs *Kp, KReq *Rq, const int4 tl, const int4 tz,
                                           RevLds<W> &L_)
 {
@@ -433,15 +436,38 @@ __device__ __forceinline__ void rev_march(KArgs &A, KArgs *Kp, KReq *Rq, const i
             const float dz_hx = hx - Hm0, dx_hz = hz - hz_x;
             const float dx_hy = hy - hy_x, dy_hx = hx - hx_y;
             const bool hex = y == 0 || a == 0, hey = x == 0 || a == 0, hez = x == 0 || y == 0;
+            // a conducting cell: E^n from the record of step n, and sigma
+            bool lossy = false;
+            float len[3] = {0.f, 0.f, 0.f}, lsg = 0.f;
+            if constexpr (LOSSY) {
+                if (interior && has_rec_h && a >= Kp->g.llo[2] && a < Kp->g.lhi[2] && x >= Kp->g.llo[0] &&
+                    x < Kp->g.lhi[0] && y >= Kp->g.llo[1] && y < Kp->g.lhi[1]) {
+                    const int bx = Kp->g.lhi[0] - Kp->g.llo[0], by = Kp->g.lhi[1] - Kp->g.llo[1];
+                    const long long li = ((long long)(a - Kp->g.llo[2]) * by + (y - Kp->g.llo[1])) * bx +
+                                         (x - Kp->g.llo[0]);
+                    const long long nb = (long long)bx * by * (Kp->g.lhi[2] - Kp->g.llo[2]);
+                    const float *lr = Rk->rec_h + Kp->R.loff + li;
+                    len[0] = gld(lr); len[1] = gld(lr + nb); len[2] = gld(lr + 2 * nb);
+                    lsg = gld(Kp->g.lsig + li);
+                    lossy = true;
+                }
+            }
             // dJ/dd += Ebar' . curl H^{n+1/2} (also in the adjoint-only mode,
-            // where the forward state comes from storage instead of the inverse)
+            // where the forward state comes from storage instead of the inverse);
+            // a conducting cell's term is Ebar' . (curl H - sigma E^n)
             if (interior && do_adj && has_gacc && own && a >= z0 && a < z1 && in_design_xy && a >= A.dlo.z &&
                 a < A.dhi.z) {
                 const long long dc = (long long)(a - A.dlo.z) * dplane + dxy;
                 float acc = gld(Rk->gacc + dc);
-                if (!hex) acc = fmaf(Pa.ae[0], dy_hz - dz_hy, acc);
-                if (!hey) acc = fmaf(Pa.ae[1], dz_hx - dx_hz, acc);
-                if (!hez) acc = fmaf(Pa.ae[2], dx_hy - dy_hx, acc);
+                if (!lossy) {
+                    if (!hex) acc = fmaf(Pa.ae[0], dy_hz - dz_hy, acc);
+                    if (!hey) acc = fmaf(Pa.ae[1], dz_hx - dx_hz, acc);
+                    if (!hez) acc = fmaf(Pa.ae[2], dx_hy - dy_hx, acc);
+                } else {
+                    if (!hex) acc = fmaf(Pa.ae[0], fmaf(-lsg, len[0], dy_hz - dz_hy), acc);
+                    if (!hey) acc = fmaf(Pa.ae[1], fmaf(-lsg, len[1], dz_hx - dx_hz), acc);
+                    if (!hez) acc = fmaf(Pa.ae[2], fmaf(-lsg, len[2], dx_hy - dy_hx), acc);
+                }
                 *(GLOBAL float *)(Rk->gacc + dc) = acc;
             }
             if (do_inv && interior) {
@@ -463,6 +489,7 @@ __device__ __forceinline__ void rev_march(KArgs &A, KArgs *Kp, KReq *Rq, const i
                 if (!hex) ex = e_unupdate(ex, ce, dy_hz, dz_hy);
                 if (!hey) ey = e_unupdate(ey, ce, dz_hx, dx_hz);
                 if (!hez) ez = e_unupdate(ez, ce, dx_hy, dy_hx);
+                if (lossy) { ex = len[0]; ey = len[1]; ez = len[2]; }
                 aEn[0] = ex; aEn[1] = ey; aEn[2] = ez;
             } else {
                 aEn[0] = Pa.e[0]; aEn[1] = Pa.e[1]; aEn[2] = Pa.e[2];
@@ -550,8 +577,21 @@ __device__ __forceinline__ void rev_march(KArgs &A, KArgs *Kp, KReq *Rq, const i
                     stf(5, h_unupdate(hz, S, ey_x - ey, ex_y - ex));
                 }
                 if (do_adj) {
-                    // adjoint E with the transposed H pairs
+                    // adjoint E with the transposed H pairs (a conducting cell
+                    // passes ca Ebar' on)
                     float ex = bAe[0], ey = bAe[1], ez = bAe[2];
+                    if constexpr (LOSSY) {
+                        if (interior && bpl >= Kp->g.llo[2] && bpl < Kp->g.lhi[2] && x >= Kp->g.llo[0] &&
+                            x < Kp->g.lhi[0] && y >= Kp->g.llo[1] && y < Kp->g.lhi[1]) {
+                            const int bx = Kp->g.lhi[0] - Kp->g.llo[0], by = Kp->g.lhi[1] - Kp->g.llo[1];
+                            const long long li = ((long long)(bpl - Kp->g.llo[2]) * by + (y - Kp->g.llo[1])) * bx +
+                                                 (x - Kp->g.llo[0]);
+                            const float ca = gld(Kp->g.lca + li);
+                            if (!hex) ex = ca * ex;
+                            if (!hey) ey = ca * ey;
+                            if (!hez) ez = ca * ez;
+                        }
+                    }
                     if (!hex) {
                         const float ra = Rz0 - bR[0];
                         const float rb = sR[0][rd][lane] - bR[1];
@@ -666,8 +706,8 @@ __device__ __forceinline__ void rev_march(KArgs &A, KArgs *Kp, KReq *Rq, const i
 
 // The kernel: block b (XCD-remapped) finds its request and tile; the tile's
 // class picks the march instance.
-template <bool WIDE, int W>
-__global__ __launch_bounds__(64 * W, W == 12 ? 3 : 4) void k_tb_reverse(RevLaunch)
+template <bool WIDE, int W, bool LOSSY>
+__global__ __launch_bounds__(64 * W, 4) void k_tb_reverse(RevLaunch)
 {
     __shared__ RevLds<W> lds;
     // (the launch block is the kernel's only parameter, at offset 0 of the
@@ -686,10 +726,10 @@ __global__ __launch_bounds__(64 * W, W == 12 ? 3 : 4) void k_tb_reverse(RevLaunc
     const int4 *tt = Rq->tiles + 2 * (b - Rq->first);
     const int4 tl = tt[0], tz = tt[1];
     switch (tz.z) {
-    case 0: rev_march<false, false, WIDE, W>(*Ap, Ap, Rq, tl, tz, lds); break;
-    case 1: rev_march<true, false, WIDE, W>(*Ap, Ap, Rq, tl, tz, lds); break;
-    case 2: rev_march<false, true, WIDE, W>(*Ap, Ap, Rq, tl, tz, lds); break;
-    default: rev_march<true, true, WIDE, W>(*Ap, Ap, Rq, tl, tz, lds); break;
+    case 0: rev_march<false, false, WIDE, W, LOSSY>(*Ap, Ap, Rq, tl, tz, lds); break;
+    case 1: rev_march<true, false, WIDE, W, LOSSY>(*Ap, Ap, Rq, tl, tz, lds); break;
+    case 2: rev_march<false, true, WIDE, W, LOSSY>(*Ap, Ap, Rq, tl, tz, lds); break;
+    default: rev_march<true, true, WIDE, W, LOSSY>(*Ap, Ap, Rq, tl, tz, lds); break;
     }
 }
 
@@ -705,10 +745,17 @@ constexpr int REV_W = 8;
 int rev_tile_y() { return rows_of(REV_W) - 2 * HALO; }
 int rev_wg_per_cu() { return 2; }
 
-hipError_t launch_tb_reverse(const RevLaunch &L, bool wide, hipStream_t s)
+hipError_t launch_tb_reverse(const RevLaunch &L, bool wide, bool lossy, hipStream_t s)
 {
     if (L.nblocks <= 0) return hipSuccess;
-    if (wide) hipLaunchKernelGGL((k_tb_reverse<true, REV_W>), dim3(L.nblocks), dim3(64 * REV_W), 0, s, L);
-    else hipLaunchKernelGGL((k_tb_reverse<false, REV_W>), dim3(L.nblocks), dim3(64 * REV_W), 0, s, L);
+    if (lossy) {
+        // conducting cells: 32-bit offsets only
+        if (wide) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_tb_reverse<false, REV_W, true>), dim3(L.nblocks), dim3(64 * REV_W), 0, s, L);
+    } else if (wide) {
+        hipLaunchKernelGGL((k_tb_reverse<true, REV_W, false>), dim3(L.nblocks), dim3(64 * REV_W), 0, s, L);
+    } else {
+        hipLaunchKernelGGL((k_tb_reverse<false, REV_W, false>), dim3(L.nblocks), dim3(64 * REV_W), 0, s, L);
+    }
     return hipGetLastError();
 }

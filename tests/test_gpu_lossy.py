@@ -4,7 +4,8 @@ A conducting cell damps E by ca = (1-u)/(1+u) < 1 per step, so the time
 reversal of section 2.2 does not invert it: the record keeps E^n of the
 lossy box every step and the inverse replays it, as it replays the PML
 interface layers.  Tolerances as in the other parity tests: fields, traces
-and records rel-L2 <= 1e-4, gradients rel-L2 <= 1e-3.
+and records rel-L2 <= 1e-4, gradients rel-L2 <= 1e-3.  The z-march's lossy
+instances are also compared bit for bit with the per-cell kernels.
 """
 import dataclasses
 
@@ -54,7 +55,7 @@ def test_lossy_forward_and_record_parity():
     announce("lossy forward + record 40x36x44 p=6 T=160")
     st, J, trace, rec = Oracle(pr).run(record=True)
     s = _solver(pr, record=True)
-    assert s.kernel_path == "per-cell"
+    assert s.kernel_path == "z-march"
     tr, Jg = s.forward()
     f = gpu_fields(s)
     assert rel_l2(f, st[:6]) <= FIELD_TOL
@@ -128,3 +129,82 @@ def test_lossy_checkpointed_refused_and_validation():
                               lossy_hi=(pr.lossy_hi[0] - sh,) + tuple(pr.lossy_hi[1:]))
     with pytest.raises(FdtdError, match="lossy box"):
         _solver(bad, record=True)
+
+
+def _run(pr, record=True):
+    s = _solver(pr, record=record)
+    path = s.kernel_path
+    tr, J = s.forward()
+    torch.cuda.synchronize()
+    f = [x.cpu().numpy().copy() for x in s.fields()]
+    rec = np.stack([s.record_step(n).cpu().numpy() for n in (0, pr.T // 2, pr.T - 1)]) if record else None
+    out = (f, tr.cpu().numpy().copy(), float(J.item()), rec)
+    g = None
+    if record:
+        dg, recon = s.grad()
+        torch.cuda.synchronize()
+        g = (dg.cpu().numpy().copy(), float(recon.item()))
+    s.close()
+    return path, out, g
+
+
+@pytest.mark.parametrize("case", ["design", "wide_box", "pec"])
+def test_lossy_zmarch_bitwise_equal_to_per_cell(case, monkeypatch):
+    """The lossy instances of the forward and fused reverse z-marches give the
+    bits of the per-cell kernels: fields, trace, J, record (interface and
+    lossy part), dJ/deps and the reconstruction error; on a grid wide enough
+    for interior and slab tiles in x and y, with the lossy box on the design
+    box, across many tiles (and their halos), and in a conducting box from
+    index 0."""
+    if case == "pec":
+        pr = W.config1(T=120)
+        lo, hi = (0, 3, 5), (20, 32, 27)
+        rng = np.random.default_rng(51)
+        sig = rng.uniform(0.0, 1.0, size=(hi[2] - lo[2], hi[1] - lo[1], hi[0] - lo[0])).astype(np.float32)
+        pr = dataclasses.replace(pr, sigma=sig, lossy_lo=lo, lossy_hi=hi)
+    else:
+        pr = W.small_cpml(nx=134, ny=74, nz=40, p=5, T=80, d=10, seed=52, name="lz")
+        if case == "design":
+            pr = W.with_lossy(pr)
+        else:
+            pr = W.with_lossy(pr, lo=(6, 7, 8), hi=(120, 66, 30), sigma_max=0.5)
+    announce(f"lossy z-march vs per-cell, case {case}")
+    path, out, g = _run(pr)
+    assert path == "z-march"
+    monkeypatch.setenv("FDTD_NAIVE", "1")
+    path0, out0, g0 = _run(pr)
+    assert path0 == "per-cell"
+    for a, b in zip(out[0], out0[0]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(out[1], out0[1]) and out[2] == out0[2]
+    assert np.array_equal(out[3], out0[3])
+    assert np.array_equal(g[0], g0[0]) and g[1] == g0[1]
+
+
+def test_lossy_handle_in_a_batch():
+    """A lossy handle batched with a lossless one: each gets the bits of its
+    own single-handle calls (the batch runs one launch per instance)."""
+    from paper_2412_12360_amd.fdtd import Solver, forward_batch, grad_steps_batch
+    a = W.with_lossy(W.small_cpml(nx=70, ny=45, nz=38, p=5, T=60, d=8, seed=53, name="la"))
+    b = W.small_cpml(nx=40, ny=36, nz=44, p=6, T=60, d=8, seed=54, name="lb")
+    announce("lossy handle in a batch")
+    ref = []
+    for pr in (a, b):
+        s = Solver(pr, record=True)
+        s.forward(25)
+        s.forward(35)
+        g, _ = s.grad()
+        torch.cuda.synchronize()
+        ref.append(g.cpu().numpy().copy())
+    st = torch.cuda.current_stream()
+    sol = [Solver(pr, record=True, stream=st) for pr in (a, b)]
+    forward_batch(sol, [25, 25])
+    forward_batch(sol, [35, 35])
+    for s in sol:
+        s.grad_begin()
+    grad_steps_batch(sol, [30, 30])
+    grad_steps_batch(sol, [30, 30])
+    for s, r in zip(sol, ref):
+        g, _ = s.grad_end()
+        torch.cuda.synchronize()
+        assert np.array_equal(g.cpu().numpy(), r)
