@@ -310,6 +310,9 @@ def fwd_grad_run(pg, Solver, torch, time_block: int, workload: str, checkpoint: 
         "avg_launch_ms": round(rev_ms, 5), "launches_timed": pg.T,
         "traffic": measured_rev_traffic(pg),
     }
+    tr = res["roofline_reverse"]["traffic"]
+    # the counted HBM bytes over the same launch time (what the memory system moved)
+    res["roofline_reverse"]["traffic_gbs"] = round(tr / (rev_ms / 1e3) / 1e9, 1) if tr else None
     if checkpoint:
         # the baseline the time reversal replaces: checkpoints every sqrt(T)
         # steps, each segment recomputed and kept, adjoint-only reverse steps
@@ -654,6 +657,9 @@ def main():
             "launches_timed": passes,
         },
     }
+    tr = out["roofline"]["traffic"]
+    # the counted HBM bytes over the same launch time (what the memory system moved)
+    out["roofline"]["traffic_gbs"] = round(tr / (pass_ms / 1e3) / 1e9, 1) if tr else None
 
     progress("headline forward")
     if not args.no_variants:
