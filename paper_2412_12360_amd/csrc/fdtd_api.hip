@@ -363,21 +363,24 @@ int zchunk(const Geometry &G, int K, bool reverse)
     const char *e = getenv(reverse ? "FDTD_REV_ZC" : "FDTD_TB_ZC");
     if (e && atoi(e) > 0) return std::min(atoi(e), G.nz);
     if (reverse) {
-        // The reverse march is kept short: the longest of at most 20 planes
-        // that still gives four workgroups per slot, else 8.  One launch holds
-        // every tile class, so many short marches balance the slab classes'
-        // longer ones.  Measured: 10-11 planes on 200^3 (0.351 against 0.376
-        // ms per step at 20, 0.391 at 5), 20 on 640x640x400 (5.26 against 5.38
-        // ms per step at 58).  Planes of 2M cells or more take even marches of
-        // up to 60 planes while those leave eight workgroups per slot: 50 x 3
-        // on 2400x1600x150 (18.0 against 20.0-21.0 ms per step at 19).
+        // The reverse march is kept short: the longest of at most 20 planes that
+        // still gives four workgroups per slot and leaves no last chunk shorter
+        // than half a march (which would hold a march of a few planes and its
+        // whole z halo), else 8.  One launch holds every tile class, so many
+        // short marches balance the slab classes' longer ones.  Measured on
+        // 200^3: 10 planes 0.346 ms per step (11 with a 2-plane last chunk
+        // 0.361, 8: 0.354, 13: 0.371, 15: 0.364, 20: 0.376).  Planes of 2M
+        // cells or more take even marches of up to 60 planes while those leave
+        // eight workgroups per slot: 58 x 7 on 640x640x400, 50 x 3 on
+        // 2400x1600x150 (18.0 against 20.0-21.0 ms per step at 19).
         const long long tx = (long long)split_uniform(G.nx, rev_tile_x()).size();
         const long long ty = (long long)split_axis(G.ny, rev_tile_y()).size();
         const long long slots = (long long)rev_wg_per_cu() * 256;
         if ((long long)G.nx * G.ny >= (2LL << 20) && tx * ty * ((G.nz + 59) / 60) >= 8 * slots)
             return even_chunk(G.nz, std::min(60, G.nz));
         for (int zc = std::min(20, G.nz); zc > 8; zc--)
-            if (tx * ty * ((G.nz + zc - 1) / zc) >= 4 * slots) return even_chunk(G.nz, zc);
+            if (tx * ty * ((G.nz + zc - 1) / zc) >= 4 * slots && (G.nz % zc == 0 || 2 * (G.nz % zc) >= zc))
+                return zc;
         return even_chunk(G.nz, std::min(8, G.nz));
     }
     // The forward march: a longer one fetches its 2K-plane z halo less often

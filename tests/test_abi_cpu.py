@@ -202,3 +202,4 @@ def test_lossy_box_record_and_validation():
     assert status(t) == F.FDTD_E_INVALID
     assert "lossy box" in F.lib().fdtd_last_error(None).decode()
     assert status(lp) == F.FDTD_OK
+

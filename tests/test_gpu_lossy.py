@@ -208,3 +208,44 @@ def test_lossy_handle_in_a_batch():
         g, _ = s.grad_end()
         torch.cuda.synchronize()
         assert np.array_equal(g.cpu().numpy(), r)
+
+
+@pytest.mark.parametrize("naive", [False, True])
+def test_lossy_adjoint_is_transpose_on_gpu(naive, monkeypatch):
+    """<M x, y> = <x, M^T y> with the GPU forward and adjoint steps of a
+    problem with a lossy box (z-march lossy instances, and per-cell)."""
+    monkeypatch.setenv("FDTD_NAIVE", "1" if naive else "0")
+    pr = W.with_lossy(W.small_cpml(nx=70, ny=45, nz=38, p=5, T=4, d=10, seed=55), sigma_max=1.5)
+    pr = dataclasses.replace(pr, pml_kappa_max=2.0)
+    announce(f"lossy dot product naive={naive}")
+    s = _solver(pr, record=True)
+    assert s.kernel_path == ("per-cell" if naive else "z-march")
+    g = torch.Generator(device="cpu").manual_seed(5)
+    k, j, i = np.meshgrid(np.arange(pr.nz), np.arange(pr.ny), np.arange(pr.nx), indexing="ij")
+    hm = torch.from_numpy(np.stack([(j == 0) | (k == 0), (i == 0) | (k == 0), (i == 0) | (j == 0)])).to(s.device)
+    xs, ys = s.state_arrays(0), s.state_arrays(1)
+    for arr in xs + ys:
+        arr.copy_(torch.randn(arr.numel(), generator=g).to(s.device))
+    for q in range(3):
+        xs[q].view(pr.nz, pr.ny, pr.nx)[hm[q]] = 0.0
+        ys[q].view(pr.nz, pr.ny, pr.nx)[hm[q]] = 0.0
+    x0 = [a.double().clone() for a in xs]
+    y0 = [a.double().clone() for a in ys]
+    s.linear_steps(3, adjoint=False)
+    s.linear_steps(3, adjoint=True)
+    torch.cuda.synchronize()
+    Mx = [a.double() for a in s.state_arrays(0)]
+    Mty = [a.double() for a in s.state_arrays(1)]
+    lhs = sum(float(torch.dot(a, b)) for a, b in zip(Mx, y0))
+    rhs = sum(float(torch.dot(a, b)) for a, b in zip(x0, Mty))
+    scale = np.sqrt(sum(float(torch.dot(a, a)) for a in Mx) * sum(float(torch.dot(b, b)) for b in y0))
+    assert abs(lhs - rhs) <= 1e-5 * scale
+    # the loss acts on this map: without it M x differs
+    s2 = _solver(dataclasses.replace(pr, sigma=None), record=True)
+    for a, b in zip(s2.state_arrays(0), x0):
+        a.copy_(b.float())
+    s2.linear_steps(3, adjoint=False)
+    torch.cuda.synchronize()
+    diff = sum(float(torch.sum((a.double() - b) ** 2)) for a, b in zip(s2.state_arrays(0), Mx))
+    norm = sum(float(torch.sum(b ** 2)) for b in Mx)
+    assert np.sqrt(diff / norm) > 1e-3
