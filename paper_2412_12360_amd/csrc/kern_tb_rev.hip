@@ -44,7 +44,22 @@ constexpr int rows_of(int W) { return 64 * W / EX; }
 // every pointer here addresses device global memory; saying so keeps the
 // loads and stores on global (not flat) instructions
 #define GLOBAL __attribute__((address_space(1)))
+#define LDSP __attribute__((address_space(3)))
 __device__ __forceinline__ float gld(const float *p) { return *(const GLOBAL float *)p; }
+
+// Workgroup barrier for the LDS exchanges: waits for this wave's LDS
+// operations only.  (__syncthreads would also wait for every vector memory
+// operation in flight, which includes the loads of the next plane that go
+// straight to LDS and are meant to stay in flight across the barrier; no
+// wave of a workgroup reads another's global writes.)  The memory clobber
+// keeps the compiler from moving memory operations across it.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// main inputs of a plane staged through LDS per thread
+constexpr int RV_NST = 13;
+// word 3 of a raw buffer resource (32-bit data format, no swizzle; the
+// range is the full 32-bit offset space)
+constexpr int BUF_WORD3 = 0x00020000;
 
 __device__ __forceinline__ int remap_xcd_r(int b, int nb)
 {
@@ -63,6 +78,19 @@ template <bool XP, bool YP> struct PsiB {
 template <bool XP, bool YP> struct RPlane {
     float e[3], h[3], ce, ae[3], ah[3];
     PsiB<XP, YP> pb;
+};
+
+// The few values of a march iteration that come from elsewhere than the
+// plane's field sets: record H of plane t on the low faces (case hc, 0 for
+// none), record E^n of plane t-1 on the high faces (case ec), the dJ/dd
+// accumulator of plane t-1 (gin), a conducting cell's E^n and sigma at
+// plane t-1 and its ca at plane t-2.  They are loaded before the next
+// plane's loads are issued, so waiting for them does not wait for those.
+struct Side {
+    float h0 = 0.f, h1 = 0.f, e0 = 0.f, e1 = 0.f, acc = 0.f;
+    float len[3] = {0.f, 0.f, 0.f}, lsg = 0.f, lca = 0.f;
+    int hc = 0, ec = 0;
+    bool gin = false, lossy = false, cin = false;
 };
 
 // WIDE: field and adjoint sets of 4 GiB or more, addressed per plane from a
@@ -92,7 +120,7 @@ template <int W> struct RevLds {
 // takes -sigma E^n beside curl H, and the adjoint E passes ca Ebar' on.
 template <bool XP, bool YP, bool WIDE, int W, bool LOSSY>
 __device__ __forceinline__ void rev_march(KArgs &A, KArgs *Kp, KReq *Rq, const int4 tl, const int4 tz,
-                                          RevLds<W> &L_)
+                                          RevLds<W> &L_, float (&sSt)[RV_NST][64 * W])
 {
     constexpr int EY = rows_of(W);
     auto &sH = L_.sH;
@@ -126,7 +154,7 @@ __device__ __forceinline__ void rev_march(KArgs &A, KArgs *Kp, KReq *Rq, const i
         sGz[e][3] = gH.x; sGz[e][4] = gH.y; sGz[e][5] = gH.z;
     }
     if ((int)threadIdx.x < FD_MAXSRC) sAmp[threadIdx.x] = (int)threadIdx.x < g.nsrc ? g.samp[threadIdx.x][n] : 0.f;
-    __syncthreads();
+    lds_barrier();
     // source and detector planes (uniform; -2^31 when absent), hoisted so the
     // per-plane tests issue no scalar memory load
     constexpr int NONE = -2147483647 - 1;
@@ -190,9 +218,11 @@ __device__ __forceinline__ void rev_march(KArgs &A, KArgs *Kp, KReq *Rq, const i
     // load_raw issues the loads of plane t; finish (one iteration later, so
     // the fetch overlaps a whole plane of work) zeroes what lies outside the
     // grid, replays the record and adds the detector adjoint source.
-    auto load_raw = [&](int t, RPlane<XP, YP> &P) __attribute__((always_inline)) {
+    // fetch(t, f) hands f (component c, base, byte offset) for each of the
+    // 13 main inputs of plane t: E 0-2, H 3-5, S/eps 6, adjoint E 7-9,
+    // adjoint H 10-12.
+    auto fetch = [&](int t, auto &&f) __attribute__((always_inline)) {
         const bool tin = t >= 0 && t < nz;
-        auto ld = [&](const float *base, unsigned o) { return *(const GLOBAL float *)((const GLOBAL char *)base + o); };
         bool detp = false;
 #pragma unroll
         for (int m = 0; m < FD_MAXDET; m++) detp = detp || t == dkq[m];
@@ -203,32 +233,40 @@ __device__ __forceinline__ void rev_march(KArgs &A, KArgs *Kp, KReq *Rq, const i
             const unsigned c = off * 4u, ce_ = oe * 4u, ca_ = off_ah * 4u;
 #pragma unroll
             for (int q = 0; q < 3; q++) {
-                P.e[q] = ld(Kp->fld[ic][q] + pb, ce_);
-                P.h[q] = ld(Kp->fld[ic][3 + q] + pb, c);
+                f(q, Kp->fld[ic][q] + pb, ce_);
+                f(3 + q, Kp->fld[ic][3 + q] + pb, c);
             }
-            P.ce = ld(Kp->g.ce + pb, c);
+            f(6, Kp->g.ce + pb, c);
 #pragma unroll
             for (int q = 0; q < 3; q++) {
-                P.ae[q] = ld((do_adj ? Kp->adj[ia][q] : Kp->fld[ic][q]) + pb, c);
-                P.ah[q] = ld((do_adj ? Kp->adj[ia][3 + q] : Kp->fld[ic][3 + q]) + pb, ca_);
+                f(7 + q, (do_adj ? Kp->adj[ia][q] : Kp->fld[ic][q]) + pb, c);
+                f(10 + q, (do_adj ? Kp->adj[ia][3 + q] : Kp->fld[ic][3 + q]) + pb, ca_);
             }
         } else {
             const unsigned pl = (unsigned)(tin ? t : 0) * nxy;
             const unsigned c = (pl + off) * 4u, ce_ = (pl + oe) * 4u, ca_ = (pl + off_ah) * 4u;
 #pragma unroll
             for (int q = 0; q < 3; q++) {
-                P.e[q] = ld(fin0, ce_ + q * fs);
-                P.h[q] = ld(fin0, c + (3 + q) * fs);
+                f(q, fin0, ce_ + q * fs);
+                f(3 + q, fin0, c + (3 + q) * fs);
             }
-            P.ce = ld(g.ce, c);
+            f(6, g.ce, c);
             // (issued on every path, so the compiler's wait counts stay exact;
             // without an adjoint, ain points at a readable set and finish drops it)
 #pragma unroll
             for (int q = 0; q < 3; q++) {
-                P.ae[q] = ld(ain0, c + q * fs);
-                P.ah[q] = ld(ain0, ca_ + (3 + q) * fs);
+                f(7 + q, ain0, c + q * fs);
+                f(10 + q, ain0, ca_ + (3 + q) * fs);
             }
         }
+    };
+    auto slot = [](RPlane<XP, YP> &P, int c) -> float & {
+        return c < 3 ? P.e[c] : c < 6 ? P.h[c - 3] : c == 6 ? P.ce : c < 10 ? P.ae[c - 7] : P.ah[c - 10];
+    };
+    // psi-bar of plane t (slab cells; zero elsewhere)
+    auto load_psi = [&](int t, RPlane<XP, YP> &P) __attribute__((always_inline)) {
+        const bool tin = t >= 0 && t < nz;
+        auto ld = [&](const float *base, unsigned o) { return *(const GLOBAL float *)((const GLOBAL char *)base + o); };
 #pragma unroll
         for (int q = 0; q < 4; q++) P.pb.z[q] = 0.f;
         if constexpr (XP) {
@@ -258,7 +296,112 @@ __device__ __forceinline__ void rev_march(KArgs &A, KArgs *Kp, KReq *Rq, const i
             }
         }
     };
-    auto finish = [&](int t, const RPlane<XP, YP> &R, RPlane<XP, YP> &P) __attribute__((always_inline)) {
+    // a plane with plain loads into registers
+    auto load_raw = [&](int t, RPlane<XP, YP> &P) __attribute__((always_inline)) {
+        fetch(t, [&](int c, const float *base, unsigned o) __attribute__((always_inline)) {
+            slot(P, c) = *(const GLOBAL float *)((const GLOBAL char *)base + o);
+        });
+        load_psi(t, P);
+    };
+    // the 13 main inputs of plane t straight into the LDS staging buffer
+    // (thread i's value of component c lands at sSt[c][i]: the loads' LDS
+    // address is the wave's base plus 4 bytes per lane), so the plane in
+    // flight holds no registers
+    const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    // (buffer loads: the global_load_lds form would make the compiler treat
+    // every later wait for a plain load as a wait for all of them)
+    auto stage = [&](int t) __attribute__((always_inline)) {
+        fetch(t, [&](int c, const float *base, unsigned o) __attribute__((always_inline)) {
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, -1, BUF_WORD3);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (LDSP void *)&sSt[c][wv * 64], 4, o, 0, 0, 0);
+        });
+    };
+    auto unstage = [&](RPlane<XP, YP> &P) __attribute__((always_inline)) {
+#pragma unroll
+        for (int c = 0; c < RV_NST; c++) slot(P, c) = sSt[c][threadIdx.x];
+    };
+    // record H of plane t on the low-face layers (finish puts it in place)
+    auto load_rech = [&](int t, Side &Sd) __attribute__((always_inline)) {
+        const bool v = t >= 0 && t < nz && incol;
+        if (has_rec_h && v && t >= p - 1 && t < nz - p) {
+            const bool wz = t >= p;
+            long long e = 0, fsr = 0;
+            if (t == p - 1 && wx && wy) {
+                Sd.hc = 1;
+                e = Kp->R.off[4] + (long long)(y - p) * Kp->R.Lu[2] + (x - p);
+                fsr = (long long)Kp->R.Lu[2] * Kp->R.Lv[2];
+            } else if (wz && x == p - 1 && wy) {
+                Sd.hc = 2;
+                e = Kp->R.off[0] + (long long)(t - p) * Kp->R.Lu[0] + (y - p);
+                fsr = (long long)Kp->R.Lu[0] * Kp->R.Lv[0];
+            } else if (wz && y == p - 1 && wx) {
+                Sd.hc = 3;
+                e = Kp->R.off[2] + (long long)(t - p) * Kp->R.Lu[1] + (x - p);
+                fsr = (long long)Kp->R.Lu[1] * Kp->R.Lv[1];
+            }
+            if (Sd.hc != 0) {
+                Sd.h0 = gld(Rk->rec_h + e);
+                Sd.h1 = gld(Rk->rec_h + e + fsr);
+            }
+        }
+    };
+    // everything else of iteration t: phase A's plane a = t-1, phase B's b = t-2
+    auto side_load = [&](int t, Side &Sd) __attribute__((always_inline)) {
+        load_rech(t, Sd);
+        const int a = t - 1, bpl = t - 2;
+        const bool kin = a >= 0 && a < nz;
+        const bool interior = icol && kin && (p == 0 || (a >= p && a < nz - p));
+        if constexpr (LOSSY) {
+            if (interior && has_rec_h && a >= Kp->g.llo[2] && a < Kp->g.lhi[2] && x >= Kp->g.llo[0] &&
+                x < Kp->g.lhi[0] && y >= Kp->g.llo[1] && y < Kp->g.lhi[1]) {
+                const int bx = Kp->g.lhi[0] - Kp->g.llo[0], by = Kp->g.lhi[1] - Kp->g.llo[1];
+                const long long li = ((long long)(a - Kp->g.llo[2]) * by + (y - Kp->g.llo[1])) * bx +
+                                     (x - Kp->g.llo[0]);
+                const long long nb = (long long)bx * by * (Kp->g.lhi[2] - Kp->g.llo[2]);
+                const float *lr = Rk->rec_h + Kp->R.loff + li;
+                Sd.len[0] = gld(lr); Sd.len[1] = gld(lr + nb); Sd.len[2] = gld(lr + 2 * nb);
+                Sd.lsg = gld(Kp->g.lsig + li);
+                Sd.lossy = true;
+            }
+        }
+        Sd.gin = interior && do_adj && has_gacc && own && a >= z0 && a < z1 && in_design_xy && a >= A.dlo.z &&
+                 a < A.dhi.z;
+        if (Sd.gin) Sd.acc = gld(Rk->gacc + ((long long)(a - A.dlo.z) * dplane + dxy));
+        if (do_inv && !interior && p > 0 && incol && kin) {
+            const bool wz = a >= p && a < nz - p;
+            long long e = 0, fsr = 0;
+            if (a == nz - p && wx && wy) {
+                Sd.ec = 1;
+                e = Kp->R.off[5] + (long long)(y - p) * Kp->R.Lu[2] + (x - p);
+                fsr = (long long)Kp->R.Lu[2] * Kp->R.Lv[2];
+            } else if (wz && x == nx - p && wy) {
+                Sd.ec = 2;
+                e = Kp->R.off[1] + (long long)(a - p) * Kp->R.Lu[0] + (y - p);
+                fsr = (long long)Kp->R.Lu[0] * Kp->R.Lv[0];
+            } else if (wz && y == ny - p && wx) {
+                Sd.ec = 3;
+                e = Kp->R.off[3] + (long long)(a - p) * Kp->R.Lu[1] + (x - p);
+                fsr = (long long)Kp->R.Lu[1] * Kp->R.Lv[1];
+            }
+            if (Sd.ec != 0 && has_rec_e) {
+                Sd.e0 = gld(Rk->rec_e + e);
+                Sd.e1 = gld(Rk->rec_e + e + fsr);
+            }
+        }
+        if constexpr (LOSSY) {
+            const bool kb = bpl >= 0 && bpl < nz;
+            const bool ib = icol && kb && (p == 0 || (bpl >= p && bpl < nz - p));
+            if (do_adj && own && bpl >= z0 && bpl < z1 && ib && bpl >= Kp->g.llo[2] && bpl < Kp->g.lhi[2] &&
+                x >= Kp->g.llo[0] && x < Kp->g.lhi[0] && y >= Kp->g.llo[1] && y < Kp->g.lhi[1]) {
+                const int bx = Kp->g.lhi[0] - Kp->g.llo[0], by = Kp->g.lhi[1] - Kp->g.llo[1];
+                const long long li = ((long long)(bpl - Kp->g.llo[2]) * by + (y - Kp->g.llo[1])) * bx +
+                                     (x - Kp->g.llo[0]);
+                Sd.lca = gld(Kp->g.lca + li);
+                Sd.cin = true;
+            }
+        }
+    };
+    auto finish = [&](int t, const RPlane<XP, YP> &R, RPlane<XP, YP> &P, const Side &Sd) __attribute__((always_inline)) {
         const bool tin = t >= 0 && t < nz;
         const bool v = tin && incol;
         const bool va = v && do_adj;
@@ -272,27 +415,10 @@ __device__ __forceinline__ void rev_march(KArgs &A, KArgs *Kp, KReq *Rq, const i
         P.ce = v ? R.ce : 0.f;
         P.pb = R.pb;
         // H^{n+1/2} on the low-face layers comes from the record of step n
-        if (has_rec_h && v && t >= p - 1 && t < nz - p) {
-            const bool wz = t >= p;
-            if (t == p - 1 && wx && wy) {
-                const long long e = Kp->R.off[4] + (long long)(y - p) * Kp->R.Lu[2] + (x - p);
-                const long long fsr = (long long)Kp->R.Lu[2] * Kp->R.Lv[2];
-                P.h[0] = gld(Rk->rec_h + e);
-                P.h[1] = gld(Rk->rec_h + e + fsr);
-            }
-            if (wz && x == p - 1 && wy) {
-                const long long e = Kp->R.off[0] + (long long)(t - p) * Kp->R.Lu[0] + (y - p);
-                const long long fsr = (long long)Kp->R.Lu[0] * Kp->R.Lv[0];
-                P.h[1] = gld(Rk->rec_h + e);
-                P.h[2] = gld(Rk->rec_h + e + fsr);
-            }
-            if (wz && y == p - 1 && wx) {
-                const long long e = Kp->R.off[2] + (long long)(t - p) * Kp->R.Lu[1] + (x - p);
-                const long long fsr = (long long)Kp->R.Lu[1] * Kp->R.Lv[1];
-                P.h[2] = gld(Rk->rec_h + e);
-                P.h[0] = gld(Rk->rec_h + e + fsr);
-            }
-        }
+        // (loaded by side_load)
+        if (Sd.hc == 1) { P.h[0] = Sd.h0; P.h[1] = Sd.h1; }
+        if (Sd.hc == 2) { P.h[1] = Sd.h0; P.h[2] = Sd.h1; }
+        if (Sd.hc == 3) { P.h[2] = Sd.h0; P.h[0] = Sd.h1; }
         // detector adjoint source: dJ/dE^{n+1}, dJ/dH^{n+1/2} (uniform plane
         // test against the hoisted detector planes)
 #pragma unroll
@@ -397,11 +523,13 @@ __device__ __forceinline__ void rev_march(KArgs &A, KArgs *Kp, KReq *Rq, const i
     const int zs = z0, ze = z1 + 2;
     {
         RPlane<XP, YP> R;
+        Side S0;
         load_raw(zs - 1, R);        // plane a = zs - 1 (zero unless in the grid)
-        finish(zs - 1, R, Pa);
+        load_rech(zs - 1, S0);
+        finish(zs - 1, R, Pa, S0);
     }
     // one step of the march; L = the finished plane t
-    auto body = [&](const int t, const RPlane<XP, YP> &L) __attribute__((always_inline)) {
+    auto body = [&](const int t, const RPlane<XP, YP> &L, const Side &Sd) __attribute__((always_inline)) {
         const int a = t - 1, bpl = t - 2;
         float Qa[6], bR[6];
         qcoef(Pa, a, Qa);
@@ -420,7 +548,7 @@ __device__ __forceinline__ void rev_march(KArgs &A, KArgs *Kp, KReq *Rq, const i
         sR[1][row][lane] = bR[2];   // Hz along x
         sR[2][row][lane] = bR[4];   // Hx along y
         sR[3][row][lane] = bR[5];   // Hy along x
-        __syncthreads();
+        lds_barrier();
         const int ru = row + 1 < EY ? row + 1 : row, rd = row > 0 ? row - 1 : row;
         const int lr = lane + 1 < EX ? lane + 1 : lane, ll = lane > 0 ? lane - 1 : lane;
 
@@ -437,28 +565,13 @@ __device__ __forceinline__ void rev_march(KArgs &A, KArgs *Kp, KReq *Rq, const i
             const float dx_hy = hy - hy_x, dy_hx = hx - hx_y;
             const bool hex = y == 0 || a == 0, hey = x == 0 || a == 0, hez = x == 0 || y == 0;
             // a conducting cell: E^n from the record of step n, and sigma
-            bool lossy = false;
-            float len[3] = {0.f, 0.f, 0.f}, lsg = 0.f;
-            if constexpr (LOSSY) {
-                if (interior && has_rec_h && a >= Kp->g.llo[2] && a < Kp->g.lhi[2] && x >= Kp->g.llo[0] &&
-                    x < Kp->g.lhi[0] && y >= Kp->g.llo[1] && y < Kp->g.lhi[1]) {
-                    const int bx = Kp->g.lhi[0] - Kp->g.llo[0], by = Kp->g.lhi[1] - Kp->g.llo[1];
-                    const long long li = ((long long)(a - Kp->g.llo[2]) * by + (y - Kp->g.llo[1])) * bx +
-                                         (x - Kp->g.llo[0]);
-                    const long long nb = (long long)bx * by * (Kp->g.lhi[2] - Kp->g.llo[2]);
-                    const float *lr = Rk->rec_h + Kp->R.loff + li;
-                    len[0] = gld(lr); len[1] = gld(lr + nb); len[2] = gld(lr + 2 * nb);
-                    lsg = gld(Kp->g.lsig + li);
-                    lossy = true;
-                }
-            }
+            const bool lossy = LOSSY && Sd.lossy;
+            const float len[3] = {Sd.len[0], Sd.len[1], Sd.len[2]}, lsg = Sd.lsg;
             // dJ/dd += Ebar' . curl H^{n+1/2} (also in the adjoint-only mode,
             // where the forward state comes from storage instead of the inverse);
             // a conducting cell's term is Ebar' . (curl H - sigma E^n)
-            if (interior && do_adj && has_gacc && own && a >= z0 && a < z1 && in_design_xy && a >= A.dlo.z &&
-                a < A.dhi.z) {
-                const long long dc = (long long)(a - A.dlo.z) * dplane + dxy;
-                float acc = gld(Rk->gacc + dc);
+            if (Sd.gin) {
+                float acc = Sd.acc;
                 if (!lossy) {
                     if (!hex) acc = fmaf(Pa.ae[0], dy_hz - dz_hy, acc);
                     if (!hey) acc = fmaf(Pa.ae[1], dz_hx - dx_hz, acc);
@@ -468,7 +581,7 @@ __device__ __forceinline__ void rev_march(KArgs &A, KArgs *Kp, KReq *Rq, const i
                     if (!hey) acc = fmaf(Pa.ae[1], fmaf(-lsg, len[1], dz_hx - dx_hz), acc);
                     if (!hez) acc = fmaf(Pa.ae[2], fmaf(-lsg, len[2], dx_hy - dy_hx), acc);
                 }
-                *(GLOBAL float *)(Rk->gacc + dc) = acc;
+                *(GLOBAL float *)(Rk->gacc + ((long long)(a - A.dlo.z) * dplane + dxy)) = acc;
             }
             if (do_inv && interior) {
                 float ex = Pa.e[0], ey = Pa.e[1], ez = Pa.e[2];
@@ -493,27 +606,12 @@ __device__ __forceinline__ void rev_march(KArgs &A, KArgs *Kp, KReq *Rq, const i
                 aEn[0] = ex; aEn[1] = ey; aEn[2] = ez;
             } else {
                 aEn[0] = Pa.e[0]; aEn[1] = Pa.e[1]; aEn[2] = Pa.e[2];
-                if (do_inv && p > 0 && incol && kin) {
-                    // E^n on the high-face layers from the record of step n-1 (E^0 = 0)
-                    const bool wz = a >= p && a < nz - p;
-                    if (a == nz - p && wx && wy) {
-                        const long long e = Kp->R.off[5] + (long long)(y - p) * Kp->R.Lu[2] + (x - p);
-                        const long long fsr = (long long)Kp->R.Lu[2] * Kp->R.Lv[2];
-                        aEn[0] = has_rec_e ? gld(Rk->rec_e + e) : 0.f;
-                        aEn[1] = has_rec_e ? gld(Rk->rec_e + e + fsr) : 0.f;
-                    }
-                    if (wz && x == nx - p && wy) {
-                        const long long e = Kp->R.off[1] + (long long)(a - p) * Kp->R.Lu[0] + (y - p);
-                        const long long fsr = (long long)Kp->R.Lu[0] * Kp->R.Lv[0];
-                        aEn[1] = has_rec_e ? gld(Rk->rec_e + e) : 0.f;
-                        aEn[2] = has_rec_e ? gld(Rk->rec_e + e + fsr) : 0.f;
-                    }
-                    if (wz && y == ny - p && wx) {
-                        const long long e = Kp->R.off[3] + (long long)(a - p) * Kp->R.Lu[1] + (x - p);
-                        const long long fsr = (long long)Kp->R.Lu[1] * Kp->R.Lv[1];
-                        aEn[2] = has_rec_e ? gld(Rk->rec_e + e) : 0.f;
-                        aEn[0] = has_rec_e ? gld(Rk->rec_e + e + fsr) : 0.f;
-                    }
+                // E^n on the high-face layers from the record of step n-1 (E^0 = 0;
+                // loaded by side_load)
+                if (do_inv) {
+                    if (Sd.ec == 1) { aEn[0] = Sd.e0; aEn[1] = Sd.e1; }
+                    if (Sd.ec == 2) { aEn[1] = Sd.e0; aEn[2] = Sd.e1; }
+                    if (Sd.ec == 3) { aEn[2] = Sd.e0; aEn[0] = Sd.e1; }
                 }
             }
             if (!(incol && kin)) { aEn[0] = aEn[1] = aEn[2] = 0.f; }
@@ -581,12 +679,8 @@ __device__ __forceinline__ void rev_march(KArgs &A, KArgs *Kp, KReq *Rq, const i
                     // passes ca Ebar' on)
                     float ex = bAe[0], ey = bAe[1], ez = bAe[2];
                     if constexpr (LOSSY) {
-                        if (interior && bpl >= Kp->g.llo[2] && bpl < Kp->g.lhi[2] && x >= Kp->g.llo[0] &&
-                            x < Kp->g.lhi[0] && y >= Kp->g.llo[1] && y < Kp->g.lhi[1]) {
-                            const int bx = Kp->g.lhi[0] - Kp->g.llo[0], by = Kp->g.lhi[1] - Kp->g.llo[1];
-                            const long long li = ((long long)(bpl - Kp->g.llo[2]) * by + (y - Kp->g.llo[1])) * bx +
-                                                 (x - Kp->g.llo[0]);
-                            const float ca = gld(Kp->g.lca + li);
+                        if (Sd.cin) {
+                            const float ca = Sd.lca;
                             if (!hex) ex = ca * ex;
                             if (!hey) ey = ca * ey;
                             if (!hez) ez = ca * ez;
@@ -650,7 +744,7 @@ __device__ __forceinline__ void rev_march(KArgs &A, KArgs *Kp, KReq *Rq, const i
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
 
         // ------------------------------------------------------------ rotate
         Rz0 = bR[0];
@@ -668,40 +762,30 @@ __device__ __forceinline__ void rev_march(KArgs &A, KArgs *Kp, KReq *Rq, const i
         Hm1 = Pa.h[1];
         Pa = L;
     };
-    if constexpr (!XP && !YP) {
-        // Interior tiles: plane t+1 is fetched while plane t is worked on;
-        // two raw plane buffers used alternately (a copy of a plane in flight
-        // would be a use and stall on it).  An odd count gets one more step,
-        // which stores nothing: its planes lie beyond the owned range.
-        RPlane<XP, YP> R0, R1;
-        load_raw(zs, R0);
-        for (int t = zs; t < ze; t += 2) {
-            {
-                asm volatile("" : "+s"(Kp), "+s"(Rk));
-                load_raw(t + 1, R1);
-                RPlane<XP, YP> L;
-                finish(t, R0, L);
-                body(t, L);
-            }
-            {
-                asm volatile("" : "+s"(Kp), "+s"(Rk));
-                load_raw(t + 2, R0);
-                RPlane<XP, YP> L;
-                finish(t + 1, R1, L);
-                body(t + 1, L);
-            }
-        }
-    } else {
-        // slab tiles carry the auxiliaries too and have no registers for a
-        // second plane in flight: fetch and use
-        for (int t = zs; t < ze; t++) {
-            asm volatile("" : "+s"(Kp), "+s"(Rk));
-            RPlane<XP, YP> R, L;
-            load_raw(t, R);
-            finish(t, R, L);
-            body(t, L);
-        }
+    // Plane t+1 is in flight (in the LDS staging buffer) while plane t is
+    // worked on.  The psi-bar and side loads of an iteration are issued
+    // before the next plane's, so waiting for them does not wait for the
+    // next plane (vector memory operations complete in order); the stage
+    // reads are complete before the next plane's loads write over them.
+    stage(zs);
+    for (int t = zs; t < ze; t++) {
+        asm volatile("" : "+s"(Kp), "+s"(Rk));
+        RPlane<XP, YP> R, L;
+        Side Sd;
+        // (the compiler's own waits for loads that write LDS are not relied on)
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        unstage(R);
+        load_psi(t, R);
+        side_load(t, Sd);
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        // (issued on every iteration, so the compiler's wait counts for the
+        // side loads stay exact; the last one fetches plane t again, from L2)
+        stage(t + 1 < ze ? t + 1 : t);
+        finish(t, R, L, Sd);
+        body(t, L, Sd);
     }
+    // nothing may still be writing the workgroup's LDS when it ends
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
 // The kernel: block b (XCD-remapped) finds its request and tile; the tile's
@@ -710,6 +794,9 @@ template <bool WIDE, int W, bool LOSSY>
 __global__ __launch_bounds__(64 * W, 4) void k_tb_reverse(RevLaunch)
 {
     __shared__ RevLds<W> lds;
+    // (a variable of its own, so the compiler sees that the LDS exchanges do
+    // not touch the staging buffer and does not wait for its loads there)
+    __shared__ float sSt[RV_NST][64 * W];
     // (the launch block is the kernel's only parameter, at offset 0 of the
     // kernel-argument segment)
     KLaunch *Lp = (KLaunch *)__builtin_amdgcn_kernarg_segment_ptr();
@@ -726,10 +813,10 @@ __global__ __launch_bounds__(64 * W, 4) void k_tb_reverse(RevLaunch)
     const int4 *tt = Rq->tiles + 2 * (b - Rq->first);
     const int4 tl = tt[0], tz = tt[1];
     switch (tz.z) {
-    case 0: rev_march<false, false, WIDE, W, LOSSY>(*Ap, Ap, Rq, tl, tz, lds); break;
-    case 1: rev_march<true, false, WIDE, W, LOSSY>(*Ap, Ap, Rq, tl, tz, lds); break;
-    case 2: rev_march<false, true, WIDE, W, LOSSY>(*Ap, Ap, Rq, tl, tz, lds); break;
-    default: rev_march<true, true, WIDE, W, LOSSY>(*Ap, Ap, Rq, tl, tz, lds); break;
+    case 0: rev_march<false, false, WIDE, W, LOSSY>(*Ap, Ap, Rq, tl, tz, lds, sSt); break;
+    case 1: rev_march<true, false, WIDE, W, LOSSY>(*Ap, Ap, Rq, tl, tz, lds, sSt); break;
+    case 2: rev_march<false, true, WIDE, W, LOSSY>(*Ap, Ap, Rq, tl, tz, lds, sSt); break;
+    default: rev_march<true, true, WIDE, W, LOSSY>(*Ap, Ap, Rq, tl, tz, lds, sSt); break;
     }
 }
 
