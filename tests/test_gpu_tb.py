@@ -49,9 +49,11 @@ def assert_same(a, b):
         assert torch.equal(a["rec"], b["rec"])
 
 
-@pytest.mark.parametrize("shape,p,T", [((70, 45, 38), 5, 37), ((130, 30, 21), 3, 23), ((33, 61, 70), 6, 30)])
+@pytest.mark.parametrize("shape,p,T", [((70, 45, 38), 5, 37), ((130, 30, 21), 3, 23), ((33, 61, 70), 6, 30),
+                                       ((33, 19, 16), 5, 30), ((97, 12, 14), 3, 24), ((21, 18, 12), 0, 40)])
 def test_tb_bitwise_equal_to_naive_all_K(shape, p, T, monkeypatch):
-    pr = W.small_cpml(nx=shape[0], ny=shape[1], nz=shape[2], p=p, T=T)
+    # (a design cube that fits the interior of the thin grids)
+    pr = W.small_cpml(nx=shape[0], ny=shape[1], nz=shape[2], p=p, T=T, d=min(8, min(shape) - 2 * p - 2))
     announce(f"tb bitwise {shape} p={p} T={T} naive")
     ref = run(pr, 1, True, monkeypatch)
     for K in (1, 2, 3, 4):
@@ -91,10 +93,18 @@ def grad_run(pr, naive, monkeypatch):
     return J.clone(), g.clone(), r.clone()
 
 
-@pytest.mark.parametrize("shape,p,T,d", [((70, 45, 38), 5, 40, 8), ((33, 61, 70), 6, 33, 10), ((16, 16, 16), 3, 60, 4)])
+# Degenerate extents: a last x tile of one column (33 = 32 + 1, 97 = 3 x 32 +
+# 1), a y extent below one tile's owned rows (12, 19), a z extent of 2p + 6
+# planes (marches of a few planes, interior of six), and a PEC box (no record).
+DEGENERATE = [((33, 19, 16), 5, 30, 3), ((97, 12, 14), 3, 24, 4), ((21, 18, 12), 0, 40, 4)]
+
+
+@pytest.mark.parametrize("shape,p,T,d", [((70, 45, 38), 5, 40, 8), ((33, 61, 70), 6, 33, 10), ((16, 16, 16), 3, 60, 4)]
+                         + DEGENERATE)
 def test_fused_reverse_bitwise_equal_to_per_cell(shape, p, T, d, monkeypatch):
     """The fused reverse z-march (inverse + adjoint + record replay + detector
-    source in one pass) gives the per-cell reverse step's bits."""
+    source in one pass) gives the per-cell reverse step's bits, on ragged and
+    degenerate extents too."""
     pr = W.small_cpml(nx=shape[0], ny=shape[1], nz=shape[2], p=p, T=T, d=d, seed=31)
     announce(f"fused reverse bitwise {shape} p={p} T={T}")
     J0, g0, r0 = grad_run(pr, True, monkeypatch)
