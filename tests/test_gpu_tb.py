@@ -99,7 +99,10 @@ def grad_run(pr, naive, monkeypatch):
 DEGENERATE = [((33, 19, 16), 5, 30, 3), ((97, 12, 14), 3, 24, 4), ((21, 18, 12), 0, 40, 4)]
 
 
-@pytest.mark.parametrize("shape,p,T,d", [((70, 45, 38), 5, 40, 8), ((33, 61, 70), 6, 100, 10), ((16, 16, 16), 3, 60, 4)]
+# (enough steps for the source's wave to pass the design cube and reach the
+# detector, so every gradient carries signal: the wave moves about 0.38 cells
+# per step in the eps_r = 2.25 background)
+@pytest.mark.parametrize("shape,p,T,d", [((70, 45, 38), 5, 100, 8), ((33, 61, 70), 6, 220, 10), ((16, 16, 16), 3, 60, 4)]
                          + DEGENERATE)
 def test_fused_reverse_bitwise_equal_to_per_cell(shape, p, T, d, monkeypatch):
     """The fused reverse z-march (inverse + adjoint + record replay + detector
@@ -112,7 +115,7 @@ def test_fused_reverse_bitwise_equal_to_per_cell(shape, p, T, d, monkeypatch):
     assert torch.equal(J0, J1)
     assert torch.equal(g0, g1)
     assert torch.equal(r0, r1)
-    assert float(g1.abs().max()) > 0.0
+    assert float(g1.abs().max()) > 1e-3
 
 
 def test_fused_inverse_bitwise_equal_to_per_cell(monkeypatch):
