@@ -81,7 +81,8 @@ def test_wide_instance_bitwise_all_K(shape, p, T, monkeypatch):
         assert torch.equal(out["J"], ref["J"])
 
 
-@pytest.mark.parametrize("shape,p,T", [((70, 45, 38), 5, 37), ((33, 61, 70), 6, 30)])
+# (enough steps for the wave to pass the design cube and reach the detector)
+@pytest.mark.parametrize("shape,p,T", [((70, 45, 38), 5, 100), ((33, 61, 70), 6, 220)])
 def test_wide_gradient_bitwise(shape, p, T, monkeypatch):
     pr = problem(shape, p, T)
     outs = []
@@ -96,7 +97,7 @@ def test_wide_gradient_bitwise(shape, p, T, monkeypatch):
         g, r = s.grad()
         torch.cuda.synchronize()
         outs.append((J.clone(), rec, g.clone(), r.clone(), torch.stack([f.clone() for f in s.fields()])))
-    assert float(outs[0][2].abs().max().item()) > 0.0
+    assert float(outs[0][2].abs().max().item()) > 1e-3
     for a, b in zip(*outs):
         assert torch.equal(a, b)
 
