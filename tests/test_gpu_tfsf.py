@@ -120,11 +120,13 @@ def run(pr, K, naive, monkeypatch):
     }
 
 
-@pytest.mark.parametrize("shape,p,T", [((70, 45, 38), 5, 37), ((33, 61, 70), 6, 30)])
+# (step counts long enough for the wave to reach the detector)
+@pytest.mark.parametrize("shape,p,T", [((70, 45, 38), 5, 90), ((33, 61, 70), 6, 200)])
 def test_tfsf_and_h_source_bitwise_all_K(shape, p, T, monkeypatch):
     pr = with_h_point(tfsf_cpml(shape, p, T))
     announce(f"tfsf + H point bitwise {shape} p={p} T={T} naive")
     ref = run(pr, 1, True, monkeypatch)
+    assert float(ref["trace"].abs().max()) > 1.0
     for K in (1, 2, 3, 4):
         announce(f"tfsf + H point bitwise {shape} p={p} T={T} K={K}")
         out = run(pr, K, False, monkeypatch)

@@ -67,12 +67,15 @@ def run(pr, K, wide, monkeypatch, naive=False):
     }
 
 
-@pytest.mark.parametrize("shape,p,T", [((70, 45, 38), 5, 37), ((33, 61, 70), 6, 30), ((40, 36, 44), 0, 25)])
+# (step counts long enough for the wave to reach the detector; the PEC box
+# has no detector)
+@pytest.mark.parametrize("shape,p,T", [((70, 45, 38), 5, 90), ((33, 61, 70), 6, 200), ((40, 36, 44), 0, 25)])
 def test_wide_instance_bitwise_all_K(shape, p, T, monkeypatch):
     pr = problem(shape, p, T) if p > 0 else W.config1(T=T, n=shape[0])
     for K in (1, 2, 3, 4):
         announce(f"wide vs narrow z-march {shape} p={p} T={T} K={K}")
         _, ref = run(pr, K, False, monkeypatch)
+        assert p == 0 or float(ref["trace"].abs().max()) > 1.0
         _, out = run(pr, K, True, monkeypatch)
         assert torch.equal(out["fields"], ref["fields"])
         for x, y in zip(out["psi"], ref["psi"]):
