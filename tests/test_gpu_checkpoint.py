@@ -77,7 +77,8 @@ def test_revolve_schedules_equal_uniform_checkpointing(schedule, k):
     the same order: the bits of the uniform-segment gradient and objective;
     the oracle's stored-history gradient within the gradient tolerance."""
     from paper_2412_12360_amd.fdtd import Solver
-    T = 60 if k == 0 and schedule == "treeverse" else 90
+    # (90 steps: the wave passes the design cube and reaches the detector)
+    T = 90
     pr = W.small_cpml(nx=70, ny=45, nz=38, p=5, T=T, d=8, seed=23)
     announce(f"revolve {schedule} k={k} T={T}")
     o = Oracle(pr)
@@ -92,6 +93,7 @@ def test_revolve_schedules_equal_uniform_checkpointing(schedule, k):
     assert s.t == 0
     assert float(J.item()) == J_u
     assert np.array_equal(g.cpu().numpy(), g_u)
+    assert np.abs(ref).max() > 1e-3
     assert rel_l2(g.cpu().numpy(), ref) <= GRAD_TOL
     # the store holds the schedule's largest number of kept states
     from paper_2412_12360_amd.fdtd import revolve_plan
