@@ -215,8 +215,8 @@ __device__ __forceinline__ void rev_march(KArgs &A, KArgs *Kp, KReq *Rq, const i
     const int dplane = (A.dhi.x - A.dlo.x) * (A.dhi.y - A.dlo.y);
 
     // ---------------------------------------------------------- plane fetch
-    // load_raw issues the loads of plane t; finish (one iteration later, so
-    // the fetch overlaps a whole plane of work) zeroes what lies outside the
+    // stage issues the loads of plane t (one iteration ahead, so the fetch
+    // overlaps a whole plane of work); finish zeroes what lies outside the
     // grid, replays the record and adds the detector adjoint source.
     // fetch(t, f) hands f (component c, base, byte offset) for each of the
     // 13 main inputs of plane t: E 0-2, H 3-5, S/eps 6, adjoint E 7-9,
