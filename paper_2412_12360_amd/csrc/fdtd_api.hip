@@ -409,6 +409,39 @@ int zchunk(const Geometry &G, int K, bool reverse)
     return bz > 0 ? bz : even_chunk(G.nz, std::min(16, G.nz));
 }
 
+// The kernels hand the XCDs contiguous runs of the table (the first nb % 8
+// runs one tile longer), and each XCD starts its run's tiles in order.
+// Within each run, tiles that own under three quarters of the run's largest
+// tile (the last, partial x or y tile of a row or column) go last, so the
+// run ends on short marches rather than on a full one started late; the
+// order is otherwise kept (neighbouring tiles, which share halo lines in
+// the XCD's L2, stay together).
+void lpt_per_xcd(std::vector<int4> &out, int off, int n)
+{
+    if (n <= 0) return;
+    const int q = n / 8, rem = n % 8;
+    auto cells = [](const std::pair<int4, int4> &u) {
+        return (long long)(u.first.y - u.first.x) * (u.first.w - u.first.z) * (u.second.y - u.second.x);
+    };
+    int a = 0;
+    for (int x = 0; x < 8; x++) {
+        const int len = q + (x < rem ? 1 : 0);
+        std::vector<std::pair<int4, int4>> run(len);
+        long long big = 0;
+        for (int i = 0; i < len; i++) {
+            run[i] = {out[2 * (off + a + i)], out[2 * (off + a + i) + 1]};
+            big = std::max(big, cells(run[i]));
+        }
+        std::stable_partition(run.begin(), run.end(),
+                              [&](const std::pair<int4, int4> &u) { return 4 * cells(u) >= 3 * big; });
+        for (int i = 0; i < len; i++) {
+            out[2 * (off + a + i)] = run[i].first;
+            out[2 * (off + a + i) + 1] = run[i].second;
+        }
+        a += len;
+    }
+}
+
 // Tile tables of the z-march kernels: slot 0 for the fused reverse march,
 // slot K' for a forward sweep of K' = 1..K steps.  Each table lists every
 // tile in spatial order (x fastest, then y, then z chunks) with its class
@@ -447,6 +480,9 @@ void build_tiles(const Geometry &G, int K, std::vector<int4> &out, int off[5], i
                     cnt[kk][c]++;
                 }
         n[kk] = (int)out.size() / 2 - off[kk];
+        // (forward sweeps only: measured on 200^3, the forward with the record
+        // 214.1 against 217.9 ms for 1500 steps, the reverse 546 against 520 ms)
+        if (kk > 0) lpt_per_xcd(out, off[kk], n[kk]);
     }
 }
 
