@@ -90,6 +90,9 @@ struct fdtd_ctx {
     float *raw = nullptr, *eprev = nullptr;  // interpolated detectors: K raw plane sets, E^n planes
     float *red = nullptr;
     float *trace = nullptr, *planes = nullptr, *wdev = nullptr, *rec = nullptr, *gacc = nullptr;
+    // detector planes of up to pcap steps are summed into the trace together:
+    // pfill steps from step pbase are waiting
+    int pcap = 1, pfill = 0, pbase = 0;
     float *parts[2] = {nullptr, nullptr};
     int nparts_cap = 0;
     int4 *tiles = nullptr;                 // tile tables: the reverse march, then every K' <= K
@@ -515,7 +518,15 @@ size_t plan(fdtd_ctx *h, const fdtd_desc *d, const Geometry &G, int K, void *bas
     for (int t = 0; t < FD_MAXSRC / 2; t++) h->twave[t] = t < h->ntfsf ? B.take(d->n_steps) : nullptr;
     h->tline = h->ntfsf > 0 ? B.take(2 * (size_t)tfsf_line_nodes(d->n_steps)) : nullptr;
     h->trace = B.take((size_t)d->n_steps * std::max(1, G.D.ndet));
-    h->planes = B.take((size_t)std::max(1, K) * std::max<long long>(1, G.D.per_step));
+    // the z-march's flux planes of up to pcap steps (a multiple of K, at most
+    // 64, within 256 MB) wait for one fixed-order sum launch
+    {
+        const int k1 = std::max(1, K);
+        const long long ps = std::max<long long>(1, G.D.per_step);
+        const long long fit = std::max<long long>(1, (256LL << 20) / (4 * ps));
+        h->pcap = k1 * (int)std::max<long long>(1, std::min<long long>(64 / k1, fit / k1));
+    }
+    h->planes = B.take((size_t)h->pcap * std::max<long long>(1, G.D.per_step));
     h->raw = G.D.raw_per_step > 0 ? B.take((size_t)std::max(1, K) * G.D.raw_per_step) : nullptr;
     h->eprev = G.D.eprev_floats > 0 ? B.take(G.D.eprev_floats) : nullptr;
     // with the adjoint state, the interpolated detectors' planes of every step
@@ -528,7 +539,7 @@ size_t plan(fdtd_ctx *h, const fdtd_desc *d, const Geometry &G, int K, void *bas
         long long rs = 1;
         for (int m = 0; m < G.D.ndet; m++)
             rs = std::max(rs, reduce_scratch_floats((long long)(G.D.i1[m] - G.D.i0[m]) * (G.D.j1[m] - G.D.j0[m]),
-                                                    std::max(1, K)));
+                                                    h->pcap));
         h->red = B.take(rs);
     }
     build_tiles(G, K, h->host_tiles, h->tb_off, h->tb_n, h->tb_cnt);
@@ -674,7 +685,7 @@ TbReq tb_request(fdtd_ctx *h, int n0, int kk, int with_src, int with_rec, int wi
     q.args = (unsigned long long)(uintptr_t)h->targs;
     q.tiles = h->tiles + 2 * (size_t)h->tb_off[kk];
     q.rec = (with_rec && h->rec && G.R.per_step > 0) ? h->rec + (size_t)n0 * G.R.per_step : nullptr;
-    q.planes = (with_det && G.D.ndet > 0) ? h->planes : nullptr;
+    q.planes = (with_det && G.D.ndet > 0) ? h->planes + (size_t)h->pfill * G.D.per_step : nullptr;
     q.raw = h->drec ? h->drec + (size_t)n0 * G.D.raw_per_step : h->raw;
     q.n0 = n0;
     q.first = first;
@@ -695,20 +706,35 @@ fdtd_status tb_prologue(fdtd_ctx *h, int n0, int with_det)
     return FDTD_OK;
 }
 
+// the fixed-order sums of the waiting steps' detector planes into the trace
+// (each step's sum is the same whichever steps share the launch)
+fdtd_status flush_planes(fdtd_ctx *h)
+{
+    const Geometry &G = h->geo;
+    if (h->pfill <= 0) return FDTD_OK;
+    for (int m = 0; m < G.D.ndet; m++) {
+        const long long L = (long long)(G.D.i1[m] - G.D.i0[m]) * (G.D.j1[m] - G.D.j0[m]);
+        HIPCHK(h, launch_reduce_rows2(h->planes + G.D.off[m], L, h->pfill, G.D.per_step,
+                                      h->trace + (size_t)h->pbase * G.D.ndet + m, G.D.ndet, h->red, h->stream));
+    }
+    h->pfill = 0;
+    return FDTD_OK;
+}
+
 // what follows a forward sweep of kk steps from n0: swap the buffers, the
-// detectors' densities and fixed-order sums into the trace
+// detectors' densities; their sums into the trace once the planes of the
+// next sweep would not fit (and at the end of every forward call)
 fdtd_status tb_epilogue(fdtd_ctx *h, int n0, int kk, int with_det)
 {
     const Geometry &G = h->geo;
     h->cur ^= 1;
     if (!(with_det && G.D.ndet > 0)) return FDTD_OK;
     float *raw = h->drec ? h->drec + (size_t)n0 * G.D.raw_per_step : h->raw;
-    if (h->raw) HIPCHK(h, launch_det_interp(h->g, G.D, raw, h->eprev, kk, h->planes, h->stream));
-    for (int m = 0; m < G.D.ndet; m++) {
-        const long long L = (long long)(G.D.i1[m] - G.D.i0[m]) * (G.D.j1[m] - G.D.j0[m]);
-        HIPCHK(h, launch_reduce_rows2(h->planes + G.D.off[m], L, kk, G.D.per_step,
-                                      h->trace + (size_t)n0 * G.D.ndet + m, G.D.ndet, h->red, h->stream));
-    }
+    float *pl = h->planes + (size_t)h->pfill * G.D.per_step;
+    if (h->raw) HIPCHK(h, launch_det_interp(h->g, G.D, raw, h->eprev, kk, pl, h->stream));
+    if (h->pfill == 0) h->pbase = n0;
+    h->pfill += kk;
+    if (h->pfill + h->K > h->pcap) return flush_planes(h);
     return FDTD_OK;
 }
 
@@ -743,7 +769,7 @@ fdtd_status advance(fdtd_ctx *h, int t0, int n, int with_src, int with_rec, int 
         if (st != FDTD_OK) return st;
         s += kk;
     }
-    return FDTD_OK;
+    return flush_planes(h);
 }
 
 // one reverse step n: restore the interface layers, then the two phases
@@ -1381,6 +1407,8 @@ fdtd_status fdtd_forward_batch(const fdtd_handle *hs, int32_t nh, const int32_t 
     for (int i = 0; i < nh; i++) {
         fdtd_ctx *h = hs[i];
         const Geometry &G = h->geo;
+        st = flush_planes(h);
+        if (st != FDTD_OK) return st;
         h->t = t0[i] + n_steps[i];
         float *trace = traces ? traces[i] : nullptr;
         float *J = Js ? Js[i] : nullptr;
