@@ -1,6 +1,7 @@
 """C-ABI checks that need no GPU: the library loads, exports every entry point
 include/fdtd.h declares, and validates arguments before touching a device."""
 import ctypes as C
+import dataclasses
 import os
 import re
 
@@ -203,3 +204,20 @@ def test_lossy_box_record_and_validation():
     assert "lossy box" in F.lib().fdtd_last_error(None).decode()
     assert status(lp) == F.FDTD_OK
 
+
+
+@pytest.mark.parametrize("K", [1, 2, 3])
+def test_footprint_holds_64_steps_of_detector_planes(K):
+    """The flux planes of the z-march wait in the workspace for up to 64 steps
+    (the largest multiple of K within 64), then one fixed-order launch sums
+    them: a detector window larger by dL cells costs 64 / K * K planes of dL
+    floats more (plus the sums' scratch of ceil(L / 4096) floats per step and
+    the workspace's 256-byte alignment)."""
+    pr = W.small_cpml(nx=40, ny=36, nz=44, p=6, T=100)
+    d = pr.detectors[0]
+    small = dataclasses.replace(pr, detectors=[dataclasses.replace(d, i1=d.i0 + 5, j1=d.j0 + 4)])
+    a = _fp(small, time_block=K)
+    b = _fp(pr, time_block=K)
+    dL = (d.i1 - d.i0) * (d.j1 - d.j0) - 5 * 4
+    cap = 64 // K * K
+    assert cap * dL * 4 <= b - a <= cap * dL * 4 + cap * 4 + 8 * 256
